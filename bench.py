@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Throughput of the meshfree ALE BGK time step on one MI355X.
+
+One "step" is one full bgk_step (neighbour search, least-squares operators,
+upwind transport, moments + implicit relaxation, walls, motion) over every
+particle and velocity of the workload, with all inputs resident in HBM.  The
+metric is particle x velocity updates per second: N * N_v / t_step (a Chu
+pair g1, g2 counts once).
+
+Default workload: the 2D Chu-reduced cavity with 200 x 200 particles and
+32 x 32 velocities on [-5, 5]^2, FP64 (h = 2.5 dx, Kn = 1, lid 0.1).  The
+same run is repeated in FP32 and BF16-operand modes and their moment errors
+against the FP64 run are reported next to their rates.
+
+Printed: one JSON line (the benchmark contract), with the roofline of the
+dominant kernel (the transport, timed with HIP events on the library's
+stream inside the timed region) and the CPU oracle timed on a bounded sample
+of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+# VALU lane-operation issue rate, FP64 and unpacked FP32 alike:
+# 256 CUs x 4 SIMDs x 16 lanes/clock x 2.4 GHz = 39.3e12 lane-ops/s
+# (= the 78.6 TFLOP/s FP64 vector peak with an FMA counted as 2 flops).
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def transport_algorithmic(cav, edges, prec):
+    """Algorithmic work of one transport launch.
+
+    bytes: read every f row once, write every interior f-tilde row once, read
+    the d*d upwind vectors of every edge once.  ops: k VALU lane-ops per
+    (particle, neighbour, velocity) with k = 5 + 2 n_c (2D Chu: two
+    incremental projections, two min(0, .), one add, per component one
+    subtract and one FMA) or 8 + 2 n_c (3D: three projections, three mins,
+    two adds, subtract and FMA)."""
+    s = 8 if prec == "fp64" else 4
+    NV, nc, d = cav.n_velocities, cav.n_comp, cav.dim
+    N = cav.n_particles
+    n_wall = N - cav_interior(cav)
+    bytes_ = N * NV * nc * s + (N - n_wall) * NV * nc * s + edges * d * d * s
+    k = (5 + 2 * nc) if d == 2 else (8 + 2 * nc)
+    ops = edges * NV * k
+    return bytes_, ops, k
+
+
+def cav_interior(cav):
+    return (cav.n - 2) ** cav.dim
+
+
+def run_gpu(cav, precision, steps, warmup, timing=True):
+    import torch
+
+    import paper_2408_02350_amd.bgk as bgk
+
+    sim = bgk.Simulation(cav, precision=precision, device="cuda:0")
+    log(f"[bench] {cav.name} {precision}: N={cav.n_particles} NV={cav.n_velocities} "
+        f"warmup={warmup} steps={steps}")
+    sim.step(warmup)
+    bgk.bgk_check(sim.ctx)
+    torch.cuda.synchronize()
+    if timing:
+        bgk.bgk_timing_enable(sim.ctx, True)
+        bgk.bgk_timing_read(sim.ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bgk.bgk_check(sim.ctx)
+    ktime = bgk.bgk_timing_read(sim.ctx) if timing else (0.0, 0)
+    diag = bgk.bgk_diagnostics(sim.ctx)
+    cnt, _ = bgk.bgk_build_neighbors(sim.ctx, sim.x)
+    interior = sim.wall_id == 0
+    edges = int((cnt[interior] - 1).sum().item())
+    ms = (t1 - t0) * 1e3 / steps
+    log(f"[bench] {precision}: {ms:.4f} ms/step, transport {ktime[0] / max(ktime[1], 1):.4f} ms "
+        f"x {ktime[1]}, edges {edges}, diag {diag}")
+    state = (sim.rho.cpu().numpy(), sim.U.cpu().numpy(), sim.T.cpu().numpy())
+    return ms, ktime, edges, state, diag
+
+
+def moment_errors(state, ref, lid):
+    import numpy as np
+
+    rho, U, T = state
+    r0, U0, T0 = ref
+    e_rho = float(np.max(np.abs(rho - r0)) / np.max(np.abs(r0)))
+    e_T = float(np.max(np.abs(T - T0)) / np.max(np.abs(T0)))
+    e_u = float(np.max(np.sqrt(((U - U0) ** 2).sum(axis=0))) / abs(lid))
+    return e_rho, e_u, e_T
+
+
+def cpu_baseline(cav, budget_s):
+    """The CPU oracle on the host cores, on a bounded sample of the workload:
+    full steps of the same cloud (the first one after the initial state),
+    repeated while the budget lasts (at least one)."""
+    import oracle
+    from paper_2408_02350_amd.inputs import cloud_for
+
+    c = oracle.config(cav)
+    x, wid = cloud_for(cav)
+    f, rho, U, T = oracle.initial_state(c)
+    n, t = 0, 0.0
+    while n == 0 or t < budget_s * 0.5:
+        t0 = time.perf_counter()
+        x, f, U, rho, T, _ = oracle.step(c, wid, x, f, U)
+        t += time.perf_counter() - t0
+        n += 1
+        log(f"[bench] oracle step {n}: {t / n:.2f} s/step")
+        if t / n > budget_s:
+            break
+    per = t / n
+    return {"value": cav.n_particles * cav.n_velocities / per,
+            "unit": "particle-velocity updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n} full step(s) of {cav.name} ({cav.n_particles} particles x "
+                      f"{cav.n_velocities} velocities) from the rest state, FP64, "
+                      f"{per:.2f} s/step"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2", help="c1..c5 (default c2)")
+    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/BF16 runs")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              "(the multi-GPU velocity-sharded design is not built)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2408_02350_amd.inputs import CONFIGS
+
+    cav = CONFIGS[args.workload].replace(precision=args.precision)
+    ms, ktime, edges, state, diag = run_gpu(cav, args.precision, args.steps, args.warmup)
+    updates = cav.n_particles * cav.n_velocities
+    value = updates / (ms * 1e-3)
+
+    k_ms = ktime[0] / max(ktime[1], 1)
+    bytes_, ops, k = transport_algorithmic(cav, edges, args.precision)
+    t_alu = ops / (PEAK_VALU_TOPS * 1e12)
+    t_hbm = bytes_ / (PEAK_HBM_GBS * 1e9)
+    ach_gbs = bytes_ / (k_ms * 1e-3) / 1e9
+    ach_tops = ops / (k_ms * 1e-3) / 1e12
+    if t_alu >= t_hbm:
+        roof = {"bound": "alu", "achieved": ach_tops, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
+                "frac": ach_tops / PEAK_VALU_TOPS}
+    else:
+        roof = {"bound": "hbm", "achieved": ach_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach_gbs / PEAK_HBM_GBS}
+    roof.update({"traffic": None, "kernel": "k_transport", "kernel_ms": k_ms,
+                 "algorithmic_bytes": bytes_, "algorithmic_ops": ops, "ops_per_update": k,
+                 "hbm_frac": ach_gbs / PEAK_HBM_GBS, "alu_frac": ach_tops / PEAK_VALU_TOPS,
+                 "step_share": k_ms / ms})
+
+    out = {
+        "metric": "particle×velocity updates/sec per step (FP64 vs mixed) at stated moment error",
+        "value": value,
+        "unit": "particle-velocity updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16xf32"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": cav.name, "dim": cav.dim, "n_particles": cav.n_particles,
+                   "n_velocities": cav.n_velocities, "n_comp": cav.n_comp, "kn": cav.kn,
+                   "h_over_dx": cav.h_factor, "wls_degree": cav.wls_degree,
+                   "precision": args.precision, "move": cav.move,
+                   "parallelism": "single-gpu"},
+        "roofline": roof,
+    }
+
+    if not args.no_mixed and args.precision == "fp64":
+        mixed = {}
+        for p in ("fp32", "bf16"):
+            ms_p, kt_p, _, st_p, _ = run_gpu(cav.replace(precision=p), p, args.steps,
+                                            args.warmup)
+            e_rho, e_u, e_T = moment_errors(st_p, state, cav.lid)
+            mixed[p] = {"value": updates / (ms_p * 1e-3), "ms_per_step": ms_p,
+                        "transport_ms": kt_p[0] / max(kt_p[1], 1),
+                        "speedup_vs_fp64": ms / ms_p, "e_rho": e_rho, "e_u": e_u, "e_T": e_T,
+                        "after_steps": args.warmup + args.steps}
+        out["mixed"] = mixed
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cav.replace(precision="fp64"), args.cpu_seconds)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+/*
+ * bgk.h -- C interface of libbgk: the per-time-step update of the meshfree
+ * Arbitrary-Lagrangian-Eulerian (ALE) method for the BGK equation
+ * (Mariappan, Willems, Boregowda, Tiwari, Klar, "High-performance computing
+ * for the BGK model of the Boltzmann equation with a meshfree ALE method"),
+ * implemented as HIP kernels for AMD Instinct MI355X (gfx950).
+ *
+ * One time step (Sections 3.1-3.5):
+ *   S1  neighbour search in a cell list over the moving cloud     (Sec. 3.5.1)
+ *   S2  weighted least-squares (WLS) gradient operators           (Sec. 3.4.1)
+ *   S3  edge frames and positive-upwind vectors                   (Sec. 3.4.2)
+ *   S4  explicit transport  ft = f - dt (v-U^n).grad f            (Sec. 3.1, eq. explicit)
+ *   S5  moments of ft: rho, U, T                                  (eqs. fullmoment1a / moment1a, moment1b)
+ *   S6  implicit BGK relaxation f = (tau ft + dt M)/(tau + dt)    (Sec. 3.1, closed form after implicitfull_1)
+ *   S7  diffuse-reflection walls with a moving lid                (Sec. 5; Table 3)
+ *   S8  ALE motion  x^{n+1} = x^n + dt U^{n+1}                    (Sec. 3.1)
+ *
+ * Conventions (all entry points):
+ *   - Every function returns an int: BGK_OK (0) or a positive bgk_status.
+ *     Nothing throws across this interface and nothing aborts.
+ *   - Array arguments are DEVICE pointers owned by the caller, except where a
+ *     comment says "host".  The library never allocates device memory: it
+ *     owns only the host-side context, and uses a caller-supplied device
+ *     workspace of bgk_workspace_bytes() bytes.
+ *   - Work is enqueued on the HIP stream given to bgk_init (as void*; NULL is
+ *     the default stream).  Calls return before the GPU work finishes.
+ *   - Errors that depend on data (neighbour overflow, singular least squares,
+ *     non-physical moments) are recorded in a device error word; bgk_check()
+ *     synchronises the stream and returns (and clears) them.
+ *   - Layouts (row-major):
+ *       x, U      double [d][N]            (component-major)
+ *       rho, T    double [N]
+ *       f         [n_c][N][N_v] of double (BGK_FP64) or float (BGK_FP32,
+ *                 BGK_BF16); n_c = 2 (g1, g2) for dim 2, 1 for dim 3;
+ *                 velocity index q = k1 + nv*k2 (+ nv^2*k3)
+ *       nbr_idx   int32 [N][max_neighbors], first nbr_cnt[i] entries used,
+ *                 ascending, the particle itself included
+ *       grad      double [N][max_neighbors][d]
+ *       ops       double [N][max_neighbors][d*d]: P (d values), Q (d)
+ *                 [, R (d)] per neighbour slot
+ *   - Velocity grid (Sec. 3.2, read as nv points per axis including both
+ *     ends): v_k = vmax*(2k-(nv-1))/(nv-1), k = 0..nv-1; every node has the
+ *     weight omega = (2 vmax/(nv-1))^d.
+ *   - Particles: wall_id[i] = 0 for interior particles, else the owner wall
+ *     1..2d in the order x=0, x=1, y=0, y=1 (, z=0, z=1).  The lid is the
+ *     last wall (y=1 in 2D, z=1 in 3D) and moves along +x.  Wall particles
+ *     carry the boundary condition and never move.
+ *   - Units are nondimensional (R = 1, lengths in the box size).
+ */
+#ifndef BGK_H
+#define BGK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BGK_OK = 0,
+  BGK_EINVAL = 1,         /* bad argument or configuration                  */
+  BGK_ENOMEM = 2,         /* workspace smaller than bgk_workspace_bytes()    */
+  BGK_ENBR_OVERFLOW = 3,  /* more neighbours than max_neighbors              */
+  BGK_ESINGULAR = 4,      /* too few neighbours or non-positive pivot (WLS)  */
+  BGK_ENONPHYS = 5,       /* rho <= 0, T <= 0 or NaN after moments           */
+  BGK_EDEVICE = 6,        /* a HIP runtime call failed                       */
+  BGK_ENOTSUP = 7         /* valid but unsupported request                   */
+} bgk_status;
+
+enum { BGK_FP64 = 0, BGK_FP32 = 1, BGK_BF16 = 2 };
+
+typedef struct {
+  int32_t dim;           /* 2: Chu-reduced BGK (Sec. 2.1, g1 and g2); 3: full BGK        */
+  int32_t n_particles;   /* N, interior + wall                                           */
+  int32_t nv;            /* velocity points per axis, even, >= 2                         */
+  int32_t wls_degree;    /* 1 or 2: polynomial degree of the least-squares fit           */
+  int32_t max_neighbors; /* neighbour slots per particle (self included), <= 255         */
+  int32_t move;          /* 1: ALE motion (S8); 0: frozen cloud (geometry reused)        */
+  int32_t precision;     /* BGK_FP64, BGK_FP32 (FP32 f and transport arithmetic) or
+                            BGK_BF16 (FP32 f; transport products of BF16 operands with
+                            FP32 accumulation).  Geometry, least squares and moment
+                            sums are FP64 in every mode.                                  */
+  int32_t reserved;      /* must be 0                                                    */
+  double vmax;           /* velocity grid spans [-vmax, vmax] per axis                   */
+  double h;              /* support radius of the Gaussian weight (absolute)             */
+  double alpha;          /* weight exp(-alpha r^2/h^2), r <= h (Sec. 3.4.1, eq. weight) */
+  double kn;             /* tau = kn sqrt(2/pi)/(rho sqrt(T)) (Sec. 2, eqs. tau/lambda)  */
+  double dt;             /* time step                                                    */
+  double wall_T;         /* wall temperature                                             */
+  double lid_velocity;   /* lid speed along +x                                           */
+  double dx;             /* initial lattice spacing: interior particles stay in
+                            [0.1 dx, 1 - 0.1 dx]^d                                       */
+} bgk_config;
+
+typedef struct bgk_ctx bgk_ctx;
+
+/* Device workspace needed by bgk_init for this configuration (bytes, host). */
+int bgk_workspace_bytes(const bgk_config* cfg, size_t* bytes);
+
+/* Create a context.  cfg is copied.  wall_id: device int32 [N] (read once,
+ * synchronously, at init).  workspace: device buffer of ws_bytes bytes that
+ * the caller keeps alive until bgk_destroy.  hip_stream: hipStream_t or NULL.
+ * *out receives the context (host).  Errors: BGK_EINVAL (dim not 2/3, odd nv,
+ * N <= 0, dt <= 0, bad degree or capacity), BGK_ENOMEM (ws_bytes too small),
+ * BGK_EDEVICE. */
+int bgk_init(const bgk_config* cfg, const int32_t* wall_id, void* workspace, size_t ws_bytes,
+             void* hip_stream, bgk_ctx** out);
+
+void bgk_destroy(bgk_ctx* ctx);
+
+/* Change the lid speed used by later calls (S7). */
+int bgk_set_lid_velocity(bgk_ctx* ctx, double lid_velocity);
+
+/* S1 (Sec. 3.5.1; truncation r/h <= 1 of eq. weight): for every particle i,
+ * the particles j with |x_j - x_i|^2 <= h^2 (squared distance summed over
+ * components in order, without fused multiply-add), ascending, i included.
+ * Found with a cell list of cells no smaller than h.  nbr_cnt[i] is the true
+ * count even when it exceeds max_neighbors (then BGK_ENBR_OVERFLOW is raised
+ * in the error word and the row content is unspecified). */
+int bgk_build_neighbors(bgk_ctx* ctx, const double* x, int32_t* nbr_cnt, int32_t* nbr_idx);
+
+/* S2-S3 (Sec. 3.4.1 eqs. taylor..z_derivative, Sec. 3.4.2) for every
+ * interior particle: Gaussian-weighted least-squares fit of a full polynomial
+ * basis of degree wls_degree (constant included) in offsets scaled by h, the
+ * particle itself in its stencil; the degree drops to 1 when the stencil has
+ * fewer than twice as many points as degree-2 basis functions, and
+ * BGK_ESINGULAR is raised below d+2 points or on a non-positive Cholesky
+ * pivot.  grad[i][e] = gradient weight of neighbour slot e (so
+ * grad f(x_i) ~ sum_e grad[i][e] f_j).  ops[i][e] = (P, Q[, R]) = the gradient
+ * weight rotated into the edge frame (n, t[, b]) of x_j - x_i and mapped back:
+ * P = (g.n) n, Q = (g.t) t, R = (g.b) b, with t = n turned by +90 degrees in
+ * 2D and, in 3D, t and b the polar and azimuthal unit vectors of the edge
+ * (b horizontal).  The self slot has zero P, Q, R.  Rows of wall particles
+ * are zero.  degree: int32 [N] (0 for wall particles), may be NULL. */
+int bgk_wls_operators(bgk_ctx* ctx, const double* x, const int32_t* nbr_cnt,
+                      const int32_t* nbr_idx, double* grad, double* ops, int32_t* degree);
+
+/* Boundary interpolation rows (S7 part 1; the paper names the interpolation
+ * of f on the boundary in Table 3): for each wall particle b, the interior
+ * particles within radius hb, hb the first of h, 1.5h, 2h giving at least
+ * d+2 of them (else BGK_ESINGULAR), ascending, and the value weights
+ * c0[b][e] of a degree-1 weighted least-squares fit evaluated at x_b.
+ * Outputs are indexed by particle: wall_cnt int32 [N] (0 on interior rows),
+ * wall_idx int32 [N][max_neighbors], wall_c0 double [N][max_neighbors],
+ * wall_radius double [N] (may be NULL). */
+int bgk_wall_stencil(bgk_ctx* ctx, const double* x, int32_t* wall_cnt, int32_t* wall_idx,
+                     double* wall_c0, double* wall_radius);
+
+/* S1-S3 and the wall rows into the context's workspace (what bgk_step does
+ * first); used by the staged calls below. */
+int bgk_geometry(bgk_ctx* ctx, const double* x);
+
+/* S4 (Sec. 3.1 eq. explicit; Sec. 3.4.2 eq. flux and its 3D form), with the
+ * geometry of the last bgk_geometry/bgk_step: for interior i and every v,
+ *   ft_i(v) = f_i(v) - dt sum_{j != i} c_ij(v) (f_j(v) - f_i(v)),
+ *   c_ij(v) = g_ij.w - |P_ij.w| - |Q_ij.w| - |R_ij.w|,  w = v - U_i,
+ * which is the printed flux with its dissipation written |abar||w.n|.
+ * Wall rows of f_tilde are copies of f_in.  f_in and f_tilde must differ. */
+int bgk_transport(bgk_ctx* ctx, const void* f_in, void* f_tilde, const double* U);
+
+/* S5-S6 for interior particles: rho, U, T of ft (Chu: 3 rho T from g1 and g2,
+ * eq. moment1b; two passes, U first), tau = kn sqrt(2/pi)/(rho sqrt T), and
+ * f_out = (tau ft + dt M[rho,U,T])/(tau + dt) (Chu: G1 = rho/(2 pi T)
+ * exp(-|v-U|^2/(2T)), G2 = T G1).  f_out may equal f_tilde.  Wall rows of
+ * f_out and of rho, U, T are left untouched. */
+int bgk_collide(bgk_ctx* ctx, const void* f_tilde, void* f_out, double* rho, double* U,
+                double* T);
+
+/* S7 in place on the wall rows of f (whose interior rows hold f^{n+1}):
+ * velocities with v.n_w <= 0 (n_w the inward normal) take the interpolated
+ * interior value; the others take rho_w M[1, U_w, T_w] (Chu: g1 = rho_w G1hat,
+ * g2 = T_w rho_w G1hat) with rho_w set by zero net discrete mass flux; then
+ * the wall particles' rho, U, T are the moments of their f. */
+int bgk_wall_bc(bgk_ctx* ctx, void* f, double* rho, double* U, double* T);
+
+/* S8 (Sec. 3.1): x_i += dt U_i for interior particles, clamped to
+ * [0.1 dx, 1 - 0.1 dx]^d (clamped coordinates are counted, bgk_diagnostics). */
+int bgk_move(bgk_ctx* ctx, double* x, const double* U);
+
+/* One full step S1..S8.  f_in: state f^n (unchanged); f_out: receives
+ * f^{n+1} (must differ from f_in); x: positions, updated in place when
+ * cfg.move; U: on entry U^n (used by the transport), on exit U^{n+1};
+ * rho, T: receive the new values. */
+int bgk_step(bgk_ctx* ctx, const void* f_in, void* f_out, double* x, double* U, double* rho,
+             double* T);
+
+/* Moments (Sec. 2 eqs. moments, internal_energy; Chu eq. macroeq) of every
+ * particle: rho = omega sum f1, U = sum v f1 / sum f1, T from the centred
+ * second moment (Chu: plus sum g2) over 3 rho. */
+int bgk_moments(bgk_ctx* ctx, const void* f, double* rho, double* U, double* T);
+
+/* Maxwellian (Sec. 2 eq. maxwellian with the exponent's minus sign; Chu:
+ * G1, G2 of eqs. Maxw_G1/G2 with the v3-marginal normalisation rho/(2 pi T))
+ * of every particle on the grid, into f_out. */
+int bgk_maxwellian(bgk_ctx* ctx, const double* rho, const double* U, const double* T,
+                   void* f_out);
+
+/* Synchronise the stream; return and clear the first data error recorded on
+ * the device (or BGK_EDEVICE). */
+int bgk_check(bgk_ctx* ctx);
+
+/* Counters since init (host, int64 [4]): clamped coordinates, steps taken,
+ * the largest neighbour count seen, the largest patch union seen. Syncs. */
+int bgk_diagnostics(bgk_ctx* ctx, int64_t* out4);
+
+/* Instrumentation: while enabled, bgk_step records a pair of HIP events on
+ * the context stream around its transport kernel (S4).  bgk_timing_read
+ * synchronises and returns the summed kernel time in ms and the number of
+ * timed launches since the last read (host outputs), then resets them. */
+int bgk_timing_enable(bgk_ctx* ctx, int enable);
+int bgk_timing_read(bgk_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Text of the last error on this context (host string owned by the context). */
+const char* bgk_last_error(bgk_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BGK_H */

@@ -60,6 +60,7 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int32)
         cp = ctypes.POINTER(RefConfig)
+        L.ref_num_threads.restype = ctypes.c_int
         L.ref_velocity_node.restype = ctypes.c_double
         L.ref_velocity_node.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double]
         L.ref_velocity_weight.restype = ctypes.c_double
@@ -122,6 +123,10 @@ def config(cfg=None, **kw) -> RefConfig:
     for k, v in vals.items():
         setattr(c, k, v)
     return c
+
+
+def num_threads() -> int:
+    return lib().ref_num_threads()
 
 
 def velocity_node(k, nv, vmax):

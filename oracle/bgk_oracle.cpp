@@ -22,6 +22,8 @@
 #include <cstring>
 #include <vector>
 
+#include <omp.h>
+
 namespace {
 
 // status codes of the C interface (same numbering as the library's, which
@@ -765,6 +767,9 @@ int advance(const ref_config& c, const Geometry& g, const int32_t* wall_id, cons
 }  // namespace
 
 extern "C" {
+
+// OpenMP threads the oracle's parallel loops use.
+int ref_num_threads() { return omp_get_max_threads(); }
 
 // Velocity node and quadrature weight of the grid (for tests).
 double ref_velocity_node(int k, int nv, double vmax) { return vnode(k, nv, vmax); }

@@ -1,0 +1,405 @@
+// Host side of the libbgk C interface (include/bgk.h): argument checks,
+// workspace layout, and the order of kernel launches of one time step.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "bgk_internal.h"
+
+namespace bgk {
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Cells per axis: as many as possible with cell size 1/nca >= h (with a
+// margin against rounding), and no more than about one particle per cell.
+int cells_per_axis(const bgk_config& cfg) {
+  int nca = static_cast<int>(std::floor(1.0 / cfg.h));
+  const int cap_n = std::max(1, static_cast<int>(std::floor(
+                                    std::pow(static_cast<double>(cfg.n_particles), 1.0 / cfg.dim))));
+  nca = std::max(1, std::min(nca, cap_n));
+  while (nca > 1 && 1.0 / nca < cfg.h * (1.0 + 1e-9)) --nca;
+  return nca;
+}
+
+int64_t ipow(int64_t b, int e) {
+  int64_t r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+const char* status_text(int code) {
+  switch (code) {
+    case BGK_OK: return "ok";
+    case BGK_EINVAL: return "invalid argument or configuration";
+    case BGK_ENOMEM: return "workspace too small";
+    case BGK_ENBR_OVERFLOW: return "neighbour count exceeds max_neighbors";
+    case BGK_ESINGULAR: return "singular least-squares system (too few neighbours or pivot <= 0)";
+    case BGK_ENONPHYS: return "non-physical moments (rho <= 0, T <= 0 or NaN)";
+    case BGK_EDEVICE: return "HIP runtime error";
+    case BGK_ENOTSUP: return "not supported";
+    default: return "unknown error";
+  }
+}
+
+int fail(Ctx* c, int code, const char* what) {
+  if (c) {
+    c->last_error = std::string(status_text(code)) + ": " + what;
+  }
+  return code;
+}
+
+int hip_fail(Ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return BGK_OK;
+  if (c) c->last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return BGK_EDEVICE;
+}
+
+bool config_ok(const bgk_config& g) {
+  return (g.dim == 2 || g.dim == 3) && g.n_particles > 0 && g.nv >= 2 && g.nv % 2 == 0 &&
+         (g.wls_degree == 1 || g.wls_degree == 2) && g.max_neighbors >= g.dim + 2 &&
+         g.max_neighbors <= 255 && (g.move == 0 || g.move == 1) && g.precision >= BGK_FP64 &&
+         g.precision <= BGK_BF16 && g.reserved == 0 && g.vmax > 0 && g.h > 0 && g.alpha > 0 &&
+         g.kn > 0 && g.dt > 0 && g.wall_T > 0 && g.dx > 0 && std::isfinite(g.lid_velocity) &&
+         ipow(g.nv, g.dim) <= INT32_MAX / 4 &&
+         static_cast<int64_t>(g.n_particles) * g.max_neighbors * g.dim * g.dim < INT32_MAX;
+}
+
+}  // namespace
+
+size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d) {
+  const int64_t N = cfg.n_particles, cap = cfg.max_neighbors, D = cfg.dim, DD = D * D;
+  const int64_t ncell = ipow(cells_per_axis(cfg), cfg.dim);
+  const int64_t npatch = (N + kPatch - 1) / kPatch, ucap = static_cast<int64_t>(kPatch) * cap;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off = align_up(off + bytes);
+    return p;
+  };
+  Dev t{};
+  t.err = reinterpret_cast<int32_t*>(take(kErrWords * 4));
+  t.wall_id = reinterpret_cast<int32_t*>(take(N * 4));
+  t.wall_list = reinterpret_cast<int32_t*>(take(N * 4));
+  t.key = reinterpret_cast<int32_t*>(take(N * 4));
+  t.cstart = reinterpret_cast<int32_t*>(take((2 * ncell + 1) * 4));
+  t.ccursor = reinterpret_cast<int32_t*>(take(2 * ncell * 4));
+  t.cperm = reinterpret_cast<int32_t*>(take(N * 4));
+  t.ncnt = reinterpret_cast<int32_t*>(take(N * 4));
+  t.nidx = reinterpret_cast<int32_t*>(take(N * cap * 4));
+  t.ops64 = cfg.precision == BGK_FP64 ? reinterpret_cast<double*>(take(N * cap * DD * 8)) : nullptr;
+  t.ops32 = cfg.precision != BGK_FP64 ? reinterpret_cast<float*>(take(N * cap * DD * 4)) : nullptr;
+  t.wcnt = reinterpret_cast<int32_t*>(take(N * 4));
+  t.widx = reinterpret_cast<int32_t*>(take(N * cap * 4));
+  t.wc0 = reinterpret_cast<double*>(take(N * cap * 8));
+  t.whb = reinterpret_cast<double*>(take(N * 8));
+  t.ucount = reinterpret_cast<int32_t*>(take(npatch * 4));
+  t.uj = reinterpret_cast<int32_t*>(take(npatch * ucap * 4));
+  t.ue = reinterpret_cast<uint32_t*>(take(npatch * ucap * 4));
+  if (d) *d = t;
+  return off;
+}
+
+hipEvent_t take_event(Ctx& c) {
+  if (!c.event_pool.empty()) {
+    hipEvent_t e = c.event_pool.back();
+    c.event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// S1-S3 and the wall rows into the workspace, then the patch unions.
+static int build_geometry(Ctx& c, const double* x) {
+  hipError_t e = launch_cells(c, x);
+  if (e == hipSuccess) e = launch_neighbors(c, x, c.d.ncnt, c.d.nidx);
+  if (e == hipSuccess)
+    e = launch_wls(c, x, c.d.ncnt, c.d.nidx, nullptr, c.d.ops64, c.d.ops32, nullptr);
+  if (e == hipSuccess) e = launch_wall_stencil(c, x);
+  if (e == hipSuccess) e = launch_patches(c);
+  if (e != hipSuccess) return hip_fail(&c, e, "geometry launch");
+  c.geom_valid = true;
+  return BGK_OK;
+}
+
+}  // namespace bgk
+
+using bgk::Ctx;
+
+extern "C" {
+
+int bgk_workspace_bytes(const bgk_config* cfg, size_t* bytes) {
+  if (!cfg || !bytes || !bgk::config_ok(*cfg)) return BGK_EINVAL;
+  *bytes = bgk::workspace_layout(*cfg, nullptr, nullptr);
+  return BGK_OK;
+}
+
+int bgk_init(const bgk_config* cfg, const int32_t* wall_id, void* workspace, size_t ws_bytes,
+             void* hip_stream, bgk_ctx** out) {
+  if (!out) return BGK_EINVAL;
+  *out = nullptr;
+  if (!cfg || !wall_id || !workspace || !bgk::config_ok(*cfg)) return BGK_EINVAL;
+  const size_t need = bgk::workspace_layout(*cfg, nullptr, nullptr);
+  if (ws_bytes < need) return BGK_ENOMEM;
+  bgk_ctx* h = new (std::nothrow) bgk_ctx;
+  if (!h) return BGK_ENOMEM;
+  Ctx& c = h->c;
+  c.cfg = *cfg;
+  c.stream = static_cast<hipStream_t>(hip_stream);
+  c.N = cfg->n_particles;
+  c.D = cfg->dim;
+  c.NC = cfg->dim == 2 ? 2 : 1;
+  c.NV = static_cast<int>(bgk::ipow(cfg->nv, cfg->dim));
+  c.cap = cfg->max_neighbors;
+  c.DD = c.D * c.D;
+  c.nca = bgk::cells_per_axis(*cfg);
+  c.ncell = static_cast<int>(bgk::ipow(c.nca, c.D));
+  c.lid = cfg->lid_velocity;
+  bgk::workspace_layout(*cfg, static_cast<char*>(workspace), &c.d);
+  hipError_t e = hipGetDevice(&c.device);
+  // wall ids: read once to count and list the wall particles
+  std::vector<int32_t> wid(c.N);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(wid.data(), wall_id, sizeof(int32_t) * c.N, hipMemcpyDeviceToHost, c.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+  if (e != hipSuccess) {
+    delete h;
+    return BGK_EDEVICE;
+  }
+  std::vector<int32_t> wl;
+  for (int i = 0; i < c.N; ++i) {
+    if (wid[i] < 0 || wid[i] > 2 * c.D) {
+      delete h;
+      return BGK_EINVAL;
+    }
+    if (wid[i] != 0) wl.push_back(i);
+  }
+  c.Nw = static_cast<int>(wl.size());
+  c.Ni = c.N - c.Nw;
+  c.npatch = (c.Ni + bgk::kPatch - 1) / bgk::kPatch;
+  c.ucap = bgk::kPatch * c.cap;
+  int32_t zeros[bgk::kErrWords] = {0};
+  e = hipMemcpyAsync(c.d.wall_id, wid.data(), sizeof(int32_t) * c.N, hipMemcpyHostToDevice,
+                     c.stream);
+  if (e == hipSuccess && c.Nw > 0)
+    e = hipMemcpyAsync(c.d.wall_list, wl.data(), sizeof(int32_t) * c.Nw, hipMemcpyHostToDevice,
+                       c.stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c.d.err, zeros, sizeof(zeros), hipMemcpyHostToDevice, c.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+  if (e != hipSuccess) {
+    delete h;
+    return BGK_EDEVICE;
+  }
+  *out = h;
+  return BGK_OK;
+}
+
+void bgk_destroy(bgk_ctx* ctx) {
+  if (!ctx) return;
+  Ctx& c = ctx->c;
+  if (!c.timed.empty()) hipStreamSynchronize(c.stream);
+  for (auto& p : c.timed) {
+    hipEventDestroy(p.first);
+    hipEventDestroy(p.second);
+  }
+  for (hipEvent_t e : c.event_pool) hipEventDestroy(e);
+  delete ctx;
+}
+
+int bgk_timing_enable(bgk_ctx* ctx, int enable) {
+  if (!ctx) return BGK_EINVAL;
+  ctx->c.timing = enable != 0;
+  return BGK_OK;
+}
+
+int bgk_timing_read(bgk_ctx* ctx, double* total_ms, int64_t* launches) {
+  if (!ctx || !total_ms || !launches) return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  hipError_t e = hipStreamSynchronize(c.stream);
+  double sum = 0.0;
+  for (auto& p : c.timed) {
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.first, p.second);
+    sum += ms;
+    c.event_pool.push_back(p.first);
+    c.event_pool.push_back(p.second);
+  }
+  *total_ms = sum;
+  *launches = static_cast<int64_t>(c.timed.size());
+  c.timed.clear();
+  return bgk::hip_fail(&c, e, "bgk_timing_read");
+}
+
+int bgk_set_lid_velocity(bgk_ctx* ctx, double lid) {
+  if (!ctx || !std::isfinite(lid)) return BGK_EINVAL;
+  ctx->c.lid = lid;
+  return BGK_OK;
+}
+
+int bgk_build_neighbors(bgk_ctx* ctx, const double* x, int32_t* nbr_cnt, int32_t* nbr_idx) {
+  if (!ctx || !x || !nbr_cnt || !nbr_idx) return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  hipError_t e = bgk::launch_cells(c, x);
+  if (e == hipSuccess) e = bgk::launch_neighbors(c, x, nbr_cnt, nbr_idx);
+  c.geom_valid = false;
+  return bgk::hip_fail(&c, e, "bgk_build_neighbors");
+}
+
+int bgk_wls_operators(bgk_ctx* ctx, const double* x, const int32_t* nbr_cnt,
+                      const int32_t* nbr_idx, double* grad, double* ops, int32_t* degree) {
+  if (!ctx || !x || !nbr_cnt || !nbr_idx || !grad || !ops) return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  const int64_t slots = static_cast<int64_t>(c.N) * c.cap;
+  hipError_t e = bgk::launch_cells(c, x);
+  if (e == hipSuccess) e = bgk::launch_fill_f64(c.stream, grad, slots * c.D, 0.0);
+  if (e == hipSuccess) e = bgk::launch_fill_f64(c.stream, ops, slots * c.DD, 0.0);
+  if (e == hipSuccess && degree) e = bgk::launch_fill_i32(c.stream, degree, c.N, 0);
+  if (e == hipSuccess) e = bgk::launch_wls(c, x, nbr_cnt, nbr_idx, grad, ops, nullptr, degree);
+  c.geom_valid = false;
+  return bgk::hip_fail(&c, e, "bgk_wls_operators");
+}
+
+int bgk_wall_stencil(bgk_ctx* ctx, const double* x, int32_t* wall_cnt, int32_t* wall_idx,
+                     double* wall_c0, double* wall_radius) {
+  if (!ctx || !x || !wall_cnt || !wall_idx || !wall_c0) return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  const int64_t slots = static_cast<int64_t>(c.N) * c.cap;
+  hipError_t e = bgk::launch_cells(c, x);
+  if (e == hipSuccess) e = bgk::launch_wall_stencil(c, x);
+  if (e == hipSuccess) e = bgk::launch_fill_i32(c.stream, wall_cnt, c.N, 0);
+  if (e == hipSuccess) e = bgk::launch_fill_i32(c.stream, wall_idx, slots, 0);
+  if (e == hipSuccess) e = bgk::launch_fill_f64(c.stream, wall_c0, slots, 0.0);
+  if (e == hipSuccess && wall_radius) e = bgk::launch_fill_f64(c.stream, wall_radius, c.N, 0.0);
+  if (e == hipSuccess) e = bgk::launch_scatter_wall_rows(c, wall_cnt, wall_idx, wall_c0, wall_radius);
+  c.geom_valid = false;
+  return bgk::hip_fail(&c, e, "bgk_wall_stencil");
+}
+
+int bgk_geometry(bgk_ctx* ctx, const double* x) {
+  if (!ctx || !x) return BGK_EINVAL;
+  return bgk::build_geometry(ctx->c, x);
+}
+
+int bgk_transport(bgk_ctx* ctx, const void* f_in, void* f_tilde, const double* U) {
+  if (!ctx || !f_in || !f_tilde || !U || f_in == f_tilde) return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  if (!c.geom_valid) return bgk::fail(&c, BGK_EINVAL, "bgk_transport before bgk_geometry");
+  hipError_t e = bgk::launch_transport(c, f_in, f_tilde, U);
+  if (e == hipSuccess) e = bgk::launch_copy_wall_rows(c, f_in, f_tilde);
+  return bgk::hip_fail(&c, e, "bgk_transport");
+}
+
+int bgk_collide(bgk_ctx* ctx, const void* f_tilde, void* f_out, double* rho, double* U,
+                double* T) {
+  if (!ctx || !f_tilde || !f_out || !rho || !U || !T) return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  if (!c.geom_valid) return bgk::fail(&c, BGK_EINVAL, "bgk_collide before bgk_geometry");
+  return bgk::hip_fail(&c, bgk::launch_collide(c, f_tilde, f_out, rho, U, T), "bgk_collide");
+}
+
+int bgk_wall_bc(bgk_ctx* ctx, void* f, double* rho, double* U, double* T) {
+  if (!ctx || !f || !rho || !U || !T) return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  if (!c.geom_valid) return bgk::fail(&c, BGK_EINVAL, "bgk_wall_bc before bgk_geometry");
+  return bgk::hip_fail(&c, bgk::launch_wall_bc(c, f, rho, U, T), "bgk_wall_bc");
+}
+
+int bgk_move(bgk_ctx* ctx, double* x, const double* U) {
+  if (!ctx || !x || !U) return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  if (!c.geom_valid) return bgk::fail(&c, BGK_EINVAL, "bgk_move before bgk_geometry");
+  const hipError_t e = bgk::launch_move(c, x, U);
+  c.geom_valid = false;
+  return bgk::hip_fail(&c, e, "bgk_move");
+}
+
+int bgk_step(bgk_ctx* ctx, const void* f_in, void* f_out, double* x, double* U, double* rho,
+             double* T) {
+  if (!ctx || !f_in || !f_out || !x || !U || !rho || !T || f_in == f_out) return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  if (c.cfg.move || !c.geom_valid) {
+    const int rc = bgk::build_geometry(c, x);
+    if (rc) return rc;
+  }
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (c.timing) {
+    ev0 = bgk::take_event(c);
+    ev1 = bgk::take_event(c);
+    if (!ev0 || !ev1) return bgk::fail(&c, BGK_EDEVICE, "event creation");
+    hipEventRecord(ev0, c.stream);
+  }
+  hipError_t e = bgk::launch_transport(c, f_in, f_out, U);
+  if (c.timing) {
+    hipEventRecord(ev1, c.stream);
+    c.timed.emplace_back(ev0, ev1);
+  }
+  if (e == hipSuccess) e = bgk::launch_collide(c, f_out, f_out, rho, U, T);
+  if (e == hipSuccess) e = bgk::launch_wall_bc(c, f_out, rho, U, T);
+  if (e == hipSuccess && c.cfg.move) {
+    e = bgk::launch_move(c, x, U);
+    c.geom_valid = false;
+  }
+  if (e != hipSuccess) return bgk::hip_fail(&c, e, "bgk_step");
+  ++c.steps;
+  return BGK_OK;
+}
+
+int bgk_moments(bgk_ctx* ctx, const void* f, double* rho, double* U, double* T) {
+  if (!ctx || !f || !rho || !U || !T) return BGK_EINVAL;
+  return bgk::hip_fail(&ctx->c, bgk::launch_moments(ctx->c, f, rho, U, T), "bgk_moments");
+}
+
+int bgk_maxwellian(bgk_ctx* ctx, const double* rho, const double* U, const double* T,
+                   void* f_out) {
+  if (!ctx || !rho || !U || !T || !f_out) return BGK_EINVAL;
+  return bgk::hip_fail(&ctx->c, bgk::launch_maxwellian(ctx->c, rho, U, T, f_out),
+                       "bgk_maxwellian");
+}
+
+int bgk_check(bgk_ctx* ctx) {
+  if (!ctx) return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  int32_t w[bgk::kErrWords];
+  hipError_t e = hipStreamSynchronize(c.stream);
+  if (e == hipSuccess) e = hipMemcpy(w, c.d.err, sizeof(w), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return bgk::hip_fail(&c, e, "bgk_check");
+  if (w[0] == 0) return BGK_OK;
+  int code = BGK_EDEVICE;
+  for (int k = 1; k < 31; ++k)
+    if (w[0] & bgk::err_bit(k)) {
+      code = k;
+      break;
+    }
+  const int32_t zero = 0;
+  e = hipMemcpy(c.d.err, &zero, sizeof(zero), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return bgk::hip_fail(&c, e, "bgk_check");
+  return bgk::fail(&c, code, "reported by a kernel");
+}
+
+int bgk_diagnostics(bgk_ctx* ctx, int64_t* out4) {
+  if (!ctx || !out4) return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  int32_t w[bgk::kErrWords];
+  hipError_t e = hipStreamSynchronize(c.stream);
+  if (e == hipSuccess) e = hipMemcpy(w, c.d.err, sizeof(w), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return bgk::hip_fail(&c, e, "bgk_diagnostics");
+  out4[0] = w[1];
+  out4[1] = c.steps;
+  out4[2] = w[2];
+  out4[3] = w[3];
+  return BGK_OK;
+}
+
+const char* bgk_last_error(bgk_ctx* ctx) {
+  if (!ctx) return "null context";
+  return ctx->c.last_error.c_str();
+}
+
+}  // extern "C"

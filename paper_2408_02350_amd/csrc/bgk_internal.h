@@ -1,0 +1,96 @@
+// Internal declarations of libbgk (HIP, gfx950).  Not part of the public
+// interface: the public C ABI is include/bgk.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "bgk.h"
+
+namespace bgk {
+
+constexpr int kPatch = 4;       // interior particles per transport patch
+constexpr int kThreads = 256;   // threads per block of the per-particle kernels
+
+// bit of the device error word for each status code
+__host__ __device__ constexpr int err_bit(int code) { return 1 << code; }
+
+// Device error word layout (int32): [0] error bits, [1] clamped coordinates,
+// [2] largest neighbour count, [3] largest patch union.
+constexpr int kErrWords = 8;
+
+// Device views of the workspace for one context.
+struct Dev {
+  int32_t* err;          // [kErrWords]
+  int32_t* wall_id;      // [N]
+  int32_t* wall_list;    // [Nw]  wall particles, ascending
+  int32_t* key;          // [N]   cell key of each particle
+  int32_t* cstart;       // [2*ncell + 1] start of each (cell, interior|wall) range
+  int32_t* ccursor;      // [2*ncell]
+  int32_t* cperm;        // [N]   particles sorted by key; first Ni are interior
+  int32_t* ncnt;         // [N]
+  int32_t* nidx;         // [N][cap]
+  double* ops64;         // [N][cap][d*d]
+  float* ops32;          // [N][cap][d*d] (precision != FP64)
+  int32_t* wcnt;         // [Nw]
+  int32_t* widx;         // [Nw][cap]
+  double* wc0;           // [Nw][cap]
+  double* whb;           // [Nw]
+  int32_t* ucount;       // [npatch]
+  int32_t* uj;           // [npatch][ucap]
+  uint32_t* ue;          // [npatch][ucap] packed 8-bit slot of each patch particle
+};
+
+struct Ctx {
+  bgk_config cfg;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int N = 0, D = 0, NC = 0, NV = 0, cap = 0, DD = 0;
+  int Ni = 0, Nw = 0, npatch = 0, ucap = 0;
+  int nca = 0, ncell = 0;
+  double lid = 0.0;
+  Dev d{};
+  bool geom_valid = false;  // geometry of the current (frozen) cloud is built
+  int64_t steps = 0;
+  std::string last_error;
+  bool timing = false;                                 // event pairs around S4
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;
+  std::vector<hipEvent_t> event_pool;
+};
+
+// Workspace layout: returns total bytes; fills d when base != nullptr.
+size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d);
+
+// ---- launchers (enqueue on c.stream; return hipError_t of the launch) ----
+hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
+hipError_t launch_fill_f64(hipStream_t s, double* p, int64_t n, double v);
+hipError_t launch_copy_i32(hipStream_t s, const int32_t* src, int32_t* dst, int64_t n);
+hipError_t launch_scatter_wall_rows(const Ctx& c, int32_t* cnt_out, int32_t* idx_out,
+                                    double* c0_out, double* hb_out);
+
+hipError_t launch_cells(const Ctx& c, const double* x);              // key, cstart, cperm
+hipError_t launch_neighbors(const Ctx& c, const double* x, int32_t* cnt, int32_t* idx);
+hipError_t launch_wls(const Ctx& c, const double* x, const int32_t* cnt, const int32_t* idx,
+                      double* grad, double* ops, float* ops32, int32_t* degree);
+hipError_t launch_wall_stencil(const Ctx& c, const double* x);
+hipError_t launch_patches(const Ctx& c);
+
+hipError_t launch_transport(const Ctx& c, const void* f_in, void* f_out, const double* U);
+hipError_t launch_copy_wall_rows(const Ctx& c, const void* f_in, void* f_out);
+hipError_t launch_collide(const Ctx& c, const void* ft, void* fout, double* rho, double* U,
+                          double* T);
+hipError_t launch_wall_bc(const Ctx& c, void* f, double* rho, double* U, double* T);
+hipError_t launch_move(const Ctx& c, double* x, const double* U);
+hipError_t launch_moments(const Ctx& c, const void* f, double* rho, double* U, double* T);
+hipError_t launch_maxwellian(const Ctx& c, const double* rho, const double* U, const double* T,
+                             void* f);
+
+}  // namespace bgk
+
+struct bgk_ctx {
+  bgk::Ctx c;
+};

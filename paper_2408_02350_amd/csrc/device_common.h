@@ -1,0 +1,99 @@
+// Device helpers shared by the libbgk kernels (gfx950, wave64).
+// The library is compiled with -ffp-contract=off: every fused multiply-add
+// in these kernels is written out explicitly with fma(), so that the
+// geometry predicates and the least-squares arithmetic follow the plain
+// operation order of the method.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bgk_internal.h"
+
+namespace bgk {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Velocity node k of an axis with nv points on [-vmax, vmax], both ends
+// included (Sec. 3.2): v_k = vmax (2k - (nv-1)) / (nv-1).
+__device__ __forceinline__ double vnode(int k, int nv, double vmax) {
+  return vmax * static_cast<double>(2 * k - (nv - 1)) / static_cast<double>(nv - 1);
+}
+
+template <int D>
+__device__ __forceinline__ void velocity_of(int q, int nv, double vmax, double v[3]) {
+  v[0] = v[1] = v[2] = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    v[a] = vnode(q % nv, nv, vmax);
+    q /= nv;
+  }
+}
+
+// Maxwellian of Sec. 2 (eq. maxwellian, exponent -|v-U|^2/(2T), R = 1) for
+// D = 3; for D = 2 the Chu-reduced G1 = rho/(2 pi T) exp(-|v-U|^2/(2T)) and
+// G2 = T G1 (Sec. 2.1).  comp selects G1 (0) or G2 (1).
+template <int D>
+__device__ __forceinline__ double maxwell(int comp, double rho, const double* U, double T,
+                                          const double* v) {
+  double s2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const double wa = v[a] - U[a];
+    s2 = s2 + wa * wa;
+  }
+  const double two_pi = 2.0 * kPi;
+  double norm;
+  if (D == 3) {
+    const double tp = two_pi * T;
+    norm = rho / (tp * sqrt(tp));
+  } else {
+    norm = rho / (two_pi * T);
+  }
+  double g = norm * exp(-s2 / (2.0 * T));
+  if (comp == 1) g = T * g;
+  return g;
+}
+
+// Sum K doubles over a block of kThreads (= 4 waves of 64) in a fixed order;
+// every thread receives the totals.  sh must hold 4*K doubles.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[wid * K + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = ((sh[k] + sh[K + k]) + sh[2 * K + k]) + sh[3 * K + k];
+  __syncthreads();
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Map the hardware block id to a logical id so that each XCD works on
+// one contiguous range of logical blocks (neighbouring patches share f rows).
+__device__ __forceinline__ int xcd_logical_block(int b, int n) {
+  const int x = b & 7, local = b >> 3;
+  const int q = n >> 3, r = n & 7;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + local;
+}
+
+__device__ __forceinline__ void raise_error(int32_t* err, int code) {
+  atomicOr(&err[0], err_bit(code));
+}
+
+// Cell coordinate of a position component in [0, 1] with nca cells per axis
+// (NaN and values outside the box land in the boundary cells).
+__device__ __forceinline__ int cell_coord(double xa, int nca) {
+  const double s = xa * static_cast<double>(nca);
+  return (s >= 0.0) ? (s < static_cast<double>(nca) ? static_cast<int>(s) : nca - 1) : 0;
+}
+
+}  // namespace bgk
