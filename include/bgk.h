@@ -69,6 +69,7 @@ typedef enum {
 } bgk_status;
 
 enum { BGK_FP64 = 0, BGK_FP32 = 1, BGK_BF16 = 2 };
+enum { BGK_FLAG_GENERIC = 1 };
 
 typedef struct {
   int32_t dim;           /* 2: Chu-reduced BGK (Sec. 2.1, g1 and g2); 3: full BGK        */
@@ -81,7 +82,8 @@ typedef struct {
                             BGK_BF16 (FP32 f; transport products of BF16 operands with
                             FP32 accumulation).  Geometry, least squares and moment
                             sums are FP64 in every mode.                                  */
-  int32_t reserved;      /* must be 0                                                    */
+  int32_t flags;         /* 0, or BGK_FLAG_GENERIC: use the separate transport and
+                            relaxation kernels instead of the fused one (for testing)    */
   double vmax;           /* velocity grid spans [-vmax, vmax] per axis                   */
   double h;              /* support radius of the Gaussian weight (absolute)             */
   double alpha;          /* weight exp(-alpha r^2/h^2), r <= h (Sec. 3.4.1, eq. weight) */

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(PKG, "libbgk.so")
 BGK_OK, BGK_EINVAL, BGK_ENOMEM, BGK_ENBR_OVERFLOW, BGK_ESINGULAR, BGK_ENONPHYS, \
     BGK_EDEVICE, BGK_ENOTSUP = range(8)
 BGK_FP64, BGK_FP32, BGK_BF16 = 0, 1, 2
+BGK_FLAG_GENERIC = 1
 PRECISIONS = {"fp64": BGK_FP64, "fp32": BGK_FP32, "bf16": BGK_BF16}
 STATUS = {0: "BGK_OK", 1: "BGK_EINVAL", 2: "BGK_ENOMEM", 3: "BGK_ENBR_OVERFLOW",
           4: "BGK_ESINGULAR", 5: "BGK_ENONPHYS", 6: "BGK_EDEVICE", 7: "BGK_ENOTSUP"}
@@ -47,7 +48,7 @@ class BgkConfig(ctypes.Structure):
     _fields_ = [
         ("dim", ctypes.c_int32), ("n_particles", ctypes.c_int32), ("nv", ctypes.c_int32),
         ("wls_degree", ctypes.c_int32), ("max_neighbors", ctypes.c_int32),
-        ("move", ctypes.c_int32), ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("move", ctypes.c_int32), ("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("vmax", ctypes.c_double), ("h", ctypes.c_double), ("alpha", ctypes.c_double),
         ("kn", ctypes.c_double), ("dt", ctypes.c_double), ("wall_T", ctypes.c_double),
         ("lid_velocity", ctypes.c_double), ("dx", ctypes.c_double),
@@ -105,7 +106,7 @@ def config_from(cav, precision: str | int | None = None, **overrides) -> BgkConf
     p = cav.precision if precision is None else precision
     vals = dict(dim=cav.dim, n_particles=cav.n_particles, nv=cav.nv, wls_degree=cav.wls_degree,
                 max_neighbors=cav.capacity, move=cav.move,
-                precision=PRECISIONS[p] if isinstance(p, str) else int(p), reserved=0,
+                precision=PRECISIONS[p] if isinstance(p, str) else int(p), flags=0,
                 vmax=cav.vmax, h=cav.h, alpha=cav.alpha, kn=cav.kn, dt=cav.dt,
                 wall_T=cav.wall_T, lid_velocity=cav.lid, dx=cav.dx)
     vals.update(overrides)

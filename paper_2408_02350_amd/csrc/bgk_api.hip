@@ -63,7 +63,7 @@ bool config_ok(const bgk_config& g) {
   return (g.dim == 2 || g.dim == 3) && g.n_particles > 0 && g.nv >= 2 && g.nv % 2 == 0 &&
          (g.wls_degree == 1 || g.wls_degree == 2) && g.max_neighbors >= g.dim + 2 &&
          g.max_neighbors <= 255 && (g.move == 0 || g.move == 1) && g.precision >= BGK_FP64 &&
-         g.precision <= BGK_BF16 && g.reserved == 0 && g.vmax > 0 && g.h > 0 && g.alpha > 0 &&
+         g.precision <= BGK_BF16 && (g.flags & ~BGK_FLAG_GENERIC) == 0 && g.vmax > 0 && g.h > 0 && g.alpha > 0 &&
          g.kn > 0 && g.dt > 0 && g.wall_T > 0 && g.dx > 0 && std::isfinite(g.lid_velocity) &&
          ipow(g.nv, g.dim) <= INT32_MAX / 4 &&
          static_cast<int64_t>(g.n_particles) * g.max_neighbors * g.dim * g.dim < INT32_MAX;
@@ -102,6 +102,10 @@ size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d) {
   t.ue = reinterpret_cast<uint32_t*>(take(npatch * ucap * 4));
   if (d) *d = t;
   return off;
+}
+
+bool use_fused(const Ctx& c) {
+  return !(c.cfg.flags & BGK_FLAG_GENERIC) && fused_supported(c);
 }
 
 hipEvent_t take_event(Ctx& c) {
@@ -291,7 +295,9 @@ int bgk_transport(bgk_ctx* ctx, const void* f_in, void* f_tilde, const double* U
   if (!ctx || !f_in || !f_tilde || !U || f_in == f_tilde) return BGK_EINVAL;
   Ctx& c = ctx->c;
   if (!c.geom_valid) return bgk::fail(&c, BGK_EINVAL, "bgk_transport before bgk_geometry");
-  hipError_t e = bgk::launch_transport(c, f_in, f_tilde, U);
+  hipError_t e = bgk::use_fused(c)
+                     ? bgk::launch_fused(c, f_in, f_tilde, U, nullptr, nullptr, nullptr, false)
+                     : bgk::launch_transport(c, f_in, f_tilde, U);
   if (e == hipSuccess) e = bgk::launch_copy_wall_rows(c, f_in, f_tilde);
   return bgk::hip_fail(&c, e, "bgk_transport");
 }
@@ -335,12 +341,14 @@ int bgk_step(bgk_ctx* ctx, const void* f_in, void* f_out, double* x, double* U, 
     if (!ev0 || !ev1) return bgk::fail(&c, BGK_EDEVICE, "event creation");
     hipEventRecord(ev0, c.stream);
   }
-  hipError_t e = bgk::launch_transport(c, f_in, f_out, U);
+  const bool fused = bgk::use_fused(c);
+  hipError_t e = fused ? bgk::launch_fused(c, f_in, f_out, U, rho, U, T, true)
+                       : bgk::launch_transport(c, f_in, f_out, U);
   if (c.timing) {
     hipEventRecord(ev1, c.stream);
     c.timed.emplace_back(ev0, ev1);
   }
-  if (e == hipSuccess) e = bgk::launch_collide(c, f_out, f_out, rho, U, T);
+  if (e == hipSuccess && !fused) e = bgk::launch_collide(c, f_out, f_out, rho, U, T);
   if (e == hipSuccess) e = bgk::launch_wall_bc(c, f_out, rho, U, T);
   if (e == hipSuccess && c.cfg.move) {
     e = bgk::launch_move(c, x, U);

@@ -1,0 +1,483 @@
+// S4 + S5 + S6 fused: transport, moments and implicit relaxation of a patch
+// of kPatch interior particles over ALL velocities in one block.
+//
+//   ft_i(v) = f_i(v) - dt sum_{j != i} c_ij(v) (f_j(v) - f_i(v)),
+//   c_ij(v) = 2 sum_k min(0, a_k.(v - U_i)),  a_k in {P, Q[, R]}     (S4)
+//   rho, U, T of ft in FP64                                           (S5)
+//   f_i^{n+1} = (tau ft_i + dt M[rho, U, T]) / (tau + dt)             (S6)
+//
+// Layout of the work: a block of BT threads owns one patch; thread tid
+// handles the velocities q_r = tid + r*BTe (r < R), where BTe = N_v / R is a
+// multiple of nv^(d-1), so that the R velocities of a thread differ only in
+// the slowest velocity component: each projection a_k.(v - U) is formed once
+// and then advanced by a constant per r (one add).  The block walks the
+// sorted union of its particles' neighbour lists in chunks; per chunk the
+// per-edge data (a_k, a_k.U_i and the per-r increments) is staged in LDS
+// and read back with wave-uniform addresses, and the next f_j row segment is
+// loaded one neighbour ahead.  After the walk, ft stays in registers: the
+// moment sums are block reductions in a fixed order, the Maxwellian is the
+// product of per-axis exponentials (exp(-(v_a-U_a)^2/2T), d*nv exp per
+// particle instead of N_v), and f^{n+1} is written once.  f-tilde never goes
+// to memory when the kernel runs fused; unfused, it writes f-tilde and stops.
+#include "device_common.h"
+
+namespace bgk {
+
+template <int MODE>
+struct FPrec;
+template <>
+struct FPrec<BGK_FP64> {
+  using real = double;
+};
+template <>
+struct FPrec<BGK_FP32> {
+  using real = float;
+};
+template <>
+struct FPrec<BGK_BF16> {
+  using real = float;
+};
+
+constexpr int kChunk = 64;   // union entries staged per LDS chunk
+constexpr int kMaxNv = 64;   // velocity points per axis supported by the fused path
+
+struct FusedArgs {
+  int N, NV, nv, cap, Ni, npatch, ucap, bte;
+  double vmax, dt, kn, omega, dvs;  // dvs: slow-axis velocity step between r and r+1
+  const void* f;
+  void* fo;          // f-tilde (unfused) or f^{n+1} (fused)
+  const double* U;   // U^n
+  const void* ops;   // [N][cap][D*D] in the transport precision
+  const int32_t* plist;
+  const int32_t* ucount;
+  const int32_t* uj;
+  const uint32_t* ue;
+  double* rho;       // fused: new moments of the patch particles
+  double* Unew;
+  double* T;
+  int32_t* err;
+};
+
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double min_t(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ float min_t(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ float bf16r(float x) { return static_cast<float>(static_cast<__bf16>(x)); }
+
+template <typename T>
+__device__ __forceinline__ T uniform(T x) {
+  return __builtin_amdgcn_readfirstlane(x);
+}
+
+template <int D, int NC, int MODE, int R, bool FUSE>
+__global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
+  using Real = typename FPrec<MODE>::real;
+  constexpr int TP = kPatch, DD = D * D;
+  constexpr int REC = DD + 2 * D;              // a_k (d*d), a_k.U (d), a_k[slow]*dvs (d)
+  __shared__ Real lrec[kChunk][TP][REC];
+  __shared__ int32_t luj[kChunk];
+  __shared__ uint32_t lmask[kChunk];
+  __shared__ double vtab[kMaxNv];
+  __shared__ double red[16][TP][D + 1];
+  __shared__ double etab[TP][D][kMaxNv];
+  __shared__ double pstat[TP][D + 3];           // rho, U[d], T, tau
+
+  const int tid = threadIdx.x;
+  const int nthreads = blockDim.x;
+  const int patch = xcd_logical_block(blockIdx.x, gridDim.x);
+  const Real* __restrict__ f = static_cast<const Real*>(a.f);
+  Real* __restrict__ fo = static_cast<Real*>(a.fo);
+  const Real* __restrict__ ops = static_cast<const Real*>(a.ops);
+  const size_t NVs = static_cast<size_t>(a.NV);
+  const size_t cs = static_cast<size_t>(a.N) * NVs;
+
+  int pt[TP];
+#pragma unroll
+  for (int t = 0; t < TP; ++t) {
+    const int g = patch * TP + t;
+    pt[t] = g < a.Ni ? a.plist[g] : -1;
+  }
+  if (tid < a.nv) vtab[tid] = vnode(tid, a.nv, a.vmax);
+  __syncthreads();
+
+  // velocities of this thread: q_r = tid + r*bte, all in the same
+  // (k1[,k2]) column, k_slow advancing by bte/plane per r
+  const bool lane_on = tid < a.bte;
+  int kq[D];
+  {
+    int q = lane_on ? tid : 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      kq[k] = q % a.nv;
+      q /= a.nv;
+    }
+  }
+  const int kstep = (a.bte / (a.NV / a.nv));  // k_slow increment per r
+  Real v0[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) v0[k] = static_cast<Real>(vtab[kq[k]]);
+
+  Real fi[TP][R][NC], acc[TP][R][NC];
+#pragma unroll
+  for (int t = 0; t < TP; ++t)
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const size_t q = static_cast<size_t>(tid) + static_cast<size_t>(r) * a.bte;
+        fi[t][r][c] = (pt[t] >= 0 && lane_on)
+                          ? f[c * cs + static_cast<size_t>(pt[t]) * NVs + q]
+                          : Real(0);
+        acc[t][r][c] = Real(0);
+      }
+
+  const int nu = a.ucount[patch];
+  const int32_t* __restrict__ ujp = a.uj + static_cast<size_t>(patch) * a.ucap;
+  const uint32_t* __restrict__ uep = a.ue + static_cast<size_t>(patch) * a.ucap;
+  const Real dvs = static_cast<Real>(a.dvs);
+
+  for (int c0 = 0; c0 < nu; c0 += kChunk) {
+    const int cn = min(kChunk, nu - c0);
+    __syncthreads();  // the previous chunk is consumed
+    // stage: one (u, t) record per thread
+    for (int w = tid; w < cn * TP; w += nthreads) {
+      const int u = w / TP, t = w - u * TP;
+      const uint32_t pe = uep[c0 + u];
+      const uint32_t e = (pe >> (8 * t)) & 0xFFu;
+      Real* rec = lrec[u][t];
+      if (t == 0) {
+        luj[u] = ujp[c0 + u];
+        uint32_t m = 0;
+#pragma unroll
+        for (int s = 0; s < TP; ++s)
+          if (((pe >> (8 * s)) & 0xFFu) != 0xFFu) m |= 1u << s;
+        lmask[u] = m;
+      }
+      if (e != 0xFFu) {
+        const int i = a.plist[patch * TP + t];  // present slots are real particles
+        const Real* o = ops + (static_cast<size_t>(i) * a.cap + e) * DD;
+        Real av[DD];
+#pragma unroll
+        for (int k = 0; k < DD; ++k) av[k] = o[k];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          Real b = Real(0);
+#pragma unroll
+          for (int m = 0; m < D; ++m)
+            b = fma_t(av[k * D + m], static_cast<Real>(a.U[static_cast<size_t>(m) * a.N + i]), b);
+          rec[DD + k] = b;
+          rec[DD + D + k] = av[k * D + D - 1] * dvs;
+        }
+#pragma unroll
+        for (int k = 0; k < DD; ++k) rec[k] = av[k];
+      }
+    }
+    __syncthreads();
+
+    Real fj[R][NC], fn[R][NC];
+    {
+      const int j = uniform(luj[0]);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          fn[r][c] = lane_on ? f[c * cs + static_cast<size_t>(j) * NVs + tid +
+                                 static_cast<size_t>(r) * a.bte]
+                             : Real(0);
+    }
+    for (int u = 0; u < cn; ++u) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) fj[r][c] = fn[r][c];
+      const uint32_t mask = uniform(lmask[u]);
+      if (u + 1 < cn) {
+        const int jn = uniform(luj[u + 1]);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+            fn[r][c] = lane_on ? f[c * cs + static_cast<size_t>(jn) * NVs + tid +
+                                   static_cast<size_t>(r) * a.bte]
+                               : Real(0);
+      }
+#pragma unroll
+      for (int t = 0; t < TP; ++t) {
+        if (mask & (1u << t)) {
+          const Real* rec = lrec[u][t];
+          Real av[DD], bk[D], ik[D];
+#pragma unroll
+          for (int k = 0; k < DD; ++k) av[k] = rec[k];
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            bk[k] = rec[DD + k];
+            ik[k] = rec[DD + D + k];
+          }
+          Real p[D];
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            Real s = -bk[k];
+#pragma unroll
+            for (int m = 0; m < D; ++m) s = fma_t(av[k * D + m], v0[m], s);
+            p[k] = s;
+          }
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if (r > 0) {
+#pragma unroll
+              for (int k = 0; k < D; ++k) p[k] = p[k] + ik[k];
+            }
+            Real cm = min_t(p[0], Real(0));
+#pragma unroll
+            for (int k = 1; k < D; ++k) cm = cm + min_t(p[k], Real(0));
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              const Real df = fj[r][c] - fi[t][r][c];
+              if constexpr (MODE == BGK_BF16)
+                acc[t][r][c] = fma_t(bf16r(cm + cm), bf16r(df), acc[t][r][c]);
+              else
+                acc[t][r][c] = fma_t(cm, df, acc[t][r][c]);
+            }
+          }
+        }
+      }
+    }
+  }
+
+  // ft = f - dt * sum c (f_j - f_i); the factor 2 of c is folded into dt
+  const Real dtf = static_cast<Real>(MODE == BGK_BF16 ? a.dt : 2.0 * a.dt);
+#pragma unroll
+  for (int t = 0; t < TP; ++t)
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) fi[t][r][c] = fi[t][r][c] - dtf * acc[t][r][c];
+
+  if constexpr (!FUSE) {
+#pragma unroll
+    for (int t = 0; t < TP; ++t)
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          if (pt[t] >= 0 && lane_on)
+            fo[c * cs + static_cast<size_t>(pt[t]) * NVs + tid + static_cast<size_t>(r) * a.bte] =
+                fi[t][r][c];
+    return;
+  } else {
+    const int lane = tid & 63, wid = tid >> 6, nw = nthreads >> 6;
+    // ---- S5 pass 1: s0 = sum f1, s1 = sum v f1 (FP64)
+    double sm[TP][D + 1];
+#pragma unroll
+    for (int t = 0; t < TP; ++t)
+#pragma unroll
+      for (int k = 0; k <= D; ++k) sm[t][k] = 0.0;
+    if (lane_on) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double v[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) v[k] = vtab[k == D - 1 ? kq[k] + r * kstep : kq[k]];
+#pragma unroll
+        for (int t = 0; t < TP; ++t) {
+          const double x = static_cast<double>(fi[t][r][0]);
+          sm[t][0] = sm[t][0] + x;
+#pragma unroll
+          for (int k = 0; k < D; ++k) sm[t][1 + k] = sm[t][1 + k] + v[k] * x;
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TP; ++t)
+#pragma unroll
+      for (int k = 0; k <= D; ++k) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sm[t][k] += __shfl_xor(sm[t][k], o, 64);
+        if (lane == 0) red[wid][t][k] = sm[t][k];
+      }
+    __syncthreads();
+    if (tid < TP * (D + 1)) {
+      const int t = tid / (D + 1), k = tid - t * (D + 1);
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s = s + red[w][t][k];
+      red[0][t][k] = s;  // only wave 0's slot is overwritten after all reads below
+    }
+    __syncthreads();
+    double Ut[TP][D], s0t[TP];
+#pragma unroll
+    for (int t = 0; t < TP; ++t) {
+      s0t[t] = red[0][t][0];
+#pragma unroll
+      for (int k = 0; k < D; ++k) Ut[t][k] = red[0][t][1 + k] / s0t[t];
+    }
+    __syncthreads();
+    // ---- S5 pass 2: 3 rho T = sum |v-U|^2 f1 (+ sum f2)
+    double se[TP];
+#pragma unroll
+    for (int t = 0; t < TP; ++t) se[t] = 0.0;
+    if (lane_on) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double v[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) v[k] = vtab[k == D - 1 ? kq[k] + r * kstep : kq[k]];
+#pragma unroll
+        for (int t = 0; t < TP; ++t) {
+          double w2 = 0.0;
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            const double wk = v[k] - Ut[t][k];
+            w2 = w2 + wk * wk;
+          }
+          se[t] = se[t] + w2 * static_cast<double>(fi[t][r][0]);
+          if (NC == 2) se[t] = se[t] + static_cast<double>(fi[t][r][NC - 1]);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TP; ++t) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) se[t] += __shfl_xor(se[t], o, 64);
+      if (lane == 0) red[wid][t][0] = se[t];
+    }
+    __syncthreads();
+    if (tid < TP) {
+      const int t = tid;
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s = s + red[w][t][0];
+      const double rho = a.omega * s0t[t];
+      const double T = s / (3.0 * s0t[t]);
+      const double tau = a.kn * sqrt(2.0 / kPi) / (rho * sqrt(T));
+      pstat[t][0] = rho;
+#pragma unroll
+      for (int k = 0; k < D; ++k) pstat[t][1 + k] = Ut[t][k];
+      pstat[t][D + 1] = T;
+      pstat[t][D + 2] = tau;
+      const int g = patch * TP + t;
+      const int i = g < a.Ni ? a.plist[g] : -1;
+      if (i >= 0) {
+        a.rho[i] = rho;
+        a.T[i] = T;
+#pragma unroll
+        for (int k = 0; k < D; ++k) a.Unew[static_cast<size_t>(k) * a.N + i] = red[0][t][1 + k] / s0t[t];
+        if (!(rho > 0.0) || !(T > 0.0)) raise_error(a.err, BGK_ENONPHYS);
+      }
+    }
+    __syncthreads();
+    // ---- per-axis exponential factors exp(-(v_k - U_a)^2 / (2T))
+    for (int w = tid; w < TP * D * a.nv; w += nthreads) {
+      const int t = w / (D * a.nv), rem = w - t * (D * a.nv);
+      const int k = rem / a.nv, m = rem - k * a.nv;
+      const double dv = vtab[m] - pstat[t][1 + k];
+      etab[t][k][m] = exp(-(dv * dv) / (2.0 * pstat[t][D + 1]));
+    }
+    __syncthreads();
+    // ---- S6: f^{n+1} = (tau ft + dt M)/(tau + dt)
+    const double two_pi = 2.0 * kPi;
+#pragma unroll
+    for (int t = 0; t < TP; ++t) {
+      if (pt[t] < 0 || !lane_on) continue;
+      const double rho = pstat[t][0], T = pstat[t][D + 1], tau = pstat[t][D + 2];
+      double norm;
+      if (D == 3) {
+        const double tp = two_pi * T;
+        norm = rho / (tp * sqrt(tp));
+      } else {
+        norm = rho / (two_pi * T);
+      }
+      const double den = tau + a.dt;
+      double efix = 1.0;
+#pragma unroll
+      for (int k = 0; k < D - 1; ++k) efix = efix * etab[t][k][kq[k]];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double M1 = norm * (efix * etab[t][D - 1][kq[D - 1] + r * kstep]);
+        const size_t q = static_cast<size_t>(tid) + static_cast<size_t>(r) * a.bte;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const double M = (c == 1) ? T * M1 : M1;
+          const double x = static_cast<double>(fi[t][r][c]);
+          fo[c * cs + static_cast<size_t>(pt[t]) * NVs + q] =
+              static_cast<Real>((tau * x + a.dt * M) / den);
+        }
+      }
+    }
+  }
+}
+
+// Choose R (velocities per thread) so that N_v / R is a multiple of the
+// velocity plane nv^(d-1) (R divides nv) and fits one block.
+static int pick_r(int D, int nv, int NV) {
+  static const int c2[] = {1, 2, 4};
+  static const int c3[] = {2, 4, 8, 10};
+  const int* cand = D == 2 ? c2 : c3;
+  const int nc = D == 2 ? 3 : 4;
+  for (int i = 0; i < nc; ++i) {
+    const int R = cand[i];
+    if (nv % R) continue;
+    const int bte = NV / R;
+    if (bte <= (D == 2 ? 512 : 1024)) return R;
+  }
+  return 0;
+}
+
+bool fused_supported(const Ctx& c) {
+  return c.cfg.nv <= kMaxNv && pick_r(c.D, c.cfg.nv, c.NV) > 0;
+}
+
+template <int D, int NC, int MODE, bool FUSE>
+static hipError_t launch_fused_t(const Ctx& c, FusedArgs a) {
+  const int R = pick_r(D, c.cfg.nv, c.NV);
+  a.bte = c.NV / R;
+  const int plane = c.NV / c.cfg.nv;
+  a.dvs = (2.0 * c.cfg.vmax / (c.cfg.nv - 1)) * static_cast<double>(a.bte / plane);
+  const int bt = (a.bte + 63) / 64 * 64;
+  dim3 g(c.npatch), b(bt);
+  switch (R) {
+    case 1: hipLaunchKernelGGL((k_fused<D, NC, MODE, 1, FUSE>), g, b, 0, c.stream, a); break;
+    case 2: hipLaunchKernelGGL((k_fused<D, NC, MODE, 2, FUSE>), g, b, 0, c.stream, a); break;
+    case 4: hipLaunchKernelGGL((k_fused<D, NC, MODE, 4, FUSE>), g, b, 0, c.stream, a); break;
+    case 8:
+      if constexpr (D == 3) hipLaunchKernelGGL((k_fused<D, NC, MODE, 8, FUSE>), g, b, 0, c.stream, a);
+      break;
+    case 10:
+      if constexpr (D == 3) hipLaunchKernelGGL((k_fused<D, NC, MODE, 10, FUSE>), g, b, 0, c.stream, a);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <bool FUSE>
+static hipError_t launch_fused_any(const Ctx& c, const FusedArgs& a) {
+  const int mode = c.cfg.precision;
+  if (c.D == 2) {
+    if (mode == BGK_FP64) return launch_fused_t<2, 2, BGK_FP64, FUSE>(c, a);
+    if (mode == BGK_FP32) return launch_fused_t<2, 2, BGK_FP32, FUSE>(c, a);
+    return launch_fused_t<2, 2, BGK_BF16, FUSE>(c, a);
+  }
+  if (mode == BGK_FP64) return launch_fused_t<3, 1, BGK_FP64, FUSE>(c, a);
+  if (mode == BGK_FP32) return launch_fused_t<3, 1, BGK_FP32, FUSE>(c, a);
+  return launch_fused_t<3, 1, BGK_BF16, FUSE>(c, a);
+}
+
+static double omega_fused(const bgk_config& cfg) {
+  const double dv = 2.0 * cfg.vmax / static_cast<double>(cfg.nv - 1);
+  double w = 1.0;
+  for (int k = 0; k < cfg.dim; ++k) w = w * dv;
+  return w;
+}
+
+hipError_t launch_fused(const Ctx& c, const void* f_in, void* f_out, const double* U_in,
+                        double* rho, double* U_out, double* T, bool fuse) {
+  if (c.npatch == 0) return hipSuccess;
+  FusedArgs a{c.N, c.NV, c.cfg.nv, c.cap, c.Ni, c.npatch, c.ucap, 0,
+              c.cfg.vmax, c.cfg.dt, c.cfg.kn, omega_fused(c.cfg), 0.0,
+              f_in, f_out, U_in,
+              c.cfg.precision == BGK_FP64 ? static_cast<const void*>(c.d.ops64)
+                                          : static_cast<const void*>(c.d.ops32),
+              c.d.cperm, c.d.ucount, c.d.uj, c.d.ue, rho, U_out, T, c.d.err};
+  return fuse ? launch_fused_any<true>(c, a) : launch_fused_any<false>(c, a);
+}
+
+}  // namespace bgk

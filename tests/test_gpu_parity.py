@@ -31,7 +31,8 @@ def cavity(dim, n, nv, vmax=4.0, kn=1.0, lid=0.1, move=1, precision="fp64", **kw
 class Case:
     def __init__(self, cav, seed=0, precision=None, **over):
         self.cav = cav
-        self.c = oracle.config(cav, **{k: v for k, v in over.items() if k != "max_neighbors"})
+        self.c = oracle.config(cav, **{k: v for k, v in over.items()
+                                       if k not in ("max_neighbors", "flags")})
         if "max_neighbors" in over:
             self.c.cap = over["max_neighbors"]
         self.x, self.wid = make_cloud(cav.dim, cav.n, seed)
@@ -247,8 +248,8 @@ def test_moments_and_maxwellian_match(dim, nv):
 
 
 # ---------------------------------------------------------------- full steps
-def run_both(cav, steps, seed=0):
-    k = Case(cav, seed)
+def run_both(cav, steps, seed=0, **over):
+    k = Case(cav, seed, **over)
     sim_f = None
     c = k.c
     f0, rho0, U0, T0 = oracle.initial_state(c)
@@ -285,15 +286,34 @@ def test_step_parity_c1_full_run():
     assert bgk.bgk_diagnostics(k.ctx)["steps"] == cav.steps
 
 
-@pytest.mark.parametrize("dim,n,nv,steps,seed", [(3, 10, 8, 3, 0), (2, 9, 6, 4, 1), (3, 8, 6, 3, 2)])
-def test_step_parity_small(dim, n, nv, steps, seed):
-    k, g, r = run_both(cavity(dim, n, nv), steps, seed)
+@pytest.mark.parametrize("flags", [0, bgk.BGK_FLAG_GENERIC])
+@pytest.mark.parametrize("dim,n,nv,steps,seed", [(3, 10, 8, 3, 0), (2, 9, 6, 4, 1), (3, 8, 6, 3, 2),
+                                                 (2, 12, 24, 2, 3), (3, 7, 16, 2, 4)])
+def test_step_parity_small(dim, n, nv, steps, seed, flags):
+    k, g, r = run_both(cavity(dim, n, nv), steps, seed, flags=flags)
     assert_state_close(g, r)
 
 
-def test_step_parity_frozen_cloud():
-    k, g, r = run_both(cavity(2, 16, 8, move=0, kn=0.5), 4)
+@pytest.mark.parametrize("flags", [0, bgk.BGK_FLAG_GENERIC])
+def test_step_parity_frozen_cloud(flags):
+    k, g, r = run_both(cavity(2, 16, 8, move=0, kn=0.5), 4, flags=flags)
     assert_state_close(g, r)
+
+
+@pytest.mark.parametrize("dim,n,nv", [(2, 20, 24), (3, 8, 8)])
+def test_generic_and_fused_transport_agree(dim, n, nv):
+    f = U = None
+    outs = []
+    for flags in (0, bgk.BGK_FLAG_GENERIC):
+        k = Case(cavity(dim, n, nv), 7, flags=flags)
+        if f is None:
+            f, U = rand_state(k.c, 21)
+        bgk.bgk_geometry(k.ctx, k.x_t)
+        ft = torch.empty((k.c.nc, k.c.n_particles, k.c.NV), dtype=torch.float64, device=DEV)
+        bgk.bgk_transport(k.ctx, k.t(f), ft, k.t(U))
+        bgk.bgk_check(k.ctx)
+        outs.append(ft.cpu().numpy())
+    assert rel(outs[0], outs[1]) <= 1e-13
 
 
 @pytest.mark.parametrize("name", ["c2", "c3"])

@@ -62,7 +62,7 @@ def test_workspace_sizing_and_validation(lib):
     assert bigger > n
     for bad in (dict(nv=15), dict(dim=4), dict(n_particles=0), dict(dt=-1.0),
                 dict(wls_degree=3), dict(max_neighbors=300), dict(precision=5),
-                dict(reserved=1), dict(h=0.0)):
+                dict(flags=2), dict(h=0.0)):
         with pytest.raises(lib.BgkError) as e:
             lib.bgk_workspace_bytes(_cfg(lib, **bad))
         assert e.value.code == lib.BGK_EINVAL, bad
