@@ -202,8 +202,9 @@ int bgk_maxwellian(bgk_ctx* ctx, const double* rho, const double* U, const doubl
  * the device (or BGK_EDEVICE). */
 int bgk_check(bgk_ctx* ctx);
 
-/* Counters since init (host, int64 [4]): clamped coordinates, steps taken,
- * the largest neighbour count seen, the largest patch union seen. Syncs. */
+/* Diagnostics (host, int64 [4]): clamped coordinates since init, steps
+ * taken, and the largest neighbour count and largest patch union of the
+ * geometry built last by bgk_geometry / bgk_step.  Synchronises. */
 int bgk_diagnostics(bgk_ctx* ctx, int64_t* out4);
 
 /* Instrumentation: while enabled, bgk_step records a pair of HIP events on

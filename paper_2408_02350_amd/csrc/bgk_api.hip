@@ -89,6 +89,7 @@ size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d) {
   t.cstart = reinterpret_cast<int32_t*>(take((2 * ncell + 1) * 4));
   t.ccursor = reinterpret_cast<int32_t*>(take(2 * ncell * 4));
   t.cperm = reinterpret_cast<int32_t*>(take(N * 4));
+  t.xs = reinterpret_cast<double*>(take(N * D * 8));
   t.ncnt = reinterpret_cast<int32_t*>(take(N * 4));
   t.nidx = reinterpret_cast<int32_t*>(take(N * cap * 4));
   t.ops64 = cfg.precision == BGK_FP64 ? reinterpret_cast<double*>(take(N * cap * DD * 8)) : nullptr;
@@ -395,7 +396,12 @@ int bgk_diagnostics(bgk_ctx* ctx, int64_t* out4) {
   if (!ctx || !out4) return BGK_EINVAL;
   Ctx& c = ctx->c;
   int32_t w[bgk::kErrWords];
-  hipError_t e = hipStreamSynchronize(c.stream);
+  hipError_t e = hipSuccess;
+  if (c.geom_valid || c.steps > 0) {
+    e = bgk::launch_max_i32(c.stream, c.d.ncnt, c.N, c.d.err + 2);
+    if (e == hipSuccess) e = bgk::launch_max_i32(c.stream, c.d.ucount, c.npatch, c.d.err + 3);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
   if (e == hipSuccess) e = hipMemcpy(w, c.d.err, sizeof(w), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return bgk::hip_fail(&c, e, "bgk_diagnostics");
   out4[0] = w[1];

@@ -20,7 +20,8 @@ constexpr int kThreads = 256;   // threads per block of the per-particle kernels
 __host__ __device__ constexpr int err_bit(int code) { return 1 << code; }
 
 // Device error word layout (int32): [0] error bits, [1] clamped coordinates,
-// [2] largest neighbour count, [3] largest patch union.
+// [2] largest neighbour count, [3] largest patch union (these two are filled
+// on demand by bgk_diagnostics from the current geometry).
 constexpr int kErrWords = 8;
 
 // Device views of the workspace for one context.
@@ -32,6 +33,7 @@ struct Dev {
   int32_t* cstart;       // [2*ncell + 1] start of each (cell, interior|wall) range
   int32_t* ccursor;      // [2*ncell]
   int32_t* cperm;        // [N]   particles sorted by key; first Ni are interior
+  double* xs;            // [d][N] positions in cperm order
   int32_t* ncnt;         // [N]
   int32_t* nidx;         // [N][cap]
   double* ops64;         // [N][cap][d*d]
@@ -69,6 +71,7 @@ size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d);
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
 hipError_t launch_fill_f64(hipStream_t s, double* p, int64_t n, double v);
 hipError_t launch_copy_i32(hipStream_t s, const int32_t* src, int32_t* dst, int64_t n);
+hipError_t launch_max_i32(hipStream_t s, const int32_t* a, int n, int32_t* out);
 hipError_t launch_scatter_wall_rows(const Ctx& c, int32_t* cnt_out, int32_t* idx_out,
                                     double* c0_out, double* hb_out);
 

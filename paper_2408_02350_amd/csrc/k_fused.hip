@@ -174,33 +174,32 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
     }
     __syncthreads();
 
-    Real fj[R][NC], fn[R][NC];
-    {
-      const int j = uniform(luj[0]);
+    // Neighbour rows are loaded three union entries ahead into a ring of
+    // three register buffers (the loop is unrolled by three so the buffers
+    // never move).  Loads are unconditional (clamped entry, lane-clamped
+    // address), so the waits before each use are exact partial counts.
+    Real ra[R][NC], rb[R][NC], rc[R][NC];
+    const size_t qb = lane_on ? static_cast<size_t>(tid) : 0;
+    auto load_row = [&](int uu, Real (&buf)[R][NC]) {
+      const int j = uniform(luj[uu]);
+      const Real* src = f + static_cast<size_t>(j) * NVs + qb;
 #pragma unroll
       for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-          fn[r][c] = lane_on ? f[c * cs + static_cast<size_t>(j) * NVs + tid +
-                                 static_cast<size_t>(r) * a.bte]
-                             : Real(0);
-    }
-    for (int u = 0; u < cn; ++u) {
+        for (int c = 0; c < NC; ++c) buf[r][c] = src[c * cs + static_cast<size_t>(r) * a.bte];
+      // keep the prefetch where it is issued (the compiler would otherwise
+      // sink it down to its first use, one entry later instead of three)
+      asm volatile("" ::: "memory");
+    };
+    auto process = [&](int u, const Real (&fj)[R][NC]) {
+      // Consume the row once in straight-line code, so that the wait for
+      // its load is placed here (exact: the two newer rows stay in flight)
+      // rather than inside the per-particle branches below.
 #pragma unroll
       for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int c = 0; c < NC; ++c) fj[r][c] = fn[r][c];
+        for (int c = 0; c < NC; ++c) asm volatile("" ::"v"(fj[r][c]));
       const uint32_t mask = uniform(lmask[u]);
-      if (u + 1 < cn) {
-        const int jn = uniform(luj[u + 1]);
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-          for (int c = 0; c < NC; ++c)
-            fn[r][c] = lane_on ? f[c * cs + static_cast<size_t>(jn) * NVs + tid +
-                                   static_cast<size_t>(r) * a.bte]
-                               : Real(0);
-      }
 #pragma unroll
       for (int t = 0; t < TP; ++t) {
         if (mask & (1u << t)) {
@@ -241,6 +240,18 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
           }
         }
       }
+    };
+    const int last = cn - 1;
+    load_row(0, ra);
+    load_row(min(1, last), rb);
+    load_row(min(2, last), rc);
+    for (int u = 0; u < cn; u += 3) {
+      process(u, ra);
+      load_row(min(u + 3, last), ra);
+      if (u + 1 < cn) process(u + 1, rb);
+      load_row(min(u + 4, last), rb);
+      if (u + 2 < cn) process(u + 2, rc);
+      load_row(min(u + 5, last), rc);
     }
   }
 

@@ -7,6 +7,7 @@
 // squared-distance predicate and the normal equations in the plain operation
 // order (no contraction), deterministic outputs (sorted lists, no atomics on
 // values).
+#include <algorithm>
 #include <climits>
 
 #include "device_common.h"
@@ -42,6 +43,26 @@ hipError_t launch_fill_f64(hipStream_t s, double* p, int64_t n, double v) {
 hipError_t launch_copy_i32(hipStream_t s, const int32_t* src, int32_t* dst, int64_t n) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy_i32, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+// Largest of n int32 into *out (one atomic per block).
+__global__ void k_max_i32(const int32_t* __restrict__ a, int n, int32_t* __restrict__ out) {
+  int v = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    v = max(v, a[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  __shared__ int wmax[4];
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(out, max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3])));
+}
+
+hipError_t launch_max_i32(hipStream_t s, const int32_t* a, int n, int32_t* out) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_max_i32, dim3(std::min(64u, blocks_for(n, 256))), dim3(256), 0, s, a, n,
+                     out);
   return hipGetLastError();
 }
 
@@ -121,8 +142,12 @@ __global__ void k_cell_scatter(int N, const int32_t* __restrict__ key, int32_t* 
   perm[pos] = i;
 }
 
-// Sort each cell range ascending so that the permutation is deterministic.
-__global__ void k_cell_sort(int nkeys, const int32_t* __restrict__ start, int32_t* __restrict__ perm) {
+// Sort each cell range ascending so that the permutation is deterministic,
+// and copy the positions into cell order (xs[a][p] = x[a][perm[p]]) so that
+// candidate positions are contiguous loads in the searches below.
+__global__ void k_cell_sort(int nkeys, int N, int D, const int32_t* __restrict__ start,
+                            int32_t* __restrict__ perm, const double* __restrict__ x,
+                            double* __restrict__ xs) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nkeys) return;
   const int b = start[k], e = start[k + 1];
@@ -134,6 +159,10 @@ __global__ void k_cell_sort(int nkeys, const int32_t* __restrict__ start, int32_
       --s;
     }
     perm[s] = v;
+  }
+  for (int p = b; p < e; ++p) {
+    const int j = perm[p];
+    for (int a = 0; a < D; ++a) xs[static_cast<int64_t>(a) * N + p] = x[static_cast<int64_t>(a) * N + j];
   }
 }
 
@@ -153,22 +182,113 @@ hipError_t launch_cells(const Ctx& c, const double* x) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(c.N, 256)), dim3(256), 0, c.stream, c.N,
                      d.key, d.ccursor, d.cperm);
-  hipLaunchKernelGGL(k_cell_sort, dim3(blocks_for(nkeys, 256)), dim3(256), 0, c.stream, nkeys,
-                     d.cstart, d.cperm);
+  hipLaunchKernelGGL(k_cell_sort, dim3(blocks_for(nkeys, 64)), dim3(64), 0, c.stream, nkeys,
+                     c.N, c.D, d.cstart, d.cperm, x, d.xs);
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------ wave helpers
+// The kernels below run one wavefront (a block of 64 threads) per particle,
+// patch or wall particle; lanes work on candidates / neighbours in parallel.
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+  const int lane = threadIdx.x & 63;
+  return __popcll(mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+}
+
+// Ranges of the cells within +-S cells of cell coordinate ci (only the
+// interior part when walls == false).  Writes range starts rb[] and the
+// exclusive prefix of their lengths rpre[] (rpre[nr] = total) to LDS and
+// returns nr.  Must be called by all 64 lanes.
+template <int D, int S>
+__device__ int cell_ranges(const int* ci, int nca, int ncell, bool walls,
+                           const int32_t* __restrict__ cstart, int32_t* rb, int32_t* rpre) {
+  constexpr int W = 2 * S + 1;
+  constexpr int NC = (D == 2) ? W * W : W * W * W;
+  const int parts = walls ? 2 : 1;
+  const int nr = NC * parts;
+  const int lane = threadIdx.x;
+  int carry = 0;
+  for (int r0 = 0; r0 < nr; r0 += kWave) {
+    const int r = r0 + lane;
+    int len = 0, b = 0;
+    if (r < nr) {
+      const int part = r % parts, co = r / parts;
+      int cell = 0, mul = 1, rem = co;
+      bool ok = true;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const int cc = ci[a] + (rem % W) - S;
+        rem /= W;
+        ok = ok && cc >= 0 && cc < nca;
+        cell += cc * mul;
+        mul *= nca;
+      }
+      if (ok) {
+        const int k = cell + part * ncell;
+        b = cstart[k];
+        len = cstart[k + 1] - b;
+      }
+    }
+    int incl = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    if (r < nr) {
+      rb[r] = b;
+      rpre[r] = carry + incl - len;
+    }
+    carry += __shfl(incl, 63, 64);
+  }
+  if (lane == 0) rpre[nr] = carry;
+  __syncthreads();
+  return nr;
+}
+
+// Candidate c (0 <= c < rpre[nr]) -> its slot in the cell-ordered arrays.
+__device__ __forceinline__ int cand_slot(int c, int nr, const int32_t* rb, const int32_t* rpre) {
+  int lo = 0, hi = nr;  // rpre[lo] <= c < rpre[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (rpre[mid] <= c) lo = mid; else hi = mid;
+  }
+  return rb[lo] + (c - rpre[lo]);
+}
+
+// Write the n values of list[] to row[] in ascending order (rank sort; the
+// values are distinct particle indices); only ranks < cap are written.
+__device__ __forceinline__ void rank_sorted_store(const int32_t* list, int n, int cap,
+                                                  int32_t* __restrict__ row) {
+  for (int s = threadIdx.x; s < n; s += kWave) {
+    const int v = list[s];
+    int rank = 0;
+    for (int q = 0; q < n; ++q) rank += (list[q] < v);
+    if (rank < cap) row[rank] = v;
+  }
+}
+
 // ------------------------------------------------------------ S1 neighbours
-// One thread per particle scans the 3^D cells around its own (both the
-// interior and the wall range of each) and inserts every j with
-// |x_j - x_i|^2 <= h^2 into its row in ascending order.
+// One wave per particle: the lanes test the candidates of the 3^D cells
+// around the particle's own (interior and wall ranges) against
+// |x_j - x_i|^2 <= h^2, compact the hits, and store them ascending.
+constexpr int kHitCap = 1024;  // hits kept in LDS (more are only counted)
+
 template <int D>
-__global__ void k_neighbors(int N, int nca, int ncell, double h2, int cap,
-                            const double* __restrict__ x, const int32_t* __restrict__ cstart,
-                            const int32_t* __restrict__ cperm, int32_t* __restrict__ cnt,
-                            int32_t* __restrict__ idx, int32_t* __restrict__ err) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+__global__ __launch_bounds__(64) void k_neighbors(int N, int nca, int ncell, double h2, int cap,
+                                                  const double* __restrict__ x,
+                                                  const double* __restrict__ xs,
+                                                  const int32_t* __restrict__ cstart,
+                                                  const int32_t* __restrict__ cperm,
+                                                  int32_t* __restrict__ cnt,
+                                                  int32_t* __restrict__ idx,
+                                                  int32_t* __restrict__ err) {
+  constexpr int NR = (D == 2 ? 9 : 27) * 2;
+  __shared__ int32_t rb[NR], rpre[NR + 1];
+  __shared__ int32_t hits[kHitCap];
+  const int i = blockIdx.x, lane = threadIdx.x;
   double xi[D];
   int ci[D];
 #pragma unroll
@@ -176,59 +296,45 @@ __global__ void k_neighbors(int N, int nca, int ncell, double h2, int cap,
     xi[a] = x[static_cast<int64_t>(a) * N + i];
     ci[a] = cell_coord(xi[a], nca);
   }
-  int32_t* row = idx + static_cast<int64_t>(i) * cap;
+  const int nr = cell_ranges<D, 1>(ci, nca, ncell, true, cstart, rb, rpre);
+  const int total = rpre[nr];
   int m = 0;
-  const int zlo = (D == 3) ? -1 : 0, zhi = (D == 3) ? 1 : 0;
-  for (int dz = zlo; dz <= zhi; ++dz) {
-    const int cz = (D == 3) ? ci[D - 1] + dz : 0;
-    if (D == 3 && (cz < 0 || cz >= nca)) continue;
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int cy = ci[1] + dy;
-      if (cy < 0 || cy >= nca) continue;
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int cx = ci[0] + dx;
-        if (cx < 0 || cx >= nca) continue;
-        const int cell = cx + nca * (cy + nca * cz);
-        for (int part = 0; part < 2; ++part) {
-          const int k = cell + part * ncell;
-          const int pe = cstart[k + 1];
-          for (int p = cstart[k]; p < pe; ++p) {
-            const int j = cperm[p];
-            double r2 = 0.0;
+  for (int c0 = 0; c0 < total; c0 += kWave) {
+    const int cidx = c0 + lane;
+    bool hit = false;
+    int j = 0;
+    if (cidx < total) {
+      const int p = cand_slot(cidx, nr, rb, rpre);
+      j = cperm[p];
+      double r2 = 0.0;
 #pragma unroll
-            for (int a = 0; a < D; ++a) {
-              const double dl = x[static_cast<int64_t>(a) * N + j] - xi[a];
-              r2 = r2 + dl * dl;
-            }
-            if (r2 <= h2) {
-              if (m < cap) {
-                int s = m;
-                while (s > 0 && row[s - 1] > j) {
-                  row[s] = row[s - 1];
-                  --s;
-                }
-                row[s] = j;
-              }
-              ++m;
-            }
-          }
-        }
+      for (int a = 0; a < D; ++a) {
+        const double dl = xs[static_cast<int64_t>(a) * N + p] - xi[a];
+        r2 = r2 + dl * dl;
       }
+      hit = r2 <= h2;
     }
+    const uint64_t mask = __ballot(hit);
+    const int pos = m + lanes_below(mask);
+    if (hit && pos < kHitCap) hits[pos] = j;
+    m += __popcll(mask);
   }
-  cnt[i] = m;
-  atomicMax(&err[2], m);
-  if (m > cap) raise_error(err, BGK_ENBR_OVERFLOW);
+  __syncthreads();
+  rank_sorted_store(hits, min(m, kHitCap), cap, idx + static_cast<int64_t>(i) * cap);
+  if (lane == 0) {
+    cnt[i] = m;
+    if (m > cap) raise_error(err, BGK_ENBR_OVERFLOW);
+  }
 }
 
 hipError_t launch_neighbors(const Ctx& c, const double* x, int32_t* cnt, int32_t* idx) {
   const double h2 = c.cfg.h * c.cfg.h;
   if (c.D == 2)
-    hipLaunchKernelGGL(k_neighbors<2>, dim3(blocks_for(c.N, 128)), dim3(128), 0, c.stream, c.N,
-                       c.nca, c.ncell, h2, c.cap, x, c.d.cstart, c.d.cperm, cnt, idx, c.d.err);
+    hipLaunchKernelGGL(k_neighbors<2>, dim3(c.N), dim3(kWave), 0, c.stream, c.N, c.nca, c.ncell,
+                       h2, c.cap, x, c.d.xs, c.d.cstart, c.d.cperm, cnt, idx, c.d.err);
   else
-    hipLaunchKernelGGL(k_neighbors<3>, dim3(blocks_for(c.N, 128)), dim3(128), 0, c.stream, c.N,
-                       c.nca, c.ncell, h2, c.cap, x, c.d.cstart, c.d.cperm, cnt, idx, c.d.err);
+    hipLaunchKernelGGL(k_neighbors<3>, dim3(c.N), dim3(kWave), 0, c.stream, c.N, c.nca, c.ncell,
+                       h2, c.cap, x, c.d.xs, c.d.cstart, c.d.cperm, cnt, idx, c.d.err);
   return hipGetLastError();
 }
 
@@ -253,46 +359,64 @@ struct Basis {
 
 __device__ __forceinline__ constexpr int tri(int r, int s) { return r * (r + 1) / 2 + s; }
 
-// In-place Cholesky of a packed lower triangle; false on a non-positive pivot.
-template <int B>
-__device__ __forceinline__ bool cholesky_packed(double* A) {
-#pragma unroll
+// Weighted least squares on one wave, for the stencil already staged in LDS
+// as P[e][B] (basis values) and W[e] (weights), e < m.  Builds
+// A = sum_e W_e p_e p_e^T (each entry summed over e in order), factors it
+// A = L L^T (Cholesky, column by column, the rows of a column in parallel),
+// and solves L L^T z = e_col for the NCOL columns col0 .. col0+NCOL-1 into
+// Z[k][B].  Returns false on a non-positive pivot.  All 64 lanes call it.
+template <int B, int NCOL>
+__device__ bool wave_lsq(int m, const double* P, const double* W, double* A, double* Z, int col0,
+                         int* flag) {
+  constexpr int NT = B * (B + 1) / 2;
+  const int lane = threadIdx.x;
+  for (int l = lane; l < NT; l += kWave) {
+    int r = 0;
+    while (tri(r + 1, 0) <= l) ++r;
+    const int s = l - tri(r, 0);
+    double acc = 0.0;
+    for (int e = 0; e < m; ++e) acc = acc + (W[e] * P[e * B + r]) * P[e * B + s];
+    A[l] = acc;
+  }
+  if (lane == 0) *flag = 0;
+  __syncthreads();
   for (int j = 0; j < B; ++j) {
-    double s = A[tri(j, j)];
+    if (lane == 0) {
+      double s = A[tri(j, j)];
+      for (int k = 0; k < j; ++k) s = s - A[tri(j, k)] * A[tri(j, k)];
+      if (!(s > 0.0)) *flag = 1;
+      A[tri(j, j)] = sqrt(s);
+    }
+    __syncthreads();
+    if (*flag) return false;
+    if (lane > j && lane < B) {
+      double t = A[tri(lane, j)];
+      for (int k = 0; k < j; ++k) t = t - A[tri(lane, k)] * A[tri(j, k)];
+      A[tri(lane, j)] = t / A[tri(j, j)];
+    }
+    __syncthreads();
+  }
+  if (lane < NCOL) {
+    const int col = col0 + lane;
+    double y[B];
 #pragma unroll
-    for (int k = 0; k < j; ++k) s = s - A[tri(j, k)] * A[tri(j, k)];
-    if (!(s > 0.0)) return false;
-    const double ljj = sqrt(s);
-    A[tri(j, j)] = ljj;
+    for (int i = 0; i < B; ++i) {
+      double s = (i == col) ? 1.0 : 0.0;
 #pragma unroll
-    for (int i = j + 1; i < B; ++i) {
-      double t = A[tri(i, j)];
+      for (int k = 0; k < i; ++k) s = s - A[tri(i, k)] * y[k];
+      y[i] = s / A[tri(i, i)];
+    }
+    double* z = Z + lane * B;
 #pragma unroll
-      for (int k = 0; k < j; ++k) t = t - A[tri(i, k)] * A[tri(j, k)];
-      A[tri(i, j)] = t / ljj;
+    for (int i = B - 1; i >= 0; --i) {
+      double s = y[i];
+#pragma unroll
+      for (int k = i + 1; k < B; ++k) s = s - A[tri(k, i)] * z[k];
+      z[i] = s / A[tri(i, i)];
     }
   }
+  __syncthreads();
   return true;
-}
-
-// Solve L L^T z = e_col with L packed.
-template <int B>
-__device__ __forceinline__ void chol_solve_unit(const double* L, int col, double* z) {
-  double y[B];
-#pragma unroll
-  for (int i = 0; i < B; ++i) {
-    double s = (i == col) ? 1.0 : 0.0;
-#pragma unroll
-    for (int k = 0; k < i; ++k) s = s - L[tri(i, k)] * y[k];
-    y[i] = s / L[tri(i, i)];
-  }
-#pragma unroll
-  for (int i = B - 1; i >= 0; --i) {
-    double s = y[i];
-#pragma unroll
-    for (int k = i + 1; k < B; ++k) s = s - L[tri(k, i)] * z[k];
-    z[i] = s / L[tri(i, i)];
-  }
 }
 
 // Edge frame of x_j - x_i (Sec. 3.4.2) without trigonometric calls: in 2D
@@ -343,56 +467,48 @@ struct WlsArgs {
   int32_t* err;
 };
 
+// One interior particle per wave: stage the basis values and weights of its
+// stencil (lane = neighbour), solve the normal equations, then each lane
+// forms the gradient row of its neighbour, the edge frame and (P, Q[, R]).
 template <int D, int DEG>
-__device__ __forceinline__ bool wls_particle(const WlsArgs& a, int i, int m) {
+__device__ bool wls_wave(const WlsArgs& a, int i, int m, double* sm) {
   using Bs = Basis<D, DEG>;
   constexpr int B = Bs::B, DD = D * D;
+  double* P = sm;                     // [cap][B]
+  double* W = P + a.cap * B;          // [cap]
+  double* A = W + a.cap;              // [NT]
+  double* Z = A + Bs::NT;             // [D][B]
+  int* flag = reinterpret_cast<int*>(Z + D * B);
+  const int lane = threadIdx.x;
   const int64_t row = static_cast<int64_t>(i) * a.cap;
   double xi[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) xi[k] = a.x[static_cast<int64_t>(k) * a.N + i];
-  double A[Bs::NT];
-#pragma unroll
-  for (int k = 0; k < Bs::NT; ++k) A[k] = 0.0;
-  for (int e = 0; e < m; ++e) {
+  for (int e = lane; e < m; e += kWave) {
     const int j = a.idx[row + e];
-    double y[D], r2 = 0.0, p[B];
+    double y[D], r2 = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       y[k] = (a.x[static_cast<int64_t>(k) * a.N + j] - xi[k]) / a.h;
       r2 = r2 + y[k] * y[k];
     }
-    const double w = exp(-a.alpha * r2);
-    Bs::eval(y, p);
-#pragma unroll
-    for (int r = 0; r < B; ++r) {
-      const double wp = w * p[r];
-#pragma unroll
-      for (int s = 0; s <= r; ++s) A[tri(r, s)] = A[tri(r, s)] + wp * p[s];
-    }
+    W[e] = exp(-a.alpha * r2);
+    Bs::eval(y, P + e * B);
   }
-  if (!cholesky_packed<B>(A)) return false;
-  double z[D][B];
-#pragma unroll
-  for (int k = 0; k < D; ++k) chol_solve_unit<B>(A, 1 + k, z[k]);
-  for (int e = 0; e < m; ++e) {
+  __syncthreads();
+  if (!wave_lsq<B, D>(m, P, W, A, Z, 1, flag)) return false;
+  for (int e = lane; e < m; e += kWave) {
     const int j = a.idx[row + e];
-    double y[D], dl[D], r2 = 0.0, p[B];
+    double dl[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      dl[k] = a.x[static_cast<int64_t>(k) * a.N + j] - xi[k];
-      y[k] = dl[k] / a.h;
-      r2 = r2 + y[k] * y[k];
-    }
-    const double w = exp(-a.alpha * r2);
-    Bs::eval(y, p);
+    for (int k = 0; k < D; ++k) dl[k] = a.x[static_cast<int64_t>(k) * a.N + j] - xi[k];
     double g[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       double s = 0.0;
 #pragma unroll
-      for (int r = 0; r < B; ++r) s = s + z[k][r] * p[r];
-      g[k] = w * s / a.h;
+      for (int r = 0; r < B; ++r) s = s + Z[k * B + r] * P[e * B + r];
+      g[k] = W[e] * s / a.h;
     }
     if (a.grad) {
 #pragma unroll
@@ -431,24 +547,27 @@ __device__ __forceinline__ bool wls_particle(const WlsArgs& a, int i, int m) {
   return true;
 }
 
-// One thread per interior particle.  Degree: the configured one if the
-// stencil holds at least twice as many points as degree-2 basis functions,
-// else 1 if it holds d+2 points, else BGK_ESINGULAR.
+// Degree: the configured one if the stencil holds at least twice as many
+// points as degree-2 basis functions, else 1 if it holds d+2 points, else
+// BGK_ESINGULAR.
 template <int D>
-__global__ __launch_bounds__(128) void k_wls(const WlsArgs a) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.Ni) return;
-  const int i = a.plist[k];
+__global__ __launch_bounds__(64) void k_wls(const WlsArgs a) {
+  extern __shared__ double wls_sm[];
+  const int i = a.plist[blockIdx.x];
   const int m = min(a.cnt[i], a.cap);
   int deg = a.deg_cfg;
   if (deg == 2 && m < 2 * Basis<D, 2>::B) deg = 1;
   bool ok = m >= D + 2;
-  if (ok) ok = (deg == 2) ? wls_particle<D, 2>(a, i, m) : wls_particle<D, 1>(a, i, m);
-  if (!ok) {
-    raise_error(a.err, BGK_ESINGULAR);
-    deg = 0;
+  if (ok) ok = (deg == 2) ? wls_wave<D, 2>(a, i, m, wls_sm) : wls_wave<D, 1>(a, i, m, wls_sm);
+  if (threadIdx.x == 0) {
+    if (!ok) raise_error(a.err, BGK_ESINGULAR);
+    if (a.degree) a.degree[i] = ok ? deg : 0;
   }
-  if (a.degree) a.degree[i] = deg;
+}
+
+static size_t wls_smem(int D, int cap) {
+  const int B = (D == 2) ? 6 : 10;
+  return (static_cast<size_t>(cap) * B + cap + B * (B + 1) / 2 + D * B + 1) * sizeof(double);
 }
 
 hipError_t launch_wls(const Ctx& c, const double* x, const int32_t* cnt, const int32_t* idx,
@@ -456,21 +575,25 @@ hipError_t launch_wls(const Ctx& c, const double* x, const int32_t* cnt, const i
   WlsArgs a{c.N, c.cap, c.Ni, c.cfg.wls_degree, c.cfg.h, c.cfg.alpha, x, c.d.cperm, cnt, idx,
             grad, ops, ops32, degree, c.d.err};
   if (c.Ni == 0) return hipSuccess;
+  const size_t sm = wls_smem(c.D, c.cap);
   if (c.D == 2)
-    hipLaunchKernelGGL(k_wls<2>, dim3(blocks_for(c.Ni, 128)), dim3(128), 0, c.stream, a);
+    hipLaunchKernelGGL(k_wls<2>, dim3(c.Ni), dim3(kWave), sm, c.stream, a);
   else
-    hipLaunchKernelGGL(k_wls<3>, dim3(blocks_for(c.Ni, 128)), dim3(128), 0, c.stream, a);
+    hipLaunchKernelGGL(k_wls<3>, dim3(c.Ni), dim3(kWave), sm, c.stream, a);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------ wall rows
-// One thread per wall particle b: interior particles within hb (first of h,
-// 1.5h, 2h giving d+2 of them), ascending, and the degree-1 least-squares
-// value weights at x_b (weights exp(-alpha r^2/hb^2)).
+// One wave per wall particle b: the interior particles within 2h (cells
+// within +-2, interior ranges) are collected with their squared distances;
+// hb is the first of h, 1.5h, 2h with at least d+2 of them inside; those are
+// stored ascending with the degree-1 least-squares value weights at x_b
+// (weights exp(-alpha r^2/hb^2)).
 struct WallArgs {
   int N, cap, Nw, nca, ncell;
   double h, alpha;
   const double* x;
+  const double* xs;
   const int32_t* wall_list;
   const int32_t* cstart;
   const int32_t* cperm;
@@ -481,10 +604,19 @@ struct WallArgs {
   int32_t* err;
 };
 
+constexpr int kWallCand = 512;  // candidates within 2h kept in LDS
+
 template <int D>
-__global__ __launch_bounds__(128) void k_wall_stencil(const WallArgs a) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.Nw) return;
+__global__ __launch_bounds__(64) void k_wall_stencil(const WallArgs a) {
+  constexpr int NR = (D == 2 ? 25 : 125);
+  constexpr int B = D + 1;
+  __shared__ int32_t rb[NR], rpre[NR + 1];
+  __shared__ int32_t cj[kWallCand];
+  __shared__ double cr2[kWallCand];
+  __shared__ int32_t sel[kWallCand], srt[256];
+  __shared__ double P[256 * B], W[256], A[B * (B + 1) / 2], Z[B];
+  __shared__ int flag;
+  const int k = blockIdx.x, lane = threadIdx.x;
   const int b = a.wall_list[k];
   double xb[D];
   int cb[D];
@@ -493,117 +625,101 @@ __global__ __launch_bounds__(128) void k_wall_stencil(const WallArgs a) {
     xb[q] = a.x[static_cast<int64_t>(q) * a.N + b];
     cb[q] = cell_coord(xb[q], a.nca);
   }
+  const int nr = cell_ranges<D, 2>(cb, a.nca, a.ncell, false, a.cstart, rb, rpre);
+  const int total = rpre[nr];
+  const double h2max = (2.0 * a.h) * (2.0 * a.h);
+  int nc = 0;
+  for (int c0 = 0; c0 < total; c0 += kWave) {
+    const int cidx = c0 + lane;
+    bool hit = false;
+    int j = 0;
+    double r2 = 0.0;
+    if (cidx < total) {
+      const int p = cand_slot(cidx, nr, rb, rpre);
+      j = a.cperm[p];
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        const double dl = a.xs[static_cast<int64_t>(q) * a.N + p] - xb[q];
+        r2 = r2 + dl * dl;
+      }
+      hit = r2 <= h2max;
+    }
+    const uint64_t mask = __ballot(hit);
+    const int pos = nc + lanes_below(mask);
+    if (hit && pos < kWallCand) {
+      cj[pos] = j;
+      cr2[pos] = r2;
+    }
+    nc += __popcll(mask);
+  }
+  nc = min(nc, kWallCand);
+  __syncthreads();
   const double mults[3] = {1.0, 1.5, 2.0};
-  double hb = 0.0, hb2 = 0.0;
+  double hb = 0.0;
   int m = 0;
-  const int zlo = (D == 3) ? -2 : 0, zhi = (D == 3) ? 2 : 0;
   for (int t = 0; t < 3; ++t) {
     hb = mults[t] * a.h;
-    hb2 = hb * hb;
+    const double hb2 = hb * hb;
     m = 0;
-    for (int dz = zlo; dz <= zhi; ++dz) {
-      const int cz = (D == 3) ? cb[D - 1] + dz : 0;
-      if (D == 3 && (cz < 0 || cz >= a.nca)) continue;
-      for (int dy = -2; dy <= 2; ++dy) {
-        const int cy = cb[1] + dy;
-        if (cy < 0 || cy >= a.nca) continue;
-        for (int dx = -2; dx <= 2; ++dx) {
-          const int cx = cb[0] + dx;
-          if (cx < 0 || cx >= a.nca) continue;
-          const int cell = cx + a.nca * (cy + a.nca * cz);
-          for (int p = a.cstart[cell]; p < a.cstart[cell + 1]; ++p) {
-            const int j = a.cperm[p];
-            double r2 = 0.0;
-#pragma unroll
-            for (int q = 0; q < D; ++q) {
-              const double dl = a.x[static_cast<int64_t>(q) * a.N + j] - xb[q];
-              r2 = r2 + dl * dl;
-            }
-            if (r2 <= hb2) {
-              if (m < a.cap) {
-                int32_t* row = a.widx + static_cast<int64_t>(k) * a.cap;
-                int s = m;
-                while (s > 0 && row[s - 1] > j) {
-                  row[s] = row[s - 1];
-                  --s;
-                }
-                row[s] = j;
-              }
-              ++m;
-            }
-          }
-        }
-      }
+    for (int c0 = 0; c0 < nc; c0 += kWave) {
+      const int q = c0 + lane;
+      const bool in = q < nc && cr2[q] <= hb2;
+      const uint64_t mask = __ballot(in);
+      const int pos = m + lanes_below(mask);
+      if (in) sel[pos] = cj[q];
+      m += __popcll(mask);
     }
     if (m >= D + 2) break;
   }
-  a.whb[k] = hb;
-  if (m < D + 2) {
-    raise_error(a.err, BGK_ESINGULAR);
-    a.wcnt[k] = 0;
+  __syncthreads();
+  if (lane == 0) a.whb[k] = hb;
+  if (m < D + 2 || m > a.cap) {
+    if (lane == 0) {
+      raise_error(a.err, m < D + 2 ? BGK_ESINGULAR : BGK_ENBR_OVERFLOW);
+      a.wcnt[k] = 0;
+    }
     return;
   }
-  if (m > a.cap) {
-    raise_error(a.err, BGK_ENBR_OVERFLOW);
-    a.wcnt[k] = 0;
-    return;
-  }
-  using Bs = Basis<D, 1>;
-  constexpr int B = Bs::B;
-  const int32_t* row = a.widx + static_cast<int64_t>(k) * a.cap;
-  double A[Bs::NT];
-#pragma unroll
-  for (int q = 0; q < Bs::NT; ++q) A[q] = 0.0;
-  for (int e = 0; e < m; ++e) {
-    const int j = row[e];
-    double y[D], r2 = 0.0, p[B];
+  int32_t* row = a.widx + static_cast<int64_t>(k) * a.cap;
+  rank_sorted_store(sel, m, a.cap, srt);
+  __syncthreads();
+  for (int e = lane; e < m; e += kWave) {
+    const int j = srt[e];
+    row[e] = j;
+    double y[D], r2 = 0.0;
 #pragma unroll
     for (int q = 0; q < D; ++q) {
       y[q] = (a.x[static_cast<int64_t>(q) * a.N + j] - xb[q]) / hb;
       r2 = r2 + y[q] * y[q];
     }
-    const double w = exp(-a.alpha * r2);
-    Bs::eval(y, p);
-#pragma unroll
-    for (int r = 0; r < B; ++r) {
-      const double wp = w * p[r];
-#pragma unroll
-      for (int s = 0; s <= r; ++s) A[tri(r, s)] = A[tri(r, s)] + wp * p[s];
-    }
+    W[e] = exp(-a.alpha * r2);
+    Basis<D, 1>::eval(y, P + e * B);
   }
-  if (!cholesky_packed<B>(A)) {
-    raise_error(a.err, BGK_ESINGULAR);
-    a.wcnt[k] = 0;
+  __syncthreads();
+  if (!wave_lsq<B, 1>(m, P, W, A, Z, 0, &flag)) {
+    if (lane == 0) {
+      raise_error(a.err, BGK_ESINGULAR);
+      a.wcnt[k] = 0;
+    }
     return;
   }
-  double z[B];
-  chol_solve_unit<B>(A, 0, z);
-  for (int e = 0; e < m; ++e) {
-    const int j = row[e];
-    double y[D], r2 = 0.0, p[B];
-#pragma unroll
-    for (int q = 0; q < D; ++q) {
-      y[q] = (a.x[static_cast<int64_t>(q) * a.N + j] - xb[q]) / hb;
-      r2 = r2 + y[q] * y[q];
-    }
-    const double w = exp(-a.alpha * r2);
-    Bs::eval(y, p);
+  for (int e = lane; e < m; e += kWave) {
     double s = 0.0;
 #pragma unroll
-    for (int r = 0; r < B; ++r) s = s + z[r] * p[r];
-    a.wc0[static_cast<int64_t>(k) * a.cap + e] = w * s;
+    for (int r = 0; r < B; ++r) s = s + Z[r] * P[e * B + r];
+    a.wc0[static_cast<int64_t>(k) * a.cap + e] = W[e] * s;
   }
-  a.wcnt[k] = m;
+  if (lane == 0) a.wcnt[k] = m;
 }
 
 hipError_t launch_wall_stencil(const Ctx& c, const double* x) {
   if (c.Nw == 0) return hipSuccess;
-  WallArgs a{c.N, c.cap, c.Nw, c.nca, c.ncell, c.cfg.h, c.cfg.alpha, x, c.d.wall_list,
+  WallArgs a{c.N, c.cap, c.Nw, c.nca, c.ncell, c.cfg.h, c.cfg.alpha, x, c.d.xs, c.d.wall_list,
              c.d.cstart, c.d.cperm, c.d.wcnt, c.d.widx, c.d.wc0, c.d.whb, c.d.err};
   if (c.D == 2)
-    hipLaunchKernelGGL(k_wall_stencil<2>, dim3(blocks_for(c.Nw, 128)), dim3(128), 0, c.stream, a);
+    hipLaunchKernelGGL(k_wall_stencil<2>, dim3(c.Nw), dim3(kWave), 0, c.stream, a);
   else
-    hipLaunchKernelGGL(k_wall_stencil<3>, dim3(blocks_for(c.Nw, 128)), dim3(128), 0, c.stream, a);
+    hipLaunchKernelGGL(k_wall_stencil<3>, dim3(c.Nw), dim3(kWave), 0, c.stream, a);
   return hipGetLastError();
 }
 
@@ -639,58 +755,101 @@ hipError_t launch_scatter_wall_rows(const Ctx& c, int32_t* cnt_out, int32_t* idx
 
 // ------------------------------------------------------------ patch unions
 // Interior particles, taken kPatch at a time in cell order, form a patch.
-// The transport kernel walks the sorted union of the patch's neighbour
-// lists (self excluded) once, loading each f_j row once for all of them.
-// ue[u] holds, per patch slot t, the position of j in slot t's neighbour
-// row in byte t (0xFF: j is not a neighbour of slot t).
-__global__ void k_patches(int Ni, int cap, int ucap, const int32_t* __restrict__ plist,
-                          const int32_t* __restrict__ cnt, const int32_t* __restrict__ idx,
-                          int32_t* __restrict__ ucount, int32_t* __restrict__ uj,
-                          uint32_t* __restrict__ ue, int32_t* __restrict__ err) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p * kPatch >= Ni) return;
-  int pt[kPatch], head[kPatch], m[kPatch];
-#pragma unroll
+// The transport walks the sorted union of the patch's neighbour lists (self
+// excluded) once, loading each f_j row once for all of them.  ue[u] holds,
+// per patch slot t, the position of j in slot t's neighbour row in byte t
+// (0xFF: j is not a neighbour of slot t).
+// One wave per patch: the slot rows are merged by rank (position of each
+// entry = entries smaller than it in every row, ties ordered by slot),
+// equal indices are grouped, and each group becomes one union entry.
+__device__ __forceinline__ int lower_bound_i(const int32_t* v, int n, int x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (v[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(64) void k_patches(int Ni, int cap, int ucap,
+                                                const int32_t* __restrict__ plist,
+                                                const int32_t* __restrict__ cnt,
+                                                const int32_t* __restrict__ idx,
+                                                int32_t* __restrict__ ucount,
+                                                int32_t* __restrict__ uj, uint32_t* __restrict__ ue,
+                                                int32_t* __restrict__ err) {
+  extern __shared__ int32_t psm[];
+  int32_t* rj = psm;                        // [kPatch][cap] neighbour j (self removed)
+  int32_t* re = rj + kPatch * cap;          // [kPatch][cap] its slot in the full row
+  int32_t* mj = re + kPatch * cap;          // [kPatch*cap] merged j
+  int32_t* mt = mj + kPatch * cap;          // merged (slot t << 8 | e)
+  __shared__ int32_t rn[kPatch];
+  const int p = blockIdx.x, lane = threadIdx.x;
   for (int t = 0; t < kPatch; ++t) {
     const int g = p * kPatch + t;
-    pt[t] = g < Ni ? plist[g] : -1;
-    head[t] = 0;
-    m[t] = pt[t] >= 0 ? min(cnt[pt[t]], cap) : 0;
-  }
-  int u = 0;
-  for (;;) {
-    int jmin = INT_MAX;
-#pragma unroll
-    for (int t = 0; t < kPatch; ++t) {
-      const int32_t* row = idx + static_cast<int64_t>(max(pt[t], 0)) * cap;
-      if (head[t] < m[t] && row[head[t]] == pt[t]) ++head[t];
-      if (head[t] < m[t]) jmin = min(jmin, static_cast<int>(row[head[t]]));
+    const int pt = g < Ni ? plist[g] : -1;
+    const int m = pt >= 0 ? min(cnt[pt], cap) : 0;
+    const int32_t* row = idx + static_cast<int64_t>(max(pt, 0)) * cap;
+    // self is in the row exactly once; entries after it shift down by one
+    int self = m;
+    for (int e0 = 0; e0 < m; e0 += kWave) {
+      const int e = e0 + lane;
+      const bool is_self = e < m && row[e] == pt;
+      const uint64_t mask = __ballot(is_self);
+      if (mask) self = e0 + __ffsll(static_cast<long long>(mask)) - 1;
     }
-    if (jmin == INT_MAX) break;
-    uint32_t pe = 0xFFFFFFFFu;
-#pragma unroll
-    for (int t = 0; t < kPatch; ++t) {
-      const int32_t* row = idx + static_cast<int64_t>(max(pt[t], 0)) * cap;
-      if (head[t] < m[t] && row[head[t]] == jmin) {
-        pe = (pe & ~(0xFFu << (8 * t))) | (static_cast<uint32_t>(head[t]) << (8 * t));
-        ++head[t];
+    for (int e = lane; e < m; e += kWave) {
+      if (e == self) continue;
+      const int o = e < self ? e : e - 1;
+      rj[t * cap + o] = row[e];
+      re[t * cap + o] = e;
+    }
+    if (lane == 0) rn[t] = (self < m) ? m - 1 : m;
+  }
+  __syncthreads();
+  int total = 0;
+  for (int t = 0; t < kPatch; ++t) total += rn[t];
+  for (int t = 0; t < kPatch; ++t) {
+    for (int q = lane; q < rn[t]; q += kWave) {
+      const int j = rj[t * cap + q];
+      int pos = q;
+      for (int s = 0; s < kPatch; ++s) {
+        if (s == t) continue;
+        const int* v = rj + s * cap;
+        pos += (s < t) ? lower_bound_i(v, rn[s], j + 1) : lower_bound_i(v, rn[s], j);
+      }
+      mj[pos] = j;
+      mt[pos] = (t << 8) | re[t * cap + q];
+    }
+  }
+  __syncthreads();
+  int nu = 0;
+  for (int c0 = 0; c0 < total; c0 += kWave) {
+    const int q = c0 + lane;
+    const bool head = q < total && (q == 0 || mj[q] != mj[q - 1]);
+    const uint64_t mask = __ballot(head);
+    const int u = nu + lanes_below(mask);
+    if (head) {
+      uint32_t pe = 0xFFFFFFFFu;
+      for (int r = q; r < total && mj[r] == mj[q]; ++r) {
+        const int t = mt[r] >> 8, e = mt[r] & 0xFF;
+        pe = (pe & ~(0xFFu << (8 * t))) | (static_cast<uint32_t>(e) << (8 * t));
+      }
+      if (u < ucap) {
+        uj[static_cast<int64_t>(p) * ucap + u] = mj[q];
+        ue[static_cast<int64_t>(p) * ucap + u] = pe;
       }
     }
-    if (u < ucap) {
-      uj[static_cast<int64_t>(p) * ucap + u] = jmin;
-      ue[static_cast<int64_t>(p) * ucap + u] = pe;
-    }
-    ++u;
+    nu += __popcll(mask);
   }
-  ucount[p] = min(u, ucap);
-  atomicMax(&err[3], u);
+  if (lane == 0) ucount[p] = min(nu, ucap);
 }
 
 hipError_t launch_patches(const Ctx& c) {
   if (c.npatch == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_patches, dim3(blocks_for(c.npatch, 128)), dim3(128), 0, c.stream, c.Ni,
-                     c.cap, c.ucap, c.d.cperm, c.d.ncnt, c.d.nidx, c.d.ucount, c.d.uj, c.d.ue,
-                     c.d.err);
+  const size_t sm = static_cast<size_t>(4) * kPatch * c.cap * sizeof(int32_t);
+  hipLaunchKernelGGL(k_patches, dim3(c.npatch), dim3(kWave), sm, c.stream, c.Ni, c.cap, c.ucap,
+                     c.d.cperm, c.d.ncnt, c.d.nidx, c.d.ucount, c.d.uj, c.d.ue, c.d.err);
   return hipGetLastError();
 }
 
