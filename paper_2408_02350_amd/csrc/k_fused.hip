@@ -80,7 +80,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   __shared__ double vtab[kMaxNv];
   __shared__ double red[16][TP][D + 1];
   __shared__ double etab[TP][D][kMaxNv];
-  __shared__ double pstat[TP][D + 3];           // rho, U[d], T, tau
+  __shared__ double pstat[TP][D + 5];           // rho, U[d], T, norm, a, b
 
   const int tid = threadIdx.x;
   const int nthreads = blockDim.x;
@@ -359,11 +359,21 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
       const double rho = a.omega * s0t[t];
       const double T = s / (3.0 * s0t[t]);
       const double tau = a.kn * sqrt(2.0 / kPi) / (rho * sqrt(T));
+      const double rden = 1.0 / (tau + a.dt);
+      double norm;
+      if (D == 3) {
+        const double tp = 2.0 * kPi * T;
+        norm = rho / (tp * sqrt(tp));
+      } else {
+        norm = rho / (2.0 * kPi * T);
+      }
       pstat[t][0] = rho;
 #pragma unroll
       for (int k = 0; k < D; ++k) pstat[t][1 + k] = Ut[t][k];
       pstat[t][D + 1] = T;
-      pstat[t][D + 2] = tau;
+      pstat[t][D + 2] = norm;
+      pstat[t][D + 3] = tau * rden;   // f^{n+1} = a ft + b M, a = tau/(tau+dt)
+      pstat[t][D + 4] = a.dt * rden;  //                       b = dt/(tau+dt)
       const int g = patch * TP + t;
       const int i = g < a.Ni ? a.plist[g] : -1;
       if (i >= 0) {
@@ -383,33 +393,24 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
       etab[t][k][m] = exp(-(dv * dv) / (2.0 * pstat[t][D + 1]));
     }
     __syncthreads();
-    // ---- S6: f^{n+1} = (tau ft + dt M)/(tau + dt)
-    const double two_pi = 2.0 * kPi;
+    // ---- S6: f^{n+1} = (tau ft + dt M)/(tau + dt) = a ft + b M
 #pragma unroll
     for (int t = 0; t < TP; ++t) {
       if (pt[t] < 0 || !lane_on) continue;
-      const double rho = pstat[t][0], T = pstat[t][D + 1], tau = pstat[t][D + 2];
-      double norm;
-      if (D == 3) {
-        const double tp = two_pi * T;
-        norm = rho / (tp * sqrt(tp));
-      } else {
-        norm = rho / (two_pi * T);
-      }
-      const double den = tau + a.dt;
-      double efix = 1.0;
+      const double T = pstat[t][D + 1], norm = pstat[t][D + 2];
+      const double ca = pstat[t][D + 3], cb = pstat[t][D + 4];
+      double efix = norm;
 #pragma unroll
       for (int k = 0; k < D - 1; ++k) efix = efix * etab[t][k][kq[k]];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const double M1 = norm * (efix * etab[t][D - 1][kq[D - 1] + r * kstep]);
+        const double M1 = efix * etab[t][D - 1][kq[D - 1] + r * kstep];
         const size_t q = static_cast<size_t>(tid) + static_cast<size_t>(r) * a.bte;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           const double M = (c == 1) ? T * M1 : M1;
           const double x = static_cast<double>(fi[t][r][c]);
-          fo[c * cs + static_cast<size_t>(pt[t]) * NVs + q] =
-              static_cast<Real>((tau * x + a.dt * M) / den);
+          fo[c * cs + static_cast<size_t>(pt[t]) * NVs + q] = static_cast<Real>(fma(cb, M, ca * x));
         }
       }
     }
