@@ -83,6 +83,10 @@ def lib():
         L.ref_objective.argtypes = [cp, ip, dp, dp, dp, ctypes.c_double]
         L.ref_rollout_dual.argtypes = [cp, ip, dp, dp, dp, ctypes.c_double, ctypes.c_int,
                                        ctypes.c_double, dp, dp, dp]
+        L.ref_step_dual.argtypes = [cp, ip, dp, dp, dp, dp, dp, ctypes.c_double,
+                                    dp, dp, dp, dp, dp, dp, dp, dp]
+        L.ref_objective_dual.restype = ctypes.c_double
+        L.ref_objective_dual.argtypes = [cp, ip, dp, dp, dp, dp, dp, dp, ctypes.c_double]
         _lib = L
     return _lib
 
@@ -286,3 +290,27 @@ def rollout_dual(c, wall_id, x, f0, nsteps, f0_dot=None, lid_dot=0.0, ke_weight=
                                   ctypes.byref(J), ctypes.byref(Jd),
                                   _d(ff) if ff is not None else None), "rollout_dual")
     return J.value, Jd.value, ff
+
+
+def step_dual(c, wall_id, x, f, U, f_dot=None, U_dot=None, lid_dot=0.0):
+    """One frozen-cloud step with tangents. Returns (f1, f1_dot, U1, U1_dot,
+    rho, rho_dot, T, T_dot)."""
+    N = c.n_particles
+    f, U = _f64(f), _f64(U)
+    fd = _f64(f_dot) if f_dot is not None else None
+    Ud = _f64(U_dot) if U_dot is not None else None
+    f1, f1d = np.empty_like(f), np.empty_like(f)
+    U1, U1d = np.zeros((c.dim, N)), np.zeros((c.dim, N))
+    r, rd, T, Td = np.zeros(N), np.zeros(N), np.zeros(N), np.zeros(N)
+    _check(lib().ref_step_dual(ctypes.byref(c), _i(_i32(wall_id)), _d(_f64(x)), _d(f),
+                               _d(fd) if fd is not None else None, _d(U),
+                               _d(Ud) if Ud is not None else None, lid_dot, _d(f1), _d(f1d),
+                               _d(U1), _d(U1d), _d(r), _d(rd), _d(T), _d(Td)), "step_dual")
+    return f1, f1d, U1, U1d, r, rd, T, Td
+
+
+def objective_dual(c, wall_id, f, rho, U, f_dot=None, rho_dot=None, U_dot=None, ke_weight=1.0):
+    """Directional derivative of objective() along (f_dot, rho_dot, U_dot)."""
+    a = lambda v: _d(_f64(v)) if v is not None else None
+    return lib().ref_objective_dual(ctypes.byref(c), _i(_i32(wall_id)), _d(_f64(f)), a(f_dot),
+                                    _d(_f64(rho)), a(rho_dot), _d(_f64(U)), a(U_dot), ke_weight)

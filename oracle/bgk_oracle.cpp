@@ -923,4 +923,54 @@ int ref_rollout_dual(const ref_config* c, const int32_t* wall_id, const double* 
   return R_OK;
 }
 
+// One frozen-cloud step with tangents: (f, U) with directions (f_dot,
+// U_dot) and the lid speed's direction lid_dot -> f^{n+1}, U^{n+1}, rho, T
+// and their exact directional derivatives.  Null tangent inputs are zero.
+int ref_step_dual(const ref_config* c, const int32_t* wall_id, const double* x, const double* f,
+                  const double* f_dot, const double* U, const double* U_dot, double lid_dot,
+                  double* f_out, double* f_out_dot, double* U_out, double* U_out_dot,
+                  double* rho, double* rho_dot, double* T, double* T_dot) {
+  if (!config_ok(*c)) return R_EINVAL;
+  Geometry g;
+  int rc = g.build(*c, x, wall_id);
+  if (rc) return rc;
+  const int N = c->n_particles;
+  const int64_t total = static_cast<int64_t>(n_comp(*c)) * N * n_vel(*c);
+  std::vector<Dual> fa(total), fb(total), Ud(static_cast<size_t>(3) * N), rd(N), Td(N);
+  for (int64_t k = 0; k < total; ++k) fa[k] = Dual(f[k], f_dot ? f_dot[k] : 0.0);
+  for (int64_t k = 0; k < static_cast<int64_t>(c->dim) * N; ++k)
+    Ud[k] = Dual(U[k], U_dot ? U_dot[k] : 0.0);
+  rc = advance(*c, g, wall_id, Dual(c->lid, lid_dot), fa.data(), fb.data(), Ud.data(), rd.data(),
+               Td.data());
+  for (int64_t k = 0; k < total; ++k) {
+    f_out[k] = fb[k].v;
+    f_out_dot[k] = fb[k].d;
+  }
+  for (int64_t k = 0; k < static_cast<int64_t>(c->dim) * N; ++k) {
+    U_out[k] = Ud[k].v;
+    U_out_dot[k] = Ud[k].d;
+  }
+  for (int i = 0; i < N; ++i) {
+    rho[i] = rd[i].v;
+    rho_dot[i] = rd[i].d;
+    T[i] = Td[i].v;
+    T_dot[i] = Td[i].d;
+  }
+  return rc;
+}
+
+// Directional derivative of the objective along (f_dot, rho_dot, U_dot).
+double ref_objective_dual(const ref_config* c, const int32_t* wall_id, const double* f,
+                          const double* f_dot, const double* rho, const double* rho_dot,
+                          const double* U, const double* U_dot, double ke_weight) {
+  const int N = c->n_particles;
+  const int64_t total = static_cast<int64_t>(n_comp(*c)) * N * n_vel(*c);
+  std::vector<Dual> fa(total), ra(N), Ua(static_cast<size_t>(3) * N);
+  for (int64_t k = 0; k < total; ++k) fa[k] = Dual(f[k], f_dot ? f_dot[k] : 0.0);
+  for (int i = 0; i < N; ++i) ra[i] = Dual(rho[i], rho_dot ? rho_dot[i] : 0.0);
+  for (int64_t k = 0; k < static_cast<int64_t>(c->dim) * N; ++k)
+    Ua[k] = Dual(U[k], U_dot ? U_dot[k] : 0.0);
+  return objective(*c, wall_id, fa.data(), ra.data(), Ua.data(), ke_weight).d;
+}
+
 }  // extern "C"

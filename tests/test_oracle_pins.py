@@ -522,3 +522,100 @@ def test_dual_directional_derivative_matches_central_differences():
            - oracle.rollout_dual(cm, wid, x, f0, steps)[0]) / (2 * eps)
     assert abs(Jl - fdl) < 1e-6 * abs(fdl)
     assert abs(Jl) > 1e-6
+
+
+# --------------------------------------------------------------- objective
+def _heat_flux_state(c, a, U=None):
+    """f = M[1, 0, 1] (1 + a w_n (|w|^2 - 5)) in 3D, w = v, n the last axis;
+    in 2D its Chu reduction g1 = int f dv3 = M2 (1 + a w_n (|w|^2 - 4)),
+    g2 = int v3^2 f dv3 = M2 (1 + a w_n (|w|^2 - 2)).  The perturbation has
+    zero density, momentum and energy, and the exact heat flux along n is
+    q_n = 1/2 E[w_n^2 |w|^2 (|w|^2 - 5)] a = (35 - 25) a / 2 = 5 a."""
+    N = c.n_particles
+    rho = np.ones(N)
+    U = np.zeros((c.dim, N)) if U is None else U
+    M = oracle.maxwellian(c, rho, U, np.ones(N))
+    v = oracle.velocities(c)
+    w2 = np.sum(v ** 2, axis=1)
+    wn = v[:, c.dim - 1]
+    if c.dim == 3:
+        return M * (1 + a * wn * (w2 - 5))[None, None, :]
+    f = M.copy()
+    f[0] *= (1 + a * wn * (w2 - 4))[None, :]
+    f[1] *= (1 + a * wn * (w2 - 2))[None, :]
+    return f
+
+
+@pytest.mark.parametrize("dim,nv,vmax", [(2, 48, 7.0), (3, 32, 7.0)])
+def test_objective_heat_flux_of_a_hermite_perturbation(dim, nv, vmax):
+    # closed form: every lid particle carries q_n = 5a, weighted by dx^(d-1)
+    n = 4
+    c = cfg(dim, n, nv, vmax)
+    _, wid = make_cloud(dim, n, 0)
+    a = 0.01
+    f = _heat_flux_state(c, a)
+    rho, U, T = oracle.moments(c, f)
+    assert np.max(np.abs(U)) < 1e-9 and np.max(np.abs(rho - 1)) < 1e-9
+    J = oracle.objective(c, wid, f, rho, U, ke_weight=0.0)
+    n_lid = int(np.sum(wid == 2 * dim))
+    exact = c.dx ** (dim - 1) * n_lid * 5 * a
+    assert abs(J - exact) < 1e-6 * exact  # quadrature (grid truncation at vmax)
+    # at U = 0 the flux is odd in a: the state with -a gives -J
+    Z = np.zeros_like(U)
+    Jp = oracle.objective(c, wid, f, rho, Z, ke_weight=0.0)
+    Jm = oracle.objective(c, wid, _heat_flux_state(c, -a), rho, Z, ke_weight=0.0)
+    assert abs(Jp + Jm) < 1e-12 * exact
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_objective_is_frame_invariant_and_counts_kinetic_energy(dim):
+    # a drifting Maxwellian has no heat flux in its own frame; J is then the
+    # kinetic-energy term alone: ke/N sum rho |U|^2 / 2
+    n = 4
+    c = cfg(dim, n, 24 if dim == 2 else 16, 7.0)
+    _, wid = make_cloud(dim, n, 0)
+    N = c.n_particles
+    rng = np.random.default_rng(3)
+    U0 = rng.uniform(-0.3, 0.3, (dim, N))
+    r0 = rng.uniform(0.5, 1.5, N)
+    f = oracle.maxwellian(c, r0, U0, np.ones(N))
+    rho, U, T = oracle.moments(c, f)
+    # (quadrature error only; a lab-frame flux would be O(rho |U| T))
+    assert abs(oracle.objective(c, wid, f, rho, U, ke_weight=0.0)) < 1e-7 * c.dx ** (dim - 1)
+    ke = 0.7
+    J = oracle.objective(c, wid, f, rho, U, ke_weight=ke)
+    J0 = oracle.objective(c, wid, f, rho, U, ke_weight=0.0)
+    expect = ke / N * np.sum(0.5 * rho * np.sum(U ** 2, axis=0))
+    assert abs((J - J0) - expect) < 1e-12 * expect
+
+
+def test_step_and_objective_tangents_match_central_differences():
+    n = 8
+    x, wid = make_cloud(2, n, 1)
+    c = cfg(2, n, 8, 4.0, move=0, kn=0.5)
+    f0, rho0, U0, T0 = oracle.initial_state(c)
+    rng = np.random.default_rng(5)
+    f = f0 * (1 + 0.05 * rng.uniform(-1, 1, f0.shape))
+    U = 0.05 * rng.uniform(-1, 1, U0.shape)
+    df = f0 * rng.normal(size=f0.shape)
+    dU = rng.normal(size=U0.shape) * 0.1
+    dl = 0.7
+    out = oracle.step_dual(c, wid, x, f, U, df, dU, dl)
+    eps = 1e-6
+
+    def run(s):
+        cs = cfg(2, n, 8, 4.0, move=0, kn=0.5, lid=c.lid + s * dl)
+        return oracle.step_dual(cs, wid, x, f + s * df, U + s * dU)
+
+    p, m = run(eps), run(-eps)
+    for k in (0, 2, 4, 6):  # f1, U1, rho, T
+        fd = (p[k] - m[k]) / (2 * eps)
+        assert np.max(np.abs(out[k + 1] - fd)) < 1e-7 * np.max(np.abs(fd)), k
+    # the tangent of the lid alone is non-trivial
+    assert np.max(np.abs(oracle.step_dual(c, wid, x, f, U, lid_dot=1.0)[1])) > 1e-6
+    f1, _, U1, _, r1, _, T1, _ = out
+    dr = rng.normal(size=r1.shape)
+    d1 = oracle.objective_dual(c, wid, f1, r1, U1, df, dr, dU, ke_weight=0.5)
+    fd = (oracle.objective(c, wid, f1 + eps * df, r1 + eps * dr, U1 + eps * dU, 0.5)
+          - oracle.objective(c, wid, f1 - eps * df, r1 - eps * dr, U1 - eps * dU, 0.5)) / (2 * eps)
+    assert abs(d1 - fd) < 1e-7 * abs(fd)
