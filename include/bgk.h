@@ -69,7 +69,7 @@ typedef enum {
 } bgk_status;
 
 enum { BGK_FP64 = 0, BGK_FP32 = 1, BGK_BF16 = 2 };
-enum { BGK_FLAG_GENERIC = 1 };
+enum { BGK_FLAG_GENERIC = 1, BGK_FLAG_ADJOINT = 2 };
 
 typedef struct {
   int32_t dim;           /* 2: Chu-reduced BGK (Sec. 2.1, g1 and g2); 3: full BGK        */
@@ -82,8 +82,10 @@ typedef struct {
                             BGK_BF16 (FP32 f; transport products of BF16 operands with
                             FP32 accumulation).  Geometry, least squares and moment
                             sums are FP64 in every mode.                                  */
-  int32_t flags;         /* 0, or BGK_FLAG_GENERIC: use the separate transport and
-                            relaxation kernels instead of the fused one (for testing)    */
+  int32_t flags;         /* bit set: BGK_FLAG_GENERIC uses the separate transport and
+                            relaxation kernels instead of the fused one (for testing);
+                            BGK_FLAG_ADJOINT reserves the workspace of
+                            bgk_adjoint_step (needs BGK_FP64 and move = 0)              */
   double vmax;           /* velocity grid spans [-vmax, vmax] per axis                   */
   double h;              /* support radius of the Gaussian weight (absolute)             */
   double alpha;          /* weight exp(-alpha r^2/h^2), r <= h (Sec. 3.4.1, eq. weight) */
@@ -197,6 +199,50 @@ int bgk_moments(bgk_ctx* ctx, const void* f, double* rho, double* U, double* T);
  * of every particle on the grid, into f_out. */
 int bgk_maxwellian(bgk_ctx* ctx, const double* rho, const double* U, const double* T,
                    void* f_out);
+
+/* Objective of the lid-driven cavity at a state (f, rho, U): the lid-normal
+ * heat flux summed over the lid particles plus a weighted kinetic energy,
+ *   J = dx^(d-1) sum_{b on the lid} q_n(b) + (ke_weight/N) sum_i rho_i |U_i|^2/2,
+ *   q_n = (omega/2) sum_v (v_n - U_n) |v-U|^2 f   (Chu: |v-U|^2 g1 + g2),
+ * n the lid's axis (y in 2D, z in 3D) and U the particle's own mean velocity
+ * (q is the kinetic heat flux, the centred third moment of f; the paper
+ * defines no objective, this is the functional that the reverse mode below
+ * is exercised on).
+ * J: device double [1], overwritten.  dJ_df (like f), dJ_drho [N] and
+ * dJ_dU [d][N] receive the partial derivatives at fixed (f, rho, U); each
+ * may be NULL.  BGK_FP64 only (else BGK_ENOTSUP).  J is summed in a fixed
+ * order, so repeated calls give identical bits. */
+int bgk_objective(bgk_ctx* ctx, const void* f, const double* rho, const double* U,
+                  double ke_weight, double* J, void* dJ_df, double* dJ_drho, double* dJ_dU);
+
+/* Reverse mode of one frozen-cloud step (S4-S7 with the operators of the
+ * fixed cloud; Sec. 3.1 and Sec. 5).  The step maps the state (f^n, U^n) and
+ * the lid speed to (f^{n+1}, U^{n+1}, rho^{n+1}, T^{n+1}).  Given the
+ * adjoints lam_* of those outputs, this returns
+ *   lam_f = (d f^{n+1}/d f^n)^T lam_f1 + ... (every output's term),
+ *   lam_U = the same for U^n (which enters only the upwind weights c_ij),
+ *   dJ_dlid += the lid-speed term (through the emitted wall Maxwellian and
+ *              its zero-mass-flux density).
+ * f_n, U_n: the state the forward step started from (the step's intermediate
+ * values are recomputed into the workspace).  x: positions, used to build
+ * the geometry when none is current.  lam_U1, lam_rho1, lam_T1 may be NULL
+ * (zero).  lam_f may be the same buffer as lam_f1 and lam_U the same as
+ * lam_U1 (in place); no other overlap is allowed (BGK_EINVAL).  dJ_dlid:
+ * device double [1], accumulated (+=); may be NULL.  |.| terms take the
+ * derivative of their + branch at 0.  The transposed stencils make every
+ * sum a gather: results are deterministic.  Needs a context created with
+ * BGK_FLAG_ADJOINT (BGK_FP64, move = 0), else BGK_ENOTSUP. */
+int bgk_adjoint_step(bgk_ctx* ctx, const void* f_n, const double* U_n, const double* x,
+                     const void* lam_f1, const double* lam_U1, const double* lam_rho1,
+                     const double* lam_T1, void* lam_f, double* lam_U, double* dJ_dlid);
+
+/* Reverse mode of bgk_moments (Sec. 2 eqs. moments, internal_energy; Chu
+ * eq. macroeq): lam_f += (d(rho, U, T)/d f)^T (lam_rho, lam_U, lam_T) at the
+ * moments (rho, U, T) of f.  lam_rho, lam_U, lam_T may be NULL (zero).
+ * BGK_FP64 only (else BGK_ENOTSUP). */
+int bgk_moments_adjoint(bgk_ctx* ctx, const double* rho, const double* U, const double* T,
+                        const double* lam_rho, const double* lam_U, const double* lam_T,
+                        void* lam_f);
 
 /* Synchronise the stream; return and clear the first data error recorded on
  * the device (or BGK_EDEVICE). */

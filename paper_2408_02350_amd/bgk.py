@@ -23,6 +23,7 @@ BGK_OK, BGK_EINVAL, BGK_ENOMEM, BGK_ENBR_OVERFLOW, BGK_ESINGULAR, BGK_ENONPHYS, 
     BGK_EDEVICE, BGK_ENOTSUP = range(8)
 BGK_FP64, BGK_FP32, BGK_BF16 = 0, 1, 2
 BGK_FLAG_GENERIC = 1
+BGK_FLAG_ADJOINT = 2
 PRECISIONS = {"fp64": BGK_FP64, "fp32": BGK_FP32, "bf16": BGK_BF16}
 STATUS = {0: "BGK_OK", 1: "BGK_EINVAL", 2: "BGK_ENOMEM", 3: "BGK_ENBR_OVERFLOW",
           4: "BGK_ESINGULAR", 5: "BGK_ENONPHYS", 6: "BGK_EDEVICE", 7: "BGK_ENOTSUP"}
@@ -32,7 +33,8 @@ EXPORTS = ("bgk_workspace_bytes", "bgk_init", "bgk_destroy", "bgk_set_lid_veloci
            "bgk_build_neighbors", "bgk_wls_operators", "bgk_wall_stencil", "bgk_geometry",
            "bgk_transport", "bgk_collide", "bgk_wall_bc", "bgk_move", "bgk_step",
            "bgk_moments", "bgk_maxwellian", "bgk_check", "bgk_diagnostics", "bgk_last_error",
-           "bgk_timing_enable", "bgk_timing_read")
+           "bgk_timing_enable", "bgk_timing_read", "bgk_objective", "bgk_adjoint_step",
+           "bgk_moments_adjoint")
 
 
 class BgkError(RuntimeError):
@@ -88,6 +90,9 @@ def load_library(path: str = LIB_PATH):
         "bgk_diagnostics": [vp, ctypes.POINTER(ctypes.c_int64)],
         "bgk_timing_enable": [vp, ctypes.c_int],
         "bgk_timing_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+        "bgk_objective": [vp, vp, dp, dp, ctypes.c_double, dp, vp, dp, dp],
+        "bgk_adjoint_step": [vp, vp, dp, dp, vp, dp, dp, dp, vp, dp, dp],
+        "bgk_moments_adjoint": [vp, dp, dp, dp, dp, dp, dp, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -322,6 +327,69 @@ def bgk_maxwellian(ctx: Context, rho, U, T, f_out=None):
     _check(ctx, load_library().bgk_maxwellian(ctx.handle, _ptr(rho), _ptr(U), _ptr(T),
                                               _ptr(f_out)), "bgk_maxwellian")
     return f_out
+
+
+def bgk_objective(ctx: Context, f, rho, U, ke_weight=1.0, want_grad=True):
+    """J (0-d float64 tensor) and, if want_grad, (dJ_df, dJ_drho, dJ_dU)."""
+    _f(ctx, f, "f")
+    _sca(ctx, rho, "rho")
+    _vec(ctx, U, "U")
+    J = _empty(ctx, (), torch.float64)
+    g = None
+    if want_grad:
+        g = (_empty(ctx, (ctx.nc, ctx.N, ctx.NV), torch.float64),
+             _empty(ctx, (ctx.N,), torch.float64), _empty(ctx, (ctx.d, ctx.N), torch.float64))
+    gp = g if g is not None else (None, None, None)
+    _check(ctx, load_library().bgk_objective(ctx.handle, _ptr(f), _ptr(rho), _ptr(U),
+                                             float(ke_weight), _ptr(J), _ptr(gp[0]), _ptr(gp[1]),
+                                             _ptr(gp[2])), "bgk_objective")
+    return (J, g) if want_grad else J
+
+
+def bgk_adjoint_step(ctx: Context, f_n, U_n, x, lam_f1, lam_U1=None, lam_rho1=None,
+                     lam_T1=None, lam_f=None, lam_U=None, dJ_dlid=None):
+    """Reverse of one frozen-cloud step; returns (lam_f, lam_U).  dJ_dlid, if
+    given (float64 tensor of one element), is accumulated in place."""
+    _f(ctx, f_n, "f_n")
+    _vec(ctx, U_n, "U_n")
+    _vec(ctx, x, "x")
+    _f(ctx, lam_f1, "lam_f1")
+    if lam_U1 is not None:
+        _vec(ctx, lam_U1, "lam_U1")
+    if lam_rho1 is not None:
+        _sca(ctx, lam_rho1, "lam_rho1")
+    if lam_T1 is not None:
+        _sca(ctx, lam_T1, "lam_T1")
+    lam_f = torch.empty_like(lam_f1) if lam_f is None else lam_f
+    lam_U = _empty(ctx, (ctx.d, ctx.N), torch.float64) if lam_U is None else lam_U
+    _f(ctx, lam_f, "lam_f")
+    _vec(ctx, lam_U, "lam_U")
+    if dJ_dlid is not None:
+        _expect(dJ_dlid, torch.float64, tuple(dJ_dlid.shape), "dJ_dlid", ctx.device)
+        if dJ_dlid.numel() != 1:
+            raise ValueError("dJ_dlid must hold one element")
+    _check(ctx, load_library().bgk_adjoint_step(
+        ctx.handle, _ptr(f_n), _ptr(U_n), _ptr(x), _ptr(lam_f1), _ptr(lam_U1), _ptr(lam_rho1),
+        _ptr(lam_T1), _ptr(lam_f), _ptr(lam_U), _ptr(dJ_dlid)), "bgk_adjoint_step")
+    return lam_f, lam_U
+
+
+def bgk_moments_adjoint(ctx: Context, rho, U, T, lam_f, lam_rho=None, lam_U=None, lam_T=None):
+    """lam_f += (d(rho, U, T)/df)^T (lam_rho, lam_U, lam_T); returns lam_f."""
+    _sca(ctx, rho, "rho")
+    _vec(ctx, U, "U")
+    _sca(ctx, T, "T")
+    _f(ctx, lam_f, "lam_f")
+    if lam_rho is not None:
+        _sca(ctx, lam_rho, "lam_rho")
+    if lam_U is not None:
+        _vec(ctx, lam_U, "lam_U")
+    if lam_T is not None:
+        _sca(ctx, lam_T, "lam_T")
+    _check(ctx, load_library().bgk_moments_adjoint(ctx.handle, _ptr(rho), _ptr(U), _ptr(T),
+                                                   _ptr(lam_rho), _ptr(lam_U), _ptr(lam_T),
+                                                   _ptr(lam_f)), "bgk_moments_adjoint")
+    return lam_f
 
 
 def bgk_check(ctx: Context):

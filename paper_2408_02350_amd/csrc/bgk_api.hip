@@ -63,7 +63,8 @@ bool config_ok(const bgk_config& g) {
   return (g.dim == 2 || g.dim == 3) && g.n_particles > 0 && g.nv >= 2 && g.nv % 2 == 0 &&
          (g.wls_degree == 1 || g.wls_degree == 2) && g.max_neighbors >= g.dim + 2 &&
          g.max_neighbors <= 255 && (g.move == 0 || g.move == 1) && g.precision >= BGK_FP64 &&
-         g.precision <= BGK_BF16 && (g.flags & ~BGK_FLAG_GENERIC) == 0 && g.vmax > 0 && g.h > 0 && g.alpha > 0 &&
+         g.precision <= BGK_BF16 && (g.flags & ~(BGK_FLAG_GENERIC | BGK_FLAG_ADJOINT)) == 0 &&
+         (!(g.flags & BGK_FLAG_ADJOINT) || (g.precision == BGK_FP64 && g.move == 0)) && g.vmax > 0 && g.h > 0 && g.alpha > 0 &&
          g.kn > 0 && g.dt > 0 && g.wall_T > 0 && g.dx > 0 && std::isfinite(g.lid_velocity) &&
          ipow(g.nv, g.dim) <= INT32_MAX / 4 &&
          static_cast<int64_t>(g.n_particles) * g.max_neighbors * g.dim * g.dim < INT32_MAX;
@@ -71,7 +72,7 @@ bool config_ok(const bgk_config& g) {
 
 }  // namespace
 
-size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d) {
+size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj) {
   const int64_t N = cfg.n_particles, cap = cfg.max_neighbors, D = cfg.dim, DD = D * D;
   const int64_t ncell = ipow(cells_per_axis(cfg), cfg.dim);
   const int64_t npatch = (N + kPatch - 1) / kPatch, ucap = static_cast<int64_t>(kPatch) * cap;
@@ -101,7 +102,28 @@ size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d) {
   t.ucount = reinterpret_cast<int32_t*>(take(npatch * 4));
   t.uj = reinterpret_cast<int32_t*>(take(npatch * ucap * 4));
   t.ue = reinterpret_cast<uint32_t*>(take(npatch * ucap * 4));
+  t.jpart = reinterpret_cast<double*>(take(N * 8));
   if (d) *d = t;
+  if (cfg.flags & BGK_FLAG_ADJOINT) {
+    // The reverse step reads the wall rows of f^{n+1} before it writes the
+    // interior rows of lam_ft, and never reads a wall row of lam_ft: the two
+    // share storage.
+    const int64_t NC = D == 2 ? 2 : 1, F = NC * N * ipow(cfg.nv, cfg.dim);
+    Adj a{};
+    a.tidx = reinterpret_cast<int32_t*>(take(N * cap * 4));
+    a.wtstart = reinterpret_cast<int32_t*>(take((N + 1) * 4));
+    a.wtcursor = reinterpret_cast<int32_t*>(take(N * 4));
+    a.wt = reinterpret_cast<int32_t*>(take(N * cap * 4));
+    a.ft = reinterpret_cast<double*>(take(F * 8));
+    a.lam_ft = reinterpret_cast<double*>(take(F * 8));
+    a.f1 = a.lam_ft;
+    a.rho1 = reinterpret_cast<double*>(take(N * 8));
+    a.U1 = reinterpret_cast<double*>(take(N * D * 8));
+    a.T1 = reinterpret_cast<double*>(take(N * 8));
+    a.larr = reinterpret_cast<double*>(take(F * 8));
+    a.lidpart = reinterpret_cast<double*>(take(N * 8));
+    if (adj) *adj = a;
+  }
   return off;
 }
 
@@ -128,6 +150,7 @@ static int build_geometry(Ctx& c, const double* x) {
     e = launch_wls(c, x, c.d.ncnt, c.d.nidx, nullptr, c.d.ops64, c.d.ops32, nullptr);
   if (e == hipSuccess) e = launch_wall_stencil(c, x);
   if (e == hipSuccess) e = launch_patches(c);
+  c.adj_valid = false;
   if (e != hipSuccess) return hip_fail(&c, e, "geometry launch");
   c.geom_valid = true;
   return BGK_OK;
@@ -141,7 +164,7 @@ extern "C" {
 
 int bgk_workspace_bytes(const bgk_config* cfg, size_t* bytes) {
   if (!cfg || !bytes || !bgk::config_ok(*cfg)) return BGK_EINVAL;
-  *bytes = bgk::workspace_layout(*cfg, nullptr, nullptr);
+  *bytes = bgk::workspace_layout(*cfg, nullptr, nullptr, nullptr);
   return BGK_OK;
 }
 
@@ -150,7 +173,7 @@ int bgk_init(const bgk_config* cfg, const int32_t* wall_id, void* workspace, siz
   if (!out) return BGK_EINVAL;
   *out = nullptr;
   if (!cfg || !wall_id || !workspace || !bgk::config_ok(*cfg)) return BGK_EINVAL;
-  const size_t need = bgk::workspace_layout(*cfg, nullptr, nullptr);
+  const size_t need = bgk::workspace_layout(*cfg, nullptr, nullptr, nullptr);
   if (ws_bytes < need) return BGK_ENOMEM;
   bgk_ctx* h = new (std::nothrow) bgk_ctx;
   if (!h) return BGK_ENOMEM;
@@ -166,7 +189,7 @@ int bgk_init(const bgk_config* cfg, const int32_t* wall_id, void* workspace, siz
   c.nca = bgk::cells_per_axis(*cfg);
   c.ncell = static_cast<int>(bgk::ipow(c.nca, c.D));
   c.lid = cfg->lid_velocity;
-  bgk::workspace_layout(*cfg, static_cast<char*>(workspace), &c.d);
+  bgk::workspace_layout(*cfg, static_cast<char*>(workspace), &c.d, &c.adj);
   hipError_t e = hipGetDevice(&c.device);
   // wall ids: read once to count and list the wall particles
   std::vector<int32_t> wid(c.N);
@@ -370,6 +393,81 @@ int bgk_maxwellian(bgk_ctx* ctx, const double* rho, const double* U, const doubl
   if (!ctx || !rho || !U || !T || !f_out) return BGK_EINVAL;
   return bgk::hip_fail(&ctx->c, bgk::launch_maxwellian(ctx->c, rho, U, T, f_out),
                        "bgk_maxwellian");
+}
+
+int bgk_objective(bgk_ctx* ctx, const void* f, const double* rho, const double* U,
+                  double ke_weight, double* J, void* dJ_df, double* dJ_drho, double* dJ_dU) {
+  if (!ctx || !f || !rho || !U || !J || !std::isfinite(ke_weight)) return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  if (c.cfg.precision != BGK_FP64) return bgk::fail(&c, BGK_ENOTSUP, "bgk_objective needs FP64");
+  return bgk::hip_fail(&c,
+                       bgk::launch_objective(c, static_cast<const double*>(f), rho, U, ke_weight,
+                                             J, static_cast<double*>(dJ_df), dJ_drho, dJ_dU),
+                       "bgk_objective");
+}
+
+namespace {
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b) return false;
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+}  // namespace
+
+int bgk_adjoint_step(bgk_ctx* ctx, const void* f_n, const double* U_n, const double* x,
+                     const void* lam_f1, const double* lam_U1, const double* lam_rho1,
+                     const double* lam_T1, void* lam_f, double* lam_U, double* dJ_dlid) {
+  if (!ctx || !f_n || !U_n || !x || !lam_f1 || !lam_f || !lam_U) return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  if (!(c.cfg.flags & BGK_FLAG_ADJOINT))
+    return bgk::fail(&c, BGK_ENOTSUP, "bgk_adjoint_step needs a context with BGK_FLAG_ADJOINT");
+  const size_t F = sizeof(double) * c.NC * static_cast<size_t>(c.N) * c.NV;
+  const size_t DN = sizeof(double) * c.D * static_cast<size_t>(c.N), N8 = sizeof(double) * c.N;
+  // outputs against every input; lam_f == lam_f1 and lam_U == lam_U1 are allowed
+  const void* in[] = {f_n, U_n, x, lam_f1, lam_U1, lam_rho1, lam_T1, dJ_dlid};
+  const size_t nin[] = {F, DN, DN, F, DN, N8, N8, sizeof(double)};
+  for (int k = 0; k < 8; ++k) {
+    if (overlap(lam_f, F, in[k], nin[k]) && !(k == 3 && in[k] == lam_f))
+      return bgk::fail(&c, BGK_EINVAL, "bgk_adjoint_step: lam_f overlaps an input");
+    if (overlap(lam_U, DN, in[k], nin[k]) && !(k == 4 && in[k] == lam_U))
+      return bgk::fail(&c, BGK_EINVAL, "bgk_adjoint_step: lam_U overlaps an input");
+  }
+  if (overlap(lam_f, F, lam_U, DN))
+    return bgk::fail(&c, BGK_EINVAL, "bgk_adjoint_step: lam_f overlaps lam_U");
+  if (!c.geom_valid) {
+    const int rc = bgk::build_geometry(c, x);
+    if (rc) return rc;
+  }
+  hipError_t e = hipSuccess;
+  if (!c.adj_valid) {
+    e = bgk::launch_adjoint_transposes(c);
+    if (e != hipSuccess) return bgk::hip_fail(&c, e, "bgk_adjoint_step transposes");
+    c.adj_valid = true;
+  }
+  // recompute S4-S7 from (f_n, U_n), keeping f-tilde and the new moments
+  const bgk::Adj& a = c.adj;
+  e = bgk::launch_transport(c, f_n, a.ft, U_n);
+  if (e == hipSuccess) e = bgk::launch_collide(c, a.ft, a.f1, a.rho1, a.U1, a.T1);
+  if (e == hipSuccess) e = bgk::launch_wall_bc(c, a.f1, a.rho1, a.U1, a.T1);
+  if (e == hipSuccess)
+    e = bgk::launch_adjoint_step(c, static_cast<const double*>(f_n), U_n,
+                                 static_cast<const double*>(lam_f1), lam_U1, lam_rho1, lam_T1,
+                                 static_cast<double*>(lam_f), lam_U, dJ_dlid);
+  return bgk::hip_fail(&c, e, "bgk_adjoint_step");
+}
+
+int bgk_moments_adjoint(bgk_ctx* ctx, const double* rho, const double* U, const double* T,
+                        const double* lam_rho, const double* lam_U, const double* lam_T,
+                        void* lam_f) {
+  if (!ctx || !rho || !U || !T || !lam_f) return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  if (c.cfg.precision != BGK_FP64)
+    return bgk::fail(&c, BGK_ENOTSUP, "bgk_moments_adjoint needs FP64");
+  return bgk::hip_fail(&c,
+                       bgk::launch_moments_adjoint(c, rho, U, T, lam_rho, lam_U, lam_T,
+                                                   static_cast<double*>(lam_f)),
+                       "bgk_moments_adjoint");
 }
 
 int bgk_check(bgk_ctx* ctx) {

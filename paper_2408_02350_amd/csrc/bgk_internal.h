@@ -45,6 +45,23 @@ struct Dev {
   int32_t* ucount;       // [npatch]
   int32_t* uj;           // [npatch][ucap]
   uint32_t* ue;          // [npatch][ucap] packed 8-bit slot of each patch particle
+  double* jpart;         // [N]   per-particle terms of the objective
+};
+
+// Workspace of the reverse step (BGK_FLAG_ADJOINT; FP64, frozen cloud).
+struct Adj {
+  int32_t* tidx;      // [N][cap]  slot of j in the row of nidx[j][e] (-1: not transported)
+  int32_t* wtstart;   // [N+1]     start of particle j's wall-stencil uses
+  int32_t* wtcursor;  // [N]
+  int32_t* wt;        // [Nw*cap]  uses of j as (wall list index << 8 | slot), sorted
+  double* ft;         // [n_c][N][N_v] recomputed f-tilde
+  double* f1;         // [n_c][N][N_v] recomputed f^{n+1}; storage shared with lam_ft
+  double* lam_ft;     // [n_c][N][N_v] adjoint of f-tilde (interior rows)
+  double* rho1;       // [N]
+  double* U1;         // [d][N]
+  double* T1;         // [N]
+  double* larr;       // [Nw][n_c][N_v] adjoint reaching the interpolated wall values
+  double* lidpart;    // [max(Nw,1)]
 };
 
 struct Ctx {
@@ -56,6 +73,8 @@ struct Ctx {
   int nca = 0, ncell = 0;
   double lid = 0.0;
   Dev d{};
+  Adj adj{};
+  bool adj_valid = false;   // transposed stencils match the current geometry
   bool geom_valid = false;  // geometry of the current (frozen) cloud is built
   int64_t steps = 0;
   std::string last_error;
@@ -65,13 +84,14 @@ struct Ctx {
 };
 
 // Workspace layout: returns total bytes; fills d when base != nullptr.
-size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d);
+size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj);
 
 // ---- launchers (enqueue on c.stream; return hipError_t of the launch) ----
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
 hipError_t launch_fill_f64(hipStream_t s, double* p, int64_t n, double v);
 hipError_t launch_copy_i32(hipStream_t s, const int32_t* src, int32_t* dst, int64_t n);
 hipError_t launch_max_i32(hipStream_t s, const int32_t* a, int n, int32_t* out);
+hipError_t launch_scan(hipStream_t s, int32_t* a, int n);  // exclusive, a[n] = total
 hipError_t launch_scatter_wall_rows(const Ctx& c, int32_t* cnt_out, int32_t* idx_out,
                                     double* c0_out, double* hb_out);
 
@@ -96,6 +116,18 @@ hipError_t launch_move(const Ctx& c, double* x, const double* U);
 hipError_t launch_moments(const Ctx& c, const void* f, double* rho, double* U, double* T);
 hipError_t launch_maxwellian(const Ctx& c, const double* rho, const double* U, const double* T,
                              void* f);
+
+// Reverse mode (FP64, frozen cloud).
+hipError_t launch_adjoint_transposes(const Ctx& c);
+hipError_t launch_adjoint_step(const Ctx& c, const double* f_n, const double* U_n,
+                               const double* lam_f1, const double* lam_U1, const double* lam_rho1,
+                               const double* lam_T1, double* lam_f, double* lam_U,
+                               double* dJ_dlid);
+hipError_t launch_objective(const Ctx& c, const double* f, const double* rho, const double* U,
+                            double ke, double* J, double* dJ_df, double* dJ_drho, double* dJ_dU);
+hipError_t launch_moments_adjoint(const Ctx& c, const double* rho, const double* U,
+                                  const double* T, const double* lr, const double* lU,
+                                  const double* lT, double* lam_f);
 
 }  // namespace bgk
 

@@ -1,0 +1,563 @@
+// Hand-written adjoint of one frozen-cloud step (S4-S7) and of the
+// objective.  The step map is (f^n, U^n) -> (f^{n+1}, U^{n+1}, rho^{n+1},
+// T^{n+1}); the operators are constants (the cloud does not move).  Given the
+// adjoints of the outputs, the reverse pass runs:
+//
+//   walls      f_b = interp(f'_int) on arriving velocities, rho_w from the
+//              zero-mass-flux balance, emitted rho_w M[1, U_w(lid), T_w],
+//              then (rho, U, T)_b = moments(f_b)
+//   relaxation f' = a(tau) ft + b(tau) M(rho', U', T'), (rho', U', T') =
+//              moments(ft), tau = tau(rho', T')
+//   transport  ft_i = f_i - dt sum_j c_ij(v; U_i) (f_j - f_i)
+//
+// Every scatter of the forward map becomes a gather over a transposed
+// index (neighbour rows are symmetric: j in N_i <=> i in N_j; wall stencil
+// rows are transposed by a sorted counting pass), so there are no atomics
+// on the adjoint fields and the result is deterministic.  Reductions are
+// FP64 in a fixed order.  Derivatives of |.| at 0 follow the + branch
+// (c_ij = 2 sum_k min(0, p_k): d/dp = 1 only for p < 0).
+#include "device_common.h"
+
+namespace bgk {
+
+// ------------------------------------------------------------ transposes
+// tidx[j][e'] = position of j in the row of i = nidx[j][e'] when i is an
+// interior particle other than j, else -1.
+__global__ void k_transpose_nbr(int N, int cap, const int32_t* __restrict__ wall_id,
+                                const int32_t* __restrict__ cnt, const int32_t* __restrict__ idx,
+                                int32_t* __restrict__ tidx) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const int m = min(cnt[j], cap);
+  for (int e = 0; e < m; ++e) {
+    const int i = idx[static_cast<int64_t>(j) * cap + e];
+    int pos = -1;
+    if (i != j && wall_id[i] == 0) {
+      const int32_t* row = idx + static_cast<int64_t>(i) * cap;
+      int lo = 0, hi = min(cnt[i], cap);
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (row[mid] < j) lo = mid + 1; else hi = mid;
+      }
+      if (lo < min(cnt[i], cap) && row[lo] == j) pos = lo;
+    }
+    tidx[static_cast<int64_t>(j) * cap + e] = pos;
+  }
+}
+
+// Wall stencil transpose: for every particle j, the (wall list index k,
+// slot e) with widx[k][e] = j, sorted by k.  Count, scan, scatter, sort.
+__global__ void k_wt_count(int Nw, int cap, const int32_t* __restrict__ wcnt,
+                           const int32_t* __restrict__ widx, int32_t* __restrict__ count) {
+  const int k = blockIdx.x;
+  if (k >= Nw) return;
+  for (int e = threadIdx.x; e < wcnt[k]; e += blockDim.x)
+    atomicAdd(&count[widx[static_cast<int64_t>(k) * cap + e]], 1);
+}
+__global__ void k_wt_scatter(int Nw, int cap, const int32_t* __restrict__ wcnt,
+                             const int32_t* __restrict__ widx, int32_t* __restrict__ cursor,
+                             int32_t* __restrict__ wt) {
+  const int k = blockIdx.x;
+  if (k >= Nw) return;
+  for (int e = threadIdx.x; e < wcnt[k]; e += blockDim.x) {
+    const int pos = atomicAdd(&cursor[widx[static_cast<int64_t>(k) * cap + e]], 1);
+    wt[pos] = k * 256 + e;  // k-major key, e < 256
+  }
+}
+__global__ void k_wt_sort(int N, const int32_t* __restrict__ start, int32_t* __restrict__ wt) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const int b = start[j], e = start[j + 1];
+  for (int p = b + 1; p < e; ++p) {
+    const int v = wt[p];
+    int s = p;
+    while (s > b && wt[s - 1] > v) {
+      wt[s] = wt[s - 1];
+      --s;
+    }
+    wt[s] = v;
+  }
+}
+
+// ------------------------------------------------------------ moments adjoint
+// Adjoint of (rho, U, T) = moments(f) at one velocity: the change of f_c(v)
+// that the output adjoints (lr, lU, lT) ask for (S5 formulas; the centred
+// second moment is stationary in U, so T has no U path).
+template <int D, int NC>
+__device__ __forceinline__ double mom_adj(int c, const double* v, double omega, double s0,
+                                          const double* U, double T, double lr, const double* lU,
+                                          double lT) {
+  if (c == 1) return lT / (3.0 * s0);
+  double w2 = 0.0, g = lr * omega;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const double wa = v[a] - U[a];
+    w2 = w2 + wa * wa;
+    g = g + lU[a] * wa / s0;
+  }
+  return g + lT * (w2 / (3.0 * s0) - T / s0);
+}
+
+struct AdjArgs {
+  int N, NV, nv, cap, Nw, Ni, D;
+  double vmax, omega, kn, dt, lid, wall_T;
+  const int32_t* wall_id;
+  const int32_t* wall_list;
+  const int32_t* plist;
+  const int32_t* ncnt;
+  const int32_t* nidx;
+  const int32_t* tidx;
+  const double* ops;
+  const int32_t* wcnt;
+  const int32_t* widx;
+  const double* wc0;
+  const int32_t* wtstart;
+  const int32_t* wt;
+  const double* f_n;       // state n
+  const double* U_n;
+  const double* ft;        // recomputed f-tilde (interior rows)
+  const double* f1;        // recomputed f^{n+1} (all rows)
+  const double* rho1;      // recomputed outputs
+  const double* U1;
+  const double* T1;
+  const double* lam_f1;    // adjoint of f^{n+1}
+  const double* lam_U1;    // adjoint of U^{n+1} (nullable)
+  const double* lam_rho1;  // (nullable)
+  const double* lam_T1;    // (nullable)
+  double* larr;            // [Nw][NC][NV] adjoint reaching the interpolated (arriving) half
+  double* lam_ft;          // [NC][N][NV]
+  double* lam_f;           // out: adjoint of f^n
+  double* lam_U;           // out: adjoint of U^n
+  double* lidpart;         // [Nw] dJ/dlid contributions
+};
+
+// ------------------------------------------------------------ S7 adjoint
+template <int D, int NC>
+__global__ __launch_bounds__(kThreads) void k_adj_wall(const AdjArgs a) {
+  __shared__ double sh[4 * 4];
+  const int k = blockIdx.x;
+  const int b = a.wall_list[k];
+  const int w = a.wall_id[b];
+  const int axis = (w - 1) / 2;
+  const double sgn = ((w - 1) % 2 == 0) ? 1.0 : -1.0;
+  const bool is_lid = (w == 2 * D);
+  double Uw[3] = {is_lid ? a.lid : 0.0, 0.0, 0.0};
+  const size_t NVs = a.NV, cs = static_cast<size_t>(a.N) * NVs;
+  const double* fb = a.f1 + static_cast<size_t>(b) * NVs;
+  const double* lb = a.lam_f1 + static_cast<size_t>(b) * NVs;
+  const double rho = a.rho1[b], T = a.T1[b];
+  double U[3] = {0.0, 0.0, 0.0}, lU[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    U[q] = a.U1[static_cast<size_t>(q) * a.N + b];
+    if (a.lam_U1) lU[q] = a.lam_U1[static_cast<size_t>(q) * a.N + b];
+  }
+  const double lr = a.lam_rho1 ? a.lam_rho1[b] : 0.0;
+  const double lT = a.lam_T1 ? a.lam_T1[b] : 0.0;
+  const double s0 = rho / a.omega;
+  // pass 1: fluxes and the adjoint reaching rho_w and the lid
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // F_in, F_out, g_rhow, dF_out/dlid
+  double glid = 0.0;
+  for (int q = threadIdx.x; q < a.NV; q += kThreads) {
+    double v[3];
+    velocity_of<D>(q, a.nv, a.vmax, v);
+    const double vn = sgn * v[axis];
+    if (vn <= 0.0) {
+      acc[0] = acc[0] + (-vn) * fb[q];
+    } else {
+      const double M0 = maxwell<D>(0, 1.0, Uw, a.wall_T, v);
+      acc[1] = acc[1] + vn * M0;
+      const double dM = (v[0] - Uw[0]) / a.wall_T;  // dM/dlid / M (lid walls)
+      if (is_lid) acc[3] = acc[3] + vn * M0 * dM;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const double l = lb[c * cs + q] + mom_adj<D, NC>(c, v, a.omega, s0, U, T, lr, lU, lT);
+        const double Mc = (c == 1) ? a.wall_T * M0 : M0;
+        acc[2] = acc[2] + l * Mc;
+        if (is_lid) glid = glid + l * Mc * dM;
+      }
+    }
+  }
+  block_sum<4>(acc, sh);
+  double gl[1] = {glid};
+  block_sum<1>(gl, sh);
+  const double Fin = acc[0], Fout = acc[1], grw = acc[2];
+  const double rho_w = Fin / Fout;
+  // pass 2: adjoint on the arriving (interpolated) half
+  double* lo = a.larr + static_cast<size_t>(k) * NC * NVs;
+  for (int q = threadIdx.x; q < a.NV; q += kThreads) {
+    double v[3];
+    velocity_of<D>(q, a.nv, a.vmax, v);
+    const double vn = sgn * v[axis];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double l = 0.0;
+      if (vn <= 0.0) {
+        l = lb[c * cs + q] + mom_adj<D, NC>(c, v, a.omega, s0, U, T, lr, lU, lT);
+        if (c == 0) l = l + grw * (-vn) / Fout;
+      }
+      lo[c * NVs + q] = l;
+    }
+  }
+  if (threadIdx.x == 0)
+    a.lidpart[k] = is_lid ? (rho_w * gl[0] + grw * (-rho_w / Fout) * acc[3]) : 0.0;
+}
+
+// ------------------------------------------------------------ S5-S6 adjoint
+template <int D, int NC>
+__global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs a) {
+  __shared__ double sh[4 * (D + 4)];
+  const int i = a.plist[blockIdx.x];
+  const size_t NVs = a.NV, cs = static_cast<size_t>(a.N) * NVs;
+  const double rho = a.rho1[i], T = a.T1[i];
+  double U[3] = {0.0, 0.0, 0.0}, lU[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    U[q] = a.U1[static_cast<size_t>(q) * a.N + i];
+    if (a.lam_U1) lU[q] = a.lam_U1[static_cast<size_t>(q) * a.N + i];
+  }
+  const double lr = a.lam_rho1 ? a.lam_rho1[i] : 0.0;
+  const double lT = a.lam_T1 ? a.lam_T1[i] : 0.0;
+  const double s0 = rho / a.omega;
+  const double tau = a.kn * sqrt(2.0 / kPi) / (rho * sqrt(T));
+  const double den = tau + a.dt;
+  const double ca = tau / den, cb = a.dt / den, dtau = a.dt / (den * den);  // d f'/d tau = (ft-M) dtau
+  const double kap0 = (D == 3) ? 1.5 : 1.0;
+  const int ws = a.wtstart[i], we = a.wtstart[i + 1];
+  // adjoint of f' = lam_f1 + sum over the wall rows that interpolate from i
+  auto lam_fp = [&](int c, int q) {
+    double l = a.lam_f1[c * cs + static_cast<size_t>(i) * NVs + q];
+    for (int p = ws; p < we; ++p) {
+      const int kk = a.wt[p] >> 8, e = a.wt[p] & 0xFF;
+      l = l + a.wc0[static_cast<size_t>(kk) * a.cap + e] *
+                  a.larr[(static_cast<size_t>(kk) * NC + c) * NVs + q];
+    }
+    return l;
+  };
+  double s[D + 3];  // A1 = sum l M, A2 = sum l (ft - M), AU[d], AT
+#pragma unroll
+  for (int k = 0; k < D + 3; ++k) s[k] = 0.0;
+  for (int q = threadIdx.x; q < a.NV; q += kThreads) {
+    double v[3];
+    velocity_of<D>(q, a.nv, a.vmax, v);
+    double w2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) w2 = w2 + (v[k] - U[k]) * (v[k] - U[k]);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double M = maxwell<D>(c, rho, U, T, v);
+      const double l = lam_fp(c, q);
+      const double x = a.ft[c * cs + static_cast<size_t>(i) * NVs + q];
+      s[0] = s[0] + l * M;
+      s[1] = s[1] + l * (x - M);
+#pragma unroll
+      for (int k = 0; k < D; ++k) s[2 + k] = s[2 + k] + l * M * (v[k] - U[k]);
+      const double kap = (c == 1) ? 0.0 : kap0;
+      s[2 + D] = s[2 + D] + l * M * (-kap / T + w2 / (2.0 * T * T));
+    }
+  }
+  block_sum<D + 3>(s, sh);
+  const double g_rho = lr + cb * s[0] / rho + s[1] * dtau * (-tau / rho);
+  double gU[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < D; ++k) gU[k] = lU[k] + cb * s[2 + k] / T;
+  const double g_T = lT + cb * s[2 + D] + s[1] * dtau * (-tau / (2.0 * T));
+  for (int q = threadIdx.x; q < a.NV; q += kThreads) {
+    double v[3];
+    velocity_of<D>(q, a.nv, a.vmax, v);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double l = ca * lam_fp(c, q) + mom_adj<D, NC>(c, v, a.omega, s0, U, T, g_rho, gU, g_T);
+      a.lam_ft[c * cs + static_cast<size_t>(i) * NVs + q] = l;
+    }
+  }
+}
+
+// ------------------------------------------------------------ S4 adjoint
+// Block per particle j (interior or wall), all velocities:
+//   lam_f_j = [j interior] lam_ft_j (1 + dt sum_k c_jk)
+//             - dt sum_{i in N_j interior, i != j} c_ij lam_ft_i
+//   lam_U_j = -dt sum_v lam_ft_j . sum_k dc_jk/dU (f_k - f_j)   (interior)
+template <int D>
+__device__ __forceinline__ double cij(const double* o, const double* v, const double* U) {
+  double c = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    double p = 0.0;
+#pragma unroll
+    for (int m = 0; m < D; ++m) p = p + o[k * D + m] * (v[m] - U[m]);
+    c = c + fmin(p, 0.0);
+  }
+  return 2.0 * c;
+}
+
+template <int D, int NC>
+__global__ __launch_bounds__(kThreads) void k_adj_transport(const AdjArgs a) {
+  constexpr int DD = D * D;
+  __shared__ double sh[4 * 3];
+  const int j = blockIdx.x;
+  const bool inner = a.wall_id[j] == 0;
+  const size_t NVs = a.NV, cs = static_cast<size_t>(a.N) * NVs;
+  const int m = min(a.ncnt[j], a.cap);
+  const int64_t row = static_cast<int64_t>(j) * a.cap;
+  double Uj[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < D; ++q) Uj[q] = a.U_n[static_cast<size_t>(q) * a.N + j];
+  double gU[3] = {0.0, 0.0, 0.0};
+  for (int q = threadIdx.x; q < a.NV; q += kThreads) {
+    double v[3];
+    velocity_of<D>(q, a.nv, a.vmax, v);
+    double lf[NC], lj[NC], fj[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      lf[c] = 0.0;
+      lj[c] = inner ? a.lam_ft[c * cs + static_cast<size_t>(j) * NVs + q] : 0.0;
+      fj[c] = a.f_n[c * cs + static_cast<size_t>(j) * NVs + q];
+    }
+    double csum = 0.0;
+    for (int e = 0; e < m; ++e) {
+      const int i = a.nidx[row + e];
+      if (i == j) continue;
+      if (inner) {
+        // own transport: c_jk with k = i, and dc_jk/dU_j
+        const double* o = a.ops + (row + e) * DD;
+        double c = 0.0, dcdU[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < D; ++kk) {
+          double p = 0.0;
+#pragma unroll
+          for (int mm = 0; mm < D; ++mm) p = p + o[kk * D + mm] * (v[mm] - Uj[mm]);
+          c = c + fmin(p, 0.0);
+          if (p < 0.0) {
+#pragma unroll
+            for (int mm = 0; mm < D; ++mm) dcdU[mm] = dcdU[mm] - 2.0 * o[kk * D + mm];
+          }
+        }
+        csum = csum + 2.0 * c;
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+          const double df = a.f_n[cc * cs + static_cast<size_t>(i) * NVs + q] - fj[cc];
+#pragma unroll
+          for (int mm = 0; mm < D; ++mm) gU[mm] = gU[mm] + lj[cc] * dcdU[mm] * df;
+        }
+      }
+      const int te = a.tidx[row + e];
+      if (te >= 0) {
+        // i transports from j: c_ij with i's operators and U_i
+        double Ui[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int mm = 0; mm < D; ++mm) Ui[mm] = a.U_n[static_cast<size_t>(mm) * a.N + i];
+        const double c = cij<D>(a.ops + (static_cast<int64_t>(i) * a.cap + te) * DD, v, Ui);
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc)
+          lf[cc] = lf[cc] - a.dt * c * a.lam_ft[cc * cs + static_cast<size_t>(i) * NVs + q];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double l = lf[c];
+      if (inner) l = l + lj[c] * (1.0 + a.dt * csum);
+      a.lam_f[c * cs + static_cast<size_t>(j) * NVs + q] = l;
+    }
+  }
+  double r[3] = {gU[0], gU[1], gU[2]};
+  block_sum<3>(r, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int mm = 0; mm < D; ++mm)
+      a.lam_U[static_cast<size_t>(mm) * a.N + j] = inner ? -a.dt * r[mm] : 0.0;
+  }
+}
+
+// ------------------------------------------------------------ objective
+// J = dx^(d-1) sum_{lid b} q_n(b) + (ke/N) sum_i rho_i |U_i|^2 / 2,
+// q_n = omega/2 sum_v (v_n - U_n)(|v-U|^2 f1 [+ f2]), n = last axis.
+// Block per particle: its term of J into part[i] and its gradient rows.
+template <int D, int NC>
+__global__ __launch_bounds__(kThreads) void k_objective(int N, int NV, int nv, double vmax,
+                                                         double hw, double ke,
+                                                         const int32_t* __restrict__ wall_id,
+                                                         const double* __restrict__ f,
+                                                         const double* __restrict__ rho,
+                                                         const double* __restrict__ U,
+                                                         double* __restrict__ part,
+                                                         double* __restrict__ dJ_df,
+                                                         double* __restrict__ dJ_drho,
+                                                         double* __restrict__ dJ_dU) {
+  __shared__ double sh[4 * (D + 1)];
+  const int i = blockIdx.x;
+  const size_t NVs = NV, cs = static_cast<size_t>(N) * NVs;
+  const int an = D - 1;
+  double Ui[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) Ui[a] = U[static_cast<size_t>(a) * N + i];
+  const bool on_lid = wall_id[i] == 2 * D;  // block-uniform
+  double s[D + 1];
+#pragma unroll
+  for (int k = 0; k <= D; ++k) s[k] = 0.0;
+  for (int q = threadIdx.x; q < NV; q += kThreads) {
+    double g0 = 0.0, g1 = 0.0;
+    if (on_lid) {
+      double v[3];
+      velocity_of<D>(q, nv, vmax, v);
+      double w2 = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) w2 = w2 + (v[a] - Ui[a]) * (v[a] - Ui[a]);
+      const double wn = v[an] - Ui[an];
+      const double f1 = f[static_cast<size_t>(i) * NVs + q];
+      double e = w2 * f1;
+      if (NC == 2) e = e + f[cs + static_cast<size_t>(i) * NVs + q];
+      s[0] = s[0] + wn * e;
+#pragma unroll
+      for (int a = 0; a < D; ++a) s[1 + a] = s[1 + a] - 2.0 * wn * (v[a] - Ui[a]) * f1;
+      s[1 + an] = s[1 + an] - e;
+      g0 = hw * wn * w2;
+      g1 = hw * wn;
+    }
+    if (dJ_df) {
+      dJ_df[static_cast<size_t>(i) * NVs + q] = g0;
+      if (NC == 2) dJ_df[cs + static_cast<size_t>(i) * NVs + q] = g1;
+    }
+  }
+  if (on_lid) block_sum<D + 1>(s, sh);
+  if (threadIdx.x == 0) {
+    double u2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) u2 = u2 + Ui[a] * Ui[a];
+    part[i] = (on_lid ? hw * s[0] : 0.0) + (ke / N) * (0.5 * rho[i] * u2);
+    if (dJ_drho) dJ_drho[i] = (ke / N) * 0.5 * u2;
+    if (dJ_dU) {
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+        dJ_dU[static_cast<size_t>(a) * N + i] =
+            (ke / N) * rho[i] * Ui[a] + (on_lid ? hw * s[1 + a] : 0.0);
+    }
+  }
+}
+
+// out = sum of part[0..n) in a fixed order (one block).
+__global__ __launch_bounds__(kThreads) void k_sum_fixed(int n, const double* __restrict__ part,
+                                                         double* __restrict__ out, int accumulate) {
+  __shared__ double sh[4];
+  double s[1] = {0.0};
+  for (int k = threadIdx.x; k < n; k += kThreads) s[0] = s[0] + part[k];
+  block_sum<1>(s, sh);
+  if (threadIdx.x == 0) *out = accumulate ? *out + s[0] : s[0];
+}
+
+// lam_f += moments^T(lam_rho, lam_U, lam_T) for every particle.
+template <int D, int NC>
+__global__ __launch_bounds__(kThreads) void k_moments_adj(int N, int NV, int nv, double vmax,
+                                                           double omega,
+                                                           const double* __restrict__ rho,
+                                                           const double* __restrict__ U,
+                                                           const double* __restrict__ T,
+                                                           const double* __restrict__ lr,
+                                                           const double* __restrict__ lU,
+                                                           const double* __restrict__ lT,
+                                                           double* __restrict__ lam_f) {
+  const int i = blockIdx.x;
+  const size_t NVs = NV, cs = static_cast<size_t>(N) * NVs;
+  double Ui[3] = {0.0, 0.0, 0.0}, lUi[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    Ui[a] = U[static_cast<size_t>(a) * N + i];
+    if (lU) lUi[a] = lU[static_cast<size_t>(a) * N + i];
+  }
+  const double s0 = rho[i] / omega, lri = lr ? lr[i] : 0.0, lTi = lT ? lT[i] : 0.0;
+  for (int q = threadIdx.x; q < NV; q += kThreads) {
+    double v[3];
+    velocity_of<D>(q, nv, vmax, v);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      lam_f[c * cs + static_cast<size_t>(i) * NVs + q] +=
+          mom_adj<D, NC>(c, v, omega, s0, Ui, T[i], lri, lUi, lTi);
+  }
+}
+
+// ------------------------------------------------------------ launchers
+static double omega_adj(const bgk_config& cfg) {
+  const double dv = 2.0 * cfg.vmax / static_cast<double>(cfg.nv - 1);
+  double w = 1.0;
+  for (int k = 0; k < cfg.dim; ++k) w = w * dv;
+  return w;
+}
+
+hipError_t launch_adjoint_transposes(const Ctx& c) {
+  const Adj& j = c.adj;
+  hipLaunchKernelGGL(k_transpose_nbr, dim3((c.N + 127) / 128), dim3(128), 0, c.stream, c.N, c.cap,
+                     c.d.wall_id, c.d.ncnt, c.d.nidx, j.tidx);
+  hipError_t e = launch_fill_i32(c.stream, j.wtstart, c.N + 1, 0);
+  if (e != hipSuccess) return e;
+  if (c.Nw > 0)
+    hipLaunchKernelGGL(k_wt_count, dim3(c.Nw), dim3(64), 0, c.stream, c.Nw, c.cap, c.d.wcnt,
+                       c.d.widx, j.wtstart);
+  e = launch_scan(c.stream, j.wtstart, c.N);
+  if (e != hipSuccess) return e;
+  e = launch_copy_i32(c.stream, j.wtstart, j.wtcursor, c.N);
+  if (e != hipSuccess) return e;
+  if (c.Nw > 0)
+    hipLaunchKernelGGL(k_wt_scatter, dim3(c.Nw), dim3(64), 0, c.stream, c.Nw, c.cap, c.d.wcnt,
+                       c.d.widx, j.wtcursor, j.wt);
+  hipLaunchKernelGGL(k_wt_sort, dim3((c.N + 127) / 128), dim3(128), 0, c.stream, c.N, j.wtstart,
+                     j.wt);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(const Ctx& c, const double* f_n, const double* U_n,
+                               const double* lam_f1, const double* lam_U1, const double* lam_rho1,
+                               const double* lam_T1, double* lam_f, double* lam_U,
+                               double* dJ_dlid) {
+  const Adj& j = c.adj;
+  AdjArgs a{c.N,        c.NV,        c.cfg.nv,   c.cap,      c.Nw,     c.Ni,     c.D,
+            c.cfg.vmax, omega_adj(c.cfg), c.cfg.kn, c.cfg.dt, c.lid, c.cfg.wall_T,
+            c.d.wall_id, c.d.wall_list, c.d.cperm, c.d.ncnt, c.d.nidx, j.tidx, c.d.ops64,
+            c.d.wcnt,   c.d.widx,    c.d.wc0,    j.wtstart,  j.wt,     f_n,      U_n,
+            j.ft,       j.f1,        j.rho1,     j.U1,       j.T1,     lam_f1,   lam_U1,
+            lam_rho1,   lam_T1,      j.larr,     j.lam_ft,   lam_f,    lam_U,    j.lidpart};
+  dim3 t(kThreads);
+  if (c.D == 2) {
+    if (c.Nw) hipLaunchKernelGGL((k_adj_wall<2, 2>), dim3(c.Nw), t, 0, c.stream, a);
+    if (c.Ni) hipLaunchKernelGGL((k_adj_collide<2, 2>), dim3(c.Ni), t, 0, c.stream, a);
+    hipLaunchKernelGGL((k_adj_transport<2, 2>), dim3(c.N), t, 0, c.stream, a);
+  } else {
+    if (c.Nw) hipLaunchKernelGGL((k_adj_wall<3, 1>), dim3(c.Nw), t, 0, c.stream, a);
+    if (c.Ni) hipLaunchKernelGGL((k_adj_collide<3, 1>), dim3(c.Ni), t, 0, c.stream, a);
+    hipLaunchKernelGGL((k_adj_transport<3, 1>), dim3(c.N), t, 0, c.stream, a);
+  }
+  if (c.Nw && dJ_dlid)
+    hipLaunchKernelGGL(k_sum_fixed, dim3(1), t, 0, c.stream, c.Nw, j.lidpart, dJ_dlid, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_objective(const Ctx& c, const double* f, const double* rho, const double* U,
+                            double ke, double* J, double* dJ_df, double* dJ_drho, double* dJ_dU) {
+  double area = 1.0;
+  for (int k = 0; k < c.D - 1; ++k) area = area * c.cfg.dx;
+  const double hw = 0.5 * omega_adj(c.cfg) * area;
+  if (c.D == 2)
+    hipLaunchKernelGGL((k_objective<2, 2>), dim3(c.N), dim3(kThreads), 0, c.stream, c.N, c.NV,
+                       c.cfg.nv, c.cfg.vmax, hw, ke, c.d.wall_id, f, rho, U, c.d.jpart, dJ_df,
+                       dJ_drho, dJ_dU);
+  else
+    hipLaunchKernelGGL((k_objective<3, 1>), dim3(c.N), dim3(kThreads), 0, c.stream, c.N, c.NV,
+                       c.cfg.nv, c.cfg.vmax, hw, ke, c.d.wall_id, f, rho, U, c.d.jpart, dJ_df,
+                       dJ_drho, dJ_dU);
+  hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(kThreads), 0, c.stream, c.N, c.d.jpart, J, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments_adjoint(const Ctx& c, const double* rho, const double* U,
+                                  const double* T, const double* lr, const double* lU,
+                                  const double* lT, double* lam_f) {
+  const double om = omega_adj(c.cfg);
+  if (c.D == 2)
+    hipLaunchKernelGGL((k_moments_adj<2, 2>), dim3(c.N), dim3(kThreads), 0, c.stream, c.N, c.NV,
+                       c.cfg.nv, c.cfg.vmax, om, rho, U, T, lr, lU, lT, lam_f);
+  else
+    hipLaunchKernelGGL((k_moments_adj<3, 1>), dim3(c.N), dim3(kThreads), 0, c.stream, c.N, c.NV,
+                       c.cfg.nv, c.cfg.vmax, om, rho, U, T, lr, lU, lT, lam_f);
+  return hipGetLastError();
+}
+
+}  // namespace bgk

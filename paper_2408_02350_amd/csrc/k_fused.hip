@@ -6,11 +6,11 @@
 //   rho, U, T of ft in FP64                                           (S5)
 //   f_i^{n+1} = (tau ft_i + dt M[rho, U, T]) / (tau + dt)             (S6)
 //
-// Layout of the work: a block of BT threads owns one patch; thread tid
-// handles the velocities q_r = tid + r*BTe (r < R), where BTe = N_v / R is a
-// multiple of nv^(d-1), so that the R velocities of a thread differ only in
-// the slowest velocity component: each projection a_k.(v - U) is formed once
-// and then advanced by a constant per r (one add).  The block walks the
+// Layout of the work: a block owns one patch; thread tid handles the R
+// consecutive velocities q = R*tid + r (r < R, R divides nv), which differ
+// only in the fastest velocity component: each projection a_k.(v - U) is
+// formed once and then advanced by a constant per r (one add), and every
+// row access of a thread is one contiguous R-element vector load or store.  The block walks the
 // sorted union of its particles' neighbour lists in chunks; per chunk the
 // per-edge data (a_k, a_k.U_i and the per-r increments) is staged in LDS
 // and read back with wave-uniform addresses, and the next f_j row segment is
@@ -43,7 +43,7 @@ constexpr int kMaxNv = 64;   // velocity points per axis supported by the fused 
 
 struct FusedArgs {
   int N, NV, nv, cap, Ni, npatch, ucap, bte;
-  double vmax, dt, kn, omega, dvs;  // dvs: slow-axis velocity step between r and r+1
+  double vmax, dt, kn, omega, dvs;  // dvs: velocity step between r and r+1 (fast axis)
   const void* f;
   void* fo;          // f-tilde (unfused) or f^{n+1} (fused)
   const double* U;   // U^n
@@ -69,11 +69,44 @@ __device__ __forceinline__ T uniform(T x) {
   return __builtin_amdgcn_readfirstlane(x);
 }
 
+// R consecutive elements from / to p with the widest aligned vector
+// accesses R * sizeof(Real) allows (p is aligned to that vector: R*tid
+// offsets into rows whose length is a multiple of 4 elements).
+template <typename Real, int R>
+__device__ __forceinline__ void load_r(const Real* __restrict__ p, Real (&o)[R]) {
+  constexpr int B = R * static_cast<int>(sizeof(Real));
+  constexpr int W = (B % 16 == 0) ? 16 / static_cast<int>(sizeof(Real))
+                                  : (B % 8 == 0 ? 8 / static_cast<int>(sizeof(Real)) : 1);
+  typedef Real V __attribute__((ext_vector_type(W)));
+  const V* pv = reinterpret_cast<const V*>(__builtin_assume_aligned(p, W * sizeof(Real)));
+#pragma unroll
+  for (int i = 0; i < R / W; ++i) {
+    const V x = pv[i];
+#pragma unroll
+    for (int w = 0; w < W; ++w) o[i * W + w] = x[w];
+  }
+}
+template <typename Real, int R>
+__device__ __forceinline__ void store_r(Real* __restrict__ p, const Real (&o)[R]) {
+  constexpr int B = R * static_cast<int>(sizeof(Real));
+  constexpr int W = (B % 16 == 0) ? 16 / static_cast<int>(sizeof(Real))
+                                  : (B % 8 == 0 ? 8 / static_cast<int>(sizeof(Real)) : 1);
+  typedef Real V __attribute__((ext_vector_type(W)));
+  V* pv = reinterpret_cast<V*>(__builtin_assume_aligned(p, W * sizeof(Real)));
+#pragma unroll
+  for (int i = 0; i < R / W; ++i) {
+    V x;
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = o[i * W + w];
+    pv[i] = x;
+  }
+}
+
 template <int D, int NC, int MODE, int R, bool FUSE>
 __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   using Real = typename FPrec<MODE>::real;
   constexpr int TP = kPatch, DD = D * D;
-  constexpr int REC = DD + 2 * D;              // a_k (d*d), a_k.U (d), a_k[slow]*dvs (d)
+  constexpr int REC = DD + 2 * D;              // a_k (d*d), a_k.U (d), a_k[fast]*dvs (d)
   __shared__ Real lrec[kChunk][TP][REC];
   __shared__ int32_t luj[kChunk];
   __shared__ uint32_t lmask[kChunk];
@@ -100,19 +133,19 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   if (tid < a.nv) vtab[tid] = vnode(tid, a.nv, a.vmax);
   __syncthreads();
 
-  // velocities of this thread: q_r = tid + r*bte, all in the same
-  // (k1[,k2]) column, k_slow advancing by bte/plane per r
+  // velocities of this thread: q = q0 + r, q0 = R*tid; the fast component
+  // is kq[0] + r, the others are fixed
   const bool lane_on = tid < a.bte;
+  const int q0 = lane_on ? R * tid : 0;
   int kq[D];
   {
-    int q = lane_on ? tid : 0;
+    int q = q0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       kq[k] = q % a.nv;
       q /= a.nv;
     }
   }
-  const int kstep = (a.bte / (a.NV / a.nv));  // k_slow increment per r
   Real v0[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) v0[k] = static_cast<Real>(vtab[kq[k]]);
@@ -121,15 +154,15 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
 #pragma unroll
   for (int t = 0; t < TP; ++t)
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+    for (int c = 0; c < NC; ++c) {
+      Real tmp[R];
+      load_r<Real, R>(f + c * cs + static_cast<size_t>(max(pt[t], 0)) * NVs + q0, tmp);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const size_t q = static_cast<size_t>(tid) + static_cast<size_t>(r) * a.bte;
-        fi[t][r][c] = (pt[t] >= 0 && lane_on)
-                          ? f[c * cs + static_cast<size_t>(pt[t]) * NVs + q]
-                          : Real(0);
+      for (int r = 0; r < R; ++r) {
+        fi[t][r][c] = (pt[t] >= 0 && lane_on) ? tmp[r] : Real(0);
         acc[t][r][c] = Real(0);
       }
+    }
 
   const int nu = a.ucount[patch];
   const int32_t* __restrict__ ujp = a.uj + static_cast<size_t>(patch) * a.ucap;
@@ -166,7 +199,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
           for (int m = 0; m < D; ++m)
             b = fma_t(av[k * D + m], static_cast<Real>(a.U[static_cast<size_t>(m) * a.N + i]), b);
           rec[DD + k] = b;
-          rec[DD + D + k] = av[k * D + D - 1] * dvs;
+          rec[DD + D + k] = av[k * D] * dvs;
         }
 #pragma unroll
         for (int k = 0; k < DD; ++k) rec[k] = av[k];
@@ -179,14 +212,16 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
     // never move).  Loads are unconditional (clamped entry, lane-clamped
     // address), so the waits before each use are exact partial counts.
     Real ra[R][NC], rb[R][NC], rc[R][NC];
-    const size_t qb = lane_on ? static_cast<size_t>(tid) : 0;
     auto load_row = [&](int uu, Real (&buf)[R][NC]) {
       const int j = uniform(luj[uu]);
-      const Real* src = f + static_cast<size_t>(j) * NVs + qb;
+      const Real* src = f + static_cast<size_t>(j) * NVs + q0;
 #pragma unroll
-      for (int r = 0; r < R; ++r)
+      for (int c = 0; c < NC; ++c) {
+        Real tmp[R];
+        load_r<Real, R>(src + c * cs, tmp);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) buf[r][c] = src[c * cs + static_cast<size_t>(r) * a.bte];
+        for (int r = 0; r < R; ++r) buf[r][c] = tmp[r];
+      }
       // keep the prefetch where it is issued (the compiler would otherwise
       // sink it down to its first use, one entry later instead of three)
       asm volatile("" ::: "memory");
@@ -268,12 +303,13 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
 #pragma unroll
     for (int t = 0; t < TP; ++t)
 #pragma unroll
-      for (int r = 0; r < R; ++r)
+      for (int c = 0; c < NC; ++c)
+        if (pt[t] >= 0 && lane_on) {
+          Real tmp[R];
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-          if (pt[t] >= 0 && lane_on)
-            fo[c * cs + static_cast<size_t>(pt[t]) * NVs + tid + static_cast<size_t>(r) * a.bte] =
-                fi[t][r][c];
+          for (int r = 0; r < R; ++r) tmp[r] = fi[t][r][c];
+          store_r<Real, R>(fo + c * cs + static_cast<size_t>(pt[t]) * NVs + q0, tmp);
+        }
     return;
   } else {
     const int lane = tid & 63, wid = tid >> 6, nw = nthreads >> 6;
@@ -288,7 +324,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
       for (int r = 0; r < R; ++r) {
         double v[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) v[k] = vtab[k == D - 1 ? kq[k] + r * kstep : kq[k]];
+        for (int k = 0; k < D; ++k) v[k] = vtab[k == 0 ? kq[0] + r : kq[k]];
 #pragma unroll
         for (int t = 0; t < TP; ++t) {
           const double x = static_cast<double>(fi[t][r][0]);
@@ -331,7 +367,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
       for (int r = 0; r < R; ++r) {
         double v[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) v[k] = vtab[k == D - 1 ? kq[k] + r * kstep : kq[k]];
+        for (int k = 0; k < D; ++k) v[k] = vtab[k == 0 ? kq[0] + r : kq[k]];
 #pragma unroll
         for (int t = 0; t < TP; ++t) {
           double w2 = 0.0;
@@ -401,18 +437,21 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
       const double ca = pstat[t][D + 3], cb = pstat[t][D + 4];
       double efix = norm;
 #pragma unroll
-      for (int k = 0; k < D - 1; ++k) efix = efix * etab[t][k][kq[k]];
+      for (int k = 1; k < D; ++k) efix = efix * etab[t][k][kq[k]];
+      Real out[NC][R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const double M1 = efix * etab[t][D - 1][kq[D - 1] + r * kstep];
-        const size_t q = static_cast<size_t>(tid) + static_cast<size_t>(r) * a.bte;
+        const double M1 = efix * etab[t][0][kq[0] + r];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           const double M = (c == 1) ? T * M1 : M1;
           const double x = static_cast<double>(fi[t][r][c]);
-          fo[c * cs + static_cast<size_t>(pt[t]) * NVs + q] = static_cast<Real>(fma(cb, M, ca * x));
+          out[c][r] = static_cast<Real>(fma(cb, M, ca * x));
         }
       }
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        store_r<Real, R>(fo + c * cs + static_cast<size_t>(pt[t]) * NVs + q0, out[c]);
     }
   }
 }
@@ -441,8 +480,7 @@ template <int D, int NC, int MODE, bool FUSE>
 static hipError_t launch_fused_t(const Ctx& c, FusedArgs a) {
   const int R = pick_r(D, c.cfg.nv, c.NV);
   a.bte = c.NV / R;
-  const int plane = c.NV / c.cfg.nv;
-  a.dvs = (2.0 * c.cfg.vmax / (c.cfg.nv - 1)) * static_cast<double>(a.bte / plane);
+  a.dvs = 2.0 * c.cfg.vmax / (c.cfg.nv - 1);
   const int bt = (a.bte + 63) / 64 * 64;
   dim3 g(c.npatch), b(bt);
   switch (R) {

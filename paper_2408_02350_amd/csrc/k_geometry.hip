@@ -166,6 +166,11 @@ __global__ void k_cell_sort(int nkeys, int N, int D, const int32_t* __restrict__
   }
 }
 
+hipError_t launch_scan(hipStream_t s, int32_t* a, int n) {
+  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, a, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_cells(const Ctx& c, const double* x) {
   const Dev& d = c.d;
   const int nkeys = 2 * c.ncell;

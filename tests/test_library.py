@@ -36,7 +36,8 @@ def test_header_symbols_are_exported(lib):
 
 def test_north_star_entry_points_present(lib):
     syms = declared_symbols()
-    for s in ("bgk_init", "bgk_build_neighbors", "bgk_wls_operators", "bgk_step", "bgk_moments"):
+    for s in ("bgk_init", "bgk_build_neighbors", "bgk_wls_operators", "bgk_step", "bgk_moments",
+              "bgk_adjoint_step"):
         assert s in syms
 
 
@@ -75,3 +76,35 @@ def test_null_arguments_rejected(lib):
     assert L.bgk_step(None, None, None, None, None, None, None) == lib.BGK_EINVAL
     assert L.bgk_check(None) == lib.BGK_EINVAL
     assert L.bgk_last_error(None) == b"null context"
+
+
+def test_checkpoint_segments_cover_every_step_once():
+    from paper_2408_02350_amd.adjoint import segments
+    for nsteps in (0, 1, 5, 10, 50, 53):
+        for every in (1, 3, 10, 100):
+            seg = segments(nsteps, every)
+            steps = [s for s0, s1 in seg for s in range(s0, s1)]
+            assert steps == list(range(nsteps))
+            assert all(0 < s1 - s0 <= every for s0, s1 in seg)
+    with pytest.raises(ValueError):
+        segments(5, 0)
+
+
+def test_adjoint_flag_rules(lib):
+    bgk = lib
+    L = bgk.load_library()
+    from paper_2408_02350_amd.inputs import CONFIGS
+    n = ctypes.c_size_t(0)
+    plain = bgk.config_from(CONFIGS["c4"], "fp64")
+    L.bgk_workspace_bytes(ctypes.byref(plain), ctypes.byref(n))
+    base = n.value
+    adj = bgk.config_from(CONFIGS["c4"], "fp64", flags=bgk.BGK_FLAG_ADJOINT)
+    assert L.bgk_workspace_bytes(ctypes.byref(adj), ctypes.byref(n)) == bgk.BGK_OK
+    cav = CONFIGS["c4"]
+    f_bytes = 8 * 2 * cav.n_particles * cav.n_velocities
+    assert n.value >= base + 3 * f_bytes      # f-tilde, lam_ft, wall adjoints
+    for bad in (dict(precision=bgk.BGK_FP32), dict(move=1)):
+        c = bgk.config_from(CONFIGS["c4"], "fp64", flags=bgk.BGK_FLAG_ADJOINT)
+        for k, v in bad.items():
+            setattr(c, k, v)
+        assert L.bgk_workspace_bytes(ctypes.byref(c), ctypes.byref(n)) == bgk.BGK_EINVAL
