@@ -42,6 +42,39 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# Sources the fused kernel's machine code depends on: a traffic figure measured
+# with counters is reported only while these are unchanged.
+TRAFFIC_SOURCES = ("paper_2408_02350_amd/csrc/k_fused.hip",
+                   "paper_2408_02350_amd/csrc/device_common.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per launch of the fused kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
+    there is none for this workload or the kernel source changed since."""
+    import glob
+    import re
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*traffic*.md"))):
+        with open(path) as fh:
+            m = re.search(r"<!--\s*traffic:\s*(\{.*?\})\s*-->", fh.read(), flags=re.S)
+        if not m:
+            continue
+        rec = json.loads(m.group(1))
+        if rec.get("workload") == workload and rec.get("precision") == precision:
+            if rec.get("source_sha256") == kernel_source_hash():
+                return float(rec["bytes_per_launch"])
+    return None
+
+
 def transport_algorithmic(cav, edges, prec):
     """Algorithmic work of one transport launch.
 
@@ -184,7 +217,8 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": ach_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": ach_gbs / PEAK_HBM_GBS}
-    roof.update({"traffic": None, "kernel": "k_transport", "kernel_ms": k_ms,
+    roof.update({"traffic": measured_traffic(cav.name, args.precision), "kernel": "k_fused",
+                 "kernel_ms": k_ms,
                  "algorithmic_bytes": bytes_, "algorithmic_ops": ops, "ops_per_update": k,
                  "hbm_frac": ach_gbs / PEAK_HBM_GBS, "alu_frac": ach_tops / PEAK_VALU_TOPS,
                  "step_share": k_ms / ms})
