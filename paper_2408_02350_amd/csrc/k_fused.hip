@@ -7,18 +7,29 @@
 //   f_i^{n+1} = (tau ft_i + dt M[rho, U, T]) / (tau + dt)             (S6)
 //
 // Layout of the work: a block owns one patch; thread tid handles the R
-// consecutive velocities q = R*tid + r (r < R, R divides nv), which differ
+// consecutive velocities q = q0 + r (r < R, R divides nv), which differ
 // only in the fastest velocity component: each projection a_k.(v - U) is
 // formed once and then advanced by a constant per r (one add), and every
-// row access of a thread is one contiguous R-element vector load or store.  The block walks the
-// sorted union of its particles' neighbour lists in chunks; per chunk the
-// per-edge data (a_k, a_k.U_i and the per-r increments) is staged in LDS
-// and read back with wave-uniform addresses, and the next f_j row segment is
-// loaded one neighbour ahead.  After the walk, ft stays in registers: the
-// moment sums are block reductions in a fixed order, the Maxwellian is the
-// product of per-axis exponentials (exp(-(v_a-U_a)^2/2T), d*nv exp per
-// particle instead of N_v), and f^{n+1} is written once.  f-tilde never goes
-// to memory when the kernel runs fused; unfused, it writes f-tilde and stops.
+// row access of a thread is one contiguous R-element vector load or store.
+// The block walks the sorted union of its particles' neighbour lists in
+// chunks; per chunk the per-edge data (a_k, a_k.U_i and the per-r
+// increments) is staged in LDS and read back with wave-uniform addresses,
+// and the f_j rows are loaded three union entries ahead.
+//
+// The walk accumulates A = sum_j c_ij f_j (per component) and C = sum_j c_ij
+// (shared by the components), so f_i is not needed until the end:
+// ft = f_i (1 + dt C) - dt A.  (In the BF16-operand mode the products are
+// taken of the differences f_j - f_i instead, which keeps the BF16 rounding
+// proportional to the differences.)  After the walk ft stays in registers:
+// the moment sums are reduced in one pass and a fixed order (a wavefront
+// reduce-scatter, then the waves in order), the Maxwellian is the product of
+// per-axis exponentials (d*nv exp per particle instead of N_v), and f^{n+1}
+// is written once.
+//
+// When N_v does not fit one block at the register budget of the precision
+// (large 3D grids in FP64) the velocity range is split into tiles over
+// several blocks; the kernel then writes f-tilde and the separate
+// relaxation kernel finishes the step.
 #include "device_common.h"
 
 namespace bgk {
@@ -42,7 +53,7 @@ constexpr int kChunk = 64;   // union entries staged per LDS chunk
 constexpr int kMaxNv = 64;   // velocity points per axis supported by the fused path
 
 struct FusedArgs {
-  int N, NV, nv, cap, Ni, npatch, ucap, bte;
+  int N, NV, nv, cap, Ni, npatch, ucap, bte;  // bte: velocity lanes per block
   double vmax, dt, kn, omega, dvs;  // dvs: velocity step between r and r+1 (fast axis)
   const void* f;
   void* fo;          // f-tilde (unfused) or f^{n+1} (fused)
@@ -102,22 +113,57 @@ __device__ __forceinline__ void store_r(Real* __restrict__ p, const Real (&o)[R]
   }
 }
 
+// Sum K per-lane values (K a power of two, K <= 64) over the wavefront by
+// recursive halving: after the step with offset o every lane keeps half of
+// its values (the half selected by lane bit o) plus its partner's copy of
+// that half.  On return the lane holds the total of value
+// k = (lane / (64 / K)) % K.  The summation order is fixed.
+template <int K, int N, int O>
+__device__ __forceinline__ void halve_step(double (&v)[K], int lane) {
+  if constexpr (N > 1) {
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int i = 0; i < N / 2; ++i) {
+      const double send = up ? v[i] : v[i + N / 2];
+      const double keep = up ? v[i + N / 2] : v[i];
+      v[i] = keep + __shfl_xor(send, O, 64);
+    }
+    halve_step<K, N / 2, O / 2>(v, lane);
+  }
+}
+
+template <int K>
+__device__ __forceinline__ double wave_reduce_scatter(double (&v)[K]) {
+  const int lane = threadIdx.x & 63;
+  halve_step<K, K, 32>(v, lane);
+  double x = v[0];
+#pragma unroll
+  for (int o = 32 / K; o > 0; o >>= 1) x = x + __shfl_xor(x, o, 64);
+  return x;
+}
+
+constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) / 2); }
+
 template <int D, int NC, int MODE, int R, bool FUSE>
 __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   using Real = typename FPrec<MODE>::real;
   constexpr int TP = kPatch, DD = D * D;
-  constexpr int REC = DD + 2 * D;              // a_k (d*d), a_k.U (d), a_k[fast]*dvs (d)
+  constexpr bool DIFF = (MODE == BGK_BF16);     // products of differences
+  constexpr int REC = DD + 2 * D;               // a_k (d*d), a_k.U (d), a_k[fast]*dvs (d)
+  constexpr int KM = TP * (D + 2);              // moment sums per thread
+  constexpr int KP = pow2_at_least(KM);
   __shared__ Real lrec[kChunk][TP][REC];
   __shared__ int32_t luj[kChunk];
   __shared__ uint32_t lmask[kChunk];
   __shared__ double vtab[kMaxNv];
-  __shared__ double red[16][TP][D + 1];
+  __shared__ double red[16][KP];
   __shared__ double etab[TP][D][kMaxNv];
   __shared__ double pstat[TP][D + 5];           // rho, U[d], T, norm, a, b
 
   const int tid = threadIdx.x;
   const int nthreads = blockDim.x;
-  const int patch = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int patch = lb % a.npatch, tile = lb / a.npatch;
   const Real* __restrict__ f = static_cast<const Real*>(a.f);
   Real* __restrict__ fo = static_cast<Real*>(a.fo);
   const Real* __restrict__ ops = static_cast<const Real*>(a.ops);
@@ -133,10 +179,11 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   if (tid < a.nv) vtab[tid] = vnode(tid, a.nv, a.vmax);
   __syncthreads();
 
-  // velocities of this thread: q = q0 + r, q0 = R*tid; the fast component
-  // is kq[0] + r, the others are fixed
-  const bool lane_on = tid < a.bte;
-  const int q0 = lane_on ? R * tid : 0;
+  // velocities of this thread: q = q0 + r; the fast component is kq[0] + r,
+  // the others are fixed
+  const int qs = tile * (a.bte * R) + R * tid;
+  const bool lane_on = tid < a.bte && qs < a.NV;
+  const int q0 = lane_on ? qs : 0;
   int kq[D];
   {
     int q = q0;
@@ -150,19 +197,37 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
 #pragma unroll
   for (int k = 0; k < D; ++k) v0[k] = static_cast<Real>(vtab[kq[k]]);
 
-  Real fi[TP][R][NC], acc[TP][R][NC];
+  auto load_self = [&](int t, int c, Real (&o)[R]) {
+    Real tmp[R];
+    load_r<Real, R>(f + c * cs + static_cast<size_t>(max(pt[t], 0)) * NVs + q0, tmp);
+#pragma unroll
+    for (int r = 0; r < R; ++r) o[r] = (pt[t] >= 0 && lane_on) ? tmp[r] : Real(0);
+  };
+
+  // DIFF: fi = f_i, acc = sum c (f_j - f_i).  Otherwise acc = sum c f_j and
+  // csum = sum c.
+  Real acc[TP][R][NC];
+  Real fi[DIFF ? TP : 1][R][NC];
+  Real csum[DIFF ? 1 : TP][R];
 #pragma unroll
   for (int t = 0; t < TP; ++t)
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      Real tmp[R];
-      load_r<Real, R>(f + c * cs + static_cast<size_t>(max(pt[t], 0)) * NVs + q0, tmp);
+    for (int r = 0; r < R; ++r) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        fi[t][r][c] = (pt[t] >= 0 && lane_on) ? tmp[r] : Real(0);
-        acc[t][r][c] = Real(0);
-      }
+      for (int c = 0; c < NC; ++c) acc[t][r][c] = Real(0);
+      if constexpr (!DIFF) csum[t][r] = Real(0);
     }
+  if constexpr (DIFF) {
+#pragma unroll
+    for (int t = 0; t < TP; ++t)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        Real tmp[R];
+        load_self(t, c, tmp);
+#pragma unroll
+        for (int r = 0; r < R; ++r) fi[t][r][c] = tmp[r];
+      }
+  }
 
   const int nu = a.ucount[patch];
   const int32_t* __restrict__ ujp = a.uj + static_cast<size_t>(patch) * a.ucap;
@@ -182,8 +247,8 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
         luj[u] = ujp[c0 + u];
         uint32_t m = 0;
 #pragma unroll
-        for (int s = 0; s < TP; ++s)
-          if (((pe >> (8 * s)) & 0xFFu) != 0xFFu) m |= 1u << s;
+        for (int s2 = 0; s2 < TP; ++s2)
+          if (((pe >> (8 * s2)) & 0xFFu) != 0xFFu) m |= 1u << s2;
         lmask[u] = m;
       }
       if (e != 0xFFu) {
@@ -250,10 +315,10 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
           Real p[D];
 #pragma unroll
           for (int k = 0; k < D; ++k) {
-            Real s = -bk[k];
+            Real s1 = -bk[k];
 #pragma unroll
-            for (int m = 0; m < D; ++m) s = fma_t(av[k * D + m], v0[m], s);
-            p[k] = s;
+            for (int m = 0; m < D; ++m) s1 = fma_t(av[k * D + m], v0[m], s1);
+            p[k] = s1;
           }
 #pragma unroll
           for (int r = 0; r < R; ++r) {
@@ -264,13 +329,14 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
             Real cm = min_t(p[0], Real(0));
 #pragma unroll
             for (int k = 1; k < D; ++k) cm = cm + min_t(p[k], Real(0));
+            if constexpr (DIFF) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-              const Real df = fj[r][c] - fi[t][r][c];
-              if constexpr (MODE == BGK_BF16)
-                acc[t][r][c] = fma_t(bf16r(cm + cm), bf16r(df), acc[t][r][c]);
-              else
-                acc[t][r][c] = fma_t(cm, df, acc[t][r][c]);
+              for (int c = 0; c < NC; ++c)
+                acc[t][r][c] = fma_t(bf16r(cm + cm), bf16r(fj[r][c] - fi[t][r][c]), acc[t][r][c]);
+            } else {
+              csum[t][r] = csum[t][r] + cm;
+#pragma unroll
+              for (int c = 0; c < NC; ++c) acc[t][r][c] = fma_t(cm, fj[r][c], acc[t][r][c]);
             }
           }
         }
@@ -290,14 +356,30 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
     }
   }
 
-  // ft = f - dt * sum c (f_j - f_i); the factor 2 of c is folded into dt
-  const Real dtf = static_cast<Real>(MODE == BGK_BF16 ? a.dt : 2.0 * a.dt);
+  // ft = f - dt sum c (f_j - f_i) = f (1 + dt sum c) - dt sum c f_j; the
+  // factor 2 of c is folded into dt (except where BF16 rounds 2 cm)
+  const Real dtf = static_cast<Real>(DIFF ? a.dt : 2.0 * a.dt);
+  Real ft[TP][R][NC];
 #pragma unroll
-  for (int t = 0; t < TP; ++t)
+  for (int t = 0; t < TP; ++t) {
+    if constexpr (DIFF) {
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+      for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int c = 0; c < NC; ++c) fi[t][r][c] = fi[t][r][c] - dtf * acc[t][r][c];
+        for (int c = 0; c < NC; ++c) ft[t][r][c] = fi[t][r][c] - dtf * acc[t][r][c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        Real self[R];
+        load_self(t, c, self);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const Real g = fma_t(dtf, csum[t][r], Real(1));
+          ft[t][r][c] = fma_t(self[r], g, -(dtf * acc[t][r][c]));
+        }
+      }
+    }
+  }
 
   if constexpr (!FUSE) {
 #pragma unroll
@@ -307,93 +389,63 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
         if (pt[t] >= 0 && lane_on) {
           Real tmp[R];
 #pragma unroll
-          for (int r = 0; r < R; ++r) tmp[r] = fi[t][r][c];
+          for (int r = 0; r < R; ++r) tmp[r] = ft[t][r][c];
           store_r<Real, R>(fo + c * cs + static_cast<size_t>(pt[t]) * NVs + q0, tmp);
         }
     return;
   } else {
     const int lane = tid & 63, wid = tid >> 6, nw = nthreads >> 6;
-    // ---- S5 pass 1: s0 = sum f1, s1 = sum v f1 (FP64)
-    double sm[TP][D + 1];
+    // ---- S5 in one pass (FP64): s0 = sum f1, s1 = sum v f1,
+    //      s2 = sum |v|^2 f1 (+ sum f2); then U = s1/s0 and
+    //      3 T = s2/s0 - |U|^2
+    double sm[KP];
 #pragma unroll
-    for (int t = 0; t < TP; ++t)
-#pragma unroll
-      for (int k = 0; k <= D; ++k) sm[t][k] = 0.0;
+    for (int k = 0; k < KP; ++k) sm[k] = 0.0;
     if (lane_on) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        double v[D];
+        double v[D], v2 = 0.0;
 #pragma unroll
-        for (int k = 0; k < D; ++k) v[k] = vtab[k == 0 ? kq[0] + r : kq[k]];
+        for (int k = 0; k < D; ++k) {
+          v[k] = vtab[k == 0 ? kq[0] + r : kq[k]];
+          v2 = v2 + v[k] * v[k];
+        }
 #pragma unroll
         for (int t = 0; t < TP; ++t) {
-          const double x = static_cast<double>(fi[t][r][0]);
-          sm[t][0] = sm[t][0] + x;
+          const double x = static_cast<double>(ft[t][r][0]);
+          double* st = sm + t * (D + 2);
+          st[0] = st[0] + x;
 #pragma unroll
-          for (int k = 0; k < D; ++k) sm[t][1 + k] = sm[t][1 + k] + v[k] * x;
+          for (int k = 0; k < D; ++k) st[1 + k] = st[1 + k] + v[k] * x;
+          st[D + 1] = st[D + 1] + v2 * x;
+          if (NC == 2) st[D + 1] = st[D + 1] + static_cast<double>(ft[t][r][NC - 1]);
         }
       }
     }
-#pragma unroll
-    for (int t = 0; t < TP; ++t)
-#pragma unroll
-      for (int k = 0; k <= D; ++k) {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) sm[t][k] += __shfl_xor(sm[t][k], o, 64);
-        if (lane == 0) red[wid][t][k] = sm[t][k];
-      }
+    {
+      const double part = wave_reduce_scatter<KP>(sm);
+      constexpr int G = 64 / KP;
+      if (lane % G == 0) red[wid][(lane / G) % KP] = part;
+    }
     __syncthreads();
-    if (tid < TP * (D + 1)) {
-      const int t = tid / (D + 1), k = tid - t * (D + 1);
+    if (tid < KM) {
       double s = 0.0;
-      for (int w = 0; w < nw; ++w) s = s + red[w][t][k];
-      red[0][t][k] = s;  // only wave 0's slot is overwritten after all reads below
-    }
-    __syncthreads();
-    double Ut[TP][D], s0t[TP];
-#pragma unroll
-    for (int t = 0; t < TP; ++t) {
-      s0t[t] = red[0][t][0];
-#pragma unroll
-      for (int k = 0; k < D; ++k) Ut[t][k] = red[0][t][1 + k] / s0t[t];
-    }
-    __syncthreads();
-    // ---- S5 pass 2: 3 rho T = sum |v-U|^2 f1 (+ sum f2)
-    double se[TP];
-#pragma unroll
-    for (int t = 0; t < TP; ++t) se[t] = 0.0;
-    if (lane_on) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        double v[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) v[k] = vtab[k == 0 ? kq[0] + r : kq[k]];
-#pragma unroll
-        for (int t = 0; t < TP; ++t) {
-          double w2 = 0.0;
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            const double wk = v[k] - Ut[t][k];
-            w2 = w2 + wk * wk;
-          }
-          se[t] = se[t] + w2 * static_cast<double>(fi[t][r][0]);
-          if (NC == 2) se[t] = se[t] + static_cast<double>(fi[t][r][NC - 1]);
-        }
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < TP; ++t) {
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) se[t] += __shfl_xor(se[t], o, 64);
-      if (lane == 0) red[wid][t][0] = se[t];
+      for (int w = 0; w < nw; ++w) s = s + red[w][tid];
+      red[0][tid] = s;  // only wave 0's slot is overwritten after all reads
     }
     __syncthreads();
     if (tid < TP) {
       const int t = tid;
-      double s = 0.0;
-      for (int w = 0; w < nw; ++w) s = s + red[w][t][0];
-      const double rho = a.omega * s0t[t];
-      const double T = s / (3.0 * s0t[t]);
+      const double* st = red[0] + t * (D + 2);
+      const double s0 = st[0];
+      double Uk[D], u2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        Uk[k] = st[1 + k] / s0;
+        u2 = u2 + Uk[k] * Uk[k];
+      }
+      const double rho = a.omega * s0;
+      const double T = (st[D + 1] / s0 - u2) / 3.0;
       const double tau = a.kn * sqrt(2.0 / kPi) / (rho * sqrt(T));
       const double rden = 1.0 / (tau + a.dt);
       double norm;
@@ -405,7 +457,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
       }
       pstat[t][0] = rho;
 #pragma unroll
-      for (int k = 0; k < D; ++k) pstat[t][1 + k] = Ut[t][k];
+      for (int k = 0; k < D; ++k) pstat[t][1 + k] = Uk[k];
       pstat[t][D + 1] = T;
       pstat[t][D + 2] = norm;
       pstat[t][D + 3] = tau * rden;   // f^{n+1} = a ft + b M, a = tau/(tau+dt)
@@ -416,7 +468,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
         a.rho[i] = rho;
         a.T[i] = T;
 #pragma unroll
-        for (int k = 0; k < D; ++k) a.Unew[static_cast<size_t>(k) * a.N + i] = red[0][t][1 + k] / s0t[t];
+        for (int k = 0; k < D; ++k) a.Unew[static_cast<size_t>(k) * a.N + i] = Uk[k];
         if (!(rho > 0.0) || !(T > 0.0)) raise_error(a.err, BGK_ENONPHYS);
       }
     }
@@ -445,7 +497,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           const double M = (c == 1) ? T * M1 : M1;
-          const double x = static_cast<double>(fi[t][r][c]);
+          const double x = static_cast<double>(ft[t][r][c]);
           out[c][r] = static_cast<Real>(fma(cb, M, ca * x));
         }
       }
@@ -456,59 +508,95 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   }
 }
 
-// Choose R (velocities per thread) so that N_v / R is a multiple of the
-// velocity plane nv^(d-1) (R divides nv) and fits one block.
-static int pick_r(int D, int nv, int NV) {
-  static const int c2[] = {1, 2, 4};
-  static const int c3[] = {2, 4, 8, 10};
-  const int* cand = D == 2 ? c2 : c3;
-  const int nc = D == 2 ? 3 : 4;
-  for (int i = 0; i < nc; ++i) {
+// Launch plan: R velocities per thread along the fastest axis (R divides
+// nv, so a thread's R velocities share every other component), at most
+// Rmax for the precision and model (the per-thread accumulators are
+// kPatch * R * (n_c + 1) values), and the fewest velocity tiles of at most
+// 1024 threads (2D: at most 512, two blocks per CU).  One tile can run the
+// fused relaxation; several tiles write f-tilde for the separate kernel.
+struct FusedPlan {
+  int R = 0, tiles = 0, bte = 0;
+};
+
+static FusedPlan plan_fused(const Ctx& c) {
+  const int D = c.D, nv = c.cfg.nv, NV = c.NV;
+  const bool f64 = c.cfg.precision == BGK_FP64;
+  // instantiated R, ascending, within the register budget
+  static const int r64[] = {1, 2, 4};
+  static const int r2d[] = {1, 2, 4, 5};
+  static const int r3d[] = {1, 2, 4, 5, 8, 10};
+  const int rmax = D == 2 ? (f64 ? 2 : 4) : (f64 ? 4 : 10);
+  const int* cand = f64 ? r64 : (D == 2 ? r2d : r3d);
+  const int ncand = f64 ? 3 : (D == 2 ? 4 : 6);
+  const int lanes_max = D == 2 ? 512 : 1024;
+  FusedPlan p;
+  // one tile: the smallest admissible R that fits
+  for (int i = 0; i < ncand; ++i) {
     const int R = cand[i];
-    if (nv % R) continue;
-    const int bte = NV / R;
-    if (bte <= (D == 2 ? 512 : 1024)) return R;
+    if (R > rmax || nv % R || NV / R > lanes_max) continue;
+    p.R = R;
+    p.tiles = 1;
+    p.bte = NV / R;
+    return p;
   }
-  return 0;
+  // several tiles: the largest admissible R
+  for (int i = ncand - 1; i >= 0; --i) {
+    const int R = cand[i];
+    if (R > rmax || nv % R) continue;
+    const int lanes = NV / R;
+    p.R = R;
+    p.tiles = (lanes + 1023) / 1024;
+    p.bte = (lanes + p.tiles - 1) / p.tiles;
+    return p;
+  }
+  return p;
 }
 
-bool fused_supported(const Ctx& c) {
-  return c.cfg.nv <= kMaxNv && pick_r(c.D, c.cfg.nv, c.NV) > 0;
-}
+bool fused_supported(const Ctx& c) { return c.cfg.nv <= kMaxNv && plan_fused(c).R > 0; }
 
 template <int D, int NC, int MODE, bool FUSE>
-static hipError_t launch_fused_t(const Ctx& c, FusedArgs a) {
-  const int R = pick_r(D, c.cfg.nv, c.NV);
-  a.bte = c.NV / R;
+static hipError_t launch_fused_t(const Ctx& c, FusedArgs a, const FusedPlan& p) {
+  a.bte = p.bte;
   a.dvs = 2.0 * c.cfg.vmax / (c.cfg.nv - 1);
   const int bt = (a.bte + 63) / 64 * 64;
-  dim3 g(c.npatch), b(bt);
-  switch (R) {
-    case 1: hipLaunchKernelGGL((k_fused<D, NC, MODE, 1, FUSE>), g, b, 0, c.stream, a); break;
-    case 2: hipLaunchKernelGGL((k_fused<D, NC, MODE, 2, FUSE>), g, b, 0, c.stream, a); break;
-    case 4: hipLaunchKernelGGL((k_fused<D, NC, MODE, 4, FUSE>), g, b, 0, c.stream, a); break;
+  dim3 g(c.npatch * p.tiles), b(bt);
+  switch (p.R) {
+#define BGK_R_CASE(RR)                                                                  \
+  case RR:                                                                              \
+    hipLaunchKernelGGL((k_fused<D, NC, MODE, RR, FUSE>), g, b, 0, c.stream, a);         \
+    break;
+    BGK_R_CASE(1)
+    BGK_R_CASE(2)
+    BGK_R_CASE(4)
+    case 5:
+      if constexpr (MODE != BGK_FP64) hipLaunchKernelGGL((k_fused<D, NC, MODE, 5, FUSE>), g, b, 0, c.stream, a);
+      else return hipErrorInvalidValue;
+      break;
     case 8:
-      if constexpr (D == 3) hipLaunchKernelGGL((k_fused<D, NC, MODE, 8, FUSE>), g, b, 0, c.stream, a);
+      if constexpr (D == 3 && MODE != BGK_FP64) hipLaunchKernelGGL((k_fused<D, NC, MODE, 8, FUSE>), g, b, 0, c.stream, a);
+      else return hipErrorInvalidValue;
       break;
     case 10:
-      if constexpr (D == 3) hipLaunchKernelGGL((k_fused<D, NC, MODE, 10, FUSE>), g, b, 0, c.stream, a);
+      if constexpr (D == 3 && MODE != BGK_FP64) hipLaunchKernelGGL((k_fused<D, NC, MODE, 10, FUSE>), g, b, 0, c.stream, a);
+      else return hipErrorInvalidValue;
       break;
+#undef BGK_R_CASE
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 template <bool FUSE>
-static hipError_t launch_fused_any(const Ctx& c, const FusedArgs& a) {
+static hipError_t launch_fused_any(const Ctx& c, const FusedArgs& a, const FusedPlan& p) {
   const int mode = c.cfg.precision;
   if (c.D == 2) {
-    if (mode == BGK_FP64) return launch_fused_t<2, 2, BGK_FP64, FUSE>(c, a);
-    if (mode == BGK_FP32) return launch_fused_t<2, 2, BGK_FP32, FUSE>(c, a);
-    return launch_fused_t<2, 2, BGK_BF16, FUSE>(c, a);
+    if (mode == BGK_FP64) return launch_fused_t<2, 2, BGK_FP64, FUSE>(c, a, p);
+    if (mode == BGK_FP32) return launch_fused_t<2, 2, BGK_FP32, FUSE>(c, a, p);
+    return launch_fused_t<2, 2, BGK_BF16, FUSE>(c, a, p);
   }
-  if (mode == BGK_FP64) return launch_fused_t<3, 1, BGK_FP64, FUSE>(c, a);
-  if (mode == BGK_FP32) return launch_fused_t<3, 1, BGK_FP32, FUSE>(c, a);
-  return launch_fused_t<3, 1, BGK_BF16, FUSE>(c, a);
+  if (mode == BGK_FP64) return launch_fused_t<3, 1, BGK_FP64, FUSE>(c, a, p);
+  if (mode == BGK_FP32) return launch_fused_t<3, 1, BGK_FP32, FUSE>(c, a, p);
+  return launch_fused_t<3, 1, BGK_BF16, FUSE>(c, a, p);
 }
 
 static double omega_fused(const bgk_config& cfg) {
@@ -521,13 +609,19 @@ static double omega_fused(const bgk_config& cfg) {
 hipError_t launch_fused(const Ctx& c, const void* f_in, void* f_out, const double* U_in,
                         double* rho, double* U_out, double* T, bool fuse) {
   if (c.npatch == 0) return hipSuccess;
+  const FusedPlan p = plan_fused(c);
+  if (p.R == 0) return hipErrorInvalidValue;
   FusedArgs a{c.N, c.NV, c.cfg.nv, c.cap, c.Ni, c.npatch, c.ucap, 0,
               c.cfg.vmax, c.cfg.dt, c.cfg.kn, omega_fused(c.cfg), 0.0,
               f_in, f_out, U_in,
               c.cfg.precision == BGK_FP64 ? static_cast<const void*>(c.d.ops64)
                                           : static_cast<const void*>(c.d.ops32),
               c.d.cperm, c.d.ucount, c.d.uj, c.d.ue, rho, U_out, T, c.d.err};
-  return fuse ? launch_fused_any<true>(c, a) : launch_fused_any<false>(c, a);
+  if (fuse && p.tiles == 1) return launch_fused_any<true>(c, a, p);
+  hipError_t e = launch_fused_any<false>(c, a, p);
+  // several velocity tiles: f_out holds f-tilde; relax it in place
+  if (e == hipSuccess && fuse) e = launch_collide(c, f_out, f_out, rho, U_out, T);
+  return e;
 }
 
 }  // namespace bgk

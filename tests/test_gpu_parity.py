@@ -294,6 +294,15 @@ def test_step_parity_small(dim, n, nv, steps, seed, flags):
     assert_state_close(g, r)
 
 
+@pytest.mark.parametrize("dim,n,nv", [(3, 6, 18), (2, 8, 46)])
+def test_step_parity_velocity_tiles(dim, n, nv):
+    """Velocity grids too large for one block at the FP64 register budget
+    (18^3 in 3D, 46^2 in 2D): the transport runs over several velocity
+    tiles and the relaxation kernel finishes the step."""
+    k, g, r = run_both(cavity(dim, n, nv), 2, 5)
+    assert_state_close(g, r)
+
+
 @pytest.mark.parametrize("flags", [0, bgk.BGK_FLAG_GENERIC])
 def test_step_parity_frozen_cloud(flags):
     k, g, r = run_both(cavity(2, 16, 8, move=0, kn=0.5), 4, flags=flags)
