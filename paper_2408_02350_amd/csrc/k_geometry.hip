@@ -67,21 +67,53 @@ hipError_t launch_max_i32(hipStream_t s, const int32_t* a, int n, int32_t* out) 
 }
 
 // ------------------------------------------------------------ cell list
-// Key of a particle: its cell (cells of size 1/nca >= h, x fastest), plus
-// ncell for wall particles, so that the sorted permutation holds all interior
-// particles first (in cell order) and the wall particles after them.
+// Order of the cells.  The first d-1 axes are cut into tiles of
+// kCellTile<D> cells (strips in 2D, columns in 3D) and each tile is swept
+// along the last axis, x fastest inside the tile.  Interior particles are
+// processed in this order in patches of kPatch, and each XCD takes one
+// contiguous range of patches; sweeping a narrow tile brings a neighbour row
+// back within a few patches, while it is still in the XCD's L2 (a plain
+// row-major order returns to it only one full row of cells later).
+template <int D>
+struct CellTile;
+template <>
+struct CellTile<2> {
+  static constexpr int S = 12;
+};
+template <>
+struct CellTile<3> {
+  static constexpr int S = 4;
+};
+
+// Key of cell (cc[0], .., cc[D-1]), 0 <= cc < nca: a bijection onto
+// [0, nca^D) that lists the tiles in order (last tile of an axis narrower
+// when S does not divide nca).
+template <int D>
+__device__ __forceinline__ int cell_key(const int* cc, int nca) {
+  constexpr int S = CellTile<D>::S;
+  const int x0 = (cc[0] / S) * S, wx = min(S, nca - x0);
+  if constexpr (D == 2) {
+    return x0 * nca + cc[1] * wx + (cc[0] - x0);
+  } else {
+    const int y0 = (cc[1] / S) * S, wy = min(S, nca - y0);
+    return nca * (y0 * nca + x0 * wy) + cc[2] * (wx * wy) + (cc[1] - y0) * wx + (cc[0] - x0);
+  }
+}
+
+// Key of a particle: its cell (cells of size 1/nca >= h) in the order
+// above, plus ncell for wall particles, so that the sorted permutation
+// holds all interior particles first (in cell order) and the wall particles
+// after them.
 template <int D>
 __global__ void k_cell_count(int N, int nca, int ncell, const double* __restrict__ x,
                              const int32_t* __restrict__ wall_id, int32_t* __restrict__ key,
                              int32_t* __restrict__ count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  int c = 0, mul = 1;
+  int cc[D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) {
-    c += cell_coord(x[static_cast<int64_t>(a) * N + i], nca) * mul;
-    mul *= nca;
-  }
+  for (int a = 0; a < D; ++a) cc[a] = cell_coord(x[static_cast<int64_t>(a) * N + i], nca);
+  const int c = cell_key<D>(cc, nca);
   const int k = c + (wall_id[i] != 0 ? ncell : 0);
   key[i] = k;
   atomicAdd(&count[k], 1);
@@ -220,18 +252,16 @@ __device__ int cell_ranges(const int* ci, int nca, int ncell, bool walls,
     int len = 0, b = 0;
     if (r < nr) {
       const int part = r % parts, co = r / parts;
-      int cell = 0, mul = 1, rem = co;
+      int cc[D], rem = co;
       bool ok = true;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        const int cc = ci[a] + (rem % W) - S;
+        cc[a] = ci[a] + (rem % W) - S;
         rem /= W;
-        ok = ok && cc >= 0 && cc < nca;
-        cell += cc * mul;
-        mul *= nca;
+        ok = ok && cc[a] >= 0 && cc[a] < nca;
       }
       if (ok) {
-        const int k = cell + part * ncell;
+        const int k = cell_key<D>(cc, nca) + part * ncell;
         b = cstart[k];
         len = cstart[k + 1] - b;
       }
