@@ -85,7 +85,7 @@ typedef struct {
   int32_t flags;         /* bit set: BGK_FLAG_GENERIC uses the separate transport and
                             relaxation kernels instead of the fused one (for testing);
                             BGK_FLAG_ADJOINT reserves the workspace of
-                            bgk_adjoint_step (needs BGK_FP64 and move = 0)              */
+                            bgk_adjoint_step (needs BGK_FP64 or BGK_FP32, move = 0)     */
   double vmax;           /* velocity grid spans [-vmax, vmax] per axis                   */
   double h;              /* support radius of the Gaussian weight (absolute)             */
   double alpha;          /* weight exp(-alpha r^2/h^2), r <= h (Sec. 3.4.1, eq. weight) */
@@ -208,10 +208,11 @@ int bgk_maxwellian(bgk_ctx* ctx, const double* rho, const double* U, const doubl
  * (q is the kinetic heat flux, the centred third moment of f; the paper
  * defines no objective, this is the functional that the reverse mode below
  * is exercised on).
- * J: device double [1], overwritten.  dJ_df (like f), dJ_drho [N] and
- * dJ_dU [d][N] receive the partial derivatives at fixed (f, rho, U); each
- * may be NULL.  BGK_FP64 only (else BGK_ENOTSUP).  J is summed in a fixed
- * order, so repeated calls give identical bits. */
+ * J: device double [1], overwritten.  dJ_df (like f, in the f storage
+ * type), dJ_drho [N] and dJ_dU [d][N] receive the partial derivatives at
+ * fixed (f, rho, U); each may be NULL.  BGK_FP64 or BGK_FP32 (else
+ * BGK_ENOTSUP); sums are FP64.  J is summed in a fixed order, so repeated
+ * calls give identical bits. */
 int bgk_objective(bgk_ctx* ctx, const void* f, const double* rho, const double* U,
                   double ke_weight, double* J, void* dJ_df, double* dJ_drho, double* dJ_dU);
 
@@ -231,7 +232,9 @@ int bgk_objective(bgk_ctx* ctx, const void* f, const double* rho, const double* 
  * device double [1], accumulated (+=); may be NULL.  |.| terms take the
  * derivative of their + branch at 0.  The transposed stencils make every
  * sum a gather: results are deterministic.  Needs a context created with
- * BGK_FLAG_ADJOINT (BGK_FP64, move = 0), else BGK_ENOTSUP. */
+ * BGK_FLAG_ADJOINT (move = 0), else BGK_ENOTSUP.  f_n, lam_f1 and lam_f
+ * are in the f storage type (FP64, or FP32 with FP64 arithmetic and
+ * reductions inside). */
 int bgk_adjoint_step(bgk_ctx* ctx, const void* f_n, const double* U_n, const double* x,
                      const void* lam_f1, const double* lam_U1, const double* lam_rho1,
                      const double* lam_T1, void* lam_f, double* lam_U, double* dJ_dlid);
@@ -239,7 +242,7 @@ int bgk_adjoint_step(bgk_ctx* ctx, const void* f_n, const double* U_n, const dou
 /* Reverse mode of bgk_moments (Sec. 2 eqs. moments, internal_energy; Chu
  * eq. macroeq): lam_f += (d(rho, U, T)/d f)^T (lam_rho, lam_U, lam_T) at the
  * moments (rho, U, T) of f.  lam_rho, lam_U, lam_T may be NULL (zero).
- * BGK_FP64 only (else BGK_ENOTSUP). */
+ * lam_f in the f storage type; BGK_FP64 or BGK_FP32 (else BGK_ENOTSUP). */
 int bgk_moments_adjoint(bgk_ctx* ctx, const double* rho, const double* U, const double* T,
                         const double* lam_rho, const double* lam_U, const double* lam_T,
                         void* lam_f);

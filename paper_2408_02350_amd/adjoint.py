@@ -29,13 +29,17 @@ def segments(nsteps: int, every: int):
 
 class FrozenCavity:
     """A cavity on one GPU with a frozen cloud, set up for forward and reverse
-    passes (FP64, BGK_FLAG_ADJOINT)."""
+    passes (BGK_FLAG_ADJOINT).  precision: "fp64", or "fp32" for FP32
+    storage of f and of its adjoint (reductions stay FP64)."""
 
-    def __init__(self, cav, device="cuda", seed=None, stream=None, **overrides):
+    def __init__(self, cav, device="cuda", seed=None, stream=None, precision="fp64",
+                 **overrides):
+        if precision not in ("fp64", "fp32"):
+            raise ValueError("the reverse mode runs in fp64 or fp32 storage")
         self.cav = cav
         overrides = dict(overrides)
         overrides.update(move=0, flags=overrides.get("flags", 0) | B.BGK_FLAG_ADJOINT)
-        self.cfg = B.config_from(cav, "fp64", **overrides)
+        self.cfg = B.config_from(cav, precision, **overrides)
         x, wid = cloud_for(cav, seed)
         dev = torch.device(device)
         self.wall_id = torch.from_numpy(wid).to(dev)

@@ -330,14 +330,15 @@ def bgk_maxwellian(ctx: Context, rho, U, T, f_out=None):
 
 
 def bgk_objective(ctx: Context, f, rho, U, ke_weight=1.0, want_grad=True):
-    """J (0-d float64 tensor) and, if want_grad, (dJ_df, dJ_drho, dJ_dU)."""
+    """J (0-d float64 tensor) and, if want_grad, (dJ_df, dJ_drho, dJ_dU);
+    dJ_df has the f storage type."""
     _f(ctx, f, "f")
     _sca(ctx, rho, "rho")
     _vec(ctx, U, "U")
     J = _empty(ctx, (), torch.float64)
     g = None
     if want_grad:
-        g = (_empty(ctx, (ctx.nc, ctx.N, ctx.NV), torch.float64),
+        g = (_empty(ctx, (ctx.nc, ctx.N, ctx.NV), f_dtype(ctx.cfg)),
              _empty(ctx, (ctx.N,), torch.float64), _empty(ctx, (ctx.d, ctx.N), torch.float64))
     gp = g if g is not None else (None, None, None)
     _check(ctx, load_library().bgk_objective(ctx.handle, _ptr(f), _ptr(rho), _ptr(U),

@@ -64,7 +64,7 @@ bool config_ok(const bgk_config& g) {
          (g.wls_degree == 1 || g.wls_degree == 2) && g.max_neighbors >= g.dim + 2 &&
          g.max_neighbors <= 255 && (g.move == 0 || g.move == 1) && g.precision >= BGK_FP64 &&
          g.precision <= BGK_BF16 && (g.flags & ~(BGK_FLAG_GENERIC | BGK_FLAG_ADJOINT)) == 0 &&
-         (!(g.flags & BGK_FLAG_ADJOINT) || (g.precision == BGK_FP64 && g.move == 0)) && g.vmax > 0 && g.h > 0 && g.alpha > 0 &&
+         (!(g.flags & BGK_FLAG_ADJOINT) || (g.precision != BGK_BF16 && g.move == 0)) && g.vmax > 0 && g.h > 0 && g.alpha > 0 &&
          g.kn > 0 && g.dt > 0 && g.wall_T > 0 && g.dx > 0 && std::isfinite(g.lid_velocity) &&
          ipow(g.nv, g.dim) <= INT32_MAX / 4 &&
          static_cast<int64_t>(g.n_particles) * g.max_neighbors * g.dim * g.dim < INT32_MAX;
@@ -90,6 +90,7 @@ size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj) {
   t.cstart = reinterpret_cast<int32_t*>(take((2 * ncell + 1) * 4));
   t.ccursor = reinterpret_cast<int32_t*>(take(2 * ncell * 4));
   t.cperm = reinterpret_cast<int32_t*>(take(N * 4));
+  t.cperm2 = reinterpret_cast<int32_t*>(take(N * 4));
   t.xs = reinterpret_cast<double*>(take(N * D * 8));
   t.ncnt = reinterpret_cast<int32_t*>(take(N * 4));
   t.nidx = reinterpret_cast<int32_t*>(take(N * cap * 4));
@@ -114,13 +115,14 @@ size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj) {
     a.wtstart = reinterpret_cast<int32_t*>(take((N + 1) * 4));
     a.wtcursor = reinterpret_cast<int32_t*>(take(N * 4));
     a.wt = reinterpret_cast<int32_t*>(take(N * cap * 4));
-    a.ft = reinterpret_cast<double*>(take(F * 8));
-    a.lam_ft = reinterpret_cast<double*>(take(F * 8));
+    const int64_t fs = cfg.precision == BGK_FP64 ? 8 : 4;  // f storage
+    a.ft = take(F * fs);
+    a.lam_ft = take(F * fs);
     a.f1 = a.lam_ft;
     a.rho1 = reinterpret_cast<double*>(take(N * 8));
     a.U1 = reinterpret_cast<double*>(take(N * D * 8));
     a.T1 = reinterpret_cast<double*>(take(N * 8));
-    a.larr = reinterpret_cast<double*>(take(F * 8));
+    a.larr = take(F * fs);
     a.lidpart = reinterpret_cast<double*>(take(N * 8));
     if (adj) *adj = a;
   }
@@ -399,10 +401,9 @@ int bgk_objective(bgk_ctx* ctx, const void* f, const double* rho, const double* 
                   double ke_weight, double* J, void* dJ_df, double* dJ_drho, double* dJ_dU) {
   if (!ctx || !f || !rho || !U || !J || !std::isfinite(ke_weight)) return BGK_EINVAL;
   Ctx& c = ctx->c;
-  if (c.cfg.precision != BGK_FP64) return bgk::fail(&c, BGK_ENOTSUP, "bgk_objective needs FP64");
-  return bgk::hip_fail(&c,
-                       bgk::launch_objective(c, static_cast<const double*>(f), rho, U, ke_weight,
-                                             J, static_cast<double*>(dJ_df), dJ_drho, dJ_dU),
+  if (c.cfg.precision == BGK_BF16)
+    return bgk::fail(&c, BGK_ENOTSUP, "bgk_objective needs FP64 or FP32");
+  return bgk::hip_fail(&c, bgk::launch_objective(c, f, rho, U, ke_weight, J, dJ_df, dJ_drho, dJ_dU),
                        "bgk_objective");
 }
 
@@ -422,7 +423,7 @@ int bgk_adjoint_step(bgk_ctx* ctx, const void* f_n, const double* U_n, const dou
   Ctx& c = ctx->c;
   if (!(c.cfg.flags & BGK_FLAG_ADJOINT))
     return bgk::fail(&c, BGK_ENOTSUP, "bgk_adjoint_step needs a context with BGK_FLAG_ADJOINT");
-  const size_t F = sizeof(double) * c.NC * static_cast<size_t>(c.N) * c.NV;
+  const size_t F = (c.cfg.precision == BGK_FP64 ? 8 : 4) * c.NC * static_cast<size_t>(c.N) * c.NV;
   const size_t DN = sizeof(double) * c.D * static_cast<size_t>(c.N), N8 = sizeof(double) * c.N;
   // outputs against every input; lam_f == lam_f1 and lam_U == lam_U1 are allowed
   const void* in[] = {f_n, U_n, x, lam_f1, lam_U1, lam_rho1, lam_T1, dJ_dlid};
@@ -451,9 +452,8 @@ int bgk_adjoint_step(bgk_ctx* ctx, const void* f_n, const double* U_n, const dou
   if (e == hipSuccess) e = bgk::launch_collide(c, a.ft, a.f1, a.rho1, a.U1, a.T1);
   if (e == hipSuccess) e = bgk::launch_wall_bc(c, a.f1, a.rho1, a.U1, a.T1);
   if (e == hipSuccess)
-    e = bgk::launch_adjoint_step(c, static_cast<const double*>(f_n), U_n,
-                                 static_cast<const double*>(lam_f1), lam_U1, lam_rho1, lam_T1,
-                                 static_cast<double*>(lam_f), lam_U, dJ_dlid);
+    e = bgk::launch_adjoint_step(c, f_n, U_n, lam_f1, lam_U1, lam_rho1, lam_T1, lam_f, lam_U,
+                                 dJ_dlid);
   return bgk::hip_fail(&c, e, "bgk_adjoint_step");
 }
 
@@ -462,11 +462,9 @@ int bgk_moments_adjoint(bgk_ctx* ctx, const double* rho, const double* U, const 
                         void* lam_f) {
   if (!ctx || !rho || !U || !T || !lam_f) return BGK_EINVAL;
   Ctx& c = ctx->c;
-  if (c.cfg.precision != BGK_FP64)
-    return bgk::fail(&c, BGK_ENOTSUP, "bgk_moments_adjoint needs FP64");
-  return bgk::hip_fail(&c,
-                       bgk::launch_moments_adjoint(c, rho, U, T, lam_rho, lam_U, lam_T,
-                                                   static_cast<double*>(lam_f)),
+  if (c.cfg.precision == BGK_BF16)
+    return bgk::fail(&c, BGK_ENOTSUP, "bgk_moments_adjoint needs FP64 or FP32");
+  return bgk::hip_fail(&c, bgk::launch_moments_adjoint(c, rho, U, T, lam_rho, lam_U, lam_T, lam_f),
                        "bgk_moments_adjoint");
 }
 

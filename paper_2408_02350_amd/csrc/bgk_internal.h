@@ -33,6 +33,7 @@ struct Dev {
   int32_t* cstart;       // [2*ncell + 1] start of each (cell, interior|wall) range
   int32_t* ccursor;      // [2*ncell]
   int32_t* cperm;        // [N]   particles sorted by key; first Ni are interior
+  int32_t* cperm2;       // [N]   the same, unordered inside each key (scatter output)
   double* xs;            // [d][N] positions in cperm order
   int32_t* ncnt;         // [N]
   int32_t* nidx;         // [N][cap]
@@ -54,13 +55,13 @@ struct Adj {
   int32_t* wtstart;   // [N+1]     start of particle j's wall-stencil uses
   int32_t* wtcursor;  // [N]
   int32_t* wt;        // [Nw*cap]  uses of j as (wall list index << 8 | slot), sorted
-  double* ft;         // [n_c][N][N_v] recomputed f-tilde
-  double* f1;         // [n_c][N][N_v] recomputed f^{n+1}; storage shared with lam_ft
-  double* lam_ft;     // [n_c][N][N_v] adjoint of f-tilde (interior rows)
+  void* ft;           // [n_c][N][N_v] recomputed f-tilde (f storage type)
+  void* f1;           // [n_c][N][N_v] recomputed f^{n+1}; storage shared with lam_ft
+  void* lam_ft;       // [n_c][N][N_v] adjoint of f-tilde (interior rows)
   double* rho1;       // [N]
   double* U1;         // [d][N]
   double* T1;         // [N]
-  double* larr;       // [Nw][n_c][N_v] adjoint reaching the interpolated wall values
+  void* larr;         // [Nw][n_c][N_v] adjoint reaching the interpolated wall values
   double* lidpart;    // [max(Nw,1)]
 };
 
@@ -119,15 +120,16 @@ hipError_t launch_maxwellian(const Ctx& c, const double* rho, const double* U, c
 
 // Reverse mode (FP64, frozen cloud).
 hipError_t launch_adjoint_transposes(const Ctx& c);
-hipError_t launch_adjoint_step(const Ctx& c, const double* f_n, const double* U_n,
-                               const double* lam_f1, const double* lam_U1, const double* lam_rho1,
-                               const double* lam_T1, double* lam_f, double* lam_U,
+// f-sized arguments (f_n, lam_f1, lam_f, dJ_df) are in the f storage type.
+hipError_t launch_adjoint_step(const Ctx& c, const void* f_n, const double* U_n,
+                               const void* lam_f1, const double* lam_U1, const double* lam_rho1,
+                               const double* lam_T1, void* lam_f, double* lam_U,
                                double* dJ_dlid);
-hipError_t launch_objective(const Ctx& c, const double* f, const double* rho, const double* U,
-                            double ke, double* J, double* dJ_df, double* dJ_drho, double* dJ_dU);
+hipError_t launch_objective(const Ctx& c, const void* f, const double* rho, const double* U,
+                            double ke, double* J, void* dJ_df, double* dJ_drho, double* dJ_dU);
 hipError_t launch_moments_adjoint(const Ctx& c, const double* rho, const double* U,
                                   const double* T, const double* lr, const double* lU,
-                                  const double* lT, double* lam_f);
+                                  const double* lT, void* lam_f);
 
 }  // namespace bgk
 

@@ -16,6 +16,8 @@
 // on the adjoint fields and the result is deterministic.  Reductions are
 // FP64 in a fixed order.  Derivatives of |.| at 0 follow the + branch
 // (c_ij = 2 sum_k min(0, p_k): d/dp = 1 only for p < 0).
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace bgk {
@@ -98,7 +100,8 @@ __device__ __forceinline__ double mom_adj(int c, const double* v, double omega, 
   return g + lT * (w2 / (3.0 * s0) - T / s0);
 }
 
-struct AdjArgs {
+template <typename Real>
+struct AdjArgs {  // Real: storage of f-sized arrays and operators (FP64 or FP32)
   int N, NV, nv, cap, Nw, Ni, D;
   double vmax, omega, kn, dt, lid, wall_T;
   const int32_t* wall_id;
@@ -107,33 +110,33 @@ struct AdjArgs {
   const int32_t* ncnt;
   const int32_t* nidx;
   const int32_t* tidx;
-  const double* ops;
+  const Real* ops;
   const int32_t* wcnt;
   const int32_t* widx;
   const double* wc0;
   const int32_t* wtstart;
   const int32_t* wt;
-  const double* f_n;       // state n
+  const Real* f_n;       // state n
   const double* U_n;
-  const double* ft;        // recomputed f-tilde (interior rows)
-  const double* f1;        // recomputed f^{n+1} (all rows)
+  const Real* ft;        // recomputed f-tilde (interior rows)
+  const Real* f1;        // recomputed f^{n+1} (all rows)
   const double* rho1;      // recomputed outputs
   const double* U1;
   const double* T1;
-  const double* lam_f1;    // adjoint of f^{n+1}
+  const Real* lam_f1;    // adjoint of f^{n+1}
   const double* lam_U1;    // adjoint of U^{n+1} (nullable)
   const double* lam_rho1;  // (nullable)
   const double* lam_T1;    // (nullable)
-  double* larr;            // [Nw][NC][NV] adjoint reaching the interpolated (arriving) half
-  double* lam_ft;          // [NC][N][NV]
-  double* lam_f;           // out: adjoint of f^n
+  Real* larr;            // [Nw][NC][NV] adjoint reaching the interpolated (arriving) half
+  Real* lam_ft;          // [NC][N][NV]
+  Real* lam_f;           // out: adjoint of f^n
   double* lam_U;           // out: adjoint of U^n
   double* lidpart;         // [Nw] dJ/dlid contributions
 };
 
 // ------------------------------------------------------------ S7 adjoint
-template <int D, int NC>
-__global__ __launch_bounds__(kThreads) void k_adj_wall(const AdjArgs a) {
+template <int D, int NC, typename Real>
+__global__ __launch_bounds__(kThreads) void k_adj_wall(const AdjArgs<Real> a) {
   __shared__ double sh[4 * 4];
   const int k = blockIdx.x;
   const int b = a.wall_list[k];
@@ -143,8 +146,8 @@ __global__ __launch_bounds__(kThreads) void k_adj_wall(const AdjArgs a) {
   const bool is_lid = (w == 2 * D);
   double Uw[3] = {is_lid ? a.lid : 0.0, 0.0, 0.0};
   const size_t NVs = a.NV, cs = static_cast<size_t>(a.N) * NVs;
-  const double* fb = a.f1 + static_cast<size_t>(b) * NVs;
-  const double* lb = a.lam_f1 + static_cast<size_t>(b) * NVs;
+  const Real* fb = a.f1 + static_cast<size_t>(b) * NVs;
+  const Real* lb = a.lam_f1 + static_cast<size_t>(b) * NVs;
   const double rho = a.rho1[b], T = a.T1[b];
   double U[3] = {0.0, 0.0, 0.0}, lU[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -184,7 +187,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_wall(const AdjArgs a) {
   const double Fin = acc[0], Fout = acc[1], grw = acc[2];
   const double rho_w = Fin / Fout;
   // pass 2: adjoint on the arriving (interpolated) half
-  double* lo = a.larr + static_cast<size_t>(k) * NC * NVs;
+  Real* lo = a.larr + static_cast<size_t>(k) * NC * NVs;
   for (int q = threadIdx.x; q < a.NV; q += kThreads) {
     double v[3];
     velocity_of<D>(q, a.nv, a.vmax, v);
@@ -196,7 +199,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_wall(const AdjArgs a) {
         l = lb[c * cs + q] + mom_adj<D, NC>(c, v, a.omega, s0, U, T, lr, lU, lT);
         if (c == 0) l = l + grw * (-vn) / Fout;
       }
-      lo[c * NVs + q] = l;
+      lo[c * NVs + q] = static_cast<Real>(l);
     }
   }
   if (threadIdx.x == 0)
@@ -204,8 +207,8 @@ __global__ __launch_bounds__(kThreads) void k_adj_wall(const AdjArgs a) {
 }
 
 // ------------------------------------------------------------ S5-S6 adjoint
-template <int D, int NC>
-__global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs a) {
+template <int D, int NC, typename Real>
+__global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a) {
   __shared__ double sh[4 * (D + 4)];
   const int i = a.plist[blockIdx.x];
   const size_t NVs = a.NV, cs = static_cast<size_t>(a.N) * NVs;
@@ -268,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs a) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const double l = ca * lam_fp(c, q) + mom_adj<D, NC>(c, v, a.omega, s0, U, T, g_rho, gU, g_T);
-      a.lam_ft[c * cs + static_cast<size_t>(i) * NVs + q] = l;
+      a.lam_ft[c * cs + static_cast<size_t>(i) * NVs + q] = static_cast<Real>(l);
     }
   }
 }
@@ -278,21 +281,21 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs a) {
 //   lam_f_j = [j interior] lam_ft_j (1 + dt sum_k c_jk)
 //             - dt sum_{i in N_j interior, i != j} c_ij lam_ft_i
 //   lam_U_j = -dt sum_v lam_ft_j . sum_k dc_jk/dU (f_k - f_j)   (interior)
-template <int D>
-__device__ __forceinline__ double cij(const double* o, const double* v, const double* U) {
+template <int D, typename O>
+__device__ __forceinline__ double cij(const O* o, const double* v, const double* U) {
   double c = 0.0;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     double p = 0.0;
 #pragma unroll
-    for (int m = 0; m < D; ++m) p = p + o[k * D + m] * (v[m] - U[m]);
+    for (int m = 0; m < D; ++m) p = p + static_cast<double>(o[k * D + m]) * (v[m] - U[m]);
     c = c + fmin(p, 0.0);
   }
   return 2.0 * c;
 }
 
-template <int D, int NC>
-__global__ __launch_bounds__(kThreads) void k_adj_transport(const AdjArgs a) {
+template <int D, int NC, typename Real>
+__global__ __launch_bounds__(kThreads) void k_adj_transport(const AdjArgs<Real> a) {
   constexpr int DD = D * D;
   __shared__ double sh[4 * 3];
   const int j = blockIdx.x;
@@ -320,17 +323,17 @@ __global__ __launch_bounds__(kThreads) void k_adj_transport(const AdjArgs a) {
       if (i == j) continue;
       if (inner) {
         // own transport: c_jk with k = i, and dc_jk/dU_j
-        const double* o = a.ops + (row + e) * DD;
+        const Real* o = a.ops + (row + e) * DD;
         double c = 0.0, dcdU[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int kk = 0; kk < D; ++kk) {
           double p = 0.0;
 #pragma unroll
-          for (int mm = 0; mm < D; ++mm) p = p + o[kk * D + mm] * (v[mm] - Uj[mm]);
+          for (int mm = 0; mm < D; ++mm) p = p + static_cast<double>(o[kk * D + mm]) * (v[mm] - Uj[mm]);
           c = c + fmin(p, 0.0);
           if (p < 0.0) {
 #pragma unroll
-            for (int mm = 0; mm < D; ++mm) dcdU[mm] = dcdU[mm] - 2.0 * o[kk * D + mm];
+            for (int mm = 0; mm < D; ++mm) dcdU[mm] = dcdU[mm] - 2.0 * static_cast<double>(o[kk * D + mm]);
           }
         }
         csum = csum + 2.0 * c;
@@ -357,7 +360,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_transport(const AdjArgs a) {
     for (int c = 0; c < NC; ++c) {
       double l = lf[c];
       if (inner) l = l + lj[c] * (1.0 + a.dt * csum);
-      a.lam_f[c * cs + static_cast<size_t>(j) * NVs + q] = l;
+      a.lam_f[c * cs + static_cast<size_t>(j) * NVs + q] = static_cast<Real>(l);
     }
   }
   double r[3] = {gU[0], gU[1], gU[2]};
@@ -373,15 +376,15 @@ __global__ __launch_bounds__(kThreads) void k_adj_transport(const AdjArgs a) {
 // J = dx^(d-1) sum_{lid b} q_n(b) + (ke/N) sum_i rho_i |U_i|^2 / 2,
 // q_n = omega/2 sum_v (v_n - U_n)(|v-U|^2 f1 [+ f2]), n = last axis.
 // Block per particle: its term of J into part[i] and its gradient rows.
-template <int D, int NC>
+template <int D, int NC, typename Real>
 __global__ __launch_bounds__(kThreads) void k_objective(int N, int NV, int nv, double vmax,
                                                          double hw, double ke,
                                                          const int32_t* __restrict__ wall_id,
-                                                         const double* __restrict__ f,
+                                                         const Real* __restrict__ f,
                                                          const double* __restrict__ rho,
                                                          const double* __restrict__ U,
                                                          double* __restrict__ part,
-                                                         double* __restrict__ dJ_df,
+                                                         Real* __restrict__ dJ_df,
                                                          double* __restrict__ dJ_drho,
                                                          double* __restrict__ dJ_dU) {
   __shared__ double sh[4 * (D + 1)];
@@ -404,9 +407,9 @@ __global__ __launch_bounds__(kThreads) void k_objective(int N, int NV, int nv, d
 #pragma unroll
       for (int a = 0; a < D; ++a) w2 = w2 + (v[a] - Ui[a]) * (v[a] - Ui[a]);
       const double wn = v[an] - Ui[an];
-      const double f1 = f[static_cast<size_t>(i) * NVs + q];
+      const double f1 = static_cast<double>(f[static_cast<size_t>(i) * NVs + q]);
       double e = w2 * f1;
-      if (NC == 2) e = e + f[cs + static_cast<size_t>(i) * NVs + q];
+      if (NC == 2) e = e + static_cast<double>(f[cs + static_cast<size_t>(i) * NVs + q]);
       s[0] = s[0] + wn * e;
 #pragma unroll
       for (int a = 0; a < D; ++a) s[1 + a] = s[1 + a] - 2.0 * wn * (v[a] - Ui[a]) * f1;
@@ -415,8 +418,8 @@ __global__ __launch_bounds__(kThreads) void k_objective(int N, int NV, int nv, d
       g1 = hw * wn;
     }
     if (dJ_df) {
-      dJ_df[static_cast<size_t>(i) * NVs + q] = g0;
-      if (NC == 2) dJ_df[cs + static_cast<size_t>(i) * NVs + q] = g1;
+      dJ_df[static_cast<size_t>(i) * NVs + q] = static_cast<Real>(g0);
+      if (NC == 2) dJ_df[cs + static_cast<size_t>(i) * NVs + q] = static_cast<Real>(g1);
     }
   }
   if (on_lid) block_sum<D + 1>(s, sh);
@@ -446,7 +449,7 @@ __global__ __launch_bounds__(kThreads) void k_sum_fixed(int n, const double* __r
 }
 
 // lam_f += moments^T(lam_rho, lam_U, lam_T) for every particle.
-template <int D, int NC>
+template <int D, int NC, typename Real>
 __global__ __launch_bounds__(kThreads) void k_moments_adj(int N, int NV, int nv, double vmax,
                                                            double omega,
                                                            const double* __restrict__ rho,
@@ -455,7 +458,7 @@ __global__ __launch_bounds__(kThreads) void k_moments_adj(int N, int NV, int nv,
                                                            const double* __restrict__ lr,
                                                            const double* __restrict__ lU,
                                                            const double* __restrict__ lT,
-                                                           double* __restrict__ lam_f) {
+                                                           Real* __restrict__ lam_f) {
   const int i = blockIdx.x;
   const size_t NVs = NV, cs = static_cast<size_t>(N) * NVs;
   double Ui[3] = {0.0, 0.0, 0.0}, lUi[3] = {0.0, 0.0, 0.0};
@@ -469,9 +472,11 @@ __global__ __launch_bounds__(kThreads) void k_moments_adj(int N, int NV, int nv,
     double v[3];
     velocity_of<D>(q, nv, vmax, v);
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-      lam_f[c * cs + static_cast<size_t>(i) * NVs + q] +=
-          mom_adj<D, NC>(c, v, omega, s0, Ui, T[i], lri, lUi, lTi);
+    for (int c = 0; c < NC; ++c) {
+      Real& o = lam_f[c * cs + static_cast<size_t>(i) * NVs + q];
+      o = static_cast<Real>(static_cast<double>(o) +
+                            mom_adj<D, NC>(c, v, omega, s0, Ui, T[i], lri, lUi, lTi));
+    }
   }
 }
 
@@ -504,59 +509,98 @@ hipError_t launch_adjoint_transposes(const Ctx& c) {
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_step(const Ctx& c, const double* f_n, const double* U_n,
-                               const double* lam_f1, const double* lam_U1, const double* lam_rho1,
-                               const double* lam_T1, double* lam_f, double* lam_U,
-                               double* dJ_dlid) {
+template <typename Real>
+static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_n,
+                                 const Real* lam_f1, const double* lam_U1, const double* lam_rho1,
+                                 const double* lam_T1, Real* lam_f, double* lam_U,
+                                 double* dJ_dlid) {
   const Adj& j = c.adj;
-  AdjArgs a{c.N,        c.NV,        c.cfg.nv,   c.cap,      c.Nw,     c.Ni,     c.D,
-            c.cfg.vmax, omega_adj(c.cfg), c.cfg.kn, c.cfg.dt, c.lid, c.cfg.wall_T,
-            c.d.wall_id, c.d.wall_list, c.d.cperm, c.d.ncnt, c.d.nidx, j.tidx, c.d.ops64,
-            c.d.wcnt,   c.d.widx,    c.d.wc0,    j.wtstart,  j.wt,     f_n,      U_n,
-            j.ft,       j.f1,        j.rho1,     j.U1,       j.T1,     lam_f1,   lam_U1,
-            lam_rho1,   lam_T1,      j.larr,     j.lam_ft,   lam_f,    lam_U,    j.lidpart};
+  const Real* ops = std::is_same<Real, double>::value
+                        ? reinterpret_cast<const Real*>(c.d.ops64)
+                        : reinterpret_cast<const Real*>(c.d.ops32);
+  AdjArgs<Real> a{c.N,        c.NV,       c.cfg.nv,   c.cap,       c.Nw,     c.Ni,     c.D,
+                  c.cfg.vmax, omega_adj(c.cfg), c.cfg.kn, c.cfg.dt,  c.lid,    c.cfg.wall_T,
+                  c.d.wall_id, c.d.wall_list, c.d.cperm, c.d.ncnt, c.d.nidx, j.tidx, ops,
+                  c.d.wcnt,   c.d.widx,   c.d.wc0,    j.wtstart,   j.wt,     f_n,      U_n,
+                  static_cast<const Real*>(j.ft), static_cast<const Real*>(j.f1), j.rho1, j.U1,
+                  j.T1,       lam_f1,     lam_U1,     lam_rho1,    lam_T1,
+                  static_cast<Real*>(j.larr), static_cast<Real*>(j.lam_ft), lam_f, lam_U,
+                  j.lidpart};
   dim3 t(kThreads);
   if (c.D == 2) {
-    if (c.Nw) hipLaunchKernelGGL((k_adj_wall<2, 2>), dim3(c.Nw), t, 0, c.stream, a);
-    if (c.Ni) hipLaunchKernelGGL((k_adj_collide<2, 2>), dim3(c.Ni), t, 0, c.stream, a);
-    hipLaunchKernelGGL((k_adj_transport<2, 2>), dim3(c.N), t, 0, c.stream, a);
+    if (c.Nw) hipLaunchKernelGGL((k_adj_wall<2, 2, Real>), dim3(c.Nw), t, 0, c.stream, a);
+    if (c.Ni) hipLaunchKernelGGL((k_adj_collide<2, 2, Real>), dim3(c.Ni), t, 0, c.stream, a);
+    hipLaunchKernelGGL((k_adj_transport<2, 2, Real>), dim3(c.N), t, 0, c.stream, a);
   } else {
-    if (c.Nw) hipLaunchKernelGGL((k_adj_wall<3, 1>), dim3(c.Nw), t, 0, c.stream, a);
-    if (c.Ni) hipLaunchKernelGGL((k_adj_collide<3, 1>), dim3(c.Ni), t, 0, c.stream, a);
-    hipLaunchKernelGGL((k_adj_transport<3, 1>), dim3(c.N), t, 0, c.stream, a);
+    if (c.Nw) hipLaunchKernelGGL((k_adj_wall<3, 1, Real>), dim3(c.Nw), t, 0, c.stream, a);
+    if (c.Ni) hipLaunchKernelGGL((k_adj_collide<3, 1, Real>), dim3(c.Ni), t, 0, c.stream, a);
+    hipLaunchKernelGGL((k_adj_transport<3, 1, Real>), dim3(c.N), t, 0, c.stream, a);
   }
   if (c.Nw && dJ_dlid)
     hipLaunchKernelGGL(k_sum_fixed, dim3(1), t, 0, c.stream, c.Nw, j.lidpart, dJ_dlid, 1);
   return hipGetLastError();
 }
 
-hipError_t launch_objective(const Ctx& c, const double* f, const double* rho, const double* U,
-                            double ke, double* J, double* dJ_df, double* dJ_drho, double* dJ_dU) {
+hipError_t launch_adjoint_step(const Ctx& c, const void* f_n, const double* U_n,
+                               const void* lam_f1, const double* lam_U1, const double* lam_rho1,
+                               const double* lam_T1, void* lam_f, double* lam_U,
+                               double* dJ_dlid) {
+  if (c.cfg.precision == BGK_FP64)
+    return adjoint_step_t<double>(c, static_cast<const double*>(f_n), U_n,
+                                  static_cast<const double*>(lam_f1), lam_U1, lam_rho1, lam_T1,
+                                  static_cast<double*>(lam_f), lam_U, dJ_dlid);
+  return adjoint_step_t<float>(c, static_cast<const float*>(f_n), U_n,
+                               static_cast<const float*>(lam_f1), lam_U1, lam_rho1, lam_T1,
+                               static_cast<float*>(lam_f), lam_U, dJ_dlid);
+}
+
+template <typename Real>
+static void objective_t(const Ctx& c, const Real* f, const double* rho, const double* U,
+                        double hw, double ke, double* dJ_drho, double* dJ_dU, Real* dJ_df) {
+  if (c.D == 2)
+    hipLaunchKernelGGL((k_objective<2, 2, Real>), dim3(c.N), dim3(kThreads), 0, c.stream, c.N,
+                       c.NV, c.cfg.nv, c.cfg.vmax, hw, ke, c.d.wall_id, f, rho, U, c.d.jpart,
+                       dJ_df, dJ_drho, dJ_dU);
+  else
+    hipLaunchKernelGGL((k_objective<3, 1, Real>), dim3(c.N), dim3(kThreads), 0, c.stream, c.N,
+                       c.NV, c.cfg.nv, c.cfg.vmax, hw, ke, c.d.wall_id, f, rho, U, c.d.jpart,
+                       dJ_df, dJ_drho, dJ_dU);
+}
+
+hipError_t launch_objective(const Ctx& c, const void* f, const double* rho, const double* U,
+                            double ke, double* J, void* dJ_df, double* dJ_drho, double* dJ_dU) {
   double area = 1.0;
   for (int k = 0; k < c.D - 1; ++k) area = area * c.cfg.dx;
   const double hw = 0.5 * omega_adj(c.cfg) * area;
-  if (c.D == 2)
-    hipLaunchKernelGGL((k_objective<2, 2>), dim3(c.N), dim3(kThreads), 0, c.stream, c.N, c.NV,
-                       c.cfg.nv, c.cfg.vmax, hw, ke, c.d.wall_id, f, rho, U, c.d.jpart, dJ_df,
-                       dJ_drho, dJ_dU);
+  if (c.cfg.precision == BGK_FP64)
+    objective_t<double>(c, static_cast<const double*>(f), rho, U, hw, ke, dJ_drho, dJ_dU,
+                        static_cast<double*>(dJ_df));
   else
-    hipLaunchKernelGGL((k_objective<3, 1>), dim3(c.N), dim3(kThreads), 0, c.stream, c.N, c.NV,
-                       c.cfg.nv, c.cfg.vmax, hw, ke, c.d.wall_id, f, rho, U, c.d.jpart, dJ_df,
-                       dJ_drho, dJ_dU);
+    objective_t<float>(c, static_cast<const float*>(f), rho, U, hw, ke, dJ_drho, dJ_dU,
+                       static_cast<float*>(dJ_df));
   hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(kThreads), 0, c.stream, c.N, c.d.jpart, J, 0);
   return hipGetLastError();
 }
 
-hipError_t launch_moments_adjoint(const Ctx& c, const double* rho, const double* U,
-                                  const double* T, const double* lr, const double* lU,
-                                  const double* lT, double* lam_f) {
+template <typename Real>
+static void moments_adjoint_t(const Ctx& c, const double* rho, const double* U, const double* T,
+                              const double* lr, const double* lU, const double* lT, Real* lam_f) {
   const double om = omega_adj(c.cfg);
   if (c.D == 2)
-    hipLaunchKernelGGL((k_moments_adj<2, 2>), dim3(c.N), dim3(kThreads), 0, c.stream, c.N, c.NV,
-                       c.cfg.nv, c.cfg.vmax, om, rho, U, T, lr, lU, lT, lam_f);
+    hipLaunchKernelGGL((k_moments_adj<2, 2, Real>), dim3(c.N), dim3(kThreads), 0, c.stream, c.N,
+                       c.NV, c.cfg.nv, c.cfg.vmax, om, rho, U, T, lr, lU, lT, lam_f);
   else
-    hipLaunchKernelGGL((k_moments_adj<3, 1>), dim3(c.N), dim3(kThreads), 0, c.stream, c.N, c.NV,
-                       c.cfg.nv, c.cfg.vmax, om, rho, U, T, lr, lU, lT, lam_f);
+    hipLaunchKernelGGL((k_moments_adj<3, 1, Real>), dim3(c.N), dim3(kThreads), 0, c.stream, c.N,
+                       c.NV, c.cfg.nv, c.cfg.vmax, om, rho, U, T, lr, lU, lT, lam_f);
+}
+
+hipError_t launch_moments_adjoint(const Ctx& c, const double* rho, const double* U,
+                                  const double* T, const double* lr, const double* lU,
+                                  const double* lT, void* lam_f) {
+  if (c.cfg.precision == BGK_FP64)
+    moments_adjoint_t<double>(c, rho, U, T, lr, lU, lT, static_cast<double*>(lam_f));
+  else
+    moments_adjoint_t<float>(c, rho, U, T, lr, lU, lT, static_cast<float*>(lam_f));
   return hipGetLastError();
 }
 

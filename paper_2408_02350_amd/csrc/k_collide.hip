@@ -6,6 +6,8 @@
 // written by itself (no cross-thread hazards inside a block).  Moment sums
 // are FP64 in every precision mode, reduced in a fixed order (wavefront
 // butterflies, then the four waves in order), so results are deterministic.
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace bgk {
@@ -136,15 +138,42 @@ struct WallBcArgs {
   int32_t* err;
 };
 
-// Diffuse reflection on wall particle b (one block): arriving velocities
-// (v.n <= 0, n the inward normal) take the interpolated interior value
-// sum_e c0_e f_j; emitted ones take rho_w M[1, U_w, T_w] (Chu: G1 and
-// T_w G1 scaled by rho_w) with rho_w from zero net mass flux; then the
-// particle's moments.
+// Sum K doubles over a block of nw wavefronts in a fixed order (wavefront
+// butterflies, then the waves in order); every thread receives the totals.
+// sh must hold 16*K doubles.
+template <int K>
+__device__ __forceinline__ void block_sum_n(double (&v)[K], double* sh, int nw) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[wid * K + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s = s + sh[w * K + k];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+// Diffuse reflection on wall particle b (one block of up to 1024 threads):
+// arriving velocities (v.n <= 0, n the inward normal) take the interpolated
+// interior value sum_e c0_e f_j; emitted ones take rho_w M[1, U_w, T_w]
+// (Chu: G1 and T_w G1 scaled by rho_w) with rho_w from zero net mass flux;
+// then the particle's moments in two passes (U first, then the centred
+// second moment).  Each thread re-reads only the velocities it wrote itself.
 template <int D, int NC, typename Real>
-__global__ __launch_bounds__(kThreads) void k_wall_bc(const WallBcArgs a) {
-  __shared__ double sh[4 * (D + 1)];
+__global__ __launch_bounds__(1024) void k_wall_bc(const WallBcArgs a) {
+  __shared__ double sh[16 * (D + 1)];
   const int k = blockIdx.x;
+  const int nw = blockDim.x >> 6;
   const int b = a.wall_list[k];
   const int w = a.wall_id[b];
   const int axis = (w - 1) / 2;
@@ -158,7 +187,7 @@ __global__ __launch_bounds__(kThreads) void k_wall_bc(const WallBcArgs a) {
   Real* f = static_cast<Real*>(a.f);
   Real* fb = f + static_cast<size_t>(b) * NVs;
   double flux[2] = {0.0, 0.0};
-  for (int q = threadIdx.x; q < a.NV; q += kThreads) {
+  for (int q = threadIdx.x; q < a.NV; q += blockDim.x) {
     double v[3];
     velocity_of<D>(q, a.nv, a.vmax, v);
     const double vn = sgn * v[axis];
@@ -176,21 +205,52 @@ __global__ __launch_bounds__(kThreads) void k_wall_bc(const WallBcArgs a) {
       flux[1] = flux[1] + vn * maxwell<D>(0, 1.0, Uw, a.wall_T, v);
     }
   }
-  block_sum<2>(flux, sh);
+  block_sum_n<2>(flux, sh, nw);
   const double rho_w = flux[0] / flux[1];
-  for (int q = threadIdx.x; q < a.NV; q += kThreads) {
+  double sm[D + 1];
+#pragma unroll
+  for (int kk = 0; kk < D + 1; ++kk) sm[kk] = 0.0;
+  for (int q = threadIdx.x; q < a.NV; q += blockDim.x) {
     double v[3];
     velocity_of<D>(q, a.nv, a.vmax, v);
     const double vn = sgn * v[axis];
+    double x0;
     if (vn > 0.0) {
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        fb[c * cs + q] = static_cast<Real>(maxwell<D>(c, rho_w, Uw, a.wall_T, v));
+      for (int c = 0; c < NC; ++c) {
+        const Real y = static_cast<Real>(maxwell<D>(c, rho_w, Uw, a.wall_T, v));
+        fb[c * cs + q] = y;
+        if (c == 0) x0 = static_cast<double>(y);
+      }
+    } else {
+      x0 = static_cast<double>(fb[q]);
     }
+    sm[0] = sm[0] + x0;
+#pragma unroll
+    for (int kk = 0; kk < D; ++kk) sm[1 + kk] = sm[1 + kk] + v[kk] * x0;
   }
-  double rho, U[3] = {0.0, 0.0, 0.0}, T;
-  row_moments<D, NC, Real>(fb, cs, a.NV, a.nv, a.vmax, a.omega, sh, rho, U, T);
+  block_sum_n<D + 1>(sm, sh, nw);
+  const double s0 = sm[0];
+  double U[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < D; ++kk) U[kk] = sm[1 + kk] / s0;
+  double e[1] = {0.0};
+  for (int q = threadIdx.x; q < a.NV; q += blockDim.x) {
+    double v[3];
+    velocity_of<D>(q, a.nv, a.vmax, v);
+    double w2 = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < D; ++kk) {
+      const double wk = v[kk] - U[kk];
+      w2 = w2 + wk * wk;
+    }
+    e[0] = e[0] + w2 * static_cast<double>(fb[q]);
+    if (NC == 2) e[0] = e[0] + static_cast<double>(fb[cs + q]);
+  }
+  block_sum_n<1>(e, sh, nw);
   if (threadIdx.x == 0) {
+    const double rho = a.omega * s0;
+    const double T = e[0] / (3.0 * s0);
     a.rho[b] = rho;
     a.T[b] = T;
 #pragma unroll
@@ -205,7 +265,7 @@ hipError_t launch_wall_bc(const Ctx& c, void* f, double* rho, double* U, double*
                omega_of(c.cfg), c.lid,  c.cfg.wall_T,  c.d.wall_list, c.d.wall_id, c.d.wcnt,
                c.d.widx,     c.d.wc0,   f,             rho,    U,      T,      c.d.err};
   const bool f64 = c.cfg.precision == BGK_FP64;
-  dim3 g(c.Nw), t(kThreads);
+  dim3 g(c.Nw), t(std::min(1024, (c.NV + 63) / 64 * 64));
   if (c.D == 2) {
     if (f64) hipLaunchKernelGGL((k_wall_bc<2, 2, double>), g, t, 0, c.stream, a);
     else hipLaunchKernelGGL((k_wall_bc<2, 2, float>), g, t, 0, c.stream, a);

@@ -21,8 +21,9 @@
 // ft = f_i (1 + dt C) - dt A.  (In the BF16-operand mode the products are
 // taken of the differences f_j - f_i instead, which keeps the BF16 rounding
 // proportional to the differences.)  After the walk ft stays in registers:
-// the moment sums are reduced in one pass and a fixed order (a wavefront
-// reduce-scatter, then the waves in order), the Maxwellian is the product of
+// the moments are summed in two passes (U first, then the centred second
+// moment), each reduced in a fixed order (a wavefront reduce-scatter, then
+// the waves in order), the Maxwellian is the product of
 // per-axis exponentials (d*nv exp per particle instead of N_v), and f^{n+1}
 // is written once.
 //
@@ -150,13 +151,14 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   constexpr int TP = kPatch, DD = D * D;
   constexpr bool DIFF = (MODE == BGK_BF16);     // products of differences
   constexpr int REC = DD + 2 * D;               // a_k (d*d), a_k.U (d), a_k[fast]*dvs (d)
-  constexpr int KM = TP * (D + 2);              // moment sums per thread
+  constexpr int KM = TP * (D + 1);              // first-pass moment sums per thread
   constexpr int KP = pow2_at_least(KM);
+  constexpr int KP2 = pow2_at_least(TP);         // second pass: one sum per particle
   __shared__ Real lrec[kChunk][TP][REC];
   __shared__ int32_t luj[kChunk];
   __shared__ uint32_t lmask[kChunk];
   __shared__ double vtab[kMaxNv];
-  __shared__ double red[16][KP];
+  __shared__ double red[16][KP > KP2 ? KP : KP2];
   __shared__ double etab[TP][D][kMaxNv];
   __shared__ double pstat[TP][D + 5];           // rho, U[d], T, norm, a, b
 
@@ -395,30 +397,23 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
     return;
   } else {
     const int lane = tid & 63, wid = tid >> 6, nw = nthreads >> 6;
-    // ---- S5 in one pass (FP64): s0 = sum f1, s1 = sum v f1,
-    //      s2 = sum |v|^2 f1 (+ sum f2); then U = s1/s0 and
-    //      3 T = s2/s0 - |U|^2
+    // ---- S5 pass 1 (FP64): s0 = sum f1, s1 = sum v f1
     double sm[KP];
 #pragma unroll
     for (int k = 0; k < KP; ++k) sm[k] = 0.0;
     if (lane_on) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        double v[D], v2 = 0.0;
+        double v[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-          v[k] = vtab[k == 0 ? kq[0] + r : kq[k]];
-          v2 = v2 + v[k] * v[k];
-        }
+        for (int k = 0; k < D; ++k) v[k] = vtab[k == 0 ? kq[0] + r : kq[k]];
 #pragma unroll
         for (int t = 0; t < TP; ++t) {
           const double x = static_cast<double>(ft[t][r][0]);
-          double* st = sm + t * (D + 2);
+          double* st = sm + t * (D + 1);
           st[0] = st[0] + x;
 #pragma unroll
           for (int k = 0; k < D; ++k) st[1 + k] = st[1 + k] + v[k] * x;
-          st[D + 1] = st[D + 1] + v2 * x;
-          if (NC == 2) st[D + 1] = st[D + 1] + static_cast<double>(ft[t][r][NC - 1]);
         }
       }
     }
@@ -434,18 +429,49 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
       red[0][tid] = s;  // only wave 0's slot is overwritten after all reads
     }
     __syncthreads();
+    if (tid < TP) {  // s0 and U of each particle (red is reused below)
+      const double s0 = red[0][tid * (D + 1)];
+      pstat[tid][0] = s0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) pstat[tid][1 + k] = red[0][tid * (D + 1) + 1 + k] / s0;
+    }
+    __syncthreads();
+    // ---- S5 pass 2: 3 rho T = sum |v-U|^2 f1 (+ sum f2), U from pass 1
+    double se[KP2];
+#pragma unroll
+    for (int t = 0; t < KP2; ++t) se[t] = 0.0;
+    if (lane_on) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double v[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) v[k] = vtab[k == 0 ? kq[0] + r : kq[k]];
+#pragma unroll
+        for (int t = 0; t < TP; ++t) {
+          double w2 = 0.0;
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            const double wk = v[k] - pstat[t][1 + k];
+            w2 = w2 + wk * wk;
+          }
+          se[t] = se[t] + w2 * static_cast<double>(ft[t][r][0]);
+          if (NC == 2) se[t] = se[t] + static_cast<double>(ft[t][r][NC - 1]);
+        }
+      }
+    }
+    {
+      const double part = wave_reduce_scatter<KP2>(se);
+      constexpr int G = 64 / KP2;
+      if (lane % G == 0) red[wid][(lane / G) % KP2] = part;
+    }
+    __syncthreads();
     if (tid < TP) {
       const int t = tid;
-      const double* st = red[0] + t * (D + 2);
-      const double s0 = st[0];
-      double Uk[D], u2 = 0.0;
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        Uk[k] = st[1 + k] / s0;
-        u2 = u2 + Uk[k] * Uk[k];
-      }
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s = s + red[w][t];
+      const double s0 = pstat[t][0];
       const double rho = a.omega * s0;
-      const double T = (st[D + 1] / s0 - u2) / 3.0;
+      const double T = s / (3.0 * s0);
       const double tau = a.kn * sqrt(2.0 / kPi) / (rho * sqrt(T));
       const double rden = 1.0 / (tau + a.dt);
       double norm;
@@ -456,8 +482,6 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
         norm = rho / (2.0 * kPi * T);
       }
       pstat[t][0] = rho;
-#pragma unroll
-      for (int k = 0; k < D; ++k) pstat[t][1 + k] = Uk[k];
       pstat[t][D + 1] = T;
       pstat[t][D + 2] = norm;
       pstat[t][D + 3] = tau * rden;   // f^{n+1} = a ft + b M, a = tau/(tau+dt)
@@ -468,7 +492,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
         a.rho[i] = rho;
         a.T[i] = T;
 #pragma unroll
-        for (int k = 0; k < D; ++k) a.Unew[static_cast<size_t>(k) * a.N + i] = Uk[k];
+        for (int k = 0; k < D; ++k) a.Unew[static_cast<size_t>(k) * a.N + i] = pstat[t][1 + k];
         if (!(rho > 0.0) || !(T > 0.0)) raise_error(a.err, BGK_ENONPHYS);
       }
     }

@@ -120,8 +120,9 @@ __global__ void k_cell_count(int N, int nca, int ncell, const double* __restrict
 }
 
 // Exclusive scan of n int32 in place (one block of 1024 threads walking the
-// array in chunks); a[n] receives the total.
-__global__ __launch_bounds__(1024) void k_scan_inplace(int32_t* a, int n) {
+// array in chunks); a[n] receives the total.  copy (may be null) receives the
+// same n values.
+__global__ __launch_bounds__(1024) void k_scan_inplace(int32_t* a, int n, int32_t* copy) {
   constexpr int PER = 8;
   __shared__ int32_t wsum[16];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -157,7 +158,10 @@ __global__ __launch_bounds__(1024) void k_scan_inplace(int32_t* a, int n) {
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int idx = base + tid * PER + k;
-      if (idx < n) a[idx] = run;
+      if (idx < n) {
+        a[idx] = run;
+        if (copy) copy[idx] = run;
+      }
       run += v[k];
     }
     carry += wsum[15];
@@ -174,32 +178,29 @@ __global__ void k_cell_scatter(int N, const int32_t* __restrict__ key, int32_t* 
   perm[pos] = i;
 }
 
-// Sort each cell range ascending so that the permutation is deterministic,
-// and copy the positions into cell order (xs[a][p] = x[a][perm[p]]) so that
-// candidate positions are contiguous loads in the searches below.
-__global__ void k_cell_sort(int nkeys, int N, int D, const int32_t* __restrict__ start,
+// Final position of each particle: its cell range, ascending particle index
+// inside the range (so the permutation is deterministic).  Thread per slot p
+// of the unsorted permutation: the rank of its particle among the range's
+// entries.  The positions are copied into cell order (xs[a][q] = x[a][perm[q]])
+// so that candidate positions are contiguous loads in the searches below.
+__global__ void k_cell_rank(int N, int D, const int32_t* __restrict__ key,
+                            const int32_t* __restrict__ start, const int32_t* __restrict__ perm2,
                             int32_t* __restrict__ perm, const double* __restrict__ x,
                             double* __restrict__ xs) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nkeys) return;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const int i = perm2[p];
+  const int k = key[i];
   const int b = start[k], e = start[k + 1];
-  for (int p = b + 1; p < e; ++p) {
-    const int v = perm[p];
-    int s = p;
-    while (s > b && perm[s - 1] > v) {
-      perm[s] = perm[s - 1];
-      --s;
-    }
-    perm[s] = v;
-  }
-  for (int p = b; p < e; ++p) {
-    const int j = perm[p];
-    for (int a = 0; a < D; ++a) xs[static_cast<int64_t>(a) * N + p] = x[static_cast<int64_t>(a) * N + j];
-  }
+  int rank = 0;
+  for (int q = b; q < e; ++q) rank += perm2[q] < i;
+  const int dst = b + rank;
+  perm[dst] = i;
+  for (int a = 0; a < D; ++a) xs[static_cast<int64_t>(a) * N + dst] = x[static_cast<int64_t>(a) * N + i];
 }
 
 hipError_t launch_scan(hipStream_t s, int32_t* a, int n) {
-  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, a, n);
+  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, a, n, nullptr);
   return hipGetLastError();
 }
 
@@ -214,13 +215,12 @@ hipError_t launch_cells(const Ctx& c, const double* x) {
   else
     hipLaunchKernelGGL(k_cell_count<3>, dim3(blocks_for(c.N, 256)), dim3(256), 0, c.stream, c.N,
                        c.nca, c.ncell, x, d.wall_id, d.key, d.cstart);
-  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, c.stream, d.cstart, nkeys);
-  e = launch_copy_i32(c.stream, d.cstart, d.ccursor, nkeys);
-  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, c.stream, d.cstart, nkeys,
+                     d.ccursor);
   hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(c.N, 256)), dim3(256), 0, c.stream, c.N,
-                     d.key, d.ccursor, d.cperm);
-  hipLaunchKernelGGL(k_cell_sort, dim3(blocks_for(nkeys, 64)), dim3(64), 0, c.stream, nkeys,
-                     c.N, c.D, d.cstart, d.cperm, x, d.xs);
+                     d.key, d.ccursor, d.cperm2);
+  hipLaunchKernelGGL(k_cell_rank, dim3(blocks_for(c.N, 256)), dim3(256), 0, c.stream, c.N, c.D,
+                     d.key, d.cstart, d.cperm2, d.cperm, x, d.xs);
   return hipGetLastError();
 }
 
@@ -502,107 +502,201 @@ struct WlsArgs {
   int32_t* err;
 };
 
-// One interior particle per wave: stage the basis values and weights of its
-// stencil (lane = neighbour), solve the normal equations, then each lane
-// forms the gradient row of its neighbour, the edge frame and (P, Q[, R]).
-template <int D, int DEG>
-__device__ bool wls_wave(const WlsArgs& a, int i, int m, double* sm) {
-  using Bs = Basis<D, DEG>;
-  constexpr int B = Bs::B, DD = D * D;
-  double* P = sm;                     // [cap][B]
-  double* W = P + a.cap * B;          // [cap]
-  double* A = W + a.cap;              // [NT]
-  double* Z = A + Bs::NT;             // [D][B]
-  int* flag = reinterpret_cast<int*>(Z + D * B);
-  const int lane = threadIdx.x;
+// Value of basis function r at y (the order of Basis::eval: 1, y_a, then
+// y_a y_b for a <= b).
+template <int D>
+__device__ __forceinline__ double basis_val(int r, const double* y) {
+  if (r == 0) return 1.0;
+  if (r <= D) return y[r - 1];
+  int k = D + 1;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = a; b < D; ++b) {
+      if (k == r) return y[a] * y[b];
+      ++k;
+    }
+  return 0.0;
+}
+
+// Solve L L^T z = e_col for one column (L packed lower triangle in A).
+template <int B>
+__device__ __forceinline__ void chol_solve_col(const double* A, int col, double* z) {
+  double y[B];
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+    double s = (i == col) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < i; ++k) s = s - A[tri(i, k)] * y[k];
+    y[i] = s / A[tri(i, i)];
+  }
+#pragma unroll
+  for (int i = B - 1; i >= 0; --i) {
+    double s = y[i];
+#pragma unroll
+    for (int k = i + 1; k < B; ++k) s = s - A[tri(k, i)] * z[k];
+    z[i] = s / A[tri(i, i)];
+  }
+}
+
+// kWlsGroup interior particles per wavefront, 64 / kWlsGroup lanes each
+// (lane group g handles particle blockIdx.x * kWlsGroup + g).  Per
+// particle: the stencil's scaled offsets y = (x_j - x_i)/h and weights are
+// staged in LDS (one lane per neighbour); the normal matrix
+// A = sum_e W_e p(y_e) p(y_e)^T is summed over e in order (one lane per
+// packed entry, basis values formed on the fly); A = L L^T column by column
+// (one lane per row of a column); one lane per gradient column solves
+// L L^T z = e_col; then one lane per neighbour forms the gradient row
+// W_e z.p(y_e)/h, the edge frame of y_e and (P, Q[, R]).  Degree: the
+// configured one if the stencil holds at least twice as many points as
+// degree-2 basis functions, else 1 if it holds d+2 points, else
+// BGK_ESINGULAR (also on a non-positive pivot).  Barriers sit at points
+// every lane reaches (loops run to the degree-2 sizes; groups of lower
+// degree idle through the extra columns).
+constexpr int kWlsGroup = 4;
+
+template <int D>
+struct WlsSm {
+  static constexpr int B2 = Basis<D, 2>::B, NT2 = Basis<D, 2>::NT;
+  // doubles per group: Y [cap][D], W [cap], A [NT2], Z [D][B2], flag
+  static __host__ __device__ int doubles(int cap) { return cap * D + cap + NT2 + D * B2 + 1; }
+};
+
+template <int D>
+__global__ __launch_bounds__(64) void k_wls(const WlsArgs a) {
+  extern __shared__ double wls_sm[];
+  using S = WlsSm<D>;
+  constexpr int L = kWave / kWlsGroup, B2 = S::B2, B1 = D + 1, DD = D * D;
+  const int lane = threadIdx.x, g = lane / L, gl = lane % L;
+  const int pidx = blockIdx.x * kWlsGroup + g;
+  const bool valid = pidx < a.Ni;
+  const int i = valid ? a.plist[pidx] : 0;
+  const int m = valid ? min(a.cnt[i], a.cap) : 0;
+  int deg = a.deg_cfg;
+  if (deg == 2 && m < 2 * B2) deg = 1;
+  const int Bg = (deg == 2) ? B2 : B1;
+  const bool enough = m >= D + 2;
+  double* Y = wls_sm + g * S::doubles(a.cap);
+  double* W = Y + a.cap * D;
+  double* A = W + a.cap;
+  double* Z = A + S::NT2;
+  double* flag = Z + D * B2;
   const int64_t row = static_cast<int64_t>(i) * a.cap;
   double xi[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) xi[k] = a.x[static_cast<int64_t>(k) * a.N + i];
-  for (int e = lane; e < m; e += kWave) {
+  for (int e = gl; e < m; e += L) {
     const int j = a.idx[row + e];
-    double y[D], r2 = 0.0;
+    double r2 = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      y[k] = (a.x[static_cast<int64_t>(k) * a.N + j] - xi[k]) / a.h;
-      r2 = r2 + y[k] * y[k];
+      const double y = (a.x[static_cast<int64_t>(k) * a.N + j] - xi[k]) / a.h;
+      Y[e * D + k] = y;
+      r2 = r2 + y * y;
     }
     W[e] = exp(-a.alpha * r2);
-    Bs::eval(y, P + e * B);
+  }
+  if (gl == 0) flag[0] = 0.0;
+  __syncthreads();
+  const int nt = Bg * (Bg + 1) / 2;
+  for (int l = gl; l < S::NT2; l += L) {
+    if (l < nt) {
+      int r = 0;
+      while (tri(r + 1, 0) <= l) ++r;
+      const int s2 = l - tri(r, 0);
+      double acc = 0.0;
+      for (int e = 0; e < m; ++e) {
+        const double* y = Y + e * D;
+        acc = acc + (W[e] * basis_val<D>(r, y)) * basis_val<D>(s2, y);
+      }
+      A[l] = acc;
+    }
   }
   __syncthreads();
-  if (!wave_lsq<B, D>(m, P, W, A, Z, 1, flag)) return false;
-  for (int e = lane; e < m; e += kWave) {
-    const int j = a.idx[row + e];
-    double dl[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) dl[k] = a.x[static_cast<int64_t>(k) * a.N + j] - xi[k];
-    double g[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      double s = 0.0;
-#pragma unroll
-      for (int r = 0; r < B; ++r) s = s + Z[k * B + r] * P[e * B + r];
-      g[k] = W[e] * s / a.h;
+  for (int jc = 0; jc < B2; ++jc) {
+    if (jc < Bg && gl == 0) {
+      double s = A[tri(jc, jc)];
+      for (int k = 0; k < jc; ++k) s = s - A[tri(jc, k)] * A[tri(jc, k)];
+      if (!(s > 0.0)) flag[0] = 1.0;
+      A[tri(jc, jc)] = sqrt(s);
     }
-    if (a.grad) {
-#pragma unroll
-      for (int k = 0; k < D; ++k) a.grad[(row + e) * D + k] = g[k];
+    __syncthreads();
+    if (jc < Bg && gl > jc && gl < Bg) {
+      double t = A[tri(gl, jc)];
+      for (int k = 0; k < jc; ++k) t = t - A[tri(gl, k)] * A[tri(jc, k)];
+      A[tri(gl, jc)] = t / A[tri(jc, jc)];
     }
-    double o[DD];
-    if (j == i) {
-#pragma unroll
-      for (int k = 0; k < DD; ++k) o[k] = 0.0;
-    } else {
-      double n[3], t[3], b[3];
-      edge_frame<D>(dl, n, t, b);
-      double ab = 0.0, bb = 0.0, gb = 0.0;
+    __syncthreads();
+  }
+  const bool ok = valid && enough && flag[0] == 0.0;
+  if (ok && gl < D) {
+    if (deg == 2) chol_solve_col<B2>(A, 1 + gl, Z + gl * B2);
+    else chol_solve_col<B1>(A, 1 + gl, Z + gl * B2);
+  }
+  __syncthreads();
+  if (ok) {
+    for (int e = gl; e < m; e += L) {
+      const int j = a.idx[row + e];
+      const double* y = Y + e * D;
+      double pv[B2];
+      if (deg == 2) Basis<D, 2>::eval(y, pv);
+      else Basis<D, 1>::eval(y, pv);
+      double gk[D];
 #pragma unroll
       for (int k = 0; k < D; ++k) {
-        ab = ab + g[k] * n[k];
-        bb = bb + g[k] * t[k];
-        if (D == 3) gb = gb + g[k] * b[k];
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < B2; ++r)
+          if (r < Bg) s = s + Z[k * B2 + r] * pv[r];
+        gk[k] = W[e] * s / a.h;
       }
+      if (a.grad) {
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
-        o[k] = ab * n[k];
-        o[D + k] = bb * t[k];
-        if (D == 3) o[2 * D + k] = gb * b[k];
+        for (int k = 0; k < D; ++k) a.grad[(row + e) * D + k] = gk[k];
       }
-    }
-    if (a.ops) {
+      double o[DD];
+      if (j == i) {
 #pragma unroll
-      for (int k = 0; k < DD; ++k) a.ops[(row + e) * DD + k] = o[k];
-    }
-    if (a.ops32) {
+        for (int k = 0; k < DD; ++k) o[k] = 0.0;
+      } else {
+        double dl[D];
 #pragma unroll
-      for (int k = 0; k < DD; ++k) a.ops32[(row + e) * DD + k] = static_cast<float>(o[k]);
+        for (int k = 0; k < D; ++k) dl[k] = a.x[static_cast<int64_t>(k) * a.N + j] - xi[k];
+        double n[3], t[3], b[3];
+        edge_frame<D>(dl, n, t, b);
+        double ab = 0.0, bb = 0.0, gb = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          ab = ab + gk[k] * n[k];
+          bb = bb + gk[k] * t[k];
+          if (D == 3) gb = gb + gk[k] * b[k];
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          o[k] = ab * n[k];
+          o[D + k] = bb * t[k];
+          if (D == 3) o[2 * D + k] = gb * b[k];
+        }
+      }
+      if (a.ops) {
+#pragma unroll
+        for (int k = 0; k < DD; ++k) a.ops[(row + e) * DD + k] = o[k];
+      }
+      if (a.ops32) {
+#pragma unroll
+        for (int k = 0; k < DD; ++k) a.ops32[(row + e) * DD + k] = static_cast<float>(o[k]);
+      }
     }
   }
-  return true;
-}
-
-// Degree: the configured one if the stencil holds at least twice as many
-// points as degree-2 basis functions, else 1 if it holds d+2 points, else
-// BGK_ESINGULAR.
-template <int D>
-__global__ __launch_bounds__(64) void k_wls(const WlsArgs a) {
-  extern __shared__ double wls_sm[];
-  const int i = a.plist[blockIdx.x];
-  const int m = min(a.cnt[i], a.cap);
-  int deg = a.deg_cfg;
-  if (deg == 2 && m < 2 * Basis<D, 2>::B) deg = 1;
-  bool ok = m >= D + 2;
-  if (ok) ok = (deg == 2) ? wls_wave<D, 2>(a, i, m, wls_sm) : wls_wave<D, 1>(a, i, m, wls_sm);
-  if (threadIdx.x == 0) {
+  if (valid && gl == 0) {
     if (!ok) raise_error(a.err, BGK_ESINGULAR);
     if (a.degree) a.degree[i] = ok ? deg : 0;
   }
 }
 
 static size_t wls_smem(int D, int cap) {
-  const int B = (D == 2) ? 6 : 10;
-  return (static_cast<size_t>(cap) * B + cap + B * (B + 1) / 2 + D * B + 1) * sizeof(double);
+  const int per = D == 2 ? WlsSm<2>::doubles(cap) : WlsSm<3>::doubles(cap);
+  return static_cast<size_t>(kWlsGroup) * per * sizeof(double);
 }
 
 hipError_t launch_wls(const Ctx& c, const double* x, const int32_t* cnt, const int32_t* idx,
@@ -611,10 +705,11 @@ hipError_t launch_wls(const Ctx& c, const double* x, const int32_t* cnt, const i
             grad, ops, ops32, degree, c.d.err};
   if (c.Ni == 0) return hipSuccess;
   const size_t sm = wls_smem(c.D, c.cap);
+  const dim3 grid((c.Ni + kWlsGroup - 1) / kWlsGroup);
   if (c.D == 2)
-    hipLaunchKernelGGL(k_wls<2>, dim3(c.Ni), dim3(kWave), sm, c.stream, a);
+    hipLaunchKernelGGL(k_wls<2>, grid, dim3(kWave), sm, c.stream, a);
   else
-    hipLaunchKernelGGL(k_wls<3>, dim3(c.Ni), dim3(kWave), sm, c.stream, a);
+    hipLaunchKernelGGL(k_wls<3>, grid, dim3(kWave), sm, c.stream, a);
   return hipGetLastError();
 }
 
@@ -818,44 +913,55 @@ __global__ __launch_bounds__(64) void k_patches(int Ni, int cap, int ucap,
   int32_t* re = rj + kPatch * cap;          // [kPatch][cap] its slot in the full row
   int32_t* mj = re + kPatch * cap;          // [kPatch*cap] merged j
   int32_t* mt = mj + kPatch * cap;          // merged (slot t << 8 | e)
-  __shared__ int32_t rn[kPatch];
+  __shared__ int32_t rn[kPatch], spt[kPatch], sm_[kPatch], sself[kPatch], spre[kPatch + 1];
   const int p = blockIdx.x, lane = threadIdx.x;
-  for (int t = 0; t < kPatch; ++t) {
-    const int g = p * kPatch + t;
+  if (lane < kPatch) {
+    const int g = p * kPatch + lane;
     const int pt = g < Ni ? plist[g] : -1;
-    const int m = pt >= 0 ? min(cnt[pt], cap) : 0;
-    const int32_t* row = idx + static_cast<int64_t>(max(pt, 0)) * cap;
-    // self is in the row exactly once; entries after it shift down by one
-    int self = m;
-    for (int e0 = 0; e0 < m; e0 += kWave) {
-      const int e = e0 + lane;
-      const bool is_self = e < m && row[e] == pt;
-      const uint64_t mask = __ballot(is_self);
-      if (mask) self = e0 + __ffsll(static_cast<long long>(mask)) - 1;
-    }
-    for (int e = lane; e < m; e += kWave) {
-      if (e == self) continue;
-      const int o = e < self ? e : e - 1;
-      rj[t * cap + o] = row[e];
-      re[t * cap + o] = e;
-    }
-    if (lane == 0) rn[t] = (self < m) ? m - 1 : m;
+    spt[lane] = pt;
+    sm_[lane] = pt >= 0 ? min(cnt[pt], cap) : 0;
+    sself[lane] = 0;
   }
   __syncthreads();
-  int total = 0;
-  for (int t = 0; t < kPatch; ++t) total += rn[t];
-  for (int t = 0; t < kPatch; ++t) {
-    for (int q = lane; q < rn[t]; q += kWave) {
-      const int j = rj[t * cap + q];
-      int pos = q;
-      for (int s = 0; s < kPatch; ++s) {
-        if (s == t) continue;
-        const int* v = rj + s * cap;
-        pos += (s < t) ? lower_bound_i(v, rn[s], j + 1) : lower_bound_i(v, rn[s], j);
-      }
-      mj[pos] = j;
-      mt[pos] = (t << 8) | re[t * cap + q];
+  // self is in its row exactly once (at most once if the row overflowed):
+  // find it in all rows at once, then copy the rows without it
+  for (int w = lane; w < kPatch * cap; w += kWave) {
+    const int t = w / cap, e = w - t * cap;
+    if (e < sm_[t] && idx[static_cast<int64_t>(spt[t]) * cap + e] == spt[t]) sself[t] = e + 1;
+  }
+  __syncthreads();
+  for (int w = lane; w < kPatch * cap; w += kWave) {
+    const int t = w / cap, e = w - t * cap;
+    if (e >= sm_[t]) continue;
+    const int sp = sself[t] - 1;
+    if (e == sp) continue;
+    const int o = (sp >= 0 && e > sp) ? e - 1 : e;
+    rj[t * cap + o] = idx[static_cast<int64_t>(spt[t]) * cap + e];
+    re[t * cap + o] = e;
+  }
+  if (lane < kPatch) rn[lane] = sself[lane] ? sm_[lane] - 1 : sm_[lane];
+  __syncthreads();
+  if (lane == 0) {
+    spre[0] = 0;
+    for (int t = 0; t < kPatch; ++t) spre[t + 1] = spre[t] + rn[t];
+  }
+  __syncthreads();
+  const int total = spre[kPatch];
+  // merged position of every (t, q): q plus, in each other row, the entries
+  // before it (equal j in a lower slot t first)
+  for (int w = lane; w < total; w += kWave) {
+    int t = 0;
+    while (w >= spre[t + 1]) ++t;
+    const int q = w - spre[t];
+    const int j = rj[t * cap + q];
+    int pos = q;
+    for (int s2 = 0; s2 < kPatch; ++s2) {
+      if (s2 == t) continue;
+      const int* v = rj + s2 * cap;
+      pos += (s2 < t) ? lower_bound_i(v, rn[s2], j + 1) : lower_bound_i(v, rn[s2], j);
     }
+    mj[pos] = j;
+    mt[pos] = (t << 8) | re[t * cap + q];
   }
   __syncthreads();
   int nu = 0;

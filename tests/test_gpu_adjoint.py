@@ -53,11 +53,12 @@ def smooth_state(c, x, seed):
 
 
 class AdjCase:
-    def __init__(self, cav, seed=0):
+    def __init__(self, cav, seed=0, precision="fp64"):
         self.cav = cav
         self.c = oracle.config(cav)
         self.x, self.wid = make_cloud(cav.dim, cav.n, seed)
-        cfg = bgk.config_from(cav, "fp64", flags=bgk.BGK_FLAG_ADJOINT)
+        cfg = bgk.config_from(cav, precision, flags=bgk.BGK_FLAG_ADJOINT)
+        self.fdt = bgk.f_dtype(cfg)
         say(f"adjoint case {cav.name} seed={seed} N={cav.n_particles} NV={cav.n_velocities}")
         self.ctx = bgk.bgk_init(cfg, t(self.wid))
         self.x_t = t(self.x)
@@ -104,6 +105,35 @@ def test_adjoint_step_is_the_transpose_of_the_dual_step(dim, n, nv, kn, seed):
     assert np.all(lam_U[:, k.wid != 0] == 0)
 
 
+@pytest.mark.parametrize("dim,n,nv,kn,seed", [CASES[0], CASES[2]])
+def test_adjoint_step_fp32_storage_against_the_dual_step(dim, n, nv, kn, seed):
+    """FP32 storage of f and of the adjoints, FP64 arithmetic inside: the
+    transpose identity holds to the FP32 rounding of the inputs."""
+    k = AdjCase(cavity(dim, n, nv, kn=kn), seed, precision="fp32")
+    c = k.c
+    f, U = smooth_state(c, k.x, seed)
+    f = f.astype(np.float32).astype(np.float64)     # the state the GPU holds
+    rng = np.random.default_rng(200 + seed)
+    lf = rng.normal(size=f.shape).astype(np.float32).astype(np.float64)
+    lU = rng.normal(size=(c.dim, c.n_particles))
+    dl = t(np.zeros(1))
+    lam_f, lam_U = bgk.bgk_adjoint_step(k.ctx, t(f).float(), t(U), k.x_t, t(lf).float(), t(lU),
+                                        dJ_dlid=dl)
+    bgk.bgk_check(k.ctx)
+    lam_f, lam_U = lam_f.double().cpu().numpy(), lam_U.cpu().numpy()
+    df = f * rng.normal(size=f.shape)
+    dU = 0.1 * rng.normal(size=U.shape)
+    for name, kw, rhs in [("f", dict(f_dot=df), dot(lam_f, df)),
+                          ("U", dict(U_dot=dU), dot(lam_U, dU)),
+                          ("lid", dict(lid_dot=1.0), float(dl.item()))]:
+        out = oracle.step_dual(c, k.wid, k.x, f, U, **kw)
+        terms = [lf * out[1], lU * out[3]]
+        val = sum(float(np.sum(v)) for v in terms)
+        scale = sum(float(np.sum(np.abs(v))) for v in terms)
+        say(f"  fp32 {name}: <lam, J d> = {val:.9e}  <J^T lam, d> = {rhs:.9e}")
+        assert abs(val - rhs) <= 1e-5 * scale, name
+
+
 def test_adjoint_step_in_place_and_deterministic():
     k = AdjCase(cavity(2, 10, 8), 3)
     c = k.c
@@ -131,9 +161,10 @@ def test_adjoint_step_needs_the_adjoint_workspace():
     with pytest.raises(bgk.BgkError) as e:
         bgk.bgk_adjoint_step(ctx, f, U, t(x), f.clone())
     assert e.value.code == bgk.BGK_ENOTSUP
-    # the flag needs a frozen FP64 cloud
-    with pytest.raises(bgk.BgkError):
-        bgk.bgk_init(bgk.config_from(cav, "fp32", flags=bgk.BGK_FLAG_ADJOINT), t(wid))
+    # the flag needs a frozen cloud and FP64 or FP32 storage
+    for bad in (dict(precision=bgk.BGK_BF16), dict(move=1)):
+        with pytest.raises(bgk.BgkError):
+            bgk.bgk_init(bgk.config_from(cav, "fp64", flags=bgk.BGK_FLAG_ADJOINT, **bad), t(wid))
 
 
 @pytest.mark.parametrize("dim,n,nv", [(2, 9, 8), (3, 5, 6)])
@@ -195,6 +226,26 @@ def test_checkpoint_spacing_does_not_change_the_gradient():
         assert J == out[0][0] and gl == out[0][2] and torch.equal(gf, out[0][1])
 
 
+def test_fp32_storage_rollout_gradients_follow_fp64():
+    cav = cavity(2, 16, 12, kn=0.5)
+    g = {}
+    rng = np.random.default_rng(11)
+    delta = None
+    for p in ("fp64", "fp32"):
+        prob = FrozenCavity(cav, DEV, precision=p)
+        f0 = prob.rest_state().requires_grad_(True)
+        if delta is None:
+            delta = rng.normal(size=tuple(f0.shape))
+        lid = torch.tensor(cav.lid, dtype=torch.float64, device=DEV, requires_grad=True)
+        J = rollout_objective(prob, f0, lid, 12, 4)
+        J.backward()
+        g[p] = (J.item(), lid.grad.item(),
+                float(np.sum(f0.grad.double().cpu().numpy() * delta)))
+    say(f"  fp64 {g['fp64']}\n  fp32 {g['fp32']}")
+    for a, b in zip(g["fp32"], g["fp64"]):
+        assert abs(a - b) <= 1e-4 * abs(b)
+
+
 def test_zero_steps_is_the_objective_of_the_initial_moments():
     cav = cavity(2, 8, 8)
     prob = FrozenCavity(cav, DEV)
@@ -237,3 +288,39 @@ def test_differentiation_workload_gradients_match_central_differences():
     g = float(torch.sum(f0.grad * delta).item())
     say(f"  <grad_f0 J, delta> adjoint {g:.12e} central difference {fdf:.12e}")
     assert abs(g - fdf) <= 1e-6 * abs(fdf)
+
+
+def test_3d_window_lid_gradient_matches_central_differences():
+    # the 3D cavity at scale: 48^3 particles, 20^3 velocities, a 20-step
+    # frozen-cloud window with checkpoints every 5 steps (FP64 storage)
+    torch.cuda.empty_cache()
+    cav = CONFIGS["c5"].replace(precision="fp64", move=0)
+    prob = FrozenCavity(cav, DEV)
+    steps = 20
+    say(f"c5 window N={cav.n_particles} NV={cav.n_velocities} steps={steps}")
+    base = prob.rest_state()
+    f0 = base.clone().requires_grad_(True)
+    lid = torch.tensor(cav.lid, dtype=torch.float64, device=DEV, requires_grad=True)
+    J = rollout_objective(prob, f0, lid, steps, 5)
+    J.backward()
+    g = lid.grad.item()
+    del f0, J
+    torch.cuda.empty_cache()
+    eps = 1e-6
+    fd = (prob.objective(base, cav.lid + eps, steps)
+          - prob.objective(base, cav.lid - eps, steps)) / (2 * eps)
+    say(f"  dJ/dlid adjoint {g:.12e} central difference {fd:.12e}")
+    assert abs(g - fd) <= 1e-6 * abs(fd)
+    del prob, base
+    torch.cuda.empty_cache()
+    # the same window with FP32 storage of f and of the adjoints
+    prob = FrozenCavity(cav, DEV, precision="fp32")
+    f0 = prob.rest_state().requires_grad_(True)
+    lid = torch.tensor(cav.lid, dtype=torch.float64, device=DEV, requires_grad=True)
+    J = rollout_objective(prob, f0, lid, steps, 5)
+    J.backward()
+    g32 = lid.grad.item()
+    say(f"  dJ/dlid with FP32 storage {g32:.9e}")
+    assert abs(g32 - g) <= 1e-4 * abs(g)
+    del prob, f0, J
+    torch.cuda.empty_cache()

@@ -103,7 +103,7 @@ def test_adjoint_flag_rules(lib):
     cav = CONFIGS["c4"]
     f_bytes = 8 * 2 * cav.n_particles * cav.n_velocities
     assert n.value >= base + 3 * f_bytes      # f-tilde, lam_ft, wall adjoints
-    for bad in (dict(precision=bgk.BGK_FP32), dict(move=1)):
+    for bad in (dict(precision=bgk.BGK_BF16), dict(move=1)):
         c = bgk.config_from(CONFIGS["c4"], "fp64", flags=bgk.BGK_FLAG_ADJOINT)
         for k, v in bad.items():
             setattr(c, k, v)
