@@ -163,7 +163,8 @@ __device__ __forceinline__ void block_sum_n(double (&v)[K], double* sh, int nw) 
   __syncthreads();
 }
 
-// Diffuse reflection on wall particle b (one block of up to 1024 threads):
+// Diffuse reflection on wall particle b (one block of up to 256 threads, so
+// that every wall particle's block is resident at once):
 // arriving velocities (v.n <= 0, n the inward normal) take the interpolated
 // interior value sum_e c0_e f_j; emitted ones take rho_w M[1, U_w, T_w]
 // (Chu: G1 and T_w G1 scaled by rho_w) with rho_w from zero net mass flux;
@@ -265,7 +266,7 @@ hipError_t launch_wall_bc(const Ctx& c, void* f, double* rho, double* U, double*
                omega_of(c.cfg), c.lid,  c.cfg.wall_T,  c.d.wall_list, c.d.wall_id, c.d.wcnt,
                c.d.widx,     c.d.wc0,   f,             rho,    U,      T,      c.d.err};
   const bool f64 = c.cfg.precision == BGK_FP64;
-  dim3 g(c.Nw), t(std::min(1024, (c.NV + 63) / 64 * 64));
+  dim3 g(c.Nw), t(std::min(kThreads, (c.NV + 63) / 64 * 64));
   if (c.D == 2) {
     if (f64) hipLaunchKernelGGL((k_wall_bc<2, 2, double>), g, t, 0, c.stream, a);
     else hipLaunchKernelGGL((k_wall_bc<2, 2, float>), g, t, 0, c.stream, a);

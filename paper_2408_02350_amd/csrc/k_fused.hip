@@ -306,22 +306,34 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
       for (int t = 0; t < TP; ++t) {
         if (mask & (1u << t)) {
           const Real* rec = lrec[u][t];
-          Real av[DD], bk[D], ik[D];
+          Real ik[D], p[D];
+          if constexpr (R >= 8) {
+            // many velocities per thread: read the per-edge rows one at a
+            // time, so that their registers are not all live at once
 #pragma unroll
-          for (int k = 0; k < DD; ++k) av[k] = rec[k];
+            for (int k = 0; k < D; ++k) {
+              Real s1 = -rec[DD + k];
 #pragma unroll
-          for (int k = 0; k < D; ++k) {
-            bk[k] = rec[DD + k];
-            ik[k] = rec[DD + D + k];
+              for (int m = 0; m < D; ++m) s1 = fma_t(rec[k * D + m], v0[m], s1);
+              p[k] = s1;
+              asm volatile("" ::: "memory");
+            }
+          } else {
+            Real av[DD], bk[D];
+#pragma unroll
+            for (int k = 0; k < DD; ++k) av[k] = rec[k];
+#pragma unroll
+            for (int k = 0; k < D; ++k) bk[k] = rec[DD + k];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+              Real s1 = -bk[k];
+#pragma unroll
+              for (int m = 0; m < D; ++m) s1 = fma_t(av[k * D + m], v0[m], s1);
+              p[k] = s1;
+            }
           }
-          Real p[D];
 #pragma unroll
-          for (int k = 0; k < D; ++k) {
-            Real s1 = -bk[k];
-#pragma unroll
-            for (int m = 0; m < D; ++m) s1 = fma_t(av[k * D + m], v0[m], s1);
-            p[k] = s1;
-          }
+          for (int k = 0; k < D; ++k) ik[k] = rec[DD + D + k];
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             if (r > 0) {

@@ -162,9 +162,9 @@ def test_adjoint_step_needs_the_adjoint_workspace():
         bgk.bgk_adjoint_step(ctx, f, U, t(x), f.clone())
     assert e.value.code == bgk.BGK_ENOTSUP
     # the flag needs a frozen cloud and FP64 or FP32 storage
-    for bad in (dict(precision=bgk.BGK_BF16), dict(move=1)):
+    for prec, bad in (("bf16", {}), ("fp64", {"move": 1})):
         with pytest.raises(bgk.BgkError):
-            bgk.bgk_init(bgk.config_from(cav, "fp64", flags=bgk.BGK_FLAG_ADJOINT, **bad), t(wid))
+            bgk.bgk_init(bgk.config_from(cav, prec, flags=bgk.BGK_FLAG_ADJOINT, **bad), t(wid))
 
 
 @pytest.mark.parametrize("dim,n,nv", [(2, 9, 8), (3, 5, 6)])
