@@ -202,14 +202,18 @@ int bgk_init(const bgk_config* cfg, const int32_t* wall_id, void* workspace, siz
     delete h;
     return BGK_EDEVICE;
   }
+  // wall particles listed face by face (owner wall, then index): neighbours
+  // in the list are neighbours on the face and share interpolation stencils
   std::vector<int32_t> wl;
   for (int i = 0; i < c.N; ++i) {
     if (wid[i] < 0 || wid[i] > 2 * c.D) {
       delete h;
       return BGK_EINVAL;
     }
-    if (wid[i] != 0) wl.push_back(i);
   }
+  for (int w = 1; w <= 2 * c.D; ++w)
+    for (int i = 0; i < c.N; ++i)
+      if (wid[i] == w) wl.push_back(i);
   c.Nw = static_cast<int>(wl.size());
   c.Ni = c.N - c.Nw;
   c.npatch = (c.Ni + bgk::kPatch - 1) / bgk::kPatch;

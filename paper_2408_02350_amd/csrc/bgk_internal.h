@@ -28,7 +28,7 @@ constexpr int kErrWords = 8;
 struct Dev {
   int32_t* err;          // [kErrWords]
   int32_t* wall_id;      // [N]
-  int32_t* wall_list;    // [Nw]  wall particles, ascending
+  int32_t* wall_list;    // [Nw]  wall particles by owner wall, then ascending
   int32_t* key;          // [N]   cell key of each particle
   int32_t* cstart;       // [2*ncell + 1] start of each (cell, interior|wall) range
   int32_t* ccursor;      // [2*ncell]

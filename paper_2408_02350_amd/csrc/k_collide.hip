@@ -163,17 +163,34 @@ __device__ __forceinline__ void block_sum_n(double (&v)[K], double* sh, int nw) 
   __syncthreads();
 }
 
+// R consecutive elements of a row with the widest aligned vector access
+// (p is aligned to R elements).
+template <typename Real, int R>
+__device__ __forceinline__ void load_vec(const Real* __restrict__ p, Real (&o)[R]) {
+  constexpr int W = (R * sizeof(Real)) % 16 == 0 ? 16 / static_cast<int>(sizeof(Real)) : R;
+  typedef Real V __attribute__((ext_vector_type(W)));
+  const V* pv = reinterpret_cast<const V*>(__builtin_assume_aligned(p, W * sizeof(Real)));
+#pragma unroll
+  for (int i = 0; i < R / W; ++i) {
+    const V x = pv[i];
+#pragma unroll
+    for (int w = 0; w < W; ++w) o[i * W + w] = x[w];
+  }
+}
+
 // Diffuse reflection on wall particle b (one block of up to 256 threads, so
-// that every wall particle's block is resident at once):
-// arriving velocities (v.n <= 0, n the inward normal) take the interpolated
-// interior value sum_e c0_e f_j; emitted ones take rho_w M[1, U_w, T_w]
-// (Chu: G1 and T_w G1 scaled by rho_w) with rho_w from zero net mass flux;
-// then the particle's moments in two passes (U first, then the centred
-// second moment).  Each thread re-reads only the velocities it wrote itself.
-template <int D, int NC, typename Real>
-__global__ __launch_bounds__(1024) void k_wall_bc(const WallBcArgs a) {
+// that every wall particle's block is resident at once): arriving
+// velocities (v.n <= 0, n the inward normal) take the interpolated interior
+// value sum_e c0_e f_j; emitted ones take rho_w M[1, U_w, T_w] (Chu: G1 and
+// T_w G1 scaled by rho_w) with rho_w from zero net mass flux; then the
+// particle's moments in two passes (U first, then the centred second
+// moment).  A thread handles R consecutive velocities (one vector load per
+// stencil row and component, rows taken two at a time) and re-reads only
+// the velocities it wrote itself.
+template <int D, int NC, typename Real, int R>
+__global__ __launch_bounds__(kThreads) void k_wall_bc(const WallBcArgs a) {
   __shared__ double sh[16 * (D + 1)];
-  const int k = blockIdx.x;
+  const int k = xcd_logical_block(blockIdx.x, gridDim.x);  // neighbouring walls share an L2
   const int nw = blockDim.x >> 6;
   const int b = a.wall_list[k];
   const int w = a.wall_id[b];
@@ -187,23 +204,56 @@ __global__ __launch_bounds__(1024) void k_wall_bc(const WallBcArgs a) {
   const size_t NVs = a.NV, cs = static_cast<size_t>(a.N) * NVs;
   Real* f = static_cast<Real*>(a.f);
   Real* fb = f + static_cast<size_t>(b) * NVs;
+  const int step = R * static_cast<int>(blockDim.x);
   double flux[2] = {0.0, 0.0};
-  for (int q = threadIdx.x; q < a.NV; q += blockDim.x) {
-    double v[3];
-    velocity_of<D>(q, a.nv, a.vmax, v);
-    const double vn = sgn * v[axis];
-    if (vn <= 0.0) {
+  for (int q0 = R * static_cast<int>(threadIdx.x); q0 < a.NV; q0 += step) {
+    double s[NC][R];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int r = 0; r < R; ++r) s[c][r] = 0.0;
+    int e = 0;
+    for (; e + 1 < m; e += 2) {
+      Real x0[NC][R], x1[NC][R];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        double s = 0.0;
-        for (int e = 0; e < m; ++e)
-          s = s + c0[e] * static_cast<double>(f[c * cs + static_cast<size_t>(row[e]) * NVs + q]);
-        const Real sr = static_cast<Real>(s);
-        fb[c * cs + q] = sr;
-        if (c == 0) flux[0] = flux[0] + (-vn) * static_cast<double>(sr);
+        load_vec<Real, R>(f + c * cs + static_cast<size_t>(row[e]) * NVs + q0, x0[c]);
+        load_vec<Real, R>(f + c * cs + static_cast<size_t>(row[e + 1]) * NVs + q0, x1[c]);
       }
-    } else {
-      flux[1] = flux[1] + vn * maxwell<D>(0, 1.0, Uw, a.wall_T, v);
+      const double w0 = c0[e], w1 = c0[e + 1];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          s[c][r] = s[c][r] + w0 * static_cast<double>(x0[c][r]);
+          s[c][r] = s[c][r] + w1 * static_cast<double>(x1[c][r]);
+        }
+    }
+    if (e < m) {
+      Real x0[NC][R];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        load_vec<Real, R>(f + c * cs + static_cast<size_t>(row[e]) * NVs + q0, x0[c]);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[c][r] = s[c][r] + c0[e] * static_cast<double>(x0[c][r]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      double v[3];
+      velocity_of<D>(q0 + r, a.nv, a.vmax, v);
+      const double vn = sgn * v[axis];
+      if (vn <= 0.0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const Real sr = static_cast<Real>(s[c][r]);
+          fb[c * cs + q0 + r] = sr;
+          if (c == 0) flux[0] = flux[0] + (-vn) * static_cast<double>(sr);
+        }
+      } else {
+        flux[1] = flux[1] + vn * maxwell<D>(0, 1.0, Uw, a.wall_T, v);
+      }
     }
   }
   block_sum_n<2>(flux, sh, nw);
@@ -211,47 +261,55 @@ __global__ __launch_bounds__(1024) void k_wall_bc(const WallBcArgs a) {
   double sm[D + 1];
 #pragma unroll
   for (int kk = 0; kk < D + 1; ++kk) sm[kk] = 0.0;
-  for (int q = threadIdx.x; q < a.NV; q += blockDim.x) {
-    double v[3];
-    velocity_of<D>(q, a.nv, a.vmax, v);
-    const double vn = sgn * v[axis];
-    double x0;
-    if (vn > 0.0) {
+  for (int q0 = R * static_cast<int>(threadIdx.x); q0 < a.NV; q0 += step) {
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const Real y = static_cast<Real>(maxwell<D>(c, rho_w, Uw, a.wall_T, v));
-        fb[c * cs + q] = y;
-        if (c == 0) x0 = static_cast<double>(y);
+    for (int r = 0; r < R; ++r) {
+      const int q = q0 + r;
+      double v[3];
+      velocity_of<D>(q, a.nv, a.vmax, v);
+      const double vn = sgn * v[axis];
+      double x0;
+      if (vn > 0.0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const Real y = static_cast<Real>(maxwell<D>(c, rho_w, Uw, a.wall_T, v));
+          fb[c * cs + q] = y;
+          if (c == 0) x0 = static_cast<double>(y);
+        }
+      } else {
+        x0 = static_cast<double>(fb[q]);
       }
-    } else {
-      x0 = static_cast<double>(fb[q]);
-    }
-    sm[0] = sm[0] + x0;
+      sm[0] = sm[0] + x0;
 #pragma unroll
-    for (int kk = 0; kk < D; ++kk) sm[1 + kk] = sm[1 + kk] + v[kk] * x0;
+      for (int kk = 0; kk < D; ++kk) sm[1 + kk] = sm[1 + kk] + v[kk] * x0;
+    }
   }
   block_sum_n<D + 1>(sm, sh, nw);
   const double s0 = sm[0];
   double U[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int kk = 0; kk < D; ++kk) U[kk] = sm[1 + kk] / s0;
-  double e[1] = {0.0};
-  for (int q = threadIdx.x; q < a.NV; q += blockDim.x) {
-    double v[3];
-    velocity_of<D>(q, a.nv, a.vmax, v);
-    double w2 = 0.0;
+  double e2[1] = {0.0};
+  for (int q0 = R * static_cast<int>(threadIdx.x); q0 < a.NV; q0 += step) {
 #pragma unroll
-    for (int kk = 0; kk < D; ++kk) {
-      const double wk = v[kk] - U[kk];
-      w2 = w2 + wk * wk;
+    for (int r = 0; r < R; ++r) {
+      const int q = q0 + r;
+      double v[3];
+      velocity_of<D>(q, a.nv, a.vmax, v);
+      double w2 = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < D; ++kk) {
+        const double wk = v[kk] - U[kk];
+        w2 = w2 + wk * wk;
+      }
+      e2[0] = e2[0] + w2 * static_cast<double>(fb[q]);
+      if (NC == 2) e2[0] = e2[0] + static_cast<double>(fb[cs + q]);
     }
-    e[0] = e[0] + w2 * static_cast<double>(fb[q]);
-    if (NC == 2) e[0] = e[0] + static_cast<double>(fb[cs + q]);
   }
-  block_sum_n<1>(e, sh, nw);
+  block_sum_n<1>(e2, sh, nw);
   if (threadIdx.x == 0) {
     const double rho = a.omega * s0;
-    const double T = e[0] / (3.0 * s0);
+    const double T = e2[0] / (3.0 * s0);
     a.rho[b] = rho;
     a.T[b] = T;
 #pragma unroll
@@ -260,19 +318,25 @@ __global__ __launch_bounds__(1024) void k_wall_bc(const WallBcArgs a) {
   }
 }
 
+template <int D, int NC, typename Real>
+static void wall_bc_t(const Ctx& c, const WallBcArgs& a) {
+  const int R = (c.cfg.nv % 4 == 0) ? 4 : 2;  // nv is even
+  const int lanes = c.NV / R;
+  dim3 g(c.Nw), t(std::min(kThreads, (lanes + 63) / 64 * 64));
+  if (R == 4) hipLaunchKernelGGL((k_wall_bc<D, NC, Real, 4>), g, t, 0, c.stream, a);
+  else hipLaunchKernelGGL((k_wall_bc<D, NC, Real, 2>), g, t, 0, c.stream, a);
+}
+
 hipError_t launch_wall_bc(const Ctx& c, void* f, double* rho, double* U, double* T) {
   if (c.Nw == 0) return hipSuccess;
   WallBcArgs a{c.N,          c.NV,      c.cfg.nv,      c.cap,  c.Nw,   c.D,    c.cfg.vmax,
                omega_of(c.cfg), c.lid,  c.cfg.wall_T,  c.d.wall_list, c.d.wall_id, c.d.wcnt,
                c.d.widx,     c.d.wc0,   f,             rho,    U,      T,      c.d.err};
   const bool f64 = c.cfg.precision == BGK_FP64;
-  dim3 g(c.Nw), t(std::min(kThreads, (c.NV + 63) / 64 * 64));
   if (c.D == 2) {
-    if (f64) hipLaunchKernelGGL((k_wall_bc<2, 2, double>), g, t, 0, c.stream, a);
-    else hipLaunchKernelGGL((k_wall_bc<2, 2, float>), g, t, 0, c.stream, a);
+    if (f64) wall_bc_t<2, 2, double>(c, a); else wall_bc_t<2, 2, float>(c, a);
   } else {
-    if (f64) hipLaunchKernelGGL((k_wall_bc<3, 1, double>), g, t, 0, c.stream, a);
-    else hipLaunchKernelGGL((k_wall_bc<3, 1, float>), g, t, 0, c.stream, a);
+    if (f64) wall_bc_t<3, 1, double>(c, a); else wall_bc_t<3, 1, float>(c, a);
   }
   return hipGetLastError();
 }

@@ -120,20 +120,31 @@ __global__ void k_cell_count(int N, int nca, int ncell, const double* __restrict
 }
 
 // Exclusive scan of n int32 in place (one block of 1024 threads walking the
-// array in chunks); a[n] receives the total.  copy (may be null) receives the
-// same n values.
+// array in chunks of 1024*PER); a[n] receives the total.  copy (may be null)
+// receives the same n values.  Each chunk is read and written coalesced
+// through LDS (padded one word in 32 against bank conflicts); each thread
+// scans PER consecutive entries.
+constexpr int kScanPer = 8;
+__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }
+
 __global__ __launch_bounds__(1024) void k_scan_inplace(int32_t* a, int n, int32_t* copy) {
-  constexpr int PER = 8;
+  constexpr int PER = kScanPer, CH = 1024 * PER;
+  __shared__ int32_t buf[CH + CH / 32];
   __shared__ int32_t wsum[16];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   int carry = 0;
-  for (int base = 0; base < n; base += 1024 * PER) {
+  for (int base = 0; base < n; base += CH) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int i = k * 1024 + tid, g = base + i;
+      buf[scan_pad(i)] = g < n ? a[g] : 0;
+    }
+    __syncthreads();
     int v[PER];
     int s = 0;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int idx = base + tid * PER + k;
-      v[k] = idx < n ? a[idx] : 0;
+      v[k] = buf[scan_pad(tid * PER + k)];
       s += v[k];
     }
     int incl = s;
@@ -157,14 +168,20 @@ __global__ __launch_bounds__(1024) void k_scan_inplace(int32_t* a, int n, int32_
     int run = carry + (incl - s) + (wid > 0 ? wsum[wid - 1] : 0);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int idx = base + tid * PER + k;
-      if (idx < n) {
-        a[idx] = run;
-        if (copy) copy[idx] = run;
-      }
+      buf[scan_pad(tid * PER + k)] = run;
       run += v[k];
     }
     carry += wsum[15];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int i = k * 1024 + tid, g = base + i;
+      if (g < n) {
+        const int x = buf[scan_pad(i)];
+        a[g] = x;
+        if (copy) copy[g] = x;
+      }
+    }
     __syncthreads();
   }
   if (tid == 0) a[n] = carry;
@@ -502,21 +519,27 @@ struct WlsArgs {
   int32_t* err;
 };
 
-// Value of basis function r at y (the order of Basis::eval: 1, y_a, then
-// y_a y_b for a <= b).
+// Row entries whose product is basis function r in the order of
+// Basis::eval (index D stands for the constant 1): r = 0 -> (D, D),
+// r = 1 + a -> (a, D), then y_a y_b for a <= b -> (a, b).
 template <int D>
-__device__ __forceinline__ double basis_val(int r, const double* y) {
-  if (r == 0) return 1.0;
-  if (r <= D) return y[r - 1];
+__device__ __forceinline__ void basis_factors(int r, int& i0, int& i1) {
+  i0 = D;
+  i1 = D;
+  if (r == 0) return;
+  if (r <= D) {
+    i0 = r - 1;
+    return;
+  }
   int k = D + 1;
-#pragma unroll
   for (int a = 0; a < D; ++a)
-#pragma unroll
     for (int b = a; b < D; ++b) {
-      if (k == r) return y[a] * y[b];
+      if (k == r) {
+        i0 = a;
+        i1 = b;
+      }
       ++k;
     }
-  return 0.0;
 }
 
 // Solve L L^T z = e_col for one column (L packed lower triangle in A).
@@ -558,8 +581,8 @@ constexpr int kWlsGroup = 4;
 template <int D>
 struct WlsSm {
   static constexpr int B2 = Basis<D, 2>::B, NT2 = Basis<D, 2>::NT;
-  // doubles per group: Y [cap][D], W [cap], A [NT2], Z [D][B2], flag
-  static __host__ __device__ int doubles(int cap) { return cap * D + cap + NT2 + D * B2 + 1; }
+  // doubles per group: Y [cap][D+1] (offsets, then 1.0), W [cap], A [NT2], Z [D][B2], flag
+  static __host__ __device__ int doubles(int cap) { return cap * (D + 1) + cap + NT2 + D * B2 + 1; }
 };
 
 template <int D>
@@ -576,8 +599,9 @@ __global__ __launch_bounds__(64) void k_wls(const WlsArgs a) {
   if (deg == 2 && m < 2 * B2) deg = 1;
   const int Bg = (deg == 2) ? B2 : B1;
   const bool enough = m >= D + 2;
+  constexpr int YS = D + 1;  // Y row: y_0 .. y_{D-1}, 1.0
   double* Y = wls_sm + g * S::doubles(a.cap);
-  double* W = Y + a.cap * D;
+  double* W = Y + a.cap * YS;
   double* A = W + a.cap;
   double* Z = A + S::NT2;
   double* flag = Z + D * B2;
@@ -591,9 +615,10 @@ __global__ __launch_bounds__(64) void k_wls(const WlsArgs a) {
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       const double y = (a.x[static_cast<int64_t>(k) * a.N + j] - xi[k]) / a.h;
-      Y[e * D + k] = y;
+      Y[e * YS + k] = y;
       r2 = r2 + y * y;
     }
+    Y[e * YS + D] = 1.0;
     W[e] = exp(-a.alpha * r2);
   }
   if (gl == 0) flag[0] = 0.0;
@@ -604,10 +629,15 @@ __global__ __launch_bounds__(64) void k_wls(const WlsArgs a) {
       int r = 0;
       while (tri(r + 1, 0) <= l) ++r;
       const int s2 = l - tri(r, 0);
+      // basis function k is the product Y[i0] * Y[i1] of two row entries
+      // (index D holds 1.0): 1 = 1*1, y_a = y_a*1, y_a y_b
+      int r0, r1, s0, s1;
+      basis_factors<D>(r, r0, r1);
+      basis_factors<D>(s2, s0, s1);
       double acc = 0.0;
       for (int e = 0; e < m; ++e) {
-        const double* y = Y + e * D;
-        acc = acc + (W[e] * basis_val<D>(r, y)) * basis_val<D>(s2, y);
+        const double* y = Y + e * YS;
+        acc = acc + (W[e] * (y[r0] * y[r1])) * (y[s0] * y[s1]);
       }
       A[l] = acc;
     }
@@ -637,7 +667,7 @@ __global__ __launch_bounds__(64) void k_wls(const WlsArgs a) {
   if (ok) {
     for (int e = gl; e < m; e += L) {
       const int j = a.idx[row + e];
-      const double* y = Y + e * D;
+      const double* y = Y + e * YS;
       double pv[B2];
       if (deg == 2) Basis<D, 2>::eval(y, pv);
       else Basis<D, 1>::eval(y, pv);
