@@ -212,7 +212,16 @@ __global__ __launch_bounds__(kThreads) void k_wall_bc(const WallBcArgs a) {
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int r = 0; r < R; ++r) s[c][r] = 0.0;
-    int e = 0;
+    // only arriving velocities are interpolated: skip the gather when all R
+    // of this thread are emitted (whole waves on the faces normal to y, z)
+    bool arriving = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      double v[3];
+      velocity_of<D>(q0 + r, a.nv, a.vmax, v);
+      arriving = arriving || sgn * v[axis] <= 0.0;
+    }
+    int e = arriving ? 0 : m;
     for (; e + 1 < m; e += 2) {
       Real x0[NC][R], x1[NC][R];
 #pragma unroll
