@@ -548,7 +548,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
 // nv, so a thread's R velocities share every other component), at most
 // Rmax for the precision and model (the per-thread accumulators are
 // kPatch * R * (n_c + 1) values), and the fewest velocity tiles of at most
-// 1024 threads (2D: at most 512, two blocks per CU).  One tile can run the
+// 1024 threads (2D: fewer, see lanes_max).  One tile can run the
 // fused relaxation; several tiles write f-tilde for the separate kernel.
 struct FusedPlan {
   int R = 0, tiles = 0, bte = 0;
@@ -564,7 +564,10 @@ static FusedPlan plan_fused(const Ctx& c) {
   const int rmax = D == 2 ? (f64 ? 2 : 4) : (f64 ? 4 : 10);
   const int* cand = f64 ? r64 : (D == 2 ? r2d : r3d);
   const int ncand = f64 ? 3 : (D == 2 ? 4 : 6);
-  const int lanes_max = D == 2 ? 512 : 1024;
+  // 2D: FP64 at most 512 lanes (two blocks per CU at its register use);
+  // FP32 / BF16 at most 256 lanes, i.e. 4 velocities per lane at 32^2
+  // (fewer, wider row loads and one projection set-up per 4 velocities)
+  const int lanes_max = D == 2 ? (f64 ? 512 : 256) : 1024;
   FusedPlan p;
   // one tile: the smallest admissible R that fits
   for (int i = 0; i < ncand; ++i) {
