@@ -202,6 +202,26 @@ def test_rough_field_at_walls_flagged_like_the_oracle():
     assert eg.value.code == bgk.BGK_ENONPHYS
 
 
+@pytest.mark.parametrize("dim,n", [(2, 2), (2, 3), (3, 2), (3, 3)])
+def test_degenerate_clouds_report_singular_walls_like_the_oracle(dim, n):
+    """Clouds too small for the method (no interior particle, or one): no
+    wall particle finds d+2 interior points within 2h.  Both sides report
+    BGK_ESINGULAR, and the step neither faults nor writes out of range."""
+    k = Case(cavity(dim, n, 4), 0)
+    c = k.c
+    with pytest.raises(oracle.OracleError) as eo:
+        oracle.wall_stencil(c, k.x, k.wid)
+    assert eo.value.code == bgk.BGK_ESINGULAR
+    f0, rho0, U0, T0 = oracle.initial_state(c)
+    f, fn = k.t(f0), k.t(np.zeros_like(f0))
+    U, rho, T = k.t(U0), k.t(rho0), k.t(T0)
+    bgk.bgk_step(k.ctx, f, fn, k.x_t, U, rho, T)
+    with pytest.raises(bgk.BgkError) as eg:
+        bgk.bgk_check(k.ctx)
+    assert eg.value.code == bgk.BGK_ESINGULAR
+    assert np.all(np.isfinite(fn.cpu().numpy()[:, k.wid == 0]))
+
+
 @pytest.mark.parametrize("dim,n,nv", [(2, 12, 16), (2, 10, 24), (3, 7, 8)])
 def test_collide_and_walls_match(dim, n, nv):
     k = Case(cavity(dim, n, nv), 5)
