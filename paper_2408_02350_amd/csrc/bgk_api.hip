@@ -75,7 +75,8 @@ bool config_ok(const bgk_config& g) {
 size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj) {
   const int64_t N = cfg.n_particles, cap = cfg.max_neighbors, D = cfg.dim, DD = D * D;
   const int64_t ncell = ipow(cells_per_axis(cfg), cfg.dim);
-  const int64_t npatch = (N + kPatch - 1) / kPatch, ucap = static_cast<int64_t>(kPatch) * cap;
+  const int64_t tp = patch_size(cfg.dim, cfg.precision);
+  const int64_t npatch = (N + tp - 1) / tp, ucap = tp * cap;
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
     char* p = base ? base + off : nullptr;
@@ -216,8 +217,9 @@ int bgk_init(const bgk_config* cfg, const int32_t* wall_id, void* workspace, siz
       if (wid[i] == w) wl.push_back(i);
   c.Nw = static_cast<int>(wl.size());
   c.Ni = c.N - c.Nw;
-  c.npatch = (c.Ni + bgk::kPatch - 1) / bgk::kPatch;
-  c.ucap = bgk::kPatch * c.cap;
+  c.tp = bgk::patch_size(c.D, cfg->precision);
+  c.npatch = (c.Ni + c.tp - 1) / c.tp;
+  c.ucap = c.tp * c.cap;
   int32_t zeros[bgk::kErrWords] = {0};
   e = hipMemcpyAsync(c.d.wall_id, wid.data(), sizeof(int32_t) * c.N, hipMemcpyHostToDevice,
                      c.stream);

@@ -13,7 +13,13 @@
 
 namespace bgk {
 
-constexpr int kPatch = 4;       // interior particles per transport patch
+// Interior particles per transport patch: 2 for FP64 in 2D (its
+// accumulators then fit 4 velocities per lane in 256-lane blocks), else 4.
+// The union entries pack one byte per patch particle, so at most 4.
+constexpr int kPatchMax = 4;
+__host__ __device__ constexpr int patch_size(int dim, int precision) {
+  return (dim == 2 && precision == BGK_FP64) ? 2 : 4;
+}
 constexpr int kThreads = 256;   // threads per block of the per-particle kernels
 
 // bit of the device error word for each status code
@@ -70,7 +76,7 @@ struct Ctx {
   hipStream_t stream = nullptr;
   int device = 0;
   int N = 0, D = 0, NC = 0, NV = 0, cap = 0, DD = 0;
-  int Ni = 0, Nw = 0, npatch = 0, ucap = 0;
+  int Ni = 0, Nw = 0, npatch = 0, ucap = 0, tp = 4;  // tp: particles per patch
   int nca = 0, ncell = 0;
   double lid = 0.0;
   Dev d{};

@@ -1,5 +1,5 @@
 // S4 + S5 + S6 fused: transport, moments and implicit relaxation of a patch
-// of kPatch interior particles over ALL velocities in one block.
+// of tp interior particles over ALL velocities in one block.
 //
 //   ft_i(v) = f_i(v) - dt sum_{j != i} c_ij(v) (f_j(v) - f_i(v)),
 //   c_ij(v) = 2 sum_k min(0, a_k.(v - U_i)),  a_k in {P, Q[, R]}     (S4)
@@ -148,7 +148,7 @@ constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 
 template <int D, int NC, int MODE, int R, bool FUSE>
 __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   using Real = typename FPrec<MODE>::real;
-  constexpr int TP = kPatch, DD = D * D;
+  constexpr int TP = patch_size(D, MODE), DD = D * D;
   constexpr bool DIFF = (MODE == BGK_BF16);     // products of differences
   constexpr int REC = DD + 2 * D;               // a_k (d*d), a_k.U (d), a_k[fast]*dvs (d)
   constexpr int KM = TP * (D + 1);              // first-pass moment sums per thread
@@ -547,7 +547,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
 // Launch plan: R velocities per thread along the fastest axis (R divides
 // nv, so a thread's R velocities share every other component), at most
 // Rmax for the precision and model (the per-thread accumulators are
-// kPatch * R * (n_c + 1) values), and the fewest velocity tiles of at most
+// tp * R * (n_c + 1) values), and the fewest velocity tiles of at most
 // 1024 threads (2D: fewer, see lanes_max).  One tile can run the
 // fused relaxation; several tiles write f-tilde for the separate kernel.
 struct FusedPlan {
@@ -561,13 +561,13 @@ static FusedPlan plan_fused(const Ctx& c) {
   static const int r64[] = {1, 2, 4};
   static const int r2d[] = {1, 2, 4, 5};
   static const int r3d[] = {1, 2, 4, 5, 8, 10};
-  const int rmax = D == 2 ? (f64 ? 2 : 4) : (f64 ? 4 : 10);
+  const int rmax = D == 2 ? 4 : (f64 ? 4 : 10);
   const int* cand = f64 ? r64 : (D == 2 ? r2d : r3d);
   const int ncand = f64 ? 3 : (D == 2 ? 4 : 6);
-  // 2D: FP64 at most 512 lanes (two blocks per CU at its register use);
-  // FP32 / BF16 at most 256 lanes, i.e. 4 velocities per lane at 32^2
-  // (fewer, wider row loads and one projection set-up per 4 velocities)
-  const int lanes_max = D == 2 ? (f64 ? 512 : 256) : 1024;
+  // 2D: at most 256 lanes, i.e. 4 velocities per lane at 32^2 (fewer,
+  // wider row loads and one projection set-up per 4 velocities; FP64 gets
+  // the registers for it from its 2-particle patches)
+  const int lanes_max = D == 2 ? 256 : 1024;
   FusedPlan p;
   // one tile: the smallest admissible R that fits
   for (int i = 0; i < ncand; ++i) {

@@ -70,7 +70,7 @@ hipError_t launch_max_i32(hipStream_t s, const int32_t* a, int n, int32_t* out) 
 // Order of the cells.  The first d-1 axes are cut into tiles of
 // kCellTile<D> cells (strips in 2D, columns in 3D) and each tile is swept
 // along the last axis, x fastest inside the tile.  Interior particles are
-// processed in this order in patches of kPatch, and each XCD takes one
+// processed in this order in patches of tp, and each XCD takes one
 // contiguous range of patches; sweeping a narrow tile brings a neighbour row
 // back within a few patches, while it is still in the XCD's L2 (a plain
 // row-major order returns to it only one full row of cells later).
@@ -914,7 +914,7 @@ hipError_t launch_scatter_wall_rows(const Ctx& c, int32_t* cnt_out, int32_t* idx
 }
 
 // ------------------------------------------------------------ patch unions
-// Interior particles, taken kPatch at a time in cell order, form a patch.
+// Interior particles, taken tp at a time in cell order, form a patch.
 // The transport walks the sorted union of the patch's neighbour lists (self
 // excluded) once, loading each f_j row once for all of them.  ue[u] holds,
 // per patch slot t, the position of j in slot t's neighbour row in byte t
@@ -931,7 +931,7 @@ __device__ __forceinline__ int lower_bound_i(const int32_t* v, int n, int x) {
   return lo;
 }
 
-__global__ __launch_bounds__(64) void k_patches(int Ni, int cap, int ucap,
+__global__ __launch_bounds__(64) void k_patches(int Ni, int P, int cap, int ucap,
                                                 const int32_t* __restrict__ plist,
                                                 const int32_t* __restrict__ cnt,
                                                 const int32_t* __restrict__ idx,
@@ -939,14 +939,14 @@ __global__ __launch_bounds__(64) void k_patches(int Ni, int cap, int ucap,
                                                 int32_t* __restrict__ uj, uint32_t* __restrict__ ue,
                                                 int32_t* __restrict__ err) {
   extern __shared__ int32_t psm[];
-  int32_t* rj = psm;                        // [kPatch][cap] neighbour j (self removed)
-  int32_t* re = rj + kPatch * cap;          // [kPatch][cap] its slot in the full row
-  int32_t* mj = re + kPatch * cap;          // [kPatch*cap] merged j
-  int32_t* mt = mj + kPatch * cap;          // merged (slot t << 8 | e)
-  __shared__ int32_t rn[kPatch], spt[kPatch], sm_[kPatch], sself[kPatch], spre[kPatch + 1];
+  int32_t* rj = psm;                        // [P][cap] neighbour j (self removed)
+  int32_t* re = rj + P * cap;          // [P][cap] its slot in the full row
+  int32_t* mj = re + P * cap;          // [P*cap] merged j
+  int32_t* mt = mj + P * cap;          // merged (slot t << 8 | e)
+  __shared__ int32_t rn[kPatchMax], spt[kPatchMax], sm_[kPatchMax], sself[kPatchMax], spre[kPatchMax + 1];
   const int p = blockIdx.x, lane = threadIdx.x;
-  if (lane < kPatch) {
-    const int g = p * kPatch + lane;
+  if (lane < P) {
+    const int g = p * P + lane;
     const int pt = g < Ni ? plist[g] : -1;
     spt[lane] = pt;
     sm_[lane] = pt >= 0 ? min(cnt[pt], cap) : 0;
@@ -955,12 +955,12 @@ __global__ __launch_bounds__(64) void k_patches(int Ni, int cap, int ucap,
   __syncthreads();
   // self is in its row exactly once (at most once if the row overflowed):
   // find it in all rows at once, then copy the rows without it
-  for (int w = lane; w < kPatch * cap; w += kWave) {
+  for (int w = lane; w < P * cap; w += kWave) {
     const int t = w / cap, e = w - t * cap;
     if (e < sm_[t] && idx[static_cast<int64_t>(spt[t]) * cap + e] == spt[t]) sself[t] = e + 1;
   }
   __syncthreads();
-  for (int w = lane; w < kPatch * cap; w += kWave) {
+  for (int w = lane; w < P * cap; w += kWave) {
     const int t = w / cap, e = w - t * cap;
     if (e >= sm_[t]) continue;
     const int sp = sself[t] - 1;
@@ -969,14 +969,14 @@ __global__ __launch_bounds__(64) void k_patches(int Ni, int cap, int ucap,
     rj[t * cap + o] = idx[static_cast<int64_t>(spt[t]) * cap + e];
     re[t * cap + o] = e;
   }
-  if (lane < kPatch) rn[lane] = sself[lane] ? sm_[lane] - 1 : sm_[lane];
+  if (lane < P) rn[lane] = sself[lane] ? sm_[lane] - 1 : sm_[lane];
   __syncthreads();
   if (lane == 0) {
     spre[0] = 0;
-    for (int t = 0; t < kPatch; ++t) spre[t + 1] = spre[t] + rn[t];
+    for (int t = 0; t < P; ++t) spre[t + 1] = spre[t] + rn[t];
   }
   __syncthreads();
-  const int total = spre[kPatch];
+  const int total = spre[P];
   // merged position of every (t, q): q plus, in each other row, the entries
   // before it (equal j in a lower slot t first)
   for (int w = lane; w < total; w += kWave) {
@@ -985,7 +985,7 @@ __global__ __launch_bounds__(64) void k_patches(int Ni, int cap, int ucap,
     const int q = w - spre[t];
     const int j = rj[t * cap + q];
     int pos = q;
-    for (int s2 = 0; s2 < kPatch; ++s2) {
+    for (int s2 = 0; s2 < P; ++s2) {
       if (s2 == t) continue;
       const int* v = rj + s2 * cap;
       pos += (s2 < t) ? lower_bound_i(v, rn[s2], j + 1) : lower_bound_i(v, rn[s2], j);
@@ -1018,8 +1018,8 @@ __global__ __launch_bounds__(64) void k_patches(int Ni, int cap, int ucap,
 
 hipError_t launch_patches(const Ctx& c) {
   if (c.npatch == 0) return hipSuccess;
-  const size_t sm = static_cast<size_t>(4) * kPatch * c.cap * sizeof(int32_t);
-  hipLaunchKernelGGL(k_patches, dim3(c.npatch), dim3(kWave), sm, c.stream, c.Ni, c.cap, c.ucap,
+  const size_t sm = static_cast<size_t>(4) * c.tp * c.cap * sizeof(int32_t);
+  hipLaunchKernelGGL(k_patches, dim3(c.npatch), dim3(kWave), sm, c.stream, c.Ni, c.tp, c.cap, c.ucap,
                      c.d.cperm, c.d.ncnt, c.d.nidx, c.d.ucount, c.d.uj, c.d.ue, c.d.err);
   return hipGetLastError();
 }

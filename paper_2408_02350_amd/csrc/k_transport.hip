@@ -7,7 +7,7 @@
 //
 // Work decomposition: lanes run over velocities (f is [n_c][N][N_v] with the
 // velocity contiguous, so every f_j load of a wavefront is one coalesced
-// segment).  A block owns a patch of kPatch interior particles that are
+// segment).  A block owns a patch of tp interior particles that are
 // neighbours in the cell order and a tile of 256*R velocities; it walks the
 // sorted union of the patch's neighbour lists once, so each f_j row segment
 // is loaded once and applied to every patch particle that has j as a
@@ -59,7 +59,7 @@ __device__ __forceinline__ float bf16_round(float x) {
 template <int D, int NC, int MODE, int R>
 __global__ __launch_bounds__(kThreads) void k_transport(const TransportArgs a) {
   using Real = typename PrecT<MODE>::real;
-  constexpr int DD = D * D, TP = kPatch;
+  constexpr int DD = D * D, TP = patch_size(D, MODE);
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const int patch = lb % a.npatch, tile = lb / a.npatch;
   const Real* __restrict__ f = static_cast<const Real*>(a.f);
