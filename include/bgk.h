@@ -74,7 +74,7 @@ enum { BGK_FLAG_GENERIC = 1, BGK_FLAG_ADJOINT = 2 };
 typedef struct {
   int32_t dim;           /* 2: Chu-reduced BGK (Sec. 2.1, g1 and g2); 3: full BGK        */
   int32_t n_particles;   /* N, interior + wall                                           */
-  int32_t nv;            /* velocity points per axis, even, >= 2                         */
+  int32_t nv;            /* velocity points per axis, even, 2..1024                      */
   int32_t wls_degree;    /* 1 or 2: polynomial degree of the least-squares fit           */
   int32_t max_neighbors; /* neighbour slots per particle (self included), <= 255         */
   int32_t move;          /* 1: ALE motion (S8); 0: frozen cloud (geometry reused)        */
@@ -105,8 +105,8 @@ int bgk_workspace_bytes(const bgk_config* cfg, size_t* bytes);
 /* Create a context.  cfg is copied.  wall_id: device int32 [N] (read once,
  * synchronously, at init).  workspace: device buffer of ws_bytes bytes that
  * the caller keeps alive until bgk_destroy.  hip_stream: hipStream_t or NULL.
- * *out receives the context (host).  Errors: BGK_EINVAL (dim not 2/3, odd nv,
- * N <= 0, dt <= 0, bad degree or capacity), BGK_ENOMEM (ws_bytes too small),
+ * *out receives the context (host).  Errors: BGK_EINVAL (dim not 2/3, odd nv
+ * or nv > 1024, N <= 0, dt <= 0, bad degree or capacity), BGK_ENOMEM (ws_bytes too small),
  * BGK_EDEVICE. */
 int bgk_init(const bgk_config* cfg, const int32_t* wall_id, void* workspace, size_t ws_bytes,
              void* hip_stream, bgk_ctx** out);

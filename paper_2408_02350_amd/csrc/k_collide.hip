@@ -178,18 +178,45 @@ __device__ __forceinline__ void load_vec(const Real* __restrict__ p, Real (&o)[R
   }
 }
 
-// Diffuse reflection on wall particle b (one block of up to 256 threads, so
-// that every wall particle's block is resident at once): arriving
-// velocities (v.n <= 0, n the inward normal) take the interpolated interior
-// value sum_e c0_e f_j; emitted ones take rho_w M[1, U_w, T_w] (Chu: G1 and
-// T_w G1 scaled by rho_w) with rho_w from zero net mass flux; then the
-// particle's moments in two passes (U first, then the centred second
-// moment).  A thread handles R consecutive velocities (one vector load per
-// stencil row and component, rows taken two at a time) and re-reads only
-// the velocities it wrote itself.
+// R consecutive elements of a row written with the widest aligned vector
+// store (p is aligned to R elements).
+template <typename Real, int R>
+__device__ __forceinline__ void store_vec(Real* __restrict__ p, const Real (&x)[R]) {
+  constexpr int W = (R * sizeof(Real)) % 16 == 0 ? 16 / static_cast<int>(sizeof(Real)) : R;
+  typedef Real V __attribute__((ext_vector_type(W)));
+  V* pv = reinterpret_cast<V*>(__builtin_assume_aligned(p, W * sizeof(Real)));
+#pragma unroll
+  for (int i = 0; i < R / W; ++i) {
+    V y;
+#pragma unroll
+    for (int w = 0; w < W; ++w) y[w] = x[i * W + w];
+    pv[i] = y;
+  }
+}
+
+// Diffuse reflection on wall particle b (S7; one block of up to 256 threads
+// per wall particle).  With the owner wall's inward normal s e_a, the
+// arriving velocities (s v_a <= 0) are exactly the half k_a < nv/2 (s > 0)
+// or k_a >= nv/2 (s < 0) of axis a (v_k is odd about the grid centre and nv
+// is even), and the emitted ones the other half.  Both halves are walked as
+// groups of R consecutive velocities along the fastest axis (R divides
+// nv/2), so every lane of a gather has work:
+//   arriving: f_b(v) = sum_e c0_e f_j(v) (rows four at a time), and the
+//     inflow sum_arriving (-v.n) f_b1;
+//   emitted:  f_b = rho_w M[1, U_w, T_w] (Chu: G1 and T_w G1 scaled by rho_w),
+//     rho_w = inflow / sum_emitted (v.n) M[1, U_w, T_w].
+// The Maxwellian is a product of per-axis exponentials held in LDS, and the
+// emitted outflow sum factorises into per-axis sums.  The particle's moments
+// follow in two passes (U first, then the centred second moment).  A thread
+// re-reads only velocities it wrote itself.
 template <int D, int NC, typename Real, int R>
 __global__ __launch_bounds__(kThreads) void k_wall_bc(const WallBcArgs a) {
+  extern __shared__ double wtab[];  // v_k [nv], then exp(-(v_k - Uw_a)^2 / (2 T_w)) [D][nv]
   __shared__ double sh[16 * (D + 1)];
+  __shared__ double axsum[D];
+  const int nv = a.nv, hv = nv / 2;
+  double* vtab = wtab;
+  double* etab = wtab + nv;
   const int k = xcd_logical_block(blockIdx.x, gridDim.x);  // neighbouring walls share an L2
   const int nw = blockDim.x >> 6;
   const int b = a.wall_list[k];
@@ -197,122 +224,178 @@ __global__ __launch_bounds__(kThreads) void k_wall_bc(const WallBcArgs a) {
   const int axis = (w - 1) / 2;
   const double sgn = ((w - 1) % 2 == 0) ? 1.0 : -1.0;
   const bool is_lid = (w == 2 * D);
-  double Uw[3] = {is_lid ? a.lid : 0.0, 0.0, 0.0};
+  const double Uw[3] = {is_lid ? a.lid : 0.0, 0.0, 0.0};
+  const double Tw = a.wall_T;
+  for (int i = threadIdx.x; i < D * nv; i += blockDim.x) {
+    const int ax = i / nv, kk = i - ax * nv;
+    const double v = vnode(kk, nv, a.vmax);
+    if (ax == 0) vtab[kk] = v;
+    const double dv = v - Uw[ax];
+    etab[i] = exp(-(dv * dv) / (2.0 * Tw));
+  }
+  __syncthreads();
+  if (threadIdx.x < D) {
+    const int ax = threadIdx.x;
+    double t = 0.0;
+    for (int kk = 0; kk < nv; ++kk) {
+      const double e = etab[ax * nv + kk];
+      if (ax != axis) {
+        t = t + e;
+      } else {
+        const double vn = sgn * vtab[kk];
+        if (vn > 0.0) t = t + vn * e;
+      }
+    }
+    axsum[ax] = t;
+  }
+  // normalisation of M[1, U_w, T_w] (Sec. 2; Chu G1 in 2D)
+  const double tp = 2.0 * kPi * Tw;
+  const double norm = D == 3 ? 1.0 / (tp * sqrt(tp)) : 1.0 / tp;
+
   const int m = a.wcnt[k];
   const int32_t* row = a.widx + static_cast<size_t>(k) * a.cap;
   const double* c0 = a.wc0 + static_cast<size_t>(k) * a.cap;
   const size_t NVs = a.NV, cs = static_cast<size_t>(a.N) * NVs;
   Real* f = static_cast<Real*>(a.f);
   Real* fb = f + static_cast<size_t>(b) * NVs;
-  const int step = R * static_cast<int>(blockDim.x);
-  double flux[2] = {0.0, 0.0};
-  for (int q0 = R * static_cast<int>(threadIdx.x); q0 < a.NV; q0 += step) {
+  const int G = a.NV / (2 * R);  // groups per half
+  const int off_in = sgn > 0.0 ? 0 : hv, off_out = hv - off_in;
+  // group g of the half whose axis-a indices start at offa: first velocity
+  // index and its per-axis indices
+  auto group_q = [&](int g, int offa, int (&kq)[3]) {
+    int rest = g, q = 0, stride = 1;
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+      const int ext = (ax == axis ? hv : nv) / (ax == 0 ? R : 1);
+      int kk = rest % ext;
+      rest /= ext;
+      if (ax == 0) kk *= R;
+      if (ax == axis) kk += offa;
+      kq[ax] = kk;
+      q += kk * stride;
+      stride *= nv;
+    }
+    return q;
+  };
+
+  double inflow[1] = {0.0};
+  double sm[D + 1];
+#pragma unroll
+  for (int kk = 0; kk < D + 1; ++kk) sm[kk] = 0.0;
+  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+    int kq[3] = {0, 0, 0};
+    const int q0 = group_q(g, off_in, kq);
     double s[NC][R];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int r = 0; r < R; ++r) s[c][r] = 0.0;
-    // only arriving velocities are interpolated: skip the gather when all R
-    // of this thread are emitted (whole waves on the faces normal to y, z)
-    bool arriving = false;
+    int e = 0;
+    for (; e + 4 <= m; e += 4) {
+      Real x[4][NC][R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      double v[3];
-      velocity_of<D>(q0 + r, a.nv, a.vmax, v);
-      arriving = arriving || sgn * v[axis] <= 0.0;
-    }
-    int e = arriving ? 0 : m;
-    for (; e + 1 < m; e += 2) {
-      Real x0[NC][R], x1[NC][R];
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        load_vec<Real, R>(f + c * cs + static_cast<size_t>(row[e]) * NVs + q0, x0[c]);
-        load_vec<Real, R>(f + c * cs + static_cast<size_t>(row[e + 1]) * NVs + q0, x1[c]);
+        for (int c = 0; c < NC; ++c)
+          load_vec<Real, R>(f + c * cs + static_cast<size_t>(row[e + u]) * NVs + q0, x[u][c]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double wu = c0[e + u];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int r = 0; r < R; ++r) s[c][r] = s[c][r] + wu * static_cast<double>(x[u][c][r]);
       }
-      const double w0 = c0[e], w1 = c0[e + 1];
+    }
+    for (; e < m; ++e) {
+      Real x[NC][R];
 #pragma unroll
       for (int c = 0; c < NC; ++c)
+        load_vec<Real, R>(f + c * cs + static_cast<size_t>(row[e]) * NVs + q0, x[c]);
+      const double wu = c0[e];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[c][r] = s[c][r] + wu * static_cast<double>(x[c][r]);
+    }
+    double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ax = 1; ax < D; ++ax) v[ax] = vtab[kq[ax]];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      Real y[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) y[r] = static_cast<Real>(s[c][r]);
+      store_vec<Real, R>(fb + c * cs + q0, y);
+      if (c == 0) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          s[c][r] = s[c][r] + w0 * static_cast<double>(x0[c][r]);
-          s[c][r] = s[c][r] + w1 * static_cast<double>(x1[c][r]);
+          v[0] = vtab[kq[0] + r];
+          const double x0 = static_cast<double>(y[r]);
+          inflow[0] = inflow[0] + (-sgn * v[axis]) * x0;
+          sm[0] = sm[0] + x0;
+#pragma unroll
+          for (int ax = 0; ax < D; ++ax) sm[1 + ax] = sm[1 + ax] + v[ax] * x0;
         }
-    }
-    if (e < m) {
-      Real x0[NC][R];
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-        load_vec<Real, R>(f + c * cs + static_cast<size_t>(row[e]) * NVs + q0, x0[c]);
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int r = 0; r < R; ++r) s[c][r] = s[c][r] + c0[e] * static_cast<double>(x0[c][r]);
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      double v[3];
-      velocity_of<D>(q0 + r, a.nv, a.vmax, v);
-      const double vn = sgn * v[axis];
-      if (vn <= 0.0) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const Real sr = static_cast<Real>(s[c][r]);
-          fb[c * cs + q0 + r] = sr;
-          if (c == 0) flux[0] = flux[0] + (-vn) * static_cast<double>(sr);
-        }
-      } else {
-        flux[1] = flux[1] + vn * maxwell<D>(0, 1.0, Uw, a.wall_T, v);
       }
     }
   }
-  block_sum_n<2>(flux, sh, nw);
-  const double rho_w = flux[0] / flux[1];
-  double sm[D + 1];
+  block_sum_n<1>(inflow, sh, nw);  // its barriers also publish axsum
+  double outflow = norm;
 #pragma unroll
-  for (int kk = 0; kk < D + 1; ++kk) sm[kk] = 0.0;
-  for (int q0 = R * static_cast<int>(threadIdx.x); q0 < a.NV; q0 += step) {
+  for (int ax = 0; ax < D; ++ax) outflow = outflow * axsum[ax];
+  const double rho_w = inflow[0] / outflow;
+  const double cw = rho_w * norm;
+  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+    int kq[3] = {0, 0, 0};
+    const int q0 = group_q(g, off_out, kq);
+    double efix = cw;
+    double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ax = 1; ax < D; ++ax) {
+      efix = efix * etab[ax * nv + kq[ax]];
+      v[ax] = vtab[kq[ax]];
+    }
+    Real y[NC][R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int q = q0 + r;
-      double v[3];
-      velocity_of<D>(q, a.nv, a.vmax, v);
-      const double vn = sgn * v[axis];
-      double x0;
-      if (vn > 0.0) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const Real y = static_cast<Real>(maxwell<D>(c, rho_w, Uw, a.wall_T, v));
-          fb[c * cs + q] = y;
-          if (c == 0) x0 = static_cast<double>(y);
-        }
-      } else {
-        x0 = static_cast<double>(fb[q]);
-      }
+      const double g1 = efix * etab[kq[0] + r];
+      y[0][r] = static_cast<Real>(g1);
+      if (NC == 2) y[NC - 1][r] = static_cast<Real>(Tw * g1);
+      v[0] = vtab[kq[0] + r];
+      const double x0 = static_cast<double>(y[0][r]);
       sm[0] = sm[0] + x0;
 #pragma unroll
-      for (int kk = 0; kk < D; ++kk) sm[1 + kk] = sm[1 + kk] + v[kk] * x0;
+      for (int ax = 0; ax < D; ++ax) sm[1 + ax] = sm[1 + ax] + v[ax] * x0;
     }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) store_vec<Real, R>(fb + c * cs + q0, y[c]);
   }
   block_sum_n<D + 1>(sm, sh, nw);
   const double s0 = sm[0];
   double U[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-  for (int kk = 0; kk < D; ++kk) U[kk] = sm[1 + kk] / s0;
+  for (int ax = 0; ax < D; ++ax) U[ax] = sm[1 + ax] / s0;
   double e2[1] = {0.0};
-  for (int q0 = R * static_cast<int>(threadIdx.x); q0 < a.NV; q0 += step) {
+  for (int half = 0; half < 2; ++half) {
+    for (int g = threadIdx.x; g < G; g += blockDim.x) {
+      int kq[3] = {0, 0, 0};
+      const int q0 = group_q(g, half == 0 ? off_in : off_out, kq);
+      double wfix = 0.0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int q = q0 + r;
-      double v[3];
-      velocity_of<D>(q, a.nv, a.vmax, v);
-      double w2 = 0.0;
-#pragma unroll
-      for (int kk = 0; kk < D; ++kk) {
-        const double wk = v[kk] - U[kk];
-        w2 = w2 + wk * wk;
+      for (int ax = 1; ax < D; ++ax) {
+        const double wk = vtab[kq[ax]] - U[ax];
+        wfix = wfix + wk * wk;
       }
-      e2[0] = e2[0] + w2 * static_cast<double>(fb[q]);
-      if (NC == 2) e2[0] = e2[0] + static_cast<double>(fb[cs + q]);
+      Real x[NC][R];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) load_vec<Real, R>(fb + c * cs + q0, x[c]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double w0 = vtab[kq[0] + r] - U[0];
+        e2[0] = e2[0] + (w0 * w0 + wfix) * static_cast<double>(x[0][r]);
+        if (NC == 2) e2[0] = e2[0] + static_cast<double>(x[NC - 1][r]);
+      }
     }
   }
   block_sum_n<1>(e2, sh, nw);
@@ -322,18 +405,21 @@ __global__ __launch_bounds__(kThreads) void k_wall_bc(const WallBcArgs a) {
     a.rho[b] = rho;
     a.T[b] = T;
 #pragma unroll
-    for (int kk = 0; kk < D; ++kk) a.U[static_cast<size_t>(kk) * a.N + b] = U[kk];
+    for (int ax = 0; ax < D; ++ax) a.U[static_cast<size_t>(ax) * a.N + b] = U[ax];
     if (!(rho > 0.0) || !(T > 0.0) || m == 0) raise_error(a.err, BGK_ENONPHYS);
   }
 }
 
 template <int D, int NC, typename Real>
 static void wall_bc_t(const Ctx& c, const WallBcArgs& a) {
-  const int R = (c.cfg.nv % 4 == 0) ? 4 : 2;  // nv is even
-  const int lanes = c.NV / R;
-  dim3 g(c.Nw), t(std::min(kThreads, (lanes + 63) / 64 * 64));
-  if (R == 4) hipLaunchKernelGGL((k_wall_bc<D, NC, Real, 4>), g, t, 0, c.stream, a);
-  else hipLaunchKernelGGL((k_wall_bc<D, NC, Real, 2>), g, t, 0, c.stream, a);
+  const int hv = c.cfg.nv / 2;  // nv is even
+  const int R = hv % 4 == 0 ? 4 : (hv % 2 == 0 ? 2 : 1);
+  const int groups = c.NV / (2 * R);
+  dim3 g(c.Nw), t(std::min(kThreads, (groups + 63) / 64 * 64));
+  const size_t lds = static_cast<size_t>(D + 1) * c.cfg.nv * sizeof(double);
+  if (R == 4) hipLaunchKernelGGL((k_wall_bc<D, NC, Real, 4>), g, t, lds, c.stream, a);
+  else if (R == 2) hipLaunchKernelGGL((k_wall_bc<D, NC, Real, 2>), g, t, lds, c.stream, a);
+  else hipLaunchKernelGGL((k_wall_bc<D, NC, Real, 1>), g, t, lds, c.stream, a);
 }
 
 hipError_t launch_wall_bc(const Ctx& c, void* f, double* rho, double* U, double* T) {
