@@ -61,7 +61,10 @@ def test_workspace_sizing_and_validation(lib):
     assert n > 0
     bigger = lib.bgk_workspace_bytes(_cfg(lib, n_particles=3200))
     assert bigger > n
-    for bad in (dict(nv=15), dict(dim=4), dict(n_particles=0), dict(dt=-1.0),
+    # the largest velocity grid per axis (exponential tables of the wall
+    # condition live in LDS)
+    assert lib.bgk_workspace_bytes(_cfg(lib, nv=1024)) > 0
+    for bad in (dict(nv=15), dict(nv=1026), dict(dim=4), dict(n_particles=0), dict(dt=-1.0),
                 dict(wls_degree=3), dict(max_neighbors=300), dict(precision=5),
                 dict(flags=2), dict(h=0.0)):
         with pytest.raises(lib.BgkError) as e:
