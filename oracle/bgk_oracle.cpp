@@ -89,7 +89,7 @@ typedef struct {
   int32_t dim;          // 2: Chu-reduced (components g1, g2); 3: full BGK
   int32_t n_particles;  // N, interior and wall particles
   int32_t nv;           // velocity points per axis, both ends included
-  int32_t wls_degree;   // 1 or 2
+  int32_t wls_degree;   // 0: first-order fit of f_j - f_i (no constant); 1 or 2
   int32_t cap;          // neighbour slots per particle (self included)
   int32_t move;         // 1: x += dt U after the step; 0: frozen cloud
   double vmax;          // velocity grid spans [-vmax, vmax]
@@ -240,9 +240,20 @@ int neighbors(const ref_config& c, const double* x, int32_t* cnt, int32_t* idx) 
 // term, of degree 2 (or 1), in offsets scaled by h; the particle itself is in
 // its stencil with weight 1.  The derivative rows annihilate constants, so
 // the transport keeps the paper's difference form sum_j a_ij (f_j - f_i).
-int basis_size(int d, int deg) { return deg == 1 ? d + 1 : (d == 2 ? 6 : 10); }
+// Degree 0 is the fit exactly as printed: the unknowns are the d first
+// derivatives only, the rows of M are the offsets, and the solution is
+// a = (M^T W M)^-1 M^T W b with b_j = f_j - f_i (the particle itself has a
+// zero offset and drops out of both sums).
+int basis_size(int d, int deg) { return deg == 0 ? d : (deg == 1 ? d + 1 : (d == 2 ? 6 : 10)); }
+
+// column of the basis that carries the first derivative along axis a
+int grad_column(int deg, int a) { return deg == 0 ? a : 1 + a; }
 
 void basis(int d, int deg, const double* y, double* p) {
+  if (deg == 0) {
+    for (int a = 0; a < d; ++a) p[a] = y[a];
+    return;
+  }
   p[0] = 1.0;
   for (int a = 0; a < d; ++a) p[1 + a] = y[a];
   if (deg == 2) {
@@ -323,7 +334,8 @@ void edge_frame(int d, const double* dl, double n[3], double t[3], double b[3]) 
 // rotation of Section 3.4.2; in 3D the same rotation, which needs A, not
 // its transpose, to keep P + Q + R = g).
 // Degree: the configured degree if the stencil has at least twice as many
-// points as basis functions, else degree 1 if it has d+2 points, else error.
+// points as basis functions, else degree 1 if it has d+2 points, else error
+// (degree 0 also needs d+2 points, the particle itself included).
 int wls(const ref_config& c, const double* x, const int32_t* wall_id, const int32_t* cnt,
         const int32_t* idx, double* grad, double* ops, int32_t* degree) {
   const int N = c.n_particles, d = c.dim, cap = c.cap, dd = d * d;
@@ -368,7 +380,7 @@ int wls(const ref_config& c, const double* x, const int32_t* wall_id, const int3
       continue;
     }
     double z[3][16];
-    for (int a = 0; a < d; ++a) chol_solve_unit(B, L, 1 + a, z[a]);
+    for (int a = 0; a < d; ++a) chol_solve_unit(B, L, grad_column(deg, a), z[a]);
     for (int e = 0; e < m; ++e) {
       const int j = idx[row + e];
       double g[3] = {0, 0, 0};
@@ -679,7 +691,7 @@ int move(const ref_config& c, const int32_t* wall_id, const double* U, double* x
 
 bool config_ok(const ref_config& c) {
   return (c.dim == 2 || c.dim == 3) && c.n_particles > 0 && c.nv >= 2 && c.nv % 2 == 0 &&
-         (c.wls_degree == 1 || c.wls_degree == 2) && c.cap > 0 && c.dt > 0 && c.h > 0 &&
+         c.wls_degree >= 0 && c.wls_degree <= 2 && c.cap > 0 && c.dt > 0 && c.h > 0 &&
          c.vmax > 0 && c.kn > 0;
 }
 

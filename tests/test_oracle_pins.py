@@ -205,6 +205,72 @@ def test_wls_matches_dense_weighted_lstsq(dim, n):
         assert np.allclose(est, ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
 
 
+# Degree 0: the least-squares fit as printed in Sec. 3.1 (eqs. taylor,
+# solution, x/y/z_derivative): unknowns are the first derivatives only, the
+# rows of M are the offsets x_j - x_i, b_j = f_j - f_i, no constant column.
+@pytest.mark.parametrize("dim,n", [(2, 30), (3, 10)])
+def test_first_order_fit_reproduces_linear_functions(dim, n):
+    x, wid = make_cloud(dim, n, 2)
+    c = cfg(dim, n, 4, 4.0, wls_degree=0, h=3.1 / (n - 1), cap=200)
+    cnt, idx, grad, ops, deg = geometry(c, x, wid)
+    interior = np.nonzero(wid == 0)[0]
+    assert np.all(deg[interior] == 0) and np.all(deg[wid != 0] == 0)
+    b = np.random.default_rng(11).normal(size=dim)
+    p = b @ x + 0.7
+    for i in interior:
+        e = np.arange(cnt[i])
+        est = (grad[i, e, :] * (p[idx[i, e]] - p[i])[:, None]).sum(axis=0)
+        assert np.max(np.abs(est - b)) <= 1e-12 * np.abs(b).max(), i
+        # the particle itself has a zero offset: its row is exactly zero
+        self_e = e[idx[i, e] == i]
+        assert np.all(grad[i, self_e, :] == 0.0)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 7), (3, 5)])
+def test_first_order_fit_matches_dense_weighted_lstsq(dim, n):
+    """Brute force on the printed system: minimise sum_j w_j (b_j - M_j a)^2
+    with M_j = x_j - x_i (unscaled), b_j = f_j - f_i and the truncated
+    Gaussian weight exp(-alpha r^2 / h^2), by numpy lstsq."""
+    x, wid = make_cloud(dim, n, 4)
+    h = 3.1 / (n - 1)
+    c = cfg(dim, n, 4, 4.0, wls_degree=0, h=h, cap=200)
+    cnt, idx, grad, ops, deg = geometry(c, x, wid)
+    fv = np.random.default_rng(5).normal(size=c.n_particles)
+    for i in np.nonzero(wid == 0)[0]:
+        js = idx[i, :cnt[i]]
+        js = js[js != i]
+        M = (x[:, js] - x[:, i:i + 1]).T
+        w = np.exp(-6.0 * (M ** 2).sum(axis=1) / h ** 2)
+        sw = np.sqrt(w)
+        a, *_ = np.linalg.lstsq(sw[:, None] * M, sw * (fv[js] - fv[i]), rcond=None)
+        est = (grad[i, :cnt[i], :] * (fv[idx[i, :cnt[i]]] - fv[i])[:, None]).sum(axis=0)
+        assert np.allclose(est, a, rtol=1e-10, atol=1e-10 * np.abs(a).max()), i
+
+
+@pytest.mark.parametrize("dim,n", [(2, 16), (3, 9)])
+def test_first_order_fit_equals_linear_fit_on_symmetric_stencils(dim, n):
+    """On an unjittered lattice, a stencil that does not reach a wall is
+    point-symmetric, so sum_j w_j (x_j - x_i) = 0 and the fitted constant of
+    the degree-1 basis decouples: both fits give the same gradient rows."""
+    x, wid = make_lattice(dim, n)
+    h = 3.1 / (n - 1)
+    c0 = cfg(dim, n, 4, 4.0, wls_degree=0, h=h, cap=200)
+    c1 = cfg(dim, n, 4, 4.0, wls_degree=1, h=h, cap=200)
+    cnt, idx, g0, _, _ = geometry(c0, x, wid)
+    _, _, g1, _, deg1 = geometry(c1, x, wid)
+    assert np.all(deg1[wid == 0] == 1)
+    lo, hi = h + 1e-12, 1.0 - h - 1e-12
+    inner = [i for i in np.nonzero(wid == 0)[0] if np.all((x[:, i] > lo) & (x[:, i] < hi))]
+    assert len(inner) > 0
+    for i in inner:
+        m = cnt[i]
+        scale = np.abs(g1[i, :m]).max()
+        assert np.max(np.abs(g0[i, :m] - g1[i, :m])) <= 1e-12 * scale, i
+    # near a wall the stencil is one-sided and the two fits differ
+    edge = [i for i in np.nonzero(wid == 0)[0] if np.any(x[:, i] < lo)]
+    assert max(np.max(np.abs(g0[i, :cnt[i]] - g1[i, :cnt[i]])) for i in edge) > 1e-3
+
+
 @pytest.mark.parametrize("dim,n", [(2, 20), (3, 9)])
 def test_upwind_vectors_split_gradient_in_edge_frame(dim, n):
     """P + Q (+ R) = g; P is along the edge and carries g.n; Q, R are normal to
