@@ -179,6 +179,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/BF16 runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--paper-scales", action="store_true",
+                    help="only time the paper's own cavity sizes (20 velocity points per "
+                         "axis, h = 3.1 dx, first-derivative least squares) and print one "
+                         "JSON line with the per-step times")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference "
                          "kernel for scaling HBM byte counters) and exit")
@@ -198,7 +202,23 @@ def main():
               "(the multi-GPU velocity-sharded design is not built)", file=sys.stderr)
         sys.exit(2)
 
-    from paper_2408_02350_amd.inputs import CONFIGS
+    from paper_2408_02350_amd.inputs import CONFIGS, PAPER_SCALES
+
+    if args.paper_scales:
+        rows = []
+        for key, pc in PAPER_SCALES.items():
+            pc = pc.replace(precision=args.precision)
+            ms, ktime, edges, _, _ = run_gpu(pc, args.precision, args.steps, args.warmup)
+            interior = cav_interior(pc)
+            rows.append({"workload": pc.name, "n_particles": pc.n_particles,
+                         "n_velocities": pc.n_velocities, "h_over_dx": pc.h_factor,
+                         "wls": "first-derivative fit", "mean_neighbours": edges / interior + 1,
+                         "ms_per_step": ms,
+                         "transport_ms": ktime[0] / max(ktime[1], 1),
+                         "updates_per_s": pc.n_particles * pc.n_velocities / (ms * 1e-3)})
+        print(json.dumps({"paper_scales": rows, "precision": args.precision,
+                          "steps": args.steps, "warmup": args.warmup}), flush=True)
+        return
 
     cav = CONFIGS[args.workload].replace(precision=args.precision)
     ms, ktime, edges, state, diag = run_gpu(cav, args.precision, args.steps, args.warmup)

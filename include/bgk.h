@@ -75,7 +75,8 @@ typedef struct {
   int32_t dim;           /* 2: Chu-reduced BGK (Sec. 2.1, g1 and g2); 3: full BGK        */
   int32_t n_particles;   /* N, interior + wall                                           */
   int32_t nv;            /* velocity points per axis, even, 2..1024                      */
-  int32_t wls_degree;    /* 1 or 2: polynomial degree of the least-squares fit           */
+  int32_t wls_degree;    /* 1 or 2: degree of the full-basis least-squares fit;          *
+                          * 0: first-derivative fit as printed in Sec. 3.1              */
   int32_t max_neighbors; /* neighbour slots per particle (self included), <= 255         */
   int32_t move;          /* 1: ALE motion (S8); 0: frozen cloud (geometry reused)        */
   int32_t precision;     /* BGK_FP64, BGK_FP32 (FP32 f and transport arithmetic) or
@@ -130,13 +131,16 @@ int bgk_build_neighbors(bgk_ctx* ctx, const double* x, int32_t* nbr_cnt, int32_t
  * particle itself in its stencil; the degree drops to 1 when the stencil has
  * fewer than twice as many points as degree-2 basis functions, and
  * BGK_ESINGULAR is raised below d+2 points or on a non-positive Cholesky
- * pivot.  grad[i][e] = gradient weight of neighbour slot e (so
+ * pivot.  wls_degree 0 is the fit exactly as printed: the unknowns are the d
+ * first derivatives of f_j - f_i ~ a.(x_j - x_i), a = (M^T W M)^-1 M^T W b,
+ * no constant term (the self offset is zero and drops out).  grad[i][e] = gradient weight of neighbour slot e (so
  * grad f(x_i) ~ sum_e grad[i][e] f_j).  ops[i][e] = (P, Q[, R]) = the gradient
  * weight rotated into the edge frame (n, t[, b]) of x_j - x_i and mapped back:
  * P = (g.n) n, Q = (g.t) t, R = (g.b) b, with t = n turned by +90 degrees in
  * 2D and, in 3D, t and b the polar and azimuthal unit vectors of the edge
  * (b horizontal).  The self slot has zero P, Q, R.  Rows of wall particles
- * are zero.  degree: int32 [N] (0 for wall particles), may be NULL. */
+ * are zero.  degree: int32 [N] (the degree used; 0 for wall particles), may
+ * be NULL. */
 int bgk_wls_operators(bgk_ctx* ctx, const double* x, const int32_t* nbr_cnt,
                       const int32_t* nbr_idx, double* grad, double* ops, int32_t* degree);
 

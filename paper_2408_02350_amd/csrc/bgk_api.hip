@@ -61,7 +61,7 @@ int hip_fail(Ctx* c, hipError_t e, const char* what) {
 
 bool config_ok(const bgk_config& g) {
   return (g.dim == 2 || g.dim == 3) && g.n_particles > 0 && g.nv >= 2 && g.nv <= 1024 && g.nv % 2 == 0 &&
-         (g.wls_degree == 1 || g.wls_degree == 2) && g.max_neighbors >= g.dim + 2 &&
+         g.wls_degree >= 0 && g.wls_degree <= 2 && g.max_neighbors >= g.dim + 2 &&
          g.max_neighbors <= 255 && (g.move == 0 || g.move == 1) && g.precision >= BGK_FP64 &&
          g.precision <= BGK_BF16 && (g.flags & ~(BGK_FLAG_GENERIC | BGK_FLAG_ADJOINT)) == 0 &&
          (!(g.flags & BGK_FLAG_ADJOINT) || (g.precision != BGK_BF16 && g.move == 0)) && g.vmax > 0 && g.h > 0 && g.alpha > 0 &&

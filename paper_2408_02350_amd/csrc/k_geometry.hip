@@ -573,7 +573,10 @@ __device__ __forceinline__ void chol_solve_col(const double* A, int col, double*
 // W_e z.p(y_e)/h, the edge frame of y_e and (P, Q[, R]).  Degree: the
 // configured one if the stencil holds at least twice as many points as
 // degree-2 basis functions, else 1 if it holds d+2 points, else
-// BGK_ESINGULAR (also on a non-positive pivot).  Barriers sit at points
+// BGK_ESINGULAR (also on a non-positive pivot).  Degree 0 is the fit as
+// printed in Sec. 3.1: first derivatives only, the basis is the scaled
+// offsets y (no constant; the particle itself has y = 0 and drops out),
+// derivative k in column k.  Barriers sit at points
 // every lane reaches (loops run to the degree-2 sizes; groups of lower
 // degree idle through the extra columns).
 constexpr int kWlsGroup = 4;
@@ -597,7 +600,7 @@ __global__ __launch_bounds__(64) void k_wls(const WlsArgs a) {
   const int m = valid ? min(a.cnt[i], a.cap) : 0;
   int deg = a.deg_cfg;
   if (deg == 2 && m < 2 * B2) deg = 1;
-  const int Bg = (deg == 2) ? B2 : B1;
+  const int Bg = (deg == 2) ? B2 : (deg == 1 ? B1 : D);
   const bool enough = m >= D + 2;
   constexpr int YS = D + 1;  // Y row: y_0 .. y_{D-1}, 1.0
   double* Y = wls_sm + g * S::doubles(a.cap);
@@ -631,9 +634,12 @@ __global__ __launch_bounds__(64) void k_wls(const WlsArgs a) {
       const int s2 = l - tri(r, 0);
       // basis function k is the product Y[i0] * Y[i1] of two row entries
       // (index D holds 1.0): 1 = 1*1, y_a = y_a*1, y_a y_b
-      int r0, r1, s0, s1;
-      basis_factors<D>(r, r0, r1);
-      basis_factors<D>(s2, s0, s1);
+      // (degree 0: the basis is the offsets alone, y_r = y_r * 1)
+      int r0 = r, r1 = D, s0 = s2, s1 = D;
+      if (deg != 0) {
+        basis_factors<D>(r, r0, r1);
+        basis_factors<D>(s2, s0, s1);
+      }
       double acc = 0.0;
       for (int e = 0; e < m; ++e) {
         const double* y = Y + e * YS;
@@ -661,7 +667,8 @@ __global__ __launch_bounds__(64) void k_wls(const WlsArgs a) {
   const bool ok = valid && enough && flag[0] == 0.0;
   if (ok && gl < D) {
     if (deg == 2) chol_solve_col<B2>(A, 1 + gl, Z + gl * B2);
-    else chol_solve_col<B1>(A, 1 + gl, Z + gl * B2);
+    else if (deg == 1) chol_solve_col<B1>(A, 1 + gl, Z + gl * B2);
+    else chol_solve_col<D>(A, gl, Z + gl * B2);  // derivative k is column k
   }
   __syncthreads();
   if (ok) {
@@ -669,8 +676,14 @@ __global__ __launch_bounds__(64) void k_wls(const WlsArgs a) {
       const int j = a.idx[row + e];
       const double* y = Y + e * YS;
       double pv[B2];
-      if (deg == 2) Basis<D, 2>::eval(y, pv);
-      else Basis<D, 1>::eval(y, pv);
+      if (deg == 2) {
+        Basis<D, 2>::eval(y, pv);
+      } else if (deg == 1) {
+        Basis<D, 1>::eval(y, pv);
+      } else {
+#pragma unroll
+        for (int r = 0; r < B2; ++r) pv[r] = r < D ? y[r] : 0.0;
+      }
       double gk[D];
 #pragma unroll
       for (int k = 0; k < D; ++k) {
@@ -744,11 +757,11 @@ hipError_t launch_wls(const Ctx& c, const double* x, const int32_t* cnt, const i
 }
 
 // ------------------------------------------------------------ wall rows
-// One wave per wall particle b: the interior particles within 2h (cells
-// within +-2, interior ranges) are collected with their squared distances;
-// hb is the first of h, 1.5h, 2h with at least d+2 of them inside; those are
-// stored ascending with the degree-1 least-squares value weights at x_b
-// (weights exp(-alpha r^2/hb^2)).
+// One wave per wall particle b: hb is the first of h, 1.5h, 2h with at least
+// d+2 interior particles within it (the candidate cells within +-2 cells,
+// interior ranges, are scanned once per radius tried, keeping only the
+// particles inside it); those are stored ascending with the degree-1
+// least-squares value weights at x_b (weights exp(-alpha r^2/hb^2)).
 struct WallArgs {
   int N, cap, Nw, nca, ncell;
   double h, alpha;
@@ -764,16 +777,12 @@ struct WallArgs {
   int32_t* err;
 };
 
-constexpr int kWallCand = 512;  // candidates within 2h kept in LDS
-
 template <int D>
 __global__ __launch_bounds__(64) void k_wall_stencil(const WallArgs a) {
   constexpr int NR = (D == 2 ? 25 : 125);
   constexpr int B = D + 1;
   __shared__ int32_t rb[NR], rpre[NR + 1];
-  __shared__ int32_t cj[kWallCand];
-  __shared__ double cr2[kWallCand];
-  __shared__ int32_t sel[kWallCand], srt[256];
+  __shared__ int32_t sel[256], srt[256];  // cap <= 255
   __shared__ double P[256 * B], W[256], A[B * (B + 1) / 2], Z[B];
   __shared__ int flag;
   const int k = blockIdx.x, lane = threadIdx.x;
@@ -787,33 +796,6 @@ __global__ __launch_bounds__(64) void k_wall_stencil(const WallArgs a) {
   }
   const int nr = cell_ranges<D, 2>(cb, a.nca, a.ncell, false, a.cstart, rb, rpre);
   const int total = rpre[nr];
-  const double h2max = (2.0 * a.h) * (2.0 * a.h);
-  int nc = 0;
-  for (int c0 = 0; c0 < total; c0 += kWave) {
-    const int cidx = c0 + lane;
-    bool hit = false;
-    int j = 0;
-    double r2 = 0.0;
-    if (cidx < total) {
-      const int p = cand_slot(cidx, nr, rb, rpre);
-      j = a.cperm[p];
-#pragma unroll
-      for (int q = 0; q < D; ++q) {
-        const double dl = a.xs[static_cast<int64_t>(q) * a.N + p] - xb[q];
-        r2 = r2 + dl * dl;
-      }
-      hit = r2 <= h2max;
-    }
-    const uint64_t mask = __ballot(hit);
-    const int pos = nc + lanes_below(mask);
-    if (hit && pos < kWallCand) {
-      cj[pos] = j;
-      cr2[pos] = r2;
-    }
-    nc += __popcll(mask);
-  }
-  nc = min(nc, kWallCand);
-  __syncthreads();
   const double mults[3] = {1.0, 1.5, 2.0};
   double hb = 0.0;
   int m = 0;
@@ -821,12 +803,24 @@ __global__ __launch_bounds__(64) void k_wall_stencil(const WallArgs a) {
     hb = mults[t] * a.h;
     const double hb2 = hb * hb;
     m = 0;
-    for (int c0 = 0; c0 < nc; c0 += kWave) {
-      const int q = c0 + lane;
-      const bool in = q < nc && cr2[q] <= hb2;
+    for (int c0 = 0; c0 < total; c0 += kWave) {
+      const int cidx = c0 + lane;
+      bool in = false;
+      int j = 0;
+      if (cidx < total) {
+        const int p = cand_slot(cidx, nr, rb, rpre);
+        j = a.cperm[p];
+        double r2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+          const double dl = a.xs[static_cast<int64_t>(q) * a.N + p] - xb[q];
+          r2 = r2 + dl * dl;
+        }
+        in = r2 <= hb2;
+      }
       const uint64_t mask = __ballot(in);
       const int pos = m + lanes_below(mask);
-      if (in) sel[pos] = cj[q];
+      if (in && pos < 256) sel[pos] = j;
       m += __popcll(mask);
     }
     if (m >= D + 2) break;

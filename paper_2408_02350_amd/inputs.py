@@ -48,7 +48,7 @@ class CavityConfig:
     move: int           # 1 = particles move with the gas, 0 = frozen cloud
     precision: str = "fp64"   # "fp64", "fp32" or "bf16"
     alpha: float = 6.0        # Gaussian weight exponent
-    wls_degree: int = 2       # 1 = linear, 2 = quadratic full basis
+    wls_degree: int = 2       # 1 = linear, 2 = quadratic full basis, 0 = first-derivative fit
     wall_T: float = 1.0
     seed: int = 0
 
@@ -80,8 +80,13 @@ class CavityConfig:
 
     @property
     def capacity(self) -> int:
-        # neighbour-list slots per particle, self included
-        return 64 if self.dim == 2 else 96
+        # neighbour-list slots per particle, self included: 64 (2D) / 96 (3D),
+        # or for wider supports 1.25x the volume of the h-ball grown by the
+        # jitter, in lattice cells, rounded up to 8 (3D at h = 3.1 dx: 208)
+        base = 64 if self.dim == 2 else 96
+        r = self.h_factor + 0.3
+        vol = math.pi * r * r if self.dim == 2 else 4.0 / 3.0 * math.pi * r ** 3
+        return min(255, max(base, int(math.ceil(1.25 * vol / 8.0)) * 8))
 
     def replace(self, **kw) -> "CavityConfig":
         return dataclasses.replace(self, **kw)
@@ -97,6 +102,20 @@ CONFIGS = {
     "c4": CavityConfig("c4_2d_chu_100x100_v24_adjoint", 2, 100, 24, 4.0, 2.5, 0.5, 0.1, 50, 0),
     "c5": CavityConfig("c5_3d_48cube_v20", 3, 48, 20, 4.0, 2.2, 1.0, 0.1, 200, 1,
                        precision="fp32"),
+}
+
+
+# The paper's own cavity scales (Sec. 5, Tables 1 and 2): 20 velocity points
+# per axis, 200^2..500^2 particles in 2D and 20^3..40^3 in 3D, support
+# h = 3.1 dx and the first-derivative least-squares fit as printed
+# (Sec. 3.1).  v_max is not given there; 4 is taken as for the other
+# 20-point grid.  The paper reports whole runs in minutes without the step
+# count, so these are timed per step only.
+PAPER_SCALES = {
+    **{f"p2_{n}": CavityConfig(f"paper_2d_chu_{n}x{n}_v20", 2, n, 20, 4.0, 3.1, 1.0, 0.1, 1, 1,
+                               wls_degree=0) for n in (200, 300, 400, 500)},
+    **{f"p3_{n}": CavityConfig(f"paper_3d_{n}cube_v20", 3, n, 20, 4.0, 3.1, 1.0, 0.1, 1, 1,
+                               wls_degree=0) for n in (20, 30, 40)},
 }
 
 

@@ -23,8 +23,9 @@ def say(msg):
     print(msg, flush=True)
 
 
-def cavity(dim, n, nv, vmax=4.0, kn=1.0, lid=0.1, move=1, precision="fp64", **kw):
-    return CavityConfig(f"t{dim}d_n{n}_v{nv}", dim, n, nv, vmax, 2.5 if dim == 2 else 2.2, kn,
+def cavity(dim, n, nv, vmax=4.0, kn=1.0, lid=0.1, move=1, precision="fp64", h_factor=None, **kw):
+    hf = h_factor if h_factor is not None else (2.5 if dim == 2 else 2.2)
+    return CavityConfig(f"t{dim}d_n{n}_v{nv}", dim, n, nv, vmax, hf, kn,
                         lid, 1, move, precision=precision, **kw)
 
 
@@ -95,9 +96,13 @@ def test_neighbor_overflow_is_reported():
 
 
 # ---------------------------------------------------------------- S2-S3
-@pytest.mark.parametrize("dim,n,seed,deg", [(2, 40, 0, 2), (2, 12, 1, 1), (3, 10, 0, 2), (3, 9, 2, 1)])
-def test_wls_operators_match(dim, n, seed, deg):
-    k = Case(cavity(dim, n, 4, wls_degree=deg), seed)
+@pytest.mark.parametrize("dim,n,seed,deg,hf", [(2, 40, 0, 2, None), (2, 12, 1, 1, None),
+                                               (3, 10, 0, 2, None), (3, 9, 2, 1, None),
+                                               (2, 30, 0, 0, 3.1), (3, 9, 1, 0, 3.1)])
+def test_wls_operators_match(dim, n, seed, deg, hf):
+    """Degree 0 (the first-derivative fit as printed) runs at the paper's
+    support h = 3.1 dx."""
+    k = Case(cavity(dim, n, 4, wls_degree=deg, h_factor=hf), seed)
     cnt, idx = bgk.bgk_build_neighbors(k.ctx, k.x_t)
     grad, ops, degree = bgk.bgk_wls_operators(k.ctx, k.x_t, cnt, idx)
     bgk.bgk_check(k.ctx)
@@ -114,9 +119,12 @@ def test_wls_operators_match(dim, n, seed, deg):
     assert np.all(grad[k.wid != 0] == 0) and np.all(ops[k.wid != 0] == 0)
 
 
-@pytest.mark.parametrize("dim,n,seed", [(2, 40, 0), (2, 16, 3), (3, 10, 1)])
-def test_wall_stencil_match(dim, n, seed):
-    k = Case(cavity(dim, n, 4), seed)
+@pytest.mark.parametrize("dim,n,seed,hf", [(2, 40, 0, None), (2, 16, 3, None), (3, 10, 1, None),
+                                           (3, 16, 2, 3.1)])
+def test_wall_stencil_match(dim, n, seed, hf):
+    """(3D at h = 3.1 dx: about 500 interior particles lie within 2h of a
+    face particle; only those within the radius taken form the stencil.)"""
+    k = Case(cavity(dim, n, 4, h_factor=hf), seed)
     cnt, idx, c0, hb = bgk.bgk_wall_stencil(k.ctx, k.x_t)
     bgk.bgk_check(k.ctx)
     rcnt, ridx, rc0, rhb = oracle.wall_stencil(k.c, k.x, k.wid)
@@ -311,6 +319,15 @@ def test_step_parity_c1_full_run():
                                                  (2, 12, 24, 2, 3), (3, 7, 16, 2, 4)])
 def test_step_parity_small(dim, n, nv, steps, seed, flags):
     k, g, r = run_both(cavity(dim, n, nv), steps, seed, flags=flags)
+    assert_state_close(g, r)
+
+
+@pytest.mark.parametrize("flags", [0, bgk.BGK_FLAG_GENERIC])
+@pytest.mark.parametrize("dim,n,nv,steps", [(2, 14, 8, 4), (3, 8, 6, 3)])
+def test_step_parity_first_order_fit(dim, n, nv, steps, flags):
+    """The paper's own operator variant: first-derivative least squares at
+    h = 3.1 dx (about 30 neighbours in 2D, 120 in 3D)."""
+    k, g, r = run_both(cavity(dim, n, nv, wls_degree=0, h_factor=3.1), steps, 6, flags=flags)
     assert_state_close(g, r)
 
 
