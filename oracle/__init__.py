@@ -87,6 +87,8 @@ def lib():
                                     dp, dp, dp, dp, dp, dp, dp, dp]
         L.ref_objective_dual.restype = ctypes.c_double
         L.ref_objective_dual.argtypes = [cp, ip, dp, dp, dp, dp, dp, dp, ctypes.c_double]
+        L.ref_pm_count.argtypes = [cp, dp, ip, ctypes.c_double, ctypes.c_double, ip, ip]
+        L.ref_pm_apply.argtypes = [cp, dp, ip, dp, ctypes.c_double, ctypes.c_double, dp, ip, dp]
         _lib = L
     return _lib
 
@@ -210,6 +212,29 @@ def wall_stencil(c, x, wall_id):
     _check(lib().ref_wall_stencil(ctypes.byref(c), _d(x), _i(wall_id), _i(wcnt), _i(widx),
                                   _d(wc0), _d(hb)), "wall_stencil")
     return wcnt, widx, wc0, hb
+
+
+def pm_count(c, x, wall_id, merge_radius, hole_radius):
+    """Particle management plan: (merged pairs, hole particles)."""
+    x, wall_id = _f64(x), _i32(wall_id)
+    n_pairs = np.zeros(1, np.int32)
+    n_holes = np.zeros(1, np.int32)
+    _check(lib().ref_pm_count(ctypes.byref(c), _d(x), _i(wall_id), float(merge_radius),
+                              float(hole_radius), _i(n_pairs), _i(n_holes)), "pm_count")
+    return int(n_pairs[0]), int(n_holes[0])
+
+
+def pm_apply(c, x, wall_id, f, merge_radius, hole_radius):
+    """The managed cloud: (x_new [d][N'], wall_id_new [N'], f_new [n_c][N'][N_v])."""
+    pairs, holes = pm_count(c, x, wall_id, merge_radius, hole_radius)
+    Nn = c.n_particles - pairs + holes
+    x, wall_id, f = _f64(x), _i32(wall_id), _f64(f)
+    xn = np.zeros((c.dim, Nn))
+    wn = np.zeros(Nn, np.int32)
+    fn = np.zeros((c.nc, Nn, c.NV))
+    _check(lib().ref_pm_apply(ctypes.byref(c), _d(x), _i(wall_id), _d(f), float(merge_radius),
+                              float(hole_radius), _d(xn), _i(wn), _d(fn)), "pm_apply")
+    return xn, wn, fn
 
 
 def transport(c, wall_id, cnt, idx, grad, ops, U, f):

@@ -419,76 +419,262 @@ int wls(const ref_config& c, const double* x, const int32_t* wall_id, const int3
 // interior particles within radius hb, the first of h, 1.5h, 2h that holds
 // at least d+2 of them, by a degree-1 weighted least-squares fit (weights
 // exp(-alpha r^2/hb^2)) evaluated at x_b: f_b = sum_j c0_bj f_j.
+// Value row at a point xq: the interior particles within hb, the first of
+// h, 1.5h, 2h holding at least d+2 of them (ascending), and the degree-1
+// least-squares value weights at xq (weights exp(-alpha r^2/hb^2)), so that
+// f(xq) ~ sum_e c0[e] f_{S[e]}.
+int value_row(const ref_config& c, const double* x, const int32_t* wall_id, const double* xq,
+              std::vector<int>& S, std::vector<double>& c0, double& hb) {
+  const int N = c.n_particles, d = c.dim;
+  const double mults[3] = {1.0, 1.5, 2.0};
+  for (int k = 0; k < 3; ++k) {
+    hb = mults[k] * c.h;
+    const double hb2 = hb * hb;
+    S.clear();
+    for (int j = 0; j < N; ++j) {
+      if (wall_id[j] != 0) continue;
+      double r2 = 0.0;
+      for (int a = 0; a < d; ++a) {
+        const double dl = x[a * N + j] - xq[a];
+        r2 = r2 + dl * dl;
+      }
+      if (r2 <= hb2) S.push_back(j);
+    }
+    if (static_cast<int>(S.size()) >= d + 2) break;
+  }
+  const int m = static_cast<int>(S.size());
+  if (m < d + 2) return R_ESINGULAR;
+  if (m > c.cap) return R_ENBR_OVERFLOW;
+  const int B = d + 1;
+  double A[16] = {0}, L[16];
+  std::vector<double> P(static_cast<size_t>(m) * B), W(m);
+  for (int e = 0; e < m; ++e) {
+    double y[3], r2 = 0.0;
+    for (int a = 0; a < d; ++a) {
+      y[a] = (x[a * N + S[e]] - xq[a]) / hb;
+      r2 = r2 + y[a] * y[a];
+    }
+    W[e] = std::exp(-c.alpha * r2);
+    basis(d, 1, y, &P[static_cast<size_t>(e) * B]);
+  }
+  for (int e = 0; e < m; ++e)
+    for (int r = 0; r < B; ++r)
+      for (int s = 0; s < B; ++s)
+        A[r * B + s] = A[r * B + s] + W[e] * P[e * B + r] * P[e * B + s];
+  if (!cholesky(B, A, L)) return R_ESINGULAR;
+  double z[16];
+  chol_solve_unit(B, L, 0, z);
+  c0.assign(m, 0.0);
+  for (int e = 0; e < m; ++e) {
+    double s = 0.0;
+    for (int r = 0; r < B; ++r) s = s + z[r] * P[e * B + r];
+    c0[e] = W[e] * s;
+  }
+  return R_OK;
+}
+
 int wall_stencil(const ref_config& c, const double* x, const int32_t* wall_id, int32_t* wcnt,
                  int32_t* widx, double* wc0, double* hb_out) {
   const int N = c.n_particles, d = c.dim, cap = c.cap;
   int err = R_OK;
-  const double mults[3] = {1.0, 1.5, 2.0};
 #pragma omp parallel for schedule(dynamic, 16)
   for (int b = 0; b < N; ++b) {
     const int64_t row = static_cast<int64_t>(b) * cap;
     wcnt[b] = 0;
     if (hb_out) hb_out[b] = 0.0;
     if (wall_id[b] == 0) continue;
+    double xb[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < d; ++a) xb[a] = x[a * N + b];
     std::vector<int> S;
+    std::vector<double> c0;
     double hb = 0.0;
-    for (int k = 0; k < 3; ++k) {
-      hb = mults[k] * c.h;
-      const double hb2 = hb * hb;
-      S.clear();
-      for (int j = 0; j < N; ++j) {
-        if (wall_id[j] != 0) continue;
-        double r2 = 0.0;
-        for (int a = 0; a < d; ++a) {
-          const double dl = x[a * N + j] - x[a * N + b];
-          r2 = r2 + dl * dl;
-        }
-        if (r2 <= hb2) S.push_back(j);
-      }
-      if (static_cast<int>(S.size()) >= d + 2) break;
+    const int rc = value_row(c, x, wall_id, xb, S, c0, hb);
+    if (rc != R_OK) {
+#pragma omp critical
+      err = rc;
+      continue;
     }
     const int m = static_cast<int>(S.size());
-    if (m < d + 2) {
-#pragma omp critical
-      err = R_ESINGULAR;
-      continue;
-    }
-    if (m > cap) {
-#pragma omp critical
-      err = R_ENBR_OVERFLOW;
-      continue;
-    }
-    const int B = d + 1;
-    double A[16] = {0}, L[16];
-    std::vector<double> P(static_cast<size_t>(m) * B), W(m);
     for (int e = 0; e < m; ++e) {
-      double y[3], r2 = 0.0;
-      for (int a = 0; a < d; ++a) {
-        y[a] = (x[a * N + S[e]] - x[a * N + b]) / hb;
-        r2 = r2 + y[a] * y[a];
-      }
-      W[e] = std::exp(-c.alpha * r2);
-      basis(d, 1, y, &P[static_cast<size_t>(e) * B]);
-    }
-    for (int e = 0; e < m; ++e)
-      for (int r = 0; r < B; ++r)
-        for (int s = 0; s < B; ++s)
-          A[r * B + s] = A[r * B + s] + W[e] * P[e * B + r] * P[e * B + s];
-    if (!cholesky(B, A, L)) {
-#pragma omp critical
-      err = R_ESINGULAR;
-      continue;
-    }
-    double z[16];
-    chol_solve_unit(B, L, 0, z);
-    for (int e = 0; e < m; ++e) {
-      double s = 0.0;
-      for (int r = 0; r < B; ++r) s = s + z[r] * P[e * B + r];
       widx[row + e] = S[e];
-      wc0[row + e] = W[e] * s;
+      wc0[row + e] = c0[e];
     }
     wcnt[b] = m;
     if (hb_out) hb_out[b] = hb;
+  }
+  return err;
+}
+
+// ---------------------------------------------------------------------------
+// Particle management (Section 4.1.2: adding and removing points).  The
+// paper removes two points that come too close and puts one at their
+// midpoint, adds points where holes open, and fills f at the new points by
+// least squares; it gives no thresholds or selection rule.  Taken reading:
+//  - merge: interior particles i < j that are each other's nearest interior
+//    neighbour within h (ties to the lower index) and closer than
+//    merge_radius become one interior particle at 0.5 (x_i + x_j);
+//  - holes: an interior node of the initial lattice (coordinates k dx,
+//    0 < k < n-1) with no particle of the merged cloud within hole_radius
+//    gets a new interior particle;
+//  - f at every new particle: the value row of the old cloud at its
+//    position (the rule of the wall rows), applied to every velocity and
+//    component;
+//  - order of the new cloud: the untouched particles in their old order,
+//    then the midpoints by the lower index of their pair, then the hole
+//    particles by node index k_x + n k_y (+ n^2 k_z).
+struct PmPlan {
+  std::vector<int> partner;   // -1, or the other particle of its pair
+  std::vector<int> holes;     // node indices
+  int n_pairs = 0;
+};
+
+inline double dist2(int d, const double* p, const double* q) {
+  double r2 = 0.0;
+  for (int a = 0; a < d; ++a) {
+    const double dl = p[a] - q[a];
+    r2 = r2 + dl * dl;
+  }
+  return r2;
+}
+
+inline int lattice_n(const ref_config& c) { return static_cast<int>(std::lround(1.0 / c.dx)) + 1; }
+
+void pm_plan(const ref_config& c, const double* x, const int32_t* wall_id, double rm, double rh,
+             PmPlan& p) {
+  const int N = c.n_particles, d = c.dim;
+  auto pos = [&](int i, double* o) {
+    for (int a = 0; a < d; ++a) o[a] = x[a * N + i];
+  };
+  std::vector<int> nn(N, -1);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int i = 0; i < N; ++i) {
+    if (wall_id[i] != 0) continue;
+    double xi[3], xj[3];
+    pos(i, xi);
+    double best = c.h * c.h;
+    for (int j = 0; j < N; ++j) {
+      if (j == i || wall_id[j] != 0) continue;
+      pos(j, xj);
+      const double r2 = dist2(d, xj, xi);
+      if (r2 <= c.h * c.h && (nn[i] < 0 || r2 < best)) {
+        best = r2;
+        nn[i] = j;
+      }
+    }
+  }
+  p.partner.assign(N, -1);
+  p.n_pairs = 0;
+  for (int i = 0; i < N; ++i) {
+    const int j = nn[i];
+    if (j > i && nn[j] == i) {
+      double xi[3], xj[3];
+      pos(i, xi);
+      pos(j, xj);
+      if (dist2(d, xj, xi) < rm * rm) {
+        p.partner[i] = j;
+        p.partner[j] = i;
+        ++p.n_pairs;
+      }
+    }
+  }
+  // the merged cloud: untouched particles and the midpoints
+  std::vector<double> pts;
+  for (int i = 0; i < N; ++i) {
+    double xi[3] = {0, 0, 0}, xj[3];
+    pos(i, xi);
+    if (p.partner[i] >= 0) {
+      if (p.partner[i] < i) continue;
+      pos(p.partner[i], xj);
+      for (int a = 0; a < d; ++a) xi[a] = 0.5 * (xi[a] + xj[a]);
+    }
+    for (int a = 0; a < d; ++a) pts.push_back(xi[a]);
+  }
+  const int M = static_cast<int>(pts.size()) / d;
+  const int n = lattice_n(c);
+  int64_t nodes = 1;
+  for (int a = 0; a < d; ++a) nodes *= n;
+  std::vector<char> hole(nodes, 0);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t k = 0; k < nodes; ++k) {
+    double y[3] = {0, 0, 0};
+    int64_t r = k;
+    bool inner = true;
+    for (int a = 0; a < d; ++a) {
+      const int ka = static_cast<int>(r % n);
+      r /= n;
+      inner = inner && ka > 0 && ka < n - 1;
+      y[a] = static_cast<double>(ka) * c.dx;
+    }
+    if (!inner) continue;
+    bool covered = false;
+    for (int q = 0; q < M && !covered; ++q) covered = dist2(d, &pts[static_cast<size_t>(q) * d], y) <= rh * rh;
+    hole[k] = covered ? 0 : 1;
+  }
+  p.holes.clear();
+  for (int64_t k = 0; k < nodes; ++k)
+    if (hole[k]) p.holes.push_back(static_cast<int>(k));
+}
+
+int pm_apply(const ref_config& c, const double* x, const int32_t* wall_id, const double* f,
+             const PmPlan& p, double* x_new, int32_t* wall_id_new, double* f_new) {
+  const int N = c.n_particles, d = c.dim, nc = n_comp(c);
+  const int64_t NV = n_vel(c);
+  const int Nn = N - p.n_pairs + static_cast<int>(p.holes.size());
+  const int n = lattice_n(c);
+  // positions and owners of the new cloud, and the old row each new
+  // particle copies (-1: interpolated)
+  std::vector<int> src;
+  std::vector<double> nx;
+  for (int i = 0; i < N; ++i) {
+    if (p.partner[i] >= 0) continue;
+    src.push_back(i);
+    for (int a = 0; a < d; ++a) nx.push_back(x[a * N + i]);
+  }
+  for (int i = 0; i < N; ++i) {
+    if (p.partner[i] <= i) continue;
+    src.push_back(-1);
+    for (int a = 0; a < d; ++a) nx.push_back(0.5 * (x[a * N + i] + x[a * N + p.partner[i]]));
+  }
+  for (int k : p.holes) {
+    src.push_back(-1);
+    int64_t r = k;
+    for (int a = 0; a < d; ++a) {
+      nx.push_back(static_cast<double>(r % n) * c.dx);
+      r /= n;
+    }
+  }
+  int err = R_OK;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int q = 0; q < Nn; ++q) {
+    const double* xq = &nx[static_cast<size_t>(q) * d];
+    for (int a = 0; a < d; ++a) x_new[static_cast<int64_t>(a) * Nn + q] = xq[a];
+    wall_id_new[q] = src[q] >= 0 ? wall_id[src[q]] : 0;
+    for (int cc = 0; cc < nc; ++cc) {
+      double* out = f_new + (static_cast<int64_t>(cc) * Nn + q) * NV;
+      if (src[q] >= 0) {
+        const double* in = f + (static_cast<int64_t>(cc) * N + src[q]) * NV;
+        for (int64_t v = 0; v < NV; ++v) out[v] = in[v];
+      }
+    }
+    if (src[q] >= 0) continue;
+    std::vector<int> S;
+    std::vector<double> c0;
+    double hb = 0.0;
+    const int rc = value_row(c, x, wall_id, xq, S, c0, hb);
+    if (rc != R_OK) {
+#pragma omp critical
+      err = rc;
+      continue;
+    }
+    for (int cc = 0; cc < nc; ++cc) {
+      double* out = f_new + (static_cast<int64_t>(cc) * Nn + q) * NV;
+      for (int64_t v = 0; v < NV; ++v) {
+        double s = 0.0;
+        for (size_t e = 0; e < S.size(); ++e)
+          s = s + c0[e] * f[(static_cast<int64_t>(cc) * N + S[e]) * NV + v];
+        out[v] = s;
+      }
+    }
   }
   return err;
 }
@@ -844,6 +1030,30 @@ int ref_wall_stencil(const ref_config* c, const double* x, const int32_t* wall_i
                      int32_t* widx, double* wc0, double* hb) {
   if (!config_ok(*c)) return R_EINVAL;
   return wall_stencil(*c, x, wall_id, wcnt, widx, wc0, hb);
+}
+
+// Particle management: counts of the plan (merged pairs, hole particles).
+// The new cloud has N - n_pairs + n_holes particles.
+int ref_pm_count(const ref_config* c, const double* x, const int32_t* wall_id,
+                 double merge_radius, double hole_radius, int32_t* n_pairs, int32_t* n_holes) {
+  if (!c || !config_ok(*c) || !x || !wall_id || !n_pairs || !n_holes) return R_EINVAL;
+  PmPlan p;
+  pm_plan(*c, x, wall_id, merge_radius, hole_radius, p);
+  *n_pairs = p.n_pairs;
+  *n_holes = static_cast<int32_t>(p.holes.size());
+  return R_OK;
+}
+
+// Particle management: the new cloud (x_new [d][N'], wall_id_new [N'],
+// f_new [n_c][N'][N_v]) for the same plan.
+int ref_pm_apply(const ref_config* c, const double* x, const int32_t* wall_id, const double* f,
+                 double merge_radius, double hole_radius, double* x_new, int32_t* wall_id_new,
+                 double* f_new) {
+  if (!c || !config_ok(*c) || !x || !wall_id || !f || !x_new || !wall_id_new || !f_new)
+    return R_EINVAL;
+  PmPlan p;
+  pm_plan(*c, x, wall_id, merge_radius, hole_radius, p);
+  return pm_apply(*c, x, wall_id, f, p, x_new, wall_id_new, f_new);
 }
 
 int ref_transport(const ref_config* c, const int32_t* wall_id, const int32_t* cnt,
