@@ -88,7 +88,8 @@ def lib():
         L.ref_objective_dual.restype = ctypes.c_double
         L.ref_objective_dual.argtypes = [cp, ip, dp, dp, dp, dp, dp, dp, ctypes.c_double]
         L.ref_pm_count.argtypes = [cp, dp, ip, ctypes.c_double, ctypes.c_double, ip, ip]
-        L.ref_pm_apply.argtypes = [cp, dp, ip, dp, ctypes.c_double, ctypes.c_double, dp, ip, dp]
+        L.ref_pm_apply.argtypes = [cp, dp, ip, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                   dp, ip, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -224,17 +225,24 @@ def pm_count(c, x, wall_id, merge_radius, hole_radius):
     return int(n_pairs[0]), int(n_holes[0])
 
 
-def pm_apply(c, x, wall_id, f, merge_radius, hole_radius):
-    """The managed cloud: (x_new [d][N'], wall_id_new [N'], f_new [n_c][N'][N_v])."""
+def pm_apply(c, x, wall_id, f, merge_radius, hole_radius, rho=None, U=None, T=None):
+    """The managed cloud: (x_new [d][N'], wall_id_new [N'], f_new [n_c][N'][N_v],
+    rho_new, U_new [d][N'], T_new).  rho, U, T of the old cloud default to
+    its moments."""
     pairs, holes = pm_count(c, x, wall_id, merge_radius, hole_radius)
     Nn = c.n_particles - pairs + holes
     x, wall_id, f = _f64(x), _i32(wall_id), _f64(f)
+    if rho is None:
+        rho, U, T = moments(c, f)
+    rho, U, T = _f64(rho), _f64(U), _f64(T)
     xn = np.zeros((c.dim, Nn))
     wn = np.zeros(Nn, np.int32)
     fn = np.zeros((c.nc, Nn, c.NV))
-    _check(lib().ref_pm_apply(ctypes.byref(c), _d(x), _i(wall_id), _d(f), float(merge_radius),
-                              float(hole_radius), _d(xn), _i(wn), _d(fn)), "pm_apply")
-    return xn, wn, fn
+    rn, Un, Tn = np.zeros(Nn), np.zeros((c.dim, Nn)), np.zeros(Nn)
+    _check(lib().ref_pm_apply(ctypes.byref(c), _d(x), _i(wall_id), _d(f), _d(rho), _d(U), _d(T),
+                              float(merge_radius), float(hole_radius), _d(xn), _i(wn), _d(fn),
+                              _d(rn), _d(Un), _d(Tn)), "pm_apply")
+    return xn, wn, fn, rn, Un, Tn
 
 
 def transport(c, wall_id, cnt, idx, grad, ops, U, f):

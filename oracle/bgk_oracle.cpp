@@ -518,7 +518,8 @@ int wall_stencil(const ref_config& c, const double* x, const int32_t* wall_id, i
 //    gets a new interior particle;
 //  - f at every new particle: the value row of the old cloud at its
 //    position (the rule of the wall rows), applied to every velocity and
-//    component;
+//    component; its rho, U, T are the moments of that f, while the other
+//    particles keep theirs (U^n feeds the next transport);
 //  - order of the new cloud: the untouched particles in their old order,
 //    then the midpoints by the lower index of their pair, then the hole
 //    particles by node index k_x + n k_y (+ n^2 k_z).
@@ -616,7 +617,9 @@ void pm_plan(const ref_config& c, const double* x, const int32_t* wall_id, doubl
 }
 
 int pm_apply(const ref_config& c, const double* x, const int32_t* wall_id, const double* f,
-             const PmPlan& p, double* x_new, int32_t* wall_id_new, double* f_new) {
+             const double* rho, const double* U, const double* T, const PmPlan& p,
+             double* x_new, int32_t* wall_id_new, double* f_new, double* rho_new, double* U_new,
+             double* T_new) {
   const int N = c.n_particles, d = c.dim, nc = n_comp(c);
   const int64_t NV = n_vel(c);
   const int Nn = N - p.n_pairs + static_cast<int>(p.holes.size());
@@ -656,7 +659,12 @@ int pm_apply(const ref_config& c, const double* x, const int32_t* wall_id, const
         for (int64_t v = 0; v < NV; ++v) out[v] = in[v];
       }
     }
-    if (src[q] >= 0) continue;
+    if (src[q] >= 0) {
+      rho_new[q] = rho[src[q]];
+      T_new[q] = T[src[q]];
+      for (int a = 0; a < d; ++a) U_new[static_cast<int64_t>(a) * Nn + q] = U[a * N + src[q]];
+      continue;
+    }
     std::vector<int> S;
     std::vector<double> c0;
     double hb = 0.0;
@@ -675,6 +683,11 @@ int pm_apply(const ref_config& c, const double* x, const int32_t* wall_id, const
         out[v] = s;
       }
     }
+    double r, u[3], t;
+    moments_row(c, f_new + static_cast<int64_t>(q) * NV, static_cast<int64_t>(Nn) * NV, r, u, t);
+    rho_new[q] = r;
+    T_new[q] = t;
+    for (int a = 0; a < d; ++a) U_new[static_cast<int64_t>(a) * Nn + q] = u[a];
   }
   return err;
 }
@@ -1045,15 +1058,18 @@ int ref_pm_count(const ref_config* c, const double* x, const int32_t* wall_id,
 }
 
 // Particle management: the new cloud (x_new [d][N'], wall_id_new [N'],
-// f_new [n_c][N'][N_v]) for the same plan.
+// f_new [n_c][N'][N_v], rho/T_new [N'], U_new [d][N']) for the same plan.
 int ref_pm_apply(const ref_config* c, const double* x, const int32_t* wall_id, const double* f,
-                 double merge_radius, double hole_radius, double* x_new, int32_t* wall_id_new,
-                 double* f_new) {
-  if (!c || !config_ok(*c) || !x || !wall_id || !f || !x_new || !wall_id_new || !f_new)
+                 const double* rho, const double* U, const double* T, double merge_radius,
+                 double hole_radius, double* x_new, int32_t* wall_id_new, double* f_new,
+                 double* rho_new, double* U_new, double* T_new) {
+  if (!c || !config_ok(*c) || !x || !wall_id || !f || !rho || !U || !T || !x_new ||
+      !wall_id_new || !f_new || !rho_new || !U_new || !T_new)
     return R_EINVAL;
   PmPlan p;
   pm_plan(*c, x, wall_id, merge_radius, hole_radius, p);
-  return pm_apply(*c, x, wall_id, f, p, x_new, wall_id_new, f_new);
+  return pm_apply(*c, x, wall_id, f, rho, U, T, p, x_new, wall_id_new, f_new, rho_new, U_new,
+                  T_new);
 }
 
 int ref_transport(const ref_config* c, const int32_t* wall_id, const int32_t* cnt,

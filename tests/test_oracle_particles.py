@@ -48,7 +48,7 @@ def test_undisturbed_cloud_is_unchanged(dim, n):
     f = np.random.default_rng(2).uniform(0.1, 1.0, (c.nc, c.n_particles, c.NV))
     rm, rh = 0.25 * c.dx, 0.45 * c.h
     assert oracle.pm_count(c, x, wid, rm, rh) == (0, 0)
-    xn, wn, fn = oracle.pm_apply(c, x, wid, f, rm, rh)
+    xn, wn, fn, *_ = oracle.pm_apply(c, x, wid, f, rm, rh)
     assert np.array_equal(xn, x) and np.array_equal(wn, wid) and np.array_equal(fn, f)
 
 
@@ -68,7 +68,7 @@ def test_planted_close_pair_merges_to_midpoint(dim, n):
     assert oracle.pm_count(c, x, wid, rm, rh) == (1, 0)
     field = linear_field(c, x, 3)
     f = field(x)
-    xn, wn, fn = oracle.pm_apply(c, x, wid, f, rm, rh)
+    xn, wn, fn, *_ = oracle.pm_apply(c, x, wid, f, rm, rh)
     keep = [p for p in range(N) if p not in (i, j)]
     assert xn.shape == (dim, N - 1)
     assert np.array_equal(xn[:, :-1], x[:, keep]) and np.array_equal(wn[:-1], wid[keep])
@@ -98,7 +98,7 @@ def test_planted_hole_gets_a_particle_at_its_node(dim, n, rh_dx):
     assert oracle.pm_count(c, xk, wk, 0.25 * c.dx, rh) == (0, 1)
     field = linear_field(c, xk, 4)
     f = field(xk)
-    xn, wn, fn = oracle.pm_apply(c, xk, wk, f, 0.25 * c.dx, rh)
+    xn, wn, fn, *_ = oracle.pm_apply(c, xk, wk, f, 0.25 * c.dx, rh)
     assert xn.shape == (dim, len(keep) + 1)
     assert np.array_equal(xn[:, :-1], xk) and np.array_equal(fn[:, :-1], f)
     y = lattice_pos(centre, c.dx)
@@ -120,7 +120,7 @@ def test_three_point_cluster_merges_only_the_mutual_nearest_pair():
     x[:, k] = x[:, j] + np.array([0.15 * c.dx, 0.0])
     rm, rh = 0.25 * c.dx, 0.45 * c.h
     assert oracle.pm_count(c, x, wid, rm, rh) == (1, 0)
-    xn, _, _ = oracle.pm_apply(c, x, wid, np.ones((c.nc, c.n_particles, c.NV)), rm, rh)
+    xn, *_ = oracle.pm_apply(c, x, wid, np.ones((c.nc, c.n_particles, c.NV)), rm, rh)
     assert np.array_equal(xn[:, -1], 0.5 * (x[:, i] + x[:, j]))
     assert any(np.array_equal(xn[:, q], x[:, k]) for q in range(xn.shape[1] - 1))
     # with k moved to 0.05 dx beyond j, j's nearest is k and k's is j: now
@@ -128,7 +128,7 @@ def test_three_point_cluster_merges_only_the_mutual_nearest_pair():
     # merge radius of j
     x[:, k] = x[:, j] + np.array([0.05 * c.dx, 0.0])
     assert oracle.pm_count(c, x, wid, rm, rh) == (1, 0)
-    xn, _, _ = oracle.pm_apply(c, x, wid, np.ones((c.nc, c.n_particles, c.NV)), rm, rh)
+    xn, *_ = oracle.pm_apply(c, x, wid, np.ones((c.nc, c.n_particles, c.NV)), rm, rh)
     assert np.array_equal(xn[:, -1], 0.5 * (x[:, j] + x[:, k]))
 
 
@@ -142,3 +142,33 @@ def test_wall_particles_are_never_merged():
     assert wid[b] != 0 and wid[i] == 0
     x[:, i] = x[:, b] + np.array([0.0, 0.05 * c.dx])
     assert oracle.pm_count(c, x, wid, 0.25 * c.dx, 0.45 * c.h) == (0, 0)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 14), (3, 8)])
+def test_state_of_kept_and_new_particles(dim, n):
+    """Kept particles carry the rho, U, T given to them (U^n feeds the next
+    transport); a new particle in a uniform Maxwellian field gets exactly
+    that Maxwellian (the fit reproduces constants) and so its moments."""
+    x, wid = make_lattice(dim, n)
+    x = x.copy()
+    c = cfg(dim, n)
+    N = c.n_particles
+    i = node_index([n // 2] * dim, n)
+    x[:, i + 1] = x[:, i] + np.eye(dim)[0] * 0.1 * c.dx
+    rho0 = np.full(N, 0.9)
+    U0 = np.zeros((dim, N))
+    U0[0] = 0.05
+    T0 = np.full(N, 1.1)
+    f = oracle.maxwellian(c, rho0, U0, T0)
+    mr, mU, mT = oracle.moments(c, f)
+    rng = np.random.default_rng(9)
+    rho_in, U_in, T_in = rng.uniform(0.5, 1.5, N), rng.uniform(-0.1, 0.1, (dim, N)), \
+        rng.uniform(0.5, 1.5, N)
+    rm, rh = 0.25 * c.dx, 0.45 * c.h
+    xn, wn, fn, rn, Un, Tn = oracle.pm_apply(c, x, wid, f, rm, rh, rho_in, U_in, T_in)
+    keep = [p for p in range(N) if p not in (i, i + 1)]
+    assert np.array_equal(rn[:-1], rho_in[keep]) and np.array_equal(Tn[:-1], T_in[keep])
+    assert np.array_equal(Un[:, :-1], U_in[:, keep])
+    assert np.max(np.abs(fn[:, -1] - f[:, i])) <= 1e-12 * np.max(np.abs(f))
+    assert abs(rn[-1] - mr[i]) <= 1e-12 and abs(Tn[-1] - mT[i]) <= 1e-12
+    assert np.max(np.abs(Un[:, -1] - mU[:, i])) <= 1e-12
