@@ -45,7 +45,8 @@ def log(msg):
 # Sources the fused kernel's machine code depends on: a traffic figure measured
 # with counters is reported only while these are unchanged.
 TRAFFIC_SOURCES = ("paper_2408_02350_amd/csrc/k_fused.hip",
-                   "paper_2408_02350_amd/csrc/device_common.h")
+                   "paper_2408_02350_amd/csrc/device_common.h",
+                   "paper_2408_02350_amd/csrc/bgk_internal.h")
 
 
 def kernel_source_hash():
@@ -130,6 +131,46 @@ def run_gpu(cav, precision, steps, warmup, timing=True):
     return ms, ktime, edges, state, diag
 
 
+def time_particle_management(cav, reps):
+    """Wall time of one plan (with its host read of the counts) and one
+    apply on a disturbed cloud of the workload's lattice (interior particles
+    displaced by up to 0.45 dx, 20% removed), FP64 state at the rest
+    Maxwellian, mean over reps after one warm-up."""
+    import torch
+
+    import paper_2408_02350_amd.bgk as bgk
+    from paper_2408_02350_amd.inputs import disturbed_cloud
+
+    x, wid = disturbed_cloud(cav.dim, cav.n, 0)
+    N = x.shape[1]
+    cfg = bgk.config_from(cav, cav.precision, n_particles=N, flags=bgk.BGK_FLAG_PARTICLES)
+    dev = torch.device("cuda:0")
+    ctx = bgk.bgk_init(cfg, torch.from_numpy(wid).to(dev))
+    xt = torch.from_numpy(x).to(dev)
+    rho = torch.ones(N, dtype=torch.float64, device=dev)
+    U = torch.zeros((cav.dim, N), dtype=torch.float64, device=dev)
+    T = torch.ones(N, dtype=torch.float64, device=dev)
+    f = bgk.bgk_maxwellian(ctx, rho, U, T)
+    plan_ms, apply_ms = [], []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pairs, holes = bgk.bgk_pm_plan(ctx, xt)
+        t1 = time.perf_counter()
+        out = bgk.bgk_pm_apply(ctx, xt, f, rho, U, T, N - pairs + holes)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        bgk.bgk_check(ctx)
+        del out
+        if r > 0:
+            plan_ms.append((t1 - t0) * 1e3)
+            apply_ms.append((t2 - t1) * 1e3)
+    log(f"[bench] particle management {cav.name}: N={N} pairs={pairs} holes={holes}")
+    return {"workload": cav.name + "_disturbed", "n_particles": N, "n_velocities": cav.n_velocities,
+            "pairs": pairs, "holes": holes, "plan_ms": sum(plan_ms) / len(plan_ms),
+            "apply_ms": sum(apply_ms) / len(apply_ms), "reps": reps, "precision": cav.precision}
+
+
 def moment_errors(state, ref, lid):
     import numpy as np
 
@@ -183,6 +224,9 @@ def main():
                     help="only time the paper's own cavity sizes (20 velocity points per "
                          "axis, h = 3.1 dx, first-derivative least squares) and print one "
                          "JSON line with the per-step times")
+    ap.add_argument("--particle-management", action="store_true",
+                    help="only time bgk_pm_plan + bgk_pm_apply on a disturbed cloud of the "
+                         "workload's size and print one JSON line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference "
                          "kernel for scaling HBM byte counters) and exit")
@@ -218,6 +262,11 @@ def main():
                          "updates_per_s": pc.n_particles * pc.n_velocities / (ms * 1e-3)})
         print(json.dumps({"paper_scales": rows, "precision": args.precision,
                           "steps": args.steps, "warmup": args.warmup}), flush=True)
+        return
+
+    if args.particle_management:
+        print(json.dumps({"particle_management": time_particle_management(
+            CONFIGS[args.workload].replace(precision=args.precision), args.steps)}), flush=True)
         return
 
     cav = CONFIGS[args.workload].replace(precision=args.precision)

@@ -69,7 +69,7 @@ typedef enum {
 } bgk_status;
 
 enum { BGK_FP64 = 0, BGK_FP32 = 1, BGK_BF16 = 2 };
-enum { BGK_FLAG_GENERIC = 1, BGK_FLAG_ADJOINT = 2 };
+enum { BGK_FLAG_GENERIC = 1, BGK_FLAG_ADJOINT = 2, BGK_FLAG_PARTICLES = 4 };
 
 typedef struct {
   int32_t dim;           /* 2: Chu-reduced BGK (Sec. 2.1, g1 and g2); 3: full BGK        */
@@ -86,7 +86,9 @@ typedef struct {
   int32_t flags;         /* bit set: BGK_FLAG_GENERIC uses the separate transport and
                             relaxation kernels instead of the fused one (for testing);
                             BGK_FLAG_ADJOINT reserves the workspace of
-                            bgk_adjoint_step (needs BGK_FP64 or BGK_FP32, move = 0)     */
+                            bgk_adjoint_step (needs BGK_FP64 or BGK_FP32, move = 0);
+                            BGK_FLAG_PARTICLES reserves that of bgk_pm_plan /
+                            bgk_pm_apply                                                  */
   double vmax;           /* velocity grid spans [-vmax, vmax] per axis                   */
   double h;              /* support radius of the Gaussian weight (absolute)             */
   double alpha;          /* weight exp(-alpha r^2/h^2), r <= h (Sec. 3.4.1, eq. weight) */
@@ -192,6 +194,45 @@ int bgk_move(bgk_ctx* ctx, double* x, const double* U);
  * rho, T: receive the new values. */
 int bgk_step(bgk_ctx* ctx, const void* f_in, void* f_out, double* x, double* U, double* rho,
              double* T);
+
+/* Particle management (Sec. 4.1.2, adding and removing points), plan.  The
+ * paper replaces two points that come too close by one at their midpoint
+ * and adds points where holes open, filling f there by least squares; it
+ * states no thresholds.  The rule taken: interior particles i < j that are
+ * each other's nearest interior neighbour within h (ties to the lower
+ * index) and closer than merge_radius merge into one interior particle at
+ * 0.5 (x_i + x_j); every interior node k dx of the initial lattice
+ * (0 < k < n-1 per axis, n = round(1/dx) + 1) with no particle of the
+ * merged cloud within hole_radius gets a new interior particle.  Distances
+ * are squared, summed component by component.  x: device [d][N].  Writes
+ * the counts to the host ints *n_pairs and *n_holes (synchronises the
+ * stream); the managed cloud has N' = N - n_pairs + n_holes particles.
+ * Needs BGK_FLAG_PARTICLES and 0 < merge_radius, 0 < hole_radius,
+ * merge_radius + hole_radius <= h (else BGK_ENOTSUP / BGK_EINVAL).  It
+ * rebuilds the context's cell list from x, so a frozen cloud's geometry is
+ * rebuilt by the next step.  Defaults used by the Python layer: merge
+ * radius dx/4, hole radius 0.45 h. */
+int bgk_pm_plan(bgk_ctx* ctx, const double* x, double merge_radius, double hole_radius,
+                int32_t* n_pairs, int32_t* n_holes);
+
+/* Particle management, apply the plan of the last bgk_pm_plan (same x, no
+ * call that moves the cloud or rebuilds its cell list in between, else
+ * BGK_EINVAL).  Inputs (device, old cloud of N): x [d][N], f [n_c][N][N_v]
+ * (storage precision), rho [N], U [d][N], T [N].  Outputs (device, caller
+ * allocated for N'): x_new [d][N'], wall_id_new [N'], f_new [n_c][N'][N_v],
+ * rho_new [N'], U_new [d][N'], T_new [N'].  Order of the new cloud: the
+ * particles not merged, in their old order, with their f, rho, U, T and
+ * owner; then the midpoints by the lower index of their pair; then the
+ * hole particles by node index k_x + n k_y (+ n^2 k_z).  f at a new
+ * particle: the degree-1 least-squares value row at its position over the
+ * old cloud's interior particles within hb (the rule of the wall rows),
+ * applied to every velocity and component; its rho, U, T are the moments
+ * of that f (BGK_ENONPHYS in the error word if they are not positive;
+ * BGK_ESINGULAR / BGK_ENBR_OVERFLOW as for wall rows).  A context for the
+ * new cloud is created with bgk_init and n_particles = N'. */
+int bgk_pm_apply(bgk_ctx* ctx, const double* x, const void* f, const double* rho,
+                 const double* U, const double* T, double* x_new, int32_t* wall_id_new,
+                 void* f_new, double* rho_new, double* U_new, double* T_new);
 
 /* Moments (Sec. 2 eqs. moments, internal_energy; Chu eq. macroeq) of every
  * particle: rho = omega sum f1, U = sum v f1 / sum f1, T from the centred

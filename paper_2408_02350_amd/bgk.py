@@ -24,6 +24,7 @@ BGK_OK, BGK_EINVAL, BGK_ENOMEM, BGK_ENBR_OVERFLOW, BGK_ESINGULAR, BGK_ENONPHYS, 
 BGK_FP64, BGK_FP32, BGK_BF16 = 0, 1, 2
 BGK_FLAG_GENERIC = 1
 BGK_FLAG_ADJOINT = 2
+BGK_FLAG_PARTICLES = 4
 PRECISIONS = {"fp64": BGK_FP64, "fp32": BGK_FP32, "bf16": BGK_BF16}
 STATUS = {0: "BGK_OK", 1: "BGK_EINVAL", 2: "BGK_ENOMEM", 3: "BGK_ENBR_OVERFLOW",
           4: "BGK_ESINGULAR", 5: "BGK_ENONPHYS", 6: "BGK_EDEVICE", 7: "BGK_ENOTSUP"}
@@ -34,7 +35,7 @@ EXPORTS = ("bgk_workspace_bytes", "bgk_init", "bgk_destroy", "bgk_set_lid_veloci
            "bgk_transport", "bgk_collide", "bgk_wall_bc", "bgk_move", "bgk_step",
            "bgk_moments", "bgk_maxwellian", "bgk_check", "bgk_diagnostics", "bgk_last_error",
            "bgk_timing_enable", "bgk_timing_read", "bgk_objective", "bgk_adjoint_step",
-           "bgk_moments_adjoint")
+           "bgk_moments_adjoint", "bgk_pm_plan", "bgk_pm_apply")
 
 
 class BgkError(RuntimeError):
@@ -93,6 +94,9 @@ def load_library(path: str = LIB_PATH):
         "bgk_objective": [vp, vp, dp, dp, ctypes.c_double, dp, vp, dp, dp],
         "bgk_adjoint_step": [vp, vp, dp, dp, vp, dp, dp, dp, vp, dp, dp],
         "bgk_moments_adjoint": [vp, dp, dp, dp, dp, dp, dp, vp],
+        "bgk_pm_plan": [vp, dp, ctypes.c_double, ctypes.c_double,
+                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+        "bgk_pm_apply": [vp, dp, vp, dp, dp, dp, dp, i32p, vp, dp, dp, dp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -393,6 +397,39 @@ def bgk_moments_adjoint(ctx: Context, rho, U, T, lam_f, lam_rho=None, lam_U=None
     return lam_f
 
 
+def bgk_pm_plan(ctx: Context, x, merge_radius=None, hole_radius=None):
+    """Particle-management plan of the cloud x (needs BGK_FLAG_PARTICLES):
+    returns (n_pairs, n_holes).  Radii default to dx/4 and 0.45 h."""
+    _vec(ctx, x, "x")
+    rm = 0.25 * ctx.cfg.dx if merge_radius is None else float(merge_radius)
+    rh = 0.45 * ctx.cfg.h if hole_radius is None else float(hole_radius)
+    n_pairs, n_holes = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(ctx, load_library().bgk_pm_plan(ctx.handle, _ptr(x), rm, rh, ctypes.byref(n_pairs),
+                                           ctypes.byref(n_holes)), "bgk_pm_plan")
+    return int(n_pairs.value), int(n_holes.value)
+
+
+def bgk_pm_apply(ctx: Context, x, f, rho, U, T, n_new):
+    """The managed cloud of the last plan: (x_new, wall_id_new, f_new,
+    rho_new, U_new, T_new) with n_new = N - n_pairs + n_holes particles."""
+    _vec(ctx, x, "x")
+    _f(ctx, f, "f")
+    _sca(ctx, rho, "rho")
+    _vec(ctx, U, "U")
+    _sca(ctx, T, "T")
+    n_new = int(n_new)
+    xn = _empty(ctx, (ctx.d, n_new), torch.float64)
+    wn = _empty(ctx, (n_new,), torch.int32)
+    fn = _empty(ctx, (ctx.nc, n_new, ctx.NV), f_dtype(ctx.cfg))
+    rn = _empty(ctx, (n_new,), torch.float64)
+    Un = _empty(ctx, (ctx.d, n_new), torch.float64)
+    Tn = _empty(ctx, (n_new,), torch.float64)
+    _check(ctx, load_library().bgk_pm_apply(ctx.handle, _ptr(x), _ptr(f), _ptr(rho), _ptr(U),
+                                            _ptr(T), _ptr(xn), _ptr(wn), _ptr(fn), _ptr(rn),
+                                            _ptr(Un), _ptr(Tn)), "bgk_pm_apply")
+    return xn, wn, fn, rn, Un, Tn
+
+
 def bgk_check(ctx: Context):
     """Synchronise and raise BgkError if a kernel recorded a data error."""
     _check(ctx, load_library().bgk_check(ctx.handle), "bgk_check")
@@ -447,3 +484,25 @@ class Simulation:
         for _ in range(n):
             bgk_step(self.ctx, self.f, self.f_next, self.x, self.U, self.rho, self.T)
             self.f, self.f_next = self.f_next, self.f
+
+    def manage_particles(self, merge_radius=None, hole_radius=None):
+        """Merge close pairs and fill holes (the context must carry
+        BGK_FLAG_PARTICLES).  When the cloud changes, the state tensors are
+        replaced and a context for the new particle count is created.
+        Returns (n_pairs, n_holes)."""
+        n_pairs, n_holes = bgk_pm_plan(self.ctx, self.x, merge_radius, hole_radius)
+        if n_pairs == 0 and n_holes == 0:
+            return 0, 0
+        n_new = self.ctx.N - n_pairs + n_holes
+        x, wid, f, rho, U, T = bgk_pm_apply(self.ctx, self.x, self.f, self.rho, self.U, self.T,
+                                            n_new)
+        bgk_check(self.ctx)
+        cfg = BgkConfig.from_buffer_copy(self.cfg)
+        cfg.n_particles = n_new
+        stream = self.ctx.stream
+        self.ctx.close()
+        self.cfg, self.x, self.wall_id, self.f = cfg, x, wid, f
+        self.rho, self.U, self.T = rho, U, T
+        self.f_next = torch.empty_like(f)
+        self.ctx = bgk_init(cfg, wid, stream)
+        return n_pairs, n_holes

@@ -63,16 +63,17 @@ bool config_ok(const bgk_config& g) {
   return (g.dim == 2 || g.dim == 3) && g.n_particles > 0 && g.nv >= 2 && g.nv <= 1024 && g.nv % 2 == 0 &&
          g.wls_degree >= 0 && g.wls_degree <= 2 && g.max_neighbors >= g.dim + 2 &&
          g.max_neighbors <= 255 && (g.move == 0 || g.move == 1) && g.precision >= BGK_FP64 &&
-         g.precision <= BGK_BF16 && (g.flags & ~(BGK_FLAG_GENERIC | BGK_FLAG_ADJOINT)) == 0 &&
+         g.precision <= BGK_BF16 && (g.flags & ~(BGK_FLAG_GENERIC | BGK_FLAG_ADJOINT | BGK_FLAG_PARTICLES)) == 0 &&
          (!(g.flags & BGK_FLAG_ADJOINT) || (g.precision != BGK_BF16 && g.move == 0)) && g.vmax > 0 && g.h > 0 && g.alpha > 0 &&
          g.kn > 0 && g.dt > 0 && g.wall_T > 0 && g.dx > 0 && std::isfinite(g.lid_velocity) &&
          ipow(g.nv, g.dim) <= INT32_MAX / 4 &&
+         (!(g.flags & BGK_FLAG_PARTICLES) || ipow(lattice_nodes(g), g.dim) < INT32_MAX / 2) &&
          static_cast<int64_t>(g.n_particles) * g.max_neighbors * g.dim * g.dim < INT32_MAX;
 }
 
 }  // namespace
 
-size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj) {
+size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj, Pm* pm) {
   const int64_t N = cfg.n_particles, cap = cfg.max_neighbors, D = cfg.dim, DD = D * D;
   const int64_t ncell = ipow(cells_per_axis(cfg), cfg.dim);
   const int64_t tp = patch_size(cfg.dim, cfg.precision);
@@ -127,6 +128,16 @@ size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj) {
     a.lidpart = reinterpret_cast<double*>(take(N * 8));
     if (adj) *adj = a;
   }
+  if (cfg.flags & BGK_FLAG_PARTICLES) {
+    const int64_t nodes = ipow(lattice_nodes(cfg), cfg.dim);
+    Pm p{};
+    p.nn = reinterpret_cast<int32_t*>(take(N * 4));
+    p.partner = reinterpret_cast<int32_t*>(take(N * 4));
+    p.keep = reinterpret_cast<int32_t*>(take((N + 1) * 4));
+    p.mid = reinterpret_cast<int32_t*>(take((N + 1) * 4));
+    p.hole = reinterpret_cast<int32_t*>(take((nodes + 1) * 4));
+    if (pm) *pm = p;
+  }
   return off;
 }
 
@@ -154,6 +165,7 @@ static int build_geometry(Ctx& c, const double* x) {
   if (e == hipSuccess) e = launch_wall_stencil(c, x);
   if (e == hipSuccess) e = launch_patches(c);
   c.adj_valid = false;
+  c.pm_valid = false;
   if (e != hipSuccess) return hip_fail(&c, e, "geometry launch");
   c.geom_valid = true;
   return BGK_OK;
@@ -167,7 +179,7 @@ extern "C" {
 
 int bgk_workspace_bytes(const bgk_config* cfg, size_t* bytes) {
   if (!cfg || !bytes || !bgk::config_ok(*cfg)) return BGK_EINVAL;
-  *bytes = bgk::workspace_layout(*cfg, nullptr, nullptr, nullptr);
+  *bytes = bgk::workspace_layout(*cfg, nullptr, nullptr, nullptr, nullptr);
   return BGK_OK;
 }
 
@@ -176,7 +188,7 @@ int bgk_init(const bgk_config* cfg, const int32_t* wall_id, void* workspace, siz
   if (!out) return BGK_EINVAL;
   *out = nullptr;
   if (!cfg || !wall_id || !workspace || !bgk::config_ok(*cfg)) return BGK_EINVAL;
-  const size_t need = bgk::workspace_layout(*cfg, nullptr, nullptr, nullptr);
+  const size_t need = bgk::workspace_layout(*cfg, nullptr, nullptr, nullptr, nullptr);
   if (ws_bytes < need) return BGK_ENOMEM;
   bgk_ctx* h = new (std::nothrow) bgk_ctx;
   if (!h) return BGK_ENOMEM;
@@ -192,7 +204,9 @@ int bgk_init(const bgk_config* cfg, const int32_t* wall_id, void* workspace, siz
   c.nca = bgk::cells_per_axis(*cfg);
   c.ncell = static_cast<int>(bgk::ipow(c.nca, c.D));
   c.lid = cfg->lid_velocity;
-  bgk::workspace_layout(*cfg, static_cast<char*>(workspace), &c.d, &c.adj);
+  bgk::workspace_layout(*cfg, static_cast<char*>(workspace), &c.d, &c.adj, &c.pm);
+  c.nl = bgk::lattice_nodes(*cfg);
+  c.nodes = bgk::ipow(c.nl, c.D);
   hipError_t e = hipGetDevice(&c.device);
   // wall ids: read once to count and list the wall particles
   std::vector<int32_t> wid(c.N);
@@ -285,6 +299,7 @@ int bgk_build_neighbors(bgk_ctx* ctx, const double* x, int32_t* nbr_cnt, int32_t
   hipError_t e = bgk::launch_cells(c, x);
   if (e == hipSuccess) e = bgk::launch_neighbors(c, x, nbr_cnt, nbr_idx);
   c.geom_valid = false;
+  c.pm_valid = false;
   return bgk::hip_fail(&c, e, "bgk_build_neighbors");
 }
 
@@ -299,6 +314,7 @@ int bgk_wls_operators(bgk_ctx* ctx, const double* x, const int32_t* nbr_cnt,
   if (e == hipSuccess && degree) e = bgk::launch_fill_i32(c.stream, degree, c.N, 0);
   if (e == hipSuccess) e = bgk::launch_wls(c, x, nbr_cnt, nbr_idx, grad, ops, nullptr, degree);
   c.geom_valid = false;
+  c.pm_valid = false;
   return bgk::hip_fail(&c, e, "bgk_wls_operators");
 }
 
@@ -315,6 +331,7 @@ int bgk_wall_stencil(bgk_ctx* ctx, const double* x, int32_t* wall_cnt, int32_t* 
   if (e == hipSuccess && wall_radius) e = bgk::launch_fill_f64(c.stream, wall_radius, c.N, 0.0);
   if (e == hipSuccess) e = bgk::launch_scatter_wall_rows(c, wall_cnt, wall_idx, wall_c0, wall_radius);
   c.geom_valid = false;
+  c.pm_valid = false;
   return bgk::hip_fail(&c, e, "bgk_wall_stencil");
 }
 
@@ -355,6 +372,7 @@ int bgk_move(bgk_ctx* ctx, double* x, const double* U) {
   if (!c.geom_valid) return bgk::fail(&c, BGK_EINVAL, "bgk_move before bgk_geometry");
   const hipError_t e = bgk::launch_move(c, x, U);
   c.geom_valid = false;
+  c.pm_valid = false;
   return bgk::hip_fail(&c, e, "bgk_move");
 }
 
@@ -385,10 +403,58 @@ int bgk_step(bgk_ctx* ctx, const void* f_in, void* f_out, double* x, double* U, 
   if (e == hipSuccess && c.cfg.move) {
     e = bgk::launch_move(c, x, U);
     c.geom_valid = false;
+    c.pm_valid = false;
   }
   if (e != hipSuccess) return bgk::hip_fail(&c, e, "bgk_step");
   ++c.steps;
   return BGK_OK;
+}
+
+int bgk_pm_plan(bgk_ctx* ctx, const double* x, double merge_radius, double hole_radius,
+                int32_t* n_pairs, int32_t* n_holes) {
+  if (!ctx || !x || !n_pairs || !n_holes) return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  if (!(c.cfg.flags & BGK_FLAG_PARTICLES))
+    return bgk::fail(&c, BGK_ENOTSUP, "bgk_pm_plan needs a context with BGK_FLAG_PARTICLES");
+  if (!(merge_radius > 0.0) || !(hole_radius > 0.0) || !(merge_radius + hole_radius <= c.cfg.h))
+    return bgk::fail(&c, BGK_EINVAL, "bgk_pm_plan: radii must be > 0 with merge + hole <= h");
+  // the plan rebuilds the cell list of x: the geometry of a frozen cloud is
+  // rebuilt by the next step
+  c.geom_valid = false;
+  c.adj_valid = false;
+  c.pm_valid = false;
+  hipError_t e = bgk::launch_pm_plan(c, x, merge_radius, hole_radius);
+  int32_t tot[3] = {0, 0, 0};
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&tot[0], c.pm.keep + c.N, 4, hipMemcpyDeviceToHost, c.stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&tot[1], c.pm.mid + c.N, 4, hipMemcpyDeviceToHost, c.stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&tot[2], c.pm.hole + c.nodes, 4, hipMemcpyDeviceToHost, c.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+  if (e != hipSuccess) return bgk::hip_fail(&c, e, "bgk_pm_plan");
+  for (int k = 0; k < 3; ++k) c.pm_tot[k] = tot[k];
+  c.pm_valid = true;
+  *n_pairs = tot[1];
+  *n_holes = tot[2];
+  return BGK_OK;
+}
+
+int bgk_pm_apply(bgk_ctx* ctx, const double* x, const void* f, const double* rho,
+                 const double* U, const double* T, double* x_new, int32_t* wall_id_new,
+                 void* f_new, double* rho_new, double* U_new, double* T_new) {
+  if (!ctx || !x || !f || !rho || !U || !T || !x_new || !wall_id_new || !f_new || !rho_new ||
+      !U_new || !T_new || f == f_new || x == x_new)
+    return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  if (!(c.cfg.flags & BGK_FLAG_PARTICLES))
+    return bgk::fail(&c, BGK_ENOTSUP, "bgk_pm_apply needs a context with BGK_FLAG_PARTICLES");
+  if (!c.pm_valid) return bgk::fail(&c, BGK_EINVAL, "bgk_pm_apply without a current bgk_pm_plan");
+  const int n_keep = c.pm_tot[0], n_new = c.pm_tot[1] + c.pm_tot[2];
+  const int Nn = n_keep + n_new;
+  return bgk::hip_fail(&c, bgk::launch_pm_apply(c, x, f, rho, U, T, Nn, n_keep, n_new, x_new,
+                                                wall_id_new, f_new, rho_new, U_new, T_new),
+                       "bgk_pm_apply");
 }
 
 int bgk_moments(bgk_ctx* ctx, const void* f, double* rho, double* U, double* T) {

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <string>
 #include <utility>
@@ -71,6 +72,28 @@ struct Adj {
   double* lidpart;    // [max(Nw,1)]
 };
 
+// Workspace of the particle management (BGK_FLAG_PARTICLES).
+struct Pm {
+  int32_t* nn;        // [N]         nearest interior neighbour within h (-1: none)
+  int32_t* partner;   // [N]         other particle of a merged pair (-1: none)
+  int32_t* keep;      // [N+1]       exclusive scan of the kept particles
+  int32_t* mid;       // [N+1]       exclusive scan of the lower pair members
+  int32_t* hole;      // [nodes+1]   exclusive scan of the hole nodes
+};
+
+// Quadrature weight of every velocity node, (2 vmax/(nv-1))^d.
+inline double omega_of(const bgk_config& cfg) {
+  const double dv = 2.0 * cfg.vmax / static_cast<double>(cfg.nv - 1);
+  double w = 1.0;
+  for (int a = 0; a < cfg.dim; ++a) w = w * dv;
+  return w;
+}
+
+// Lattice nodes per axis of the initial cloud (spacing dx on [0, 1]).
+inline int lattice_nodes(const bgk_config& cfg) {
+  return static_cast<int>(std::lround(1.0 / cfg.dx)) + 1;
+}
+
 struct Ctx {
   bgk_config cfg;
   hipStream_t stream = nullptr;
@@ -81,6 +104,11 @@ struct Ctx {
   double lid = 0.0;
   Dev d{};
   Adj adj{};
+  Pm pm{};
+  int nl = 0;               // lattice nodes per axis (particle management)
+  int64_t nodes = 0;        // nl^d
+  bool pm_valid = false;    // a particle-management plan of the current cloud is held
+  int32_t pm_tot[3] = {0, 0, 0};  // kept, midpoints, holes of that plan
   bool adj_valid = false;   // transposed stencils match the current geometry
   bool geom_valid = false;  // geometry of the current (frozen) cloud is built
   int64_t steps = 0;
@@ -91,7 +119,7 @@ struct Ctx {
 };
 
 // Workspace layout: returns total bytes; fills d when base != nullptr.
-size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj);
+size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj, Pm* pm);
 
 // ---- launchers (enqueue on c.stream; return hipError_t of the launch) ----
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
@@ -125,6 +153,11 @@ hipError_t launch_maxwellian(const Ctx& c, const double* rho, const double* U, c
                              void* f);
 
 // Reverse mode (FP64, frozen cloud).
+hipError_t launch_pm_plan(Ctx& c, const double* x, double rm, double rh);
+hipError_t launch_pm_apply(const Ctx& c, const double* x, const void* f, const double* rho,
+                           const double* U, const double* T, int Nn, int n_keep, int n_new,
+                           double* x_new, int32_t* wall_id_new, void* f_new, double* rho_new,
+                           double* U_new, double* T_new);
 hipError_t launch_adjoint_transposes(const Ctx& c);
 // f-sized arguments (f_n, lam_f1, lam_f, dJ_df) are in the f storage type.
 hipError_t launch_adjoint_step(const Ctx& c, const void* f_n, const double* U_n,

@@ -101,13 +101,6 @@ static void collide_t(const Ctx& c, const CollideArgs& a) {
   hipLaunchKernelGGL((k_collide<D, NC, Real>), dim3(a.count), dim3(kThreads), 0, c.stream, a);
 }
 
-static double omega_of(const bgk_config& cfg) {
-  const double dv = 2.0 * cfg.vmax / static_cast<double>(cfg.nv - 1);
-  double w = 1.0;
-  for (int a = 0; a < cfg.dim; ++a) w = w * dv;
-  return w;
-}
-
 hipError_t launch_collide(const Ctx& c, const void* ft, void* fout, double* rho, double* U,
                           double* T) {
   if (c.Ni == 0) return hipSuccess;

@@ -10,7 +10,7 @@
 #include <algorithm>
 #include <climits>
 
-#include "device_common.h"
+#include "cloud_common.h"
 
 namespace bgk {
 
@@ -67,39 +67,6 @@ hipError_t launch_max_i32(hipStream_t s, const int32_t* a, int n, int32_t* out) 
 }
 
 // ------------------------------------------------------------ cell list
-// Order of the cells.  The first d-1 axes are cut into tiles of
-// kCellTile<D> cells (strips in 2D, columns in 3D) and each tile is swept
-// along the last axis, x fastest inside the tile.  Interior particles are
-// processed in this order in patches of tp, and each XCD takes one
-// contiguous range of patches; sweeping a narrow tile brings a neighbour row
-// back within a few patches, while it is still in the XCD's L2 (a plain
-// row-major order returns to it only one full row of cells later).
-template <int D>
-struct CellTile;
-template <>
-struct CellTile<2> {
-  static constexpr int S = 12;
-};
-template <>
-struct CellTile<3> {
-  static constexpr int S = 4;
-};
-
-// Key of cell (cc[0], .., cc[D-1]), 0 <= cc < nca: a bijection onto
-// [0, nca^D) that lists the tiles in order (last tile of an axis narrower
-// when S does not divide nca).
-template <int D>
-__device__ __forceinline__ int cell_key(const int* cc, int nca) {
-  constexpr int S = CellTile<D>::S;
-  const int x0 = (cc[0] / S) * S, wx = min(S, nca - x0);
-  if constexpr (D == 2) {
-    return x0 * nca + cc[1] * wx + (cc[0] - x0);
-  } else {
-    const int y0 = (cc[1] / S) * S, wy = min(S, nca - y0);
-    return nca * (y0 * nca + x0 * wy) + cc[2] * (wx * wy) + (cc[1] - y0) * wx + (cc[0] - x0);
-  }
-}
-
 // Key of a particle: its cell (cells of size 1/nca >= h) in the order
 // above, plus ncell for wall particles, so that the sorted permutation
 // holds all interior particles first (in cell order) and the wall particles
@@ -241,87 +208,6 @@ hipError_t launch_cells(const Ctx& c, const double* x) {
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------ wave helpers
-// The kernels below run one wavefront (a block of 64 threads) per particle,
-// patch or wall particle; lanes work on candidates / neighbours in parallel.
-constexpr int kWave = 64;
-
-__device__ __forceinline__ int lanes_below(uint64_t mask) {
-  const int lane = threadIdx.x & 63;
-  return __popcll(mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-}
-
-// Ranges of the cells within +-S cells of cell coordinate ci (only the
-// interior part when walls == false).  Writes range starts rb[] and the
-// exclusive prefix of their lengths rpre[] (rpre[nr] = total) to LDS and
-// returns nr.  Must be called by all 64 lanes.
-template <int D, int S>
-__device__ int cell_ranges(const int* ci, int nca, int ncell, bool walls,
-                           const int32_t* __restrict__ cstart, int32_t* rb, int32_t* rpre) {
-  constexpr int W = 2 * S + 1;
-  constexpr int NC = (D == 2) ? W * W : W * W * W;
-  const int parts = walls ? 2 : 1;
-  const int nr = NC * parts;
-  const int lane = threadIdx.x;
-  int carry = 0;
-  for (int r0 = 0; r0 < nr; r0 += kWave) {
-    const int r = r0 + lane;
-    int len = 0, b = 0;
-    if (r < nr) {
-      const int part = r % parts, co = r / parts;
-      int cc[D], rem = co;
-      bool ok = true;
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        cc[a] = ci[a] + (rem % W) - S;
-        rem /= W;
-        ok = ok && cc[a] >= 0 && cc[a] < nca;
-      }
-      if (ok) {
-        const int k = cell_key<D>(cc, nca) + part * ncell;
-        b = cstart[k];
-        len = cstart[k + 1] - b;
-      }
-    }
-    int incl = len;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int t = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += t;
-    }
-    if (r < nr) {
-      rb[r] = b;
-      rpre[r] = carry + incl - len;
-    }
-    carry += __shfl(incl, 63, 64);
-  }
-  if (lane == 0) rpre[nr] = carry;
-  __syncthreads();
-  return nr;
-}
-
-// Candidate c (0 <= c < rpre[nr]) -> its slot in the cell-ordered arrays.
-__device__ __forceinline__ int cand_slot(int c, int nr, const int32_t* rb, const int32_t* rpre) {
-  int lo = 0, hi = nr;  // rpre[lo] <= c < rpre[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (rpre[mid] <= c) lo = mid; else hi = mid;
-  }
-  return rb[lo] + (c - rpre[lo]);
-}
-
-// Write the n values of list[] to row[] in ascending order (rank sort; the
-// values are distinct particle indices); only ranks < cap are written.
-__device__ __forceinline__ void rank_sorted_store(const int32_t* list, int n, int cap,
-                                                  int32_t* __restrict__ row) {
-  for (int s = threadIdx.x; s < n; s += kWave) {
-    const int v = list[s];
-    int rank = 0;
-    for (int q = 0; q < n; ++q) rank += (list[q] < v);
-    if (rank < cap) row[rank] = v;
-  }
-}
-
 // ------------------------------------------------------------ S1 neighbours
 // One wave per particle: the lanes test the candidates of the 3^D cells
 // around the particle's own (interior and wall ranges) against
@@ -391,86 +277,6 @@ hipError_t launch_neighbors(const Ctx& c, const double* x, int32_t* cnt, int32_t
 }
 
 // ------------------------------------------------------------ S2-S3 WLS
-template <int D, int DEG>
-struct Basis {
-  static constexpr int B = (DEG == 1) ? D + 1 : (D == 2 ? 6 : 10);
-  static constexpr int NT = B * (B + 1) / 2;  // packed lower triangle
-  __device__ static __forceinline__ void eval(const double* y, double* p) {
-    p[0] = 1.0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) p[1 + a] = y[a];
-    if (DEG == 2) {
-      int k = D + 1;
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = a; b < D; ++b) p[k++] = y[a] * y[b];
-    }
-  }
-};
-
-__device__ __forceinline__ constexpr int tri(int r, int s) { return r * (r + 1) / 2 + s; }
-
-// Weighted least squares on one wave, for the stencil already staged in LDS
-// as P[e][B] (basis values) and W[e] (weights), e < m.  Builds
-// A = sum_e W_e p_e p_e^T (each entry summed over e in order), factors it
-// A = L L^T (Cholesky, column by column, the rows of a column in parallel),
-// and solves L L^T z = e_col for the NCOL columns col0 .. col0+NCOL-1 into
-// Z[k][B].  Returns false on a non-positive pivot.  All 64 lanes call it.
-template <int B, int NCOL>
-__device__ bool wave_lsq(int m, const double* P, const double* W, double* A, double* Z, int col0,
-                         int* flag) {
-  constexpr int NT = B * (B + 1) / 2;
-  const int lane = threadIdx.x;
-  for (int l = lane; l < NT; l += kWave) {
-    int r = 0;
-    while (tri(r + 1, 0) <= l) ++r;
-    const int s = l - tri(r, 0);
-    double acc = 0.0;
-    for (int e = 0; e < m; ++e) acc = acc + (W[e] * P[e * B + r]) * P[e * B + s];
-    A[l] = acc;
-  }
-  if (lane == 0) *flag = 0;
-  __syncthreads();
-  for (int j = 0; j < B; ++j) {
-    if (lane == 0) {
-      double s = A[tri(j, j)];
-      for (int k = 0; k < j; ++k) s = s - A[tri(j, k)] * A[tri(j, k)];
-      if (!(s > 0.0)) *flag = 1;
-      A[tri(j, j)] = sqrt(s);
-    }
-    __syncthreads();
-    if (*flag) return false;
-    if (lane > j && lane < B) {
-      double t = A[tri(lane, j)];
-      for (int k = 0; k < j; ++k) t = t - A[tri(lane, k)] * A[tri(j, k)];
-      A[tri(lane, j)] = t / A[tri(j, j)];
-    }
-    __syncthreads();
-  }
-  if (lane < NCOL) {
-    const int col = col0 + lane;
-    double y[B];
-#pragma unroll
-    for (int i = 0; i < B; ++i) {
-      double s = (i == col) ? 1.0 : 0.0;
-#pragma unroll
-      for (int k = 0; k < i; ++k) s = s - A[tri(i, k)] * y[k];
-      y[i] = s / A[tri(i, i)];
-    }
-    double* z = Z + lane * B;
-#pragma unroll
-    for (int i = B - 1; i >= 0; --i) {
-      double s = y[i];
-#pragma unroll
-      for (int k = i + 1; k < B; ++k) s = s - A[tri(k, i)] * z[k];
-      z[i] = s / A[tri(i, i)];
-    }
-  }
-  __syncthreads();
-  return true;
-}
-
 // Edge frame of x_j - x_i (Sec. 3.4.2) without trigonometric calls: in 2D
 // n = dl/|dl|, t = n turned by +90 degrees; in 3D n = dl/r, t = (cos th cos
 // phi, cos th sin phi, -sin th), b = (-sin phi, cos phi, 0) with sin th =
@@ -757,19 +563,12 @@ hipError_t launch_wls(const Ctx& c, const double* x, const int32_t* cnt, const i
 }
 
 // ------------------------------------------------------------ wall rows
-// One wave per wall particle b: hb is the first of h, 1.5h, 2h with at least
-// d+2 interior particles within it (the candidate cells within +-2 cells,
-// interior ranges, are scanned once per radius tried, keeping only the
-// particles inside it); those are stored ascending with the degree-1
-// least-squares value weights at x_b (weights exp(-alpha r^2/hb^2)).
+// One wave per wall particle b: its value row at x_b (interior particles
+// within hb, ascending, with their degree-1 least-squares value weights;
+// value_row).
 struct WallArgs {
-  int N, cap, Nw, nca, ncell;
-  double h, alpha;
-  const double* x;
-  const double* xs;
+  CloudView cv;
   const int32_t* wall_list;
-  const int32_t* cstart;
-  const int32_t* cperm;
   int32_t* wcnt;
   int32_t* widx;
   double* wc0;
@@ -779,97 +578,38 @@ struct WallArgs {
 
 template <int D>
 __global__ __launch_bounds__(64) void k_wall_stencil(const WallArgs a) {
-  constexpr int NR = (D == 2 ? 25 : 125);
-  constexpr int B = D + 1;
-  __shared__ int32_t rb[NR], rpre[NR + 1];
-  __shared__ int32_t sel[256], srt[256];  // cap <= 255
-  __shared__ double P[256 * B], W[256], A[B * (B + 1) / 2], Z[B];
-  __shared__ int flag;
+  __shared__ ValueRowSm<D> sm;
   const int k = blockIdx.x, lane = threadIdx.x;
   const int b = a.wall_list[k];
   double xb[D];
-  int cb[D];
 #pragma unroll
-  for (int q = 0; q < D; ++q) {
-    xb[q] = a.x[static_cast<int64_t>(q) * a.N + b];
-    cb[q] = cell_coord(xb[q], a.nca);
-  }
-  const int nr = cell_ranges<D, 2>(cb, a.nca, a.ncell, false, a.cstart, rb, rpre);
-  const int total = rpre[nr];
-  const double mults[3] = {1.0, 1.5, 2.0};
+  for (int q = 0; q < D; ++q) xb[q] = a.cv.x[static_cast<int64_t>(q) * a.cv.N + b];
   double hb = 0.0;
-  int m = 0;
-  for (int t = 0; t < 3; ++t) {
-    hb = mults[t] * a.h;
-    const double hb2 = hb * hb;
-    m = 0;
-    for (int c0 = 0; c0 < total; c0 += kWave) {
-      const int cidx = c0 + lane;
-      bool in = false;
-      int j = 0;
-      if (cidx < total) {
-        const int p = cand_slot(cidx, nr, rb, rpre);
-        j = a.cperm[p];
-        double r2 = 0.0;
-#pragma unroll
-        for (int q = 0; q < D; ++q) {
-          const double dl = a.xs[static_cast<int64_t>(q) * a.N + p] - xb[q];
-          r2 = r2 + dl * dl;
-        }
-        in = r2 <= hb2;
-      }
-      const uint64_t mask = __ballot(in);
-      const int pos = m + lanes_below(mask);
-      if (in && pos < 256) sel[pos] = j;
-      m += __popcll(mask);
-    }
-    if (m >= D + 2) break;
-  }
-  __syncthreads();
+  const int m = value_row<D>(a.cv, xb, sm, hb);
   if (lane == 0) a.whb[k] = hb;
-  if (m < D + 2 || m > a.cap) {
+  if (m < 0) {
     if (lane == 0) {
-      raise_error(a.err, m < D + 2 ? BGK_ESINGULAR : BGK_ENBR_OVERFLOW);
+      raise_error(a.err, m == -2 ? BGK_ENBR_OVERFLOW : BGK_ESINGULAR);
       a.wcnt[k] = 0;
     }
     return;
   }
-  int32_t* row = a.widx + static_cast<int64_t>(k) * a.cap;
-  rank_sorted_store(sel, m, a.cap, srt);
-  __syncthreads();
+  const int64_t row = static_cast<int64_t>(k) * a.cv.cap;
   for (int e = lane; e < m; e += kWave) {
-    const int j = srt[e];
-    row[e] = j;
-    double y[D], r2 = 0.0;
-#pragma unroll
-    for (int q = 0; q < D; ++q) {
-      y[q] = (a.x[static_cast<int64_t>(q) * a.N + j] - xb[q]) / hb;
-      r2 = r2 + y[q] * y[q];
-    }
-    W[e] = exp(-a.alpha * r2);
-    Basis<D, 1>::eval(y, P + e * B);
-  }
-  __syncthreads();
-  if (!wave_lsq<B, 1>(m, P, W, A, Z, 0, &flag)) {
-    if (lane == 0) {
-      raise_error(a.err, BGK_ESINGULAR);
-      a.wcnt[k] = 0;
-    }
-    return;
-  }
-  for (int e = lane; e < m; e += kWave) {
-    double s = 0.0;
-#pragma unroll
-    for (int r = 0; r < B; ++r) s = s + Z[r] * P[e * B + r];
-    a.wc0[static_cast<int64_t>(k) * a.cap + e] = W[e] * s;
+    a.widx[row + e] = sm.srt[e];
+    a.wc0[row + e] = value_weight<D>(sm, e);
   }
   if (lane == 0) a.wcnt[k] = m;
 }
 
+CloudView cloud_view(const Ctx& c, const double* x) {
+  return CloudView{c.N, c.cap, c.nca, c.ncell, c.cfg.h, c.cfg.alpha, x, c.d.xs, c.d.cstart,
+                   c.d.cperm};
+}
+
 hipError_t launch_wall_stencil(const Ctx& c, const double* x) {
   if (c.Nw == 0) return hipSuccess;
-  WallArgs a{c.N, c.cap, c.Nw, c.nca, c.ncell, c.cfg.h, c.cfg.alpha, x, c.d.xs, c.d.wall_list,
-             c.d.cstart, c.d.cperm, c.d.wcnt, c.d.widx, c.d.wc0, c.d.whb, c.d.err};
+  WallArgs a{cloud_view(c, x), c.d.wall_list, c.d.wcnt, c.d.widx, c.d.wc0, c.d.whb, c.d.err};
   if (c.D == 2)
     hipLaunchKernelGGL(k_wall_stencil<2>, dim3(c.Nw), dim3(kWave), 0, c.stream, a);
   else

@@ -164,6 +164,23 @@ def make_lattice(dim: int, n: int):
     return make_cloud(dim, n, seed=0, jitter=0.0)
 
 
+def disturbed_cloud(dim: int, n: int, seed: int = 0, amp: float = 0.45, drop: float = 0.2):
+    """A cloud as particle management meets it after the particles have
+    moved: the jittered lattice with every interior particle displaced by up
+    to amp * dx more (uniform per component, kept inside [0.1 dx, 1 - 0.1 dx])
+    and a fraction drop of the interior particles removed.  Returns
+    (x, wall_id) like make_cloud."""
+    x, wid = make_cloud(dim, n, seed)
+    x = x.copy()
+    dx = 1.0 / (n - 1)
+    rng = np.random.default_rng(100 + seed)
+    inner = wid == 0
+    x[:, inner] += rng.uniform(-amp * dx, amp * dx, (dim, int(inner.sum())))
+    np.clip(x, 0.1 * dx, 1 - 0.1 * dx, out=x, where=np.broadcast_to(inner, x.shape))
+    keep = ~inner | (rng.uniform(size=wid.size) >= drop)
+    return np.ascontiguousarray(x[:, keep]), np.ascontiguousarray(wid[keep])
+
+
 def cloud_for(cfg: CavityConfig, seed: int | None = None):
     return make_cloud(cfg.dim, cfg.n, cfg.seed if seed is None else seed)
 
