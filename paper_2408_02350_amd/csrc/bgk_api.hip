@@ -76,8 +76,8 @@ bool config_ok(const bgk_config& g) {
 size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj, Pm* pm) {
   const int64_t N = cfg.n_particles, cap = cfg.max_neighbors, D = cfg.dim, DD = D * D;
   const int64_t ncell = ipow(cells_per_axis(cfg), cfg.dim);
-  const int64_t tp = patch_size(cfg.dim, cfg.precision);
-  const int64_t npatch = (N + tp - 1) / tp, ucap = tp * cap;
+  // patch unions for any patch size (chosen at init): at most (N+1)/2
+  // patches and (N+3)*cap entries
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
     char* p = base ? base + off : nullptr;
@@ -102,9 +102,9 @@ size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj, Pm*
   t.widx = reinterpret_cast<int32_t*>(take(N * cap * 4));
   t.wc0 = reinterpret_cast<double*>(take(N * cap * 8));
   t.whb = reinterpret_cast<double*>(take(N * 8));
-  t.ucount = reinterpret_cast<int32_t*>(take(npatch * 4));
-  t.uj = reinterpret_cast<int32_t*>(take(npatch * ucap * 4));
-  t.ue = reinterpret_cast<uint32_t*>(take(npatch * ucap * 4));
+  t.ucount = reinterpret_cast<int32_t*>(take((N + 1) / 2 * 4));
+  t.uj = reinterpret_cast<int32_t*>(take((N + 3) * cap * 4));
+  t.ue = reinterpret_cast<uint32_t*>(take((N + 3) * cap * 4));
   t.jpart = reinterpret_cast<double*>(take(N * 8));
   if (d) *d = t;
   if (cfg.flags & BGK_FLAG_ADJOINT) {
@@ -231,7 +231,7 @@ int bgk_init(const bgk_config* cfg, const int32_t* wall_id, void* workspace, siz
       if (wid[i] == w) wl.push_back(i);
   c.Nw = static_cast<int>(wl.size());
   c.Ni = c.N - c.Nw;
-  c.tp = bgk::patch_size(c.D, cfg->precision);
+  c.tp = bgk::choose_patch(c.D, cfg->precision, c.NV, c.Ni);
   c.npatch = (c.Ni + c.tp - 1) / c.tp;
   c.ucap = c.tp * c.cap;
   int32_t zeros[bgk::kErrWords] = {0};

@@ -14,12 +14,18 @@
 
 namespace bgk {
 
-// Interior particles per transport patch: 2 for FP64 in 2D (its
-// accumulators then fit 4 velocities per lane in 256-lane blocks), else 4.
-// The union entries pack one byte per patch particle, so at most 4.
+// Interior particles per transport patch (the union entries pack one byte
+// per patch particle, so at most 4).  Four particles share each row load.
+// FP64 in 2D has the registers for 4 particles only at 2 velocities per
+// lane (512-lane blocks); it takes them when half the velocity grid fills
+// whole waves and the patches fill the chip (at least 1024 of them), and
+// otherwise runs 2-particle patches with 4 velocities per lane (256-lane
+// blocks), which fill ragged grids and small clouds better.
 constexpr int kPatchMax = 4;
-__host__ __device__ constexpr int patch_size(int dim, int precision) {
-  return (dim == 2 && precision == BGK_FP64) ? 2 : 4;
+inline int choose_patch(int dim, int precision, int NV, int Ni) {
+  if (dim != 2 || precision != BGK_FP64) return 4;
+  const int lanes = NV / 2;
+  return (lanes % 64 == 0 && lanes <= 512 && (Ni + 3) / 4 >= 1024) ? 4 : 2;
 }
 constexpr int kThreads = 256;   // threads per block of the per-particle kernels
 

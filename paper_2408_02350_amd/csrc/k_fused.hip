@@ -145,10 +145,10 @@ __device__ __forceinline__ double wave_reduce_scatter(double (&v)[K]) {
 
 constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) / 2); }
 
-template <int D, int NC, int MODE, int R, bool FUSE>
+template <int D, int NC, int MODE, int R, bool FUSE, int TP>
 __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   using Real = typename FPrec<MODE>::real;
-  constexpr int TP = patch_size(D, MODE), DD = D * D;
+  constexpr int DD = D * D;
   constexpr bool DIFF = (MODE == BGK_BF16);     // products of differences
   constexpr int REC = DD + 2 * D;               // a_k (d*d), a_k.U (d), a_k[fast]*dvs (d)
   constexpr int KM = TP * (D + 1);              // first-pass moment sums per thread
@@ -554,20 +554,30 @@ struct FusedPlan {
   int R = 0, tiles = 0, bte = 0;
 };
 
+// Instantiated (patch size, R) pairs per model and precision, within the
+// register budget.
+template <int D, int MODE, int TP, int R>
+constexpr bool fused_instance() {
+  if (MODE == BGK_FP64) return (R == 1 || R == 2 || R == 4) && !(D == 2 && TP == 4 && R == 4);
+  if (D == 2) return TP == 4 && (R == 1 || R == 2 || R == 4 || R == 5);
+  return TP == 4 && (R == 1 || R == 2 || R == 4 || R == 5 || R == 8 || R == 10);
+}
+
 static FusedPlan plan_fused(const Ctx& c) {
   const int D = c.D, nv = c.cfg.nv, NV = c.NV;
   const bool f64 = c.cfg.precision == BGK_FP64;
-  // instantiated R, ascending, within the register budget
+  // instantiated R, ascending
   static const int r64[] = {1, 2, 4};
   static const int r2d[] = {1, 2, 4, 5};
   static const int r3d[] = {1, 2, 4, 5, 8, 10};
-  const int rmax = D == 2 ? 4 : (f64 ? 4 : 10);
+  const bool wide = D == 2 && f64 && c.tp == 4;  // FP64 2D with 4-particle patches
+  const int rmax = D == 2 ? (wide ? 2 : 4) : (f64 ? 4 : 10);
   const int* cand = f64 ? r64 : (D == 2 ? r2d : r3d);
   const int ncand = f64 ? 3 : (D == 2 ? 4 : 6);
   // 2D: at most 256 lanes, i.e. 4 velocities per lane at 32^2 (fewer,
-  // wider row loads and one projection set-up per 4 velocities; FP64 gets
-  // the registers for it from its 2-particle patches)
-  const int lanes_max = D == 2 ? 256 : 1024;
+  // wider row loads and one projection set-up per 4 velocities), or 512
+  // lanes of 2 velocities for FP64 with 4-particle patches
+  const int lanes_max = D == 2 ? (wide ? 512 : 256) : 1024;
   FusedPlan p;
   // one tile: the smallest admissible R that fits
   for (int i = 0; i < ncand; ++i) {
@@ -593,32 +603,26 @@ static FusedPlan plan_fused(const Ctx& c) {
 
 bool fused_supported(const Ctx& c) { return c.cfg.nv <= kMaxNv && plan_fused(c).R > 0; }
 
-template <int D, int NC, int MODE, bool FUSE>
+template <int D, int NC, int MODE, bool FUSE, int TP>
 static hipError_t launch_fused_t(const Ctx& c, FusedArgs a, const FusedPlan& p) {
   a.bte = p.bte;
   a.dvs = 2.0 * c.cfg.vmax / (c.cfg.nv - 1);
   const int bt = (a.bte + 63) / 64 * 64;
   dim3 g(c.npatch * p.tiles), b(bt);
   switch (p.R) {
-#define BGK_R_CASE(RR)                                                                  \
-  case RR:                                                                              \
-    hipLaunchKernelGGL((k_fused<D, NC, MODE, RR, FUSE>), g, b, 0, c.stream, a);         \
+#define BGK_R_CASE(RR)                                                                    \
+  case RR:                                                                                \
+    if constexpr (fused_instance<D, MODE, TP, RR>())                                      \
+      hipLaunchKernelGGL((k_fused<D, NC, MODE, RR, FUSE, TP>), g, b, 0, c.stream, a);     \
+    else                                                                                  \
+      return hipErrorInvalidValue;                                                        \
     break;
     BGK_R_CASE(1)
     BGK_R_CASE(2)
     BGK_R_CASE(4)
-    case 5:
-      if constexpr (MODE != BGK_FP64) hipLaunchKernelGGL((k_fused<D, NC, MODE, 5, FUSE>), g, b, 0, c.stream, a);
-      else return hipErrorInvalidValue;
-      break;
-    case 8:
-      if constexpr (D == 3 && MODE != BGK_FP64) hipLaunchKernelGGL((k_fused<D, NC, MODE, 8, FUSE>), g, b, 0, c.stream, a);
-      else return hipErrorInvalidValue;
-      break;
-    case 10:
-      if constexpr (D == 3 && MODE != BGK_FP64) hipLaunchKernelGGL((k_fused<D, NC, MODE, 10, FUSE>), g, b, 0, c.stream, a);
-      else return hipErrorInvalidValue;
-      break;
+    BGK_R_CASE(5)
+    BGK_R_CASE(8)
+    BGK_R_CASE(10)
 #undef BGK_R_CASE
     default: return hipErrorInvalidValue;
   }
@@ -629,13 +633,15 @@ template <bool FUSE>
 static hipError_t launch_fused_any(const Ctx& c, const FusedArgs& a, const FusedPlan& p) {
   const int mode = c.cfg.precision;
   if (c.D == 2) {
-    if (mode == BGK_FP64) return launch_fused_t<2, 2, BGK_FP64, FUSE>(c, a, p);
-    if (mode == BGK_FP32) return launch_fused_t<2, 2, BGK_FP32, FUSE>(c, a, p);
-    return launch_fused_t<2, 2, BGK_BF16, FUSE>(c, a, p);
+    if (mode == BGK_FP64)
+      return c.tp == 2 ? launch_fused_t<2, 2, BGK_FP64, FUSE, 2>(c, a, p)
+                       : launch_fused_t<2, 2, BGK_FP64, FUSE, 4>(c, a, p);
+    if (mode == BGK_FP32) return launch_fused_t<2, 2, BGK_FP32, FUSE, 4>(c, a, p);
+    return launch_fused_t<2, 2, BGK_BF16, FUSE, 4>(c, a, p);
   }
-  if (mode == BGK_FP64) return launch_fused_t<3, 1, BGK_FP64, FUSE>(c, a, p);
-  if (mode == BGK_FP32) return launch_fused_t<3, 1, BGK_FP32, FUSE>(c, a, p);
-  return launch_fused_t<3, 1, BGK_BF16, FUSE>(c, a, p);
+  if (mode == BGK_FP64) return launch_fused_t<3, 1, BGK_FP64, FUSE, 4>(c, a, p);
+  if (mode == BGK_FP32) return launch_fused_t<3, 1, BGK_FP32, FUSE, 4>(c, a, p);
+  return launch_fused_t<3, 1, BGK_BF16, FUSE, 4>(c, a, p);
 }
 
 static double omega_fused(const bgk_config& cfg) {

@@ -56,10 +56,10 @@ __device__ __forceinline__ float bf16_round(float x) {
   return static_cast<float>(static_cast<__bf16>(x));
 }
 
-template <int D, int NC, int MODE, int R>
+template <int D, int NC, int MODE, int R, int TP>
 __global__ __launch_bounds__(kThreads) void k_transport(const TransportArgs a) {
   using Real = typename PrecT<MODE>::real;
-  constexpr int DD = D * D, TP = patch_size(D, MODE);
+  constexpr int DD = D * D;
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const int patch = lb % a.npatch, tile = lb / a.npatch;
   const Real* __restrict__ f = static_cast<const Real*>(a.f);
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kThreads) void k_transport(const TransportArgs a) {
               fi[t][r][c] - dt * acc[t][r][c];
 }
 
-template <int D, int NC, int MODE>
+template <int D, int NC, int MODE, int TP>
 static hipError_t launch_transport_t(const Ctx& c, const TransportArgs& a) {
   const int R = (c.NV >= 2 * kThreads) ? 2 : 1;
   const int ntile = (c.NV + kThreads * R - 1) / (kThreads * R);
@@ -181,10 +181,10 @@ static hipError_t launch_transport_t(const Ctx& c, const TransportArgs& a) {
   if (nblocks == 0) return hipSuccess;
   if (nblocks > INT32_MAX) return hipErrorInvalidValue;
   if (R == 2)
-    hipLaunchKernelGGL((k_transport<D, NC, MODE, 2>), dim3(static_cast<unsigned>(nblocks)),
+    hipLaunchKernelGGL((k_transport<D, NC, MODE, 2, TP>), dim3(static_cast<unsigned>(nblocks)),
                        dim3(kThreads), 0, c.stream, a);
   else
-    hipLaunchKernelGGL((k_transport<D, NC, MODE, 1>), dim3(static_cast<unsigned>(nblocks)),
+    hipLaunchKernelGGL((k_transport<D, NC, MODE, 1, TP>), dim3(static_cast<unsigned>(nblocks)),
                        dim3(kThreads), 0, c.stream, a);
   return hipGetLastError();
 }
@@ -197,13 +197,15 @@ hipError_t launch_transport(const Ctx& c, const void* f_in, void* f_out, const d
                                    : static_cast<const void*>(c.d.ops32),
                   c.d.cperm, c.d.ucount, c.d.uj, c.d.ue};
   if (c.D == 2) {
-    if (mode == BGK_FP64) return launch_transport_t<2, 2, BGK_FP64>(c, a);
-    if (mode == BGK_FP32) return launch_transport_t<2, 2, BGK_FP32>(c, a);
-    return launch_transport_t<2, 2, BGK_BF16>(c, a);
+    if (mode == BGK_FP64)
+      return c.tp == 2 ? launch_transport_t<2, 2, BGK_FP64, 2>(c, a)
+                       : launch_transport_t<2, 2, BGK_FP64, 4>(c, a);
+    if (mode == BGK_FP32) return launch_transport_t<2, 2, BGK_FP32, 4>(c, a);
+    return launch_transport_t<2, 2, BGK_BF16, 4>(c, a);
   }
-  if (mode == BGK_FP64) return launch_transport_t<3, 1, BGK_FP64>(c, a);
-  if (mode == BGK_FP32) return launch_transport_t<3, 1, BGK_FP32>(c, a);
-  return launch_transport_t<3, 1, BGK_BF16>(c, a);
+  if (mode == BGK_FP64) return launch_transport_t<3, 1, BGK_FP64, 4>(c, a);
+  if (mode == BGK_FP32) return launch_transport_t<3, 1, BGK_FP32, 4>(c, a);
+  return launch_transport_t<3, 1, BGK_BF16, 4>(c, a);
 }
 
 // Wall rows of the transported field are copies of the input (the staged
