@@ -12,7 +12,9 @@
 // formed once and then advanced by a constant per r (one add), and every
 // row access of a thread is one contiguous R-element vector load or store.
 // The block walks the sorted union of its particles' neighbour lists in
-// chunks; per chunk the per-edge data (a_k, a_k.U_i and the per-r
+// chunks of one wave width: every wave holds the chunk's row indices and
+// slot masks one per lane (read back with readlane, no LDS round trip on
+// the row-load path), the per-edge data (a_k, a_k.U_i and the per-r
 // increments) is staged in LDS and read back with wave-uniform addresses,
 // and the f_j rows are loaded three union entries ahead.
 //
@@ -75,11 +77,6 @@ __device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(
 __device__ __forceinline__ double min_t(double a, double b) { return fmin(a, b); }
 __device__ __forceinline__ float min_t(float a, float b) { return fminf(a, b); }
 __device__ __forceinline__ float bf16r(float x) { return static_cast<float>(static_cast<__bf16>(x)); }
-
-template <typename T>
-__device__ __forceinline__ T uniform(T x) {
-  return __builtin_amdgcn_readfirstlane(x);
-}
 
 // R consecutive elements from / to p with the widest aligned vector
 // accesses R * sizeof(Real) allows (p is aligned to that vector: R*tid
@@ -155,8 +152,6 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   constexpr int KP = pow2_at_least(KM);
   constexpr int KP2 = pow2_at_least(TP);         // second pass: one sum per particle
   __shared__ Real lrec[kChunk][TP][REC];
-  __shared__ int32_t luj[kChunk];
-  __shared__ uint32_t lmask[kChunk];
   __shared__ double vtab[kMaxNv];
   __shared__ double red[16][KP > KP2 ? KP : KP2];
   __shared__ double etab[TP][D][kMaxNv];
@@ -238,6 +233,21 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
 
   for (int c0 = 0; c0 < nu; c0 += kChunk) {
     const int cn = min(kChunk, nu - c0);
+    // the chunk's union entries, one per lane of every wave (kChunk is the
+    // wave width), read back with readlane: row index j << 4 | the mask of
+    // the patch slots that have it (N < 2^27 under the size limits)
+    uint32_t vju = 0;
+    {
+      const int l = tid & 63;
+      if (l < cn) {
+        const uint32_t pe = uep[c0 + l];
+        uint32_t m = 0;
+#pragma unroll
+        for (int s2 = 0; s2 < TP; ++s2)
+          if (((pe >> (8 * s2)) & 0xFFu) != 0xFFu) m |= 1u << s2;
+        vju = (static_cast<uint32_t>(ujp[c0 + l]) << 4) | m;
+      }
+    }
     __syncthreads();  // the previous chunk is consumed
     // stage: one (u, t) record per thread
     for (int w = tid; w < cn * TP; w += nthreads) {
@@ -245,14 +255,6 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
       const uint32_t pe = uep[c0 + u];
       const uint32_t e = (pe >> (8 * t)) & 0xFFu;
       Real* rec = lrec[u][t];
-      if (t == 0) {
-        luj[u] = ujp[c0 + u];
-        uint32_t m = 0;
-#pragma unroll
-        for (int s2 = 0; s2 < TP; ++s2)
-          if (((pe >> (8 * s2)) & 0xFFu) != 0xFFu) m |= 1u << s2;
-        lmask[u] = m;
-      }
       if (e != 0xFFu) {
         const int i = a.plist[patch * TP + t];  // present slots are real particles
         const Real* o = ops + (static_cast<size_t>(i) * a.cap + e) * DD;
@@ -280,7 +282,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
     // address), so the waits before each use are exact partial counts.
     Real ra[R][NC], rb[R][NC], rc[R][NC];
     auto load_row = [&](int uu, Real (&buf)[R][NC]) {
-      const int j = uniform(luj[uu]);
+      const int j = static_cast<int>(static_cast<uint32_t>(__builtin_amdgcn_readlane(vju, uu)) >> 4);
       const Real* src = f + static_cast<size_t>(j) * NVs + q0;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
@@ -301,7 +303,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
       for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int c = 0; c < NC; ++c) asm volatile("" ::"v"(fj[r][c]));
-      const uint32_t mask = uniform(lmask[u]);
+      const uint32_t mask = static_cast<uint32_t>(__builtin_amdgcn_readlane(vju, u)) & 15u;
 #pragma unroll
       for (int t = 0; t < TP; ++t) {
         if (mask & (1u << t)) {
