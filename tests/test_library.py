@@ -34,7 +34,7 @@ def test_header_symbols_are_exported(lib):
     assert sorted(lib.EXPORTS) == syms
 
 
-def test_north_star_entry_points_present(lib):
+def test_hot_path_entry_points_present(lib):
     syms = declared_symbols()
     for s in ("bgk_init", "bgk_build_neighbors", "bgk_wls_operators", "bgk_step", "bgk_moments",
               "bgk_adjoint_step"):
