@@ -16,7 +16,8 @@
 // slot masks one per lane (read back with readlane, no LDS round trip on
 // the row-load path), the per-edge data (a_k, a_k.U_i and the per-r
 // increments) is staged in LDS and read back with wave-uniform addresses,
-// and the f_j rows are loaded three union entries ahead.
+// and the f_j rows are loaded three union entries ahead (two for FP64 in
+// 3D).
 //
 // The walk accumulates A = sum_j c_ij f_j (per component) and C = sum_j c_ij
 // (shared by the components), so f_i is not needed until the end:
@@ -359,16 +360,29 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
       }
     };
     const int last = cn - 1;
-    load_row(0, ra);
-    load_row(min(1, last), rb);
-    load_row(min(2, last), rc);
-    for (int u = 0; u < cn; u += 3) {
-      process(u, ra);
-      load_row(min(u + 3, last), ra);
-      if (u + 1 < cn) process(u + 1, rb);
-      load_row(min(u + 4, last), rb);
-      if (u + 2 < cn) process(u + 2, rc);
-      load_row(min(u + 5, last), rc);
+    // FP64 in 3D at 4 velocities per lane fills the 128 registers of a
+    // 1024-lane block: a two-row ring keeps it from spilling
+    if constexpr (D == 3 && MODE == BGK_FP64 && R >= 4) {
+      load_row(0, ra);
+      load_row(min(1, last), rb);
+      for (int u = 0; u < cn; u += 2) {
+        process(u, ra);
+        load_row(min(u + 2, last), ra);
+        if (u + 1 < cn) process(u + 1, rb);
+        load_row(min(u + 3, last), rb);
+      }
+    } else {
+      load_row(0, ra);
+      load_row(min(1, last), rb);
+      load_row(min(2, last), rc);
+      for (int u = 0; u < cn; u += 3) {
+        process(u, ra);
+        load_row(min(u + 3, last), ra);
+        if (u + 1 < cn) process(u + 1, rb);
+        load_row(min(u + 4, last), rb);
+        if (u + 2 < cn) process(u + 2, rc);
+        load_row(min(u + 5, last), rc);
+      }
     }
   }
 
