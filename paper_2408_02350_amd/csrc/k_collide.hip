@@ -12,24 +12,63 @@
 
 namespace bgk {
 
+// Tables of one block in LDS (dynamic, (D+1)*nv doubles): the velocity
+// nodes v_k, then per axis a the factor exp(-(v_k - U_a)^2 / (2T)) of one
+// particle's Maxwellian, so that M = norm * prod_a e_a[k_a] (d*nv
+// exponentials per particle instead of N_v).
+__device__ __forceinline__ void fill_vtab(double* vt, int nv, double vmax) {
+  for (int k = threadIdx.x; k < nv; k += blockDim.x) vt[k] = vnode(k, nv, vmax);
+}
+
+template <int D>
+__device__ __forceinline__ void fill_etab(double* et, const double* vt, int nv, const double* U,
+                                          double T) {
+  for (int i = threadIdx.x; i < D * nv; i += blockDim.x) {
+    const int a = i / nv, k = i - a * nv;
+    const double d = vt[k] - U[a];
+    et[i] = exp(-(d * d) / (2.0 * T));
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void vel_index(int q, int nv, int* kq) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    kq[a] = q % nv;
+    q /= nv;
+  }
+}
+
+// Normalisation of the Maxwellian (Sec. 2 eq. maxwellian; Chu G1 in 2D).
+template <int D>
+__device__ __forceinline__ double maxwell_norm(double rho, double T) {
+  const double tp = 2.0 * kPi * T;
+  return D == 3 ? rho / (tp * sqrt(tp)) : rho / tp;
+}
+
+template <int D>
+static inline size_t row_tab_bytes(int nv) {
+  return static_cast<size_t>(D + 1) * nv * sizeof(double);
+}
+
 // rho, U, T of one particle's row (Sec. 2 eqs. moments, internal_energy;
 // Chu eq. macroeq; time-discrete fullmoment1a / moment1a, moment1b):
 // rho = omega sum f1, U = sum v f1 / sum f1, then 3 rho T from the centred
-// second moment (Chu: plus sum g2).  Returns the FP64 sums through refs.
+// second moment (Chu: plus sum g2).  vt: the velocity nodes in LDS.
 template <int D, int NC, typename Real>
-__device__ __forceinline__ void row_moments(const Real* row, size_t cs, int NV, int nv, double vmax,
-                                            double omega, double* sh, double& rho, double* U,
-                                            double& T) {
+__device__ __forceinline__ void row_moments(const Real* row, size_t cs, int NV, int nv,
+                                            const double* vt, double omega, double* sh,
+                                            double& rho, double* U, double& T) {
   double s[D + 1];
 #pragma unroll
   for (int k = 0; k <= D; ++k) s[k] = 0.0;
   for (int q = threadIdx.x; q < NV; q += kThreads) {
-    double v[3];
-    velocity_of<D>(q, nv, vmax, v);
+    int kq[D];
+    vel_index<D>(q, nv, kq);
     const double f1 = static_cast<double>(row[q]);
     s[0] = s[0] + f1;
 #pragma unroll
-    for (int k = 0; k < D; ++k) s[1 + k] = s[1 + k] + v[k] * f1;
+    for (int k = 0; k < D; ++k) s[1 + k] = s[1 + k] + vt[kq[k]] * f1;
   }
   block_sum<D + 1>(s, sh);
   const double s0 = s[0];
@@ -38,12 +77,12 @@ __device__ __forceinline__ void row_moments(const Real* row, size_t cs, int NV, 
   for (int k = 0; k < D; ++k) U[k] = s[1 + k] / s0;
   double e[1] = {0.0};
   for (int q = threadIdx.x; q < NV; q += kThreads) {
-    double v[3];
-    velocity_of<D>(q, nv, vmax, v);
+    int kq[D];
+    vel_index<D>(q, nv, kq);
     double w2 = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      const double wk = v[k] - U[k];
+      const double wk = vt[kq[k]] - U[k];
       w2 = w2 + wk * wk;
     }
     e[0] = e[0] + w2 * static_cast<double>(row[q]);
@@ -69,12 +108,15 @@ struct CollideArgs {
 template <int D, int NC, typename Real>
 __global__ __launch_bounds__(kThreads) void k_collide(const CollideArgs a) {
   __shared__ double sh[4 * (D + 1)];
+  extern __shared__ double vt[];  // nodes, then per-axis Maxwellian factors
   const int i = a.plist[blockIdx.x];
+  fill_vtab(vt, a.nv, a.vmax);
+  __syncthreads();
   const size_t NVs = a.NV, cs = static_cast<size_t>(a.N) * NVs;
   const Real* ft = static_cast<const Real*>(a.ft) + static_cast<size_t>(i) * NVs;
   Real* fo = static_cast<Real*>(a.fo) + static_cast<size_t>(i) * NVs;
   double rho, U[3] = {0.0, 0.0, 0.0}, T;
-  row_moments<D, NC, Real>(ft, cs, a.NV, a.nv, a.vmax, a.omega, sh, rho, U, T);
+  row_moments<D, NC, Real>(ft, cs, a.NV, a.nv, vt, a.omega, sh, rho, U, T);
   if (threadIdx.x == 0) {
     a.rho[i] = rho;
     a.T[i] = T;
@@ -84,21 +126,29 @@ __global__ __launch_bounds__(kThreads) void k_collide(const CollideArgs a) {
   }
   const double tau = a.kn * sqrt(2.0 / kPi) / (rho * sqrt(T));
   const double den = tau + a.dt;
+  double* et = vt + a.nv;
+  fill_etab<D>(et, vt, a.nv, U, T);
+  __syncthreads();
+  const double norm = maxwell_norm<D>(rho, T);
   for (int q = threadIdx.x; q < a.NV; q += kThreads) {
-    double v[3];
-    velocity_of<D>(q, a.nv, a.vmax, v);
+    int kq[D];
+    vel_index<D>(q, a.nv, kq);
+    double M = norm;
+#pragma unroll
+    for (int k = 0; k < D; ++k) M = M * et[k * a.nv + kq[k]];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const double M = maxwell<D>(c, rho, U, T, v);
+      const double Mc = c == 0 ? M : T * M;  // Chu: G2 = T G1
       const double x = static_cast<double>(ft[c * cs + q]);
-      fo[c * cs + q] = static_cast<Real>((tau * x + a.dt * M) / den);
+      fo[c * cs + q] = static_cast<Real>((tau * x + a.dt * Mc) / den);
     }
   }
 }
 
 template <typename Real, int D, int NC>
 static void collide_t(const Ctx& c, const CollideArgs& a) {
-  hipLaunchKernelGGL((k_collide<D, NC, Real>), dim3(a.count), dim3(kThreads), 0, c.stream, a);
+  hipLaunchKernelGGL((k_collide<D, NC, Real>), dim3(a.count), dim3(kThreads),
+                     row_tab_bytes<D>(c.cfg.nv), c.stream, a);
 }
 
 hipError_t launch_collide(const Ctx& c, const void* ft, void* fout, double* rho, double* U,
@@ -466,11 +516,14 @@ __global__ __launch_bounds__(kThreads) void k_moments(int N, int NV, int nv, dou
                                                        double omega, const void* fv, double* rho,
                                                        double* U, double* T) {
   __shared__ double sh[4 * (D + 1)];
+  extern __shared__ double vt[];
   const int i = blockIdx.x;
   const size_t NVs = NV, cs = static_cast<size_t>(N) * NVs;
   const Real* row = static_cast<const Real*>(fv) + static_cast<size_t>(i) * NVs;
+  fill_vtab(vt, nv, vmax);
+  __syncthreads();
   double r, u[3] = {0.0, 0.0, 0.0}, t;
-  row_moments<D, NC, Real>(row, cs, NV, nv, vmax, omega, sh, r, u, t);
+  row_moments<D, NC, Real>(row, cs, NV, nv, vt, omega, sh, r, u, t);
   if (threadIdx.x == 0) {
     rho[i] = r;
     T[i] = t;
@@ -483,12 +536,13 @@ hipError_t launch_moments(const Ctx& c, const void* f, double* rho, double* U, d
   const bool f64 = c.cfg.precision == BGK_FP64;
   const double om = omega_of(c.cfg);
   dim3 g(c.N), t(kThreads);
+  const size_t lds = static_cast<size_t>(c.D + 1) * c.cfg.nv * sizeof(double);
   if (c.D == 2) {
-    if (f64) hipLaunchKernelGGL((k_moments<2, 2, double>), g, t, 0, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, om, f, rho, U, T);
-    else hipLaunchKernelGGL((k_moments<2, 2, float>), g, t, 0, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, om, f, rho, U, T);
+    if (f64) hipLaunchKernelGGL((k_moments<2, 2, double>), g, t, lds, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, om, f, rho, U, T);
+    else hipLaunchKernelGGL((k_moments<2, 2, float>), g, t, lds, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, om, f, rho, U, T);
   } else {
-    if (f64) hipLaunchKernelGGL((k_moments<3, 1, double>), g, t, 0, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, om, f, rho, U, T);
-    else hipLaunchKernelGGL((k_moments<3, 1, float>), g, t, 0, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, om, f, rho, U, T);
+    if (f64) hipLaunchKernelGGL((k_moments<3, 1, double>), g, t, lds, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, om, f, rho, U, T);
+    else hipLaunchKernelGGL((k_moments<3, 1, float>), g, t, lds, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, om, f, rho, U, T);
   }
   return hipGetLastError();
 }
@@ -498,6 +552,7 @@ __global__ __launch_bounds__(kThreads) void k_maxwellian(int N, int NV, int nv, 
                                                           const double* __restrict__ rho,
                                                           const double* __restrict__ U,
                                                           const double* __restrict__ T, void* fv) {
+  extern __shared__ double vt[];
   const int i = blockIdx.x;
   const size_t NVs = NV, cs = static_cast<size_t>(N) * NVs;
   Real* row = static_cast<Real*>(fv) + static_cast<size_t>(i) * NVs;
@@ -505,11 +560,20 @@ __global__ __launch_bounds__(kThreads) void k_maxwellian(int N, int NV, int nv, 
 #pragma unroll
   for (int k = 0; k < D; ++k) u[k] = U[static_cast<size_t>(k) * N + i];
   const double r = rho[i], t = T[i];
+  fill_vtab(vt, nv, vmax);
+  __syncthreads();
+  double* et = vt + nv;
+  fill_etab<D>(et, vt, nv, u, t);
+  __syncthreads();
+  const double norm = maxwell_norm<D>(r, t);
   for (int q = threadIdx.x; q < NV; q += kThreads) {
-    double v[3];
-    velocity_of<D>(q, nv, vmax, v);
+    int kq[D];
+    vel_index<D>(q, nv, kq);
+    double M = norm;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) row[c * cs + q] = static_cast<Real>(maxwell<D>(c, r, u, t, v));
+    for (int k = 0; k < D; ++k) M = M * et[k * nv + kq[k]];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) row[c * cs + q] = static_cast<Real>(c == 0 ? M : t * M);
   }
 }
 
@@ -517,12 +581,13 @@ hipError_t launch_maxwellian(const Ctx& c, const double* rho, const double* U, c
                              void* f) {
   const bool f64 = c.cfg.precision == BGK_FP64;
   dim3 g(c.N), t(kThreads);
+  const size_t lds = static_cast<size_t>(c.D + 1) * c.cfg.nv * sizeof(double);
   if (c.D == 2) {
-    if (f64) hipLaunchKernelGGL((k_maxwellian<2, 2, double>), g, t, 0, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, rho, U, T, f);
-    else hipLaunchKernelGGL((k_maxwellian<2, 2, float>), g, t, 0, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, rho, U, T, f);
+    if (f64) hipLaunchKernelGGL((k_maxwellian<2, 2, double>), g, t, lds, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, rho, U, T, f);
+    else hipLaunchKernelGGL((k_maxwellian<2, 2, float>), g, t, lds, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, rho, U, T, f);
   } else {
-    if (f64) hipLaunchKernelGGL((k_maxwellian<3, 1, double>), g, t, 0, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, rho, U, T, f);
-    else hipLaunchKernelGGL((k_maxwellian<3, 1, float>), g, t, 0, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, rho, U, T, f);
+    if (f64) hipLaunchKernelGGL((k_maxwellian<3, 1, double>), g, t, lds, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, rho, U, T, f);
+    else hipLaunchKernelGGL((k_maxwellian<3, 1, float>), g, t, lds, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, rho, U, T, f);
   }
   return hipGetLastError();
 }
