@@ -78,6 +78,11 @@ __device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(
 __device__ __forceinline__ double min_t(double a, double b) { return fmin(a, b); }
 __device__ __forceinline__ float min_t(float a, float b) { return fminf(a, b); }
 __device__ __forceinline__ float bf16r(float x) { return static_cast<float>(static_cast<__bf16>(x)); }
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+// (x, y) rounded to a BF16 pair (round to nearest even, one instruction)
+__device__ __forceinline__ bf16x2 bf16_pair(float x, float y) {
+  return bf16x2{static_cast<__bf16>(x), static_cast<__bf16>(y)};
+}
 
 // R consecutive elements from / to p with the widest aligned vector
 // accesses R * sizeof(Real) allows (p is aligned to that vector: R*tid
@@ -360,9 +365,90 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
       }
     };
     const int last = cn - 1;
-    // FP64 in 3D at 4 velocities per lane fills the 128 registers of a
-    // 1024-lane block: a two-row ring keeps it from spilling
-    if constexpr (D == 3 && MODE == BGK_FP64 && R >= 4) {
+    if constexpr (DIFF && D == 2 && R <= 4) {
+      // BF16 operands in 2D: the union is walked two rows at a time, and the
+      // two products of a (slot, velocity, component) go through one packed
+      // BF16 dot product with FP32 accumulation.  A slot that lacks one of
+      // the two rows gets zero projections there, hence c = 0.  (Up to 4
+      // velocities per lane: the four-row ring fits the registers.  In 3D,
+      // with one component, the doubled per-edge set-up costs more than the
+      // packed products save.)
+      auto setup = [&](int uu, int t, bool on, Real (&p)[D], Real (&ik)[D]) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          p[k] = Real(0);
+          ik[k] = Real(0);
+        }
+        if (!on) return;
+        const Real* rec = lrec[uu][t];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          Real s1 = -rec[DD + k];
+#pragma unroll
+          for (int m = 0; m < D; ++m) s1 = fma_t(rec[k * D + m], v0[m], s1);
+          p[k] = s1;
+          ik[k] = rec[DD + D + k];
+        }
+      };
+      auto process2 = [&](int u, const Real (&fa)[R][NC], const Real (&fb)[R][NC]) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            asm volatile("" ::"v"(fa[r][c]));
+            asm volatile("" ::"v"(fb[r][c]));
+          }
+        const bool has_b = u + 1 < cn;
+        const uint32_t ma = static_cast<uint32_t>(__builtin_amdgcn_readlane(vju, u)) & 15u;
+        const uint32_t mb =
+            has_b ? static_cast<uint32_t>(__builtin_amdgcn_readlane(vju, u + 1)) & 15u : 0u;
+#pragma unroll
+        for (int t = 0; t < TP; ++t) {
+          const bool ta = (ma >> t) & 1u, tb = (mb >> t) & 1u;
+          if (!(ta || tb)) continue;
+          Real pa[D], ia[D], pb[D], ib[D];
+          setup(u, t, ta, pa, ia);
+          setup(u + 1, t, tb, pb, ib);
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if (r > 0) {
+#pragma unroll
+              for (int k = 0; k < D; ++k) {
+                pa[k] = pa[k] + ia[k];
+                pb[k] = pb[k] + ib[k];
+              }
+            }
+            Real ca = min_t(pa[0], Real(0)), cb = min_t(pb[0], Real(0));
+#pragma unroll
+            for (int k = 1; k < D; ++k) {
+              ca = ca + min_t(pa[k], Real(0));
+              cb = cb + min_t(pb[k], Real(0));
+            }
+            const bf16x2 cp = bf16_pair(ca + ca, cb + cb);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              const bf16x2 dp = bf16_pair(fa[r][c] - fi[t][r][c], fb[r][c] - fi[t][r][c]);
+              acc[t][r][c] = __builtin_amdgcn_fdot2_f32_bf16(cp, dp, acc[t][r][c], false);
+            }
+          }
+        }
+      };
+      Real rd[R][NC];
+      load_row(0, ra);
+      load_row(min(1, last), rb);
+      load_row(min(2, last), rc);
+      load_row(min(3, last), rd);
+      for (int u = 0; u < cn; u += 4) {
+        process2(u, ra, rb);
+        load_row(min(u + 4, last), ra);
+        load_row(min(u + 5, last), rb);
+        if (u + 2 < cn) process2(u + 2, rc, rd);
+        load_row(min(u + 6, last), rc);
+        load_row(min(u + 7, last), rd);
+      }
+    } else if constexpr (D == 3 && MODE == BGK_FP64 && R >= 4) {
+      // FP64 in 3D at 4 velocities per lane fills the 128 registers of a
+      // 1024-lane block: a two-row ring keeps it from spilling
       load_row(0, ra);
       load_row(min(1, last), rb);
       for (int u = 0; u < cn; u += 2) {
