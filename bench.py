@@ -171,6 +171,69 @@ def time_particle_management(cav, reps):
             "apply_ms": sum(apply_ms) / len(apply_ms), "reps": reps, "precision": cav.precision}
 
 
+def time_adjoint(cav, precision, nsteps, every, reps):
+    """The reverse mode on one GPU: wall time of one checkpointed rollout
+    (forward pass, then backward pass: segment recomputation plus the
+    reverse steps) and the device time of one reverse step alone
+    (bgk_adjoint_step, HIP events on the library stream, mean over reps).
+
+    Roofline of the reverse step: bytes = 3 n_c N N_v s (read the adjoint
+    of f-tilde and f^n, write lam_f; s = 8 in FP64, 4 in FP32 storage);
+    ops = 2 k per (particle, neighbour, velocity) with k the forward count
+    (the flux and its U-derivative)."""
+    import torch
+
+    import paper_2408_02350_amd.bgk as bgk
+    from paper_2408_02350_amd.adjoint import FrozenCavity, rollout_objective
+
+    dev = torch.device("cuda:0")
+    problem = FrozenCavity(cav, device=dev, precision=precision)
+    f0 = problem.rest_state()
+    lid = torch.tensor(cav.lid, dtype=torch.float64, device=dev, requires_grad=True)
+    walls = []
+    for r in range(2):
+        f0g = f0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = rollout_objective(problem, f0g, lid, nsteps, every)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        walls.append(((t1 - t0) * 1e3, (t2 - t1) * 1e3))
+    fwd_ms, bwd_ms = walls[-1]
+    # one reverse step alone, on the state after the rollout
+    (f, rho, U, T), _ = problem.forward(f0, cav.lid, 5)
+    c = problem.ctx
+    lam_f = torch.rand_like(f)
+    lam_U = torch.zeros_like(U)
+    out_f, out_U = torch.empty_like(f), torch.empty_like(U)
+    bgk.bgk_adjoint_step(c, f, U, problem.x, lam_f, lam_U, None, None, out_f, out_U)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    stream = c.stream
+    ev[0].record(stream)
+    for _ in range(reps):
+        bgk.bgk_adjoint_step(c, f, U, problem.x, lam_f, lam_U, None, None, out_f, out_U)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    bgk.bgk_check(c)
+    step_ms = ev[0].elapsed_time(ev[1]) / reps
+    cnt, _ = bgk.bgk_build_neighbors(c, problem.x)
+    edges = int((cnt[problem.wall_id == 0] - 1).sum().item())
+    s = 8 if precision == "fp64" else 4
+    nc, NV, N = cav.n_comp, cav.n_velocities, cav.n_particles
+    k = (5 + 2 * nc) if cav.dim == 2 else (8 + 2 * nc)
+    bytes_, ops = 3 * nc * N * NV * s, edges * NV * 2 * k
+    return {"workload": cav.name, "precision": precision, "steps": nsteps,
+            "checkpoint_every": every, "rollout_forward_ms": fwd_ms,
+            "rollout_backward_ms": bwd_ms, "reverse_step_ms": step_ms,
+            "reverse_step_hbm_frac": bytes_ / (step_ms * 1e-3) / (PEAK_HBM_GBS * 1e9),
+            "reverse_step_alu_frac": ops / (step_ms * 1e-3) / (PEAK_VALU_TOPS * 1e12),
+            "algorithmic_bytes": bytes_, "algorithmic_ops": ops}
+
+
 def moment_errors(state, ref, lid):
     import numpy as np
 
@@ -227,6 +290,10 @@ def main():
     ap.add_argument("--particle-management", action="store_true",
                     help="only time bgk_pm_plan + bgk_pm_apply on a disturbed cloud of the "
                          "workload's size and print one JSON line")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="only time the reverse mode (checkpointed rollouts of the 100^2 x 24^2 "
+                         "cavity, FP64, and of a 20-step window of the 48^3 x 20^3 cavity, FP32 "
+                         "storage; --workload c4 or c5 for one of them) and print one JSON line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference "
                          "kernel for scaling HBM byte counters) and exit")
@@ -262,6 +329,15 @@ def main():
                          "updates_per_s": pc.n_particles * pc.n_velocities / (ms * 1e-3)})
         print(json.dumps({"paper_scales": rows, "precision": args.precision,
                           "steps": args.steps, "warmup": args.warmup}), flush=True)
+        return
+
+    if args.adjoint:
+        rows = []
+        if args.workload in ("c2", "c4"):
+            rows.append(time_adjoint(CONFIGS["c4"], "fp64", 50, 10, 10))
+        if args.workload in ("c2", "c5"):
+            rows.append(time_adjoint(CONFIGS["c5"].replace(move=0), "fp32", 20, 5, 3))
+        print(json.dumps({"adjoint": rows}), flush=True)
         return
 
     if args.particle_management:

@@ -126,6 +126,7 @@ size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj, Pm*
     a.T1 = reinterpret_cast<double*>(take(N * 8));
     a.larr = take(F * fs);
     a.lidpart = reinterpret_cast<double*>(take(N * 8));
+    a.gpart = reinterpret_cast<double*>(take(adj_tiles(cfg) * D * N * 8));
     if (adj) *adj = a;
   }
   if (cfg.flags & BGK_FLAG_PARTICLES) {
@@ -520,7 +521,9 @@ int bgk_adjoint_step(bgk_ctx* ctx, const void* f_n, const double* U_n, const dou
   }
   // recompute S4-S7 from (f_n, U_n), keeping f-tilde and the new moments
   const bgk::Adj& a = c.adj;
-  e = bgk::launch_transport(c, f_n, a.ft, U_n);
+  // f-tilde by the fused kernel without its relaxation (or the generic one)
+  e = bgk::use_fused(c) ? bgk::launch_fused(c, f_n, a.ft, U_n, nullptr, nullptr, nullptr, false)
+                        : bgk::launch_transport(c, f_n, a.ft, U_n);
   if (e == hipSuccess) e = bgk::launch_collide(c, a.ft, a.f1, a.rho1, a.U1, a.T1);
   if (e == hipSuccess) e = bgk::launch_wall_bc(c, a.f1, a.rho1, a.U1, a.T1);
   if (e == hipSuccess)

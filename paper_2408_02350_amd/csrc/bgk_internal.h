@@ -76,6 +76,7 @@ struct Adj {
   double* T1;         // [N]
   void* larr;         // [Nw][n_c][N_v] adjoint reaching the interpolated wall values
   double* lidpart;    // [max(Nw,1)]
+  double* gpart;      // [tiles][d][N] per-tile parts of lam_U (reverse transport)
 };
 
 // Workspace of the particle management (BGK_FLAG_PARTICLES).
@@ -93,6 +94,14 @@ inline double omega_of(const bgk_config& cfg) {
   double w = 1.0;
   for (int a = 0; a < cfg.dim; ++a) w = w * dv;
   return w;
+}
+
+// Velocity tiles of the reverse transport: one wavefront of 64 threads per
+// (particle, tile), 2 velocities per thread.
+inline int64_t adj_tiles(const bgk_config& cfg) {
+  int64_t nvel = 1;
+  for (int a = 0; a < cfg.dim; ++a) nvel *= cfg.nv;
+  return (nvel / 2 + 63) / 64;
 }
 
 // Lattice nodes per axis of the initial cloud (spacing dx on [0, 1]).

@@ -16,6 +16,8 @@
 // on the adjoint fields and the result is deterministic.  Reductions are
 // FP64 in a fixed order.  Derivatives of |.| at 0 follow the + branch
 // (c_ij = 2 sum_k min(0, p_k): d/dp = 1 only for p < 0).
+#include <algorithm>
+#include <climits>
 #include <type_traits>
 
 #include "device_common.h"
@@ -132,6 +134,8 @@ struct AdjArgs {  // Real: storage of f-sized arrays and operators (FP64 or FP32
   Real* lam_f;           // out: adjoint of f^n
   double* lam_U;           // out: adjoint of U^n
   double* lidpart;         // [Nw] dJ/dlid contributions
+  double* gpart;           // [tiles][D][N] per-tile parts of lam_U
+  int tiles;
 };
 
 // ------------------------------------------------------------ S7 adjoint
@@ -277,99 +281,255 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
 }
 
 // ------------------------------------------------------------ S4 adjoint
-// Block per particle j (interior or wall), all velocities:
+// One wavefront per (particle j, tile of 64 groups of R velocities), for
+// interior and wall particles:
 //   lam_f_j = [j interior] lam_ft_j (1 + dt sum_k c_jk)
 //             - dt sum_{i in N_j interior, i != j} c_ij lam_ft_i
 //   lam_U_j = -dt sum_v lam_ft_j . sum_k dc_jk/dU (f_k - f_j)   (interior)
-template <int D, typename O>
-__device__ __forceinline__ double cij(const O* o, const double* v, const double* U) {
-  double c = 0.0;
+// with c = 2 sum_a min(0, a_a.(v - U)) and dc/dU = -2 sum_{a: a_a.(v-U) < 0} a_a.
+// A thread handles groups of R consecutive velocities along the fastest
+// axis: each projection is formed once per group and advanced by a constant
+// per velocity.  The per-edge data of both directions (j's own edge to i,
+// with U_j; i's edge to j, with U_i) is staged in LDS per chunk of 32
+// neighbours; the two rows an edge needs (f^n_i for the U-derivative,
+// lam_ft_i for the transposed term) are loaded one edge ahead.  The
+// U-derivative is summed per (edge, projection) over the group and folded
+// with a_a once per edge; each tile writes its part of lam_U, and the parts
+// are summed in tile order by a second kernel (deterministic, no atomics).
+constexpr int kAdjChunk = 32;
+
+template <typename Real, int R>
+__device__ __forceinline__ void load_rr(const Real* __restrict__ p, double (&o)[R]) {
+  constexpr int W = (R * sizeof(Real)) % 16 == 0 ? 16 / static_cast<int>(sizeof(Real)) : R;
+  typedef Real V __attribute__((ext_vector_type(W)));
+  const V* pv = reinterpret_cast<const V*>(__builtin_assume_aligned(p, W * sizeof(Real)));
 #pragma unroll
-  for (int k = 0; k < D; ++k) {
-    double p = 0.0;
+  for (int i = 0; i < R / W; ++i) {
+    const V x = pv[i];
 #pragma unroll
-    for (int m = 0; m < D; ++m) p = p + static_cast<double>(o[k * D + m]) * (v[m] - U[m]);
-    c = c + fmin(p, 0.0);
+    for (int w = 0; w < W; ++w) o[i * W + w] = static_cast<double>(x[w]);
   }
-  return 2.0 * c;
 }
 
-template <int D, int NC, typename Real>
-__global__ __launch_bounds__(kThreads) void k_adj_transport(const AdjArgs<Real> a) {
-  constexpr int DD = D * D;
-  __shared__ double sh[4 * 3];
-  const int j = blockIdx.x;
+template <int D, int NC, typename Real, int R>
+__global__ __launch_bounds__(64) void k_adj_transport(const AdjArgs<Real> a) {
+  constexpr int DD = D * D, REC = DD + 2 * D;  // a (d*d), a.U (d), a[fast]*dv (d)
+  __shared__ double rown[kAdjChunk][REC], rtr[kAdjChunk][REC];
+  __shared__ int32_t ri[kAdjChunk], rfl[kAdjChunk];
+  const int j = blockIdx.x / a.tiles, tile = blockIdx.x - j * a.tiles;
+  const int tid = threadIdx.x, nt = blockDim.x;
   const bool inner = a.wall_id[j] == 0;
   const size_t NVs = a.NV, cs = static_cast<size_t>(a.N) * NVs;
   const int m = min(a.ncnt[j], a.cap);
   const int64_t row = static_cast<int64_t>(j) * a.cap;
+  const double dv = 2.0 * a.vmax / static_cast<double>(a.nv - 1);
   double Uj[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < D; ++q) Uj[q] = a.U_n[static_cast<size_t>(q) * a.N + j];
   double gU[3] = {0.0, 0.0, 0.0};
-  for (int q = threadIdx.x; q < a.NV; q += kThreads) {
-    double v[3];
-    velocity_of<D>(q, a.nv, a.vmax, v);
-    double lf[NC], lj[NC], fj[NC];
+  const int ngroups = a.NV / R;
+  {
+    const int g = tile * nt + tid;
+    const bool on = g < ngroups;
+    const int q0 = on ? g * R : 0;
+    double v0[D];
+    {
+      int q = q0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        v0[k] = vnode(q % a.nv, a.nv, a.vmax);
+        q /= a.nv;
+      }
+    }
+    double lf[R][NC], lj[R][NC], fj[R][NC], csum[R];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      lf[c] = 0.0;
-      lj[c] = inner ? a.lam_ft[c * cs + static_cast<size_t>(j) * NVs + q] : 0.0;
-      fj[c] = a.f_n[c * cs + static_cast<size_t>(j) * NVs + q];
+      double t1[R], t2[R];
+      load_rr<Real, R>(a.lam_ft + c * cs + static_cast<size_t>(j) * NVs + q0, t1);
+      load_rr<Real, R>(a.f_n + c * cs + static_cast<size_t>(j) * NVs + q0, t2);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        lf[r][c] = 0.0;
+        lj[r][c] = inner ? t1[r] : 0.0;
+        fj[r][c] = t2[r];
+      }
     }
-    double csum = 0.0;
-    for (int e = 0; e < m; ++e) {
-      const int i = a.nidx[row + e];
-      if (i == j) continue;
-      if (inner) {
-        // own transport: c_jk with k = i, and dc_jk/dU_j
-        const Real* o = a.ops + (row + e) * DD;
-        double c = 0.0, dcdU[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-        for (int kk = 0; kk < D; ++kk) {
-          double p = 0.0;
+    for (int r = 0; r < R; ++r) csum[r] = 0.0;
+
+    for (int c0 = 0; c0 < m; c0 += kAdjChunk) {
+      const int cn = min(kAdjChunk, m - c0);
+      __syncthreads();
+      for (int w = tid; w < cn; w += nt) {
+        const int e = c0 + w;
+        const int i = a.nidx[row + e];
+        const int te = a.tidx[row + e];
+        const bool own = inner && i != j, tr = te >= 0 && i != j;
+        ri[w] = i;
+        rfl[w] = (own ? 1 : 0) | (tr ? 2 : 0);
+        if (own) {
+          const Real* o = a.ops + (row + e) * DD;
 #pragma unroll
-          for (int mm = 0; mm < D; ++mm) p = p + static_cast<double>(o[kk * D + mm]) * (v[mm] - Uj[mm]);
-          c = c + fmin(p, 0.0);
-          if (p < 0.0) {
+          for (int k = 0; k < D; ++k) {
+            double b = 0.0;
 #pragma unroll
-            for (int mm = 0; mm < D; ++mm) dcdU[mm] = dcdU[mm] - 2.0 * static_cast<double>(o[kk * D + mm]);
+            for (int mm = 0; mm < D; ++mm) {
+              const double x = static_cast<double>(o[k * D + mm]);
+              rown[w][k * D + mm] = x;
+              b = b + x * Uj[mm];
+            }
+            rown[w][DD + k] = b;
+            rown[w][DD + D + k] = static_cast<double>(o[k * D]) * dv;
           }
         }
-        csum = csum + 2.0 * c;
+        if (tr) {
+          const Real* o = a.ops + (static_cast<int64_t>(i) * a.cap + te) * DD;
 #pragma unroll
-        for (int cc = 0; cc < NC; ++cc) {
-          const double df = a.f_n[cc * cs + static_cast<size_t>(i) * NVs + q] - fj[cc];
+          for (int k = 0; k < D; ++k) {
+            double b = 0.0;
 #pragma unroll
-          for (int mm = 0; mm < D; ++mm) gU[mm] = gU[mm] + lj[cc] * dcdU[mm] * df;
+            for (int mm = 0; mm < D; ++mm) {
+              const double x = static_cast<double>(o[k * D + mm]);
+              rtr[w][k * D + mm] = x;
+              b = b + x * a.U_n[static_cast<size_t>(mm) * a.N + i];
+            }
+            rtr[w][DD + k] = b;
+            rtr[w][DD + D + k] = static_cast<double>(o[k * D]) * dv;
+          }
         }
       }
-      const int te = a.tidx[row + e];
-      if (te >= 0) {
-        // i transports from j: c_ij with i's operators and U_i
-        double Ui[3] = {0.0, 0.0, 0.0};
+      __syncthreads();
+      // rows of edge w: fi (f^n_i, own) and li (lam_ft_i, transposed)
+      double fa[R][NC], la[R][NC], fb[R][NC], lb[R][NC];
+      auto load_edge = [&](int w, double (&fi)[R][NC], double (&li)[R][NC]) {
+        const int i = ri[w], fl = rfl[w];
 #pragma unroll
-        for (int mm = 0; mm < D; ++mm) Ui[mm] = a.U_n[static_cast<size_t>(mm) * a.N + i];
-        const double c = cij<D>(a.ops + (static_cast<int64_t>(i) * a.cap + te) * DD, v, Ui);
+        for (int c = 0; c < NC; ++c) {
+          double t[R];
+          if (fl & 1) {
+            load_rr<Real, R>(a.f_n + c * cs + static_cast<size_t>(i) * NVs + q0, t);
 #pragma unroll
-        for (int cc = 0; cc < NC; ++cc)
-          lf[cc] = lf[cc] - a.dt * c * a.lam_ft[cc * cs + static_cast<size_t>(i) * NVs + q];
+            for (int r = 0; r < R; ++r) fi[r][c] = t[r];
+          }
+          if (fl & 2) {
+            load_rr<Real, R>(a.lam_ft + c * cs + static_cast<size_t>(i) * NVs + q0, t);
+#pragma unroll
+            for (int r = 0; r < R; ++r) li[r][c] = t[r];
+          }
+        }
+        asm volatile("" ::: "memory");
+      };
+      auto edge = [&](int w, const double (&fi)[R][NC], const double (&li)[R][NC]) {
+        const int fl = rfl[w];
+        if (fl & 1) {
+          const double* rc = rown[w];
+          double p[D], S[D];
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            double s1 = -rc[DD + k];
+#pragma unroll
+            for (int mm = 0; mm < D; ++mm) s1 = s1 + rc[k * D + mm] * v0[mm];
+            p[k] = s1;
+            S[k] = 0.0;
+          }
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if (r > 0) {
+#pragma unroll
+              for (int k = 0; k < D; ++k) p[k] = p[k] + rc[DD + D + k];
+            }
+            double cm = fmin(p[0], 0.0);
+#pragma unroll
+            for (int k = 1; k < D; ++k) cm = cm + fmin(p[k], 0.0);
+            csum[r] = csum[r] + 2.0 * cm;
+            double sdf = 0.0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sdf = sdf + lj[r][c] * (fi[r][c] - fj[r][c]);
+#pragma unroll
+            for (int k = 0; k < D; ++k) S[k] = S[k] + (p[k] < 0.0 ? sdf : 0.0);
+          }
+          if (on) {
+#pragma unroll
+            for (int mm = 0; mm < D; ++mm) {
+              double t = 0.0;
+#pragma unroll
+              for (int k = 0; k < D; ++k) t = t + rc[k * D + mm] * S[k];
+              gU[mm] = gU[mm] - 2.0 * t;
+            }
+          }
+        }
+        if (fl & 2) {
+          const double* rc = rtr[w];
+          double p[D];
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            double s1 = -rc[DD + k];
+#pragma unroll
+            for (int mm = 0; mm < D; ++mm) s1 = s1 + rc[k * D + mm] * v0[mm];
+            p[k] = s1;
+          }
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if (r > 0) {
+#pragma unroll
+              for (int k = 0; k < D; ++k) p[k] = p[k] + rc[DD + D + k];
+            }
+            double cm = fmin(p[0], 0.0);
+#pragma unroll
+            for (int k = 1; k < D; ++k) cm = cm + fmin(p[k], 0.0);
+            const double dc = a.dt * (2.0 * cm);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) lf[r][c] = lf[r][c] - dc * li[r][c];
+          }
+        }
+      };
+      load_edge(0, fa, la);
+      for (int w = 0; w < cn; w += 2) {
+        if (w + 1 < cn) load_edge(w + 1, fb, lb);
+        edge(w, fa, la);
+        if (w + 1 < cn) {
+          if (w + 2 < cn) load_edge(w + 2, fa, la);
+          edge(w + 1, fb, lb);
+        }
       }
     }
+    if (on) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      double l = lf[c];
-      if (inner) l = l + lj[c] * (1.0 + a.dt * csum);
-      a.lam_f[c * cs + static_cast<size_t>(j) * NVs + q] = static_cast<Real>(l);
+      for (int c = 0; c < NC; ++c) {
+        Real out[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          double l = lf[r][c];
+          if (inner) l = l + lj[r][c] * (1.0 + a.dt * csum[r]);
+          out[r] = static_cast<Real>(l);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) a.lam_f[c * cs + static_cast<size_t>(j) * NVs + q0 + r] = out[r];
+      }
     }
   }
-  double r[3] = {gU[0], gU[1], gU[2]};
-  block_sum<3>(r, sh);
-  if (threadIdx.x == 0) {
+#pragma unroll
+  for (int mm = 0; mm < D; ++mm) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) gU[mm] += __shfl_xor(gU[mm], o, 64);
+  }
+  if (tid == 0) {
 #pragma unroll
     for (int mm = 0; mm < D; ++mm)
-      a.lam_U[static_cast<size_t>(mm) * a.N + j] = inner ? -a.dt * r[mm] : 0.0;
+      a.gpart[(static_cast<size_t>(tile) * D + mm) * a.N + j] = gU[mm];
   }
+}
+
+// lam_U_j = -dt * (sum over the tiles of j, in tile order)  (interior j)
+__global__ void k_adj_sum_tiles(int N, int D, int tiles, double dt,
+                                const int32_t* __restrict__ wall_id,
+                                const double* __restrict__ gpart, double* __restrict__ lam_U) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= static_cast<int64_t>(N) * D) return;
+  const int mm = static_cast<int>(k / N), j = static_cast<int>(k - static_cast<int64_t>(mm) * N);
+  double s = 0.0;
+  for (int t = 0; t < tiles; ++t) s = s + gpart[(static_cast<size_t>(t) * D + mm) * N + j];
+  lam_U[static_cast<size_t>(mm) * N + j] = wall_id[j] == 0 ? -dt * s : 0.0;
 }
 
 // ------------------------------------------------------------ objective
@@ -525,17 +685,25 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
                   static_cast<const Real*>(j.ft), static_cast<const Real*>(j.f1), j.rho1, j.U1,
                   j.T1,       lam_f1,     lam_U1,     lam_rho1,    lam_T1,
                   static_cast<Real*>(j.larr), static_cast<Real*>(j.lam_ft), lam_f, lam_U,
-                  j.lidpart};
+                  j.lidpart, j.gpart, static_cast<int>(adj_tiles(c.cfg))};
   dim3 t(kThreads);
+  // reverse transport: one wavefront per (particle, tile of 64 groups of 2
+  // velocities), then the tile parts of lam_U summed in tile order
+  const int64_t nblk = static_cast<int64_t>(c.N) * a.tiles;
+  if (nblk > INT32_MAX) return hipErrorInvalidValue;
+  const dim3 tg(static_cast<unsigned>(nblk)), tt(64);
   if (c.D == 2) {
     if (c.Nw) hipLaunchKernelGGL((k_adj_wall<2, 2, Real>), dim3(c.Nw), t, 0, c.stream, a);
     if (c.Ni) hipLaunchKernelGGL((k_adj_collide<2, 2, Real>), dim3(c.Ni), t, 0, c.stream, a);
-    hipLaunchKernelGGL((k_adj_transport<2, 2, Real>), dim3(c.N), t, 0, c.stream, a);
+    hipLaunchKernelGGL((k_adj_transport<2, 2, Real, 2>), tg, tt, 0, c.stream, a);
   } else {
     if (c.Nw) hipLaunchKernelGGL((k_adj_wall<3, 1, Real>), dim3(c.Nw), t, 0, c.stream, a);
     if (c.Ni) hipLaunchKernelGGL((k_adj_collide<3, 1, Real>), dim3(c.Ni), t, 0, c.stream, a);
-    hipLaunchKernelGGL((k_adj_transport<3, 1, Real>), dim3(c.N), t, 0, c.stream, a);
+    hipLaunchKernelGGL((k_adj_transport<3, 1, Real, 2>), tg, tt, 0, c.stream, a);
   }
+  const int64_t nu = static_cast<int64_t>(c.N) * c.D;
+  hipLaunchKernelGGL(k_adj_sum_tiles, dim3(static_cast<unsigned>((nu + 255) / 256)), dim3(256), 0,
+                     c.stream, c.N, c.D, a.tiles, c.cfg.dt, c.d.wall_id, j.gpart, lam_U);
   if (c.Nw && dJ_dlid)
     hipLaunchKernelGGL(k_sum_fixed, dim3(1), t, 0, c.stream, c.Nw, j.lidpart, dJ_dlid, 1);
   return hipGetLastError();
