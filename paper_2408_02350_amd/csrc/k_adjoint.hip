@@ -211,9 +211,13 @@ __global__ __launch_bounds__(kThreads) void k_adj_wall(const AdjArgs<Real> a) {
 }
 
 // ------------------------------------------------------------ S5-S6 adjoint
+// The velocity nodes and the per-axis factors exp(-(v_k - U_a)^2 / (2T)) of
+// the particle's Maxwellian are tabulated in LDS (dynamic, (D+1)*nv doubles):
+// M = norm * prod_a e_a[k_a], Chu G2 = T G1.
 template <int D, int NC, typename Real>
 __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a) {
   __shared__ double sh[4 * (D + 4)];
+  extern __shared__ double vt[];  // nodes [nv], then factors [D][nv]
   const int i = a.plist[blockIdx.x];
   const size_t NVs = a.NV, cs = static_cast<size_t>(a.N) * NVs;
   const double rho = a.rho1[i], T = a.T1[i];
@@ -231,6 +235,28 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
   const double ca = tau / den, cb = a.dt / den, dtau = a.dt / (den * den);  // d f'/d tau = (ft-M) dtau
   const double kap0 = (D == 3) ? 1.5 : 1.0;
   const int ws = a.wtstart[i], we = a.wtstart[i + 1];
+  double* et = vt + a.nv;
+  for (int k = threadIdx.x; k < a.nv; k += blockDim.x) vt[k] = vnode(k, a.nv, a.vmax);
+  __syncthreads();
+  for (int t = threadIdx.x; t < D * a.nv; t += blockDim.x) {
+    const int ax = t / a.nv, k = t - ax * a.nv;
+    const double d = vt[k] - U[ax];
+    et[t] = exp(-(d * d) / (2.0 * T));
+  }
+  __syncthreads();
+  const double tp = 2.0 * kPi * T;
+  const double norm = D == 3 ? rho / (tp * sqrt(tp)) : rho / tp;
+  auto vel = [&](int q, double (&v)[3], double& M1) {
+    v[0] = v[1] = v[2] = 0.0;
+    M1 = norm;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const int kk = q % a.nv;
+      q /= a.nv;
+      v[k] = vt[kk];
+      M1 = M1 * et[k * a.nv + kk];
+    }
+  };
   // adjoint of f' = lam_f1 + sum over the wall rows that interpolate from i
   auto lam_fp = [&](int c, int q) {
     double l = a.lam_f1[c * cs + static_cast<size_t>(i) * NVs + q];
@@ -245,14 +271,14 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
 #pragma unroll
   for (int k = 0; k < D + 3; ++k) s[k] = 0.0;
   for (int q = threadIdx.x; q < a.NV; q += kThreads) {
-    double v[3];
-    velocity_of<D>(q, a.nv, a.vmax, v);
+    double v[3], M1;
+    vel(q, v, M1);
     double w2 = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) w2 = w2 + (v[k] - U[k]) * (v[k] - U[k]);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const double M = maxwell<D>(c, rho, U, T, v);
+      const double M = c == 0 ? M1 : T * M1;
       const double l = lam_fp(c, q);
       const double x = a.ft[c * cs + static_cast<size_t>(i) * NVs + q];
       s[0] = s[0] + l * M;
@@ -270,8 +296,8 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
   for (int k = 0; k < D; ++k) gU[k] = lU[k] + cb * s[2 + k] / T;
   const double g_T = lT + cb * s[2 + D] + s[1] * dtau * (-tau / (2.0 * T));
   for (int q = threadIdx.x; q < a.NV; q += kThreads) {
-    double v[3];
-    velocity_of<D>(q, a.nv, a.vmax, v);
+    double v[3], M1;
+    vel(q, v, M1);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const double l = ca * lam_fp(c, q) + mom_adj<D, NC>(c, v, a.omega, s0, U, T, g_rho, gU, g_T);
@@ -687,6 +713,7 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
                   static_cast<Real*>(j.larr), static_cast<Real*>(j.lam_ft), lam_f, lam_U,
                   j.lidpart, j.gpart, static_cast<int>(adj_tiles(c.cfg))};
   dim3 t(kThreads);
+  const size_t lds = static_cast<size_t>(c.D + 1) * c.cfg.nv * sizeof(double);
   // reverse transport: one wavefront per (particle, tile of 64 groups of 2
   // velocities), then the tile parts of lam_U summed in tile order
   const int64_t nblk = static_cast<int64_t>(c.N) * a.tiles;
@@ -694,11 +721,11 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
   const dim3 tg(static_cast<unsigned>(nblk)), tt(64);
   if (c.D == 2) {
     if (c.Nw) hipLaunchKernelGGL((k_adj_wall<2, 2, Real>), dim3(c.Nw), t, 0, c.stream, a);
-    if (c.Ni) hipLaunchKernelGGL((k_adj_collide<2, 2, Real>), dim3(c.Ni), t, 0, c.stream, a);
+    if (c.Ni) hipLaunchKernelGGL((k_adj_collide<2, 2, Real>), dim3(c.Ni), t, lds, c.stream, a);
     hipLaunchKernelGGL((k_adj_transport<2, 2, Real, 2>), tg, tt, 0, c.stream, a);
   } else {
     if (c.Nw) hipLaunchKernelGGL((k_adj_wall<3, 1, Real>), dim3(c.Nw), t, 0, c.stream, a);
-    if (c.Ni) hipLaunchKernelGGL((k_adj_collide<3, 1, Real>), dim3(c.Ni), t, 0, c.stream, a);
+    if (c.Ni) hipLaunchKernelGGL((k_adj_collide<3, 1, Real>), dim3(c.Ni), t, lds, c.stream, a);
     hipLaunchKernelGGL((k_adj_transport<3, 1, Real, 2>), tg, tt, 0, c.stream, a);
   }
   const int64_t nu = static_cast<int64_t>(c.N) * c.D;
