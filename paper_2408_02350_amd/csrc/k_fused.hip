@@ -101,6 +101,29 @@ __device__ __forceinline__ void load_r(const Real* __restrict__ p, Real (&o)[R])
     for (int w = 0; w < W; ++w) o[i * W + w] = x[w];
   }
 }
+// R consecutive elements of a row through a buffer resource: the row base
+// is wave-uniform (scalar registers), the lane's byte offset a 32-bit
+// vector register, so no per-load 64-bit address arithmetic.  Needs
+// R * sizeof(Real) to be a multiple of 16 bytes.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <typename Real, int R>
+__device__ __forceinline__ void load_rb(const Real* row, uint32_t lane_off, Real (&o)[R]) {
+  constexpr int B = R * static_cast<int>(sizeof(Real));
+  static_assert(B % 16 == 0, "buffer row loads take 16-byte pieces");
+  constexpr int W = 16 / static_cast<int>(sizeof(Real));
+  typedef Real V __attribute__((ext_vector_type(W)));
+  // raw buffer of the row: stride 0, byte count beyond any row, and the
+  // descriptor format word of the gfx9 family
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<Real*>(row), 0, 0x7fffffff, 0x00020000);
+#pragma unroll
+  for (int i = 0; i < B / 16; ++i) {
+    const V x = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rs, lane_off + 16 * i, 0, 0));
+#pragma unroll
+    for (int w = 0; w < W; ++w) o[i * W + w] = x[w];
+  }
+}
+
 template <typename Real, int R>
 __device__ __forceinline__ void store_r(Real* __restrict__ p, const Real (&o)[R]) {
   constexpr int B = R * static_cast<int>(sizeof(Real));
@@ -287,13 +310,17 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
     // never move).  Loads are unconditional (clamped entry, lane-clamped
     // address), so the waits before each use are exact partial counts.
     Real ra[R][NC], rb[R][NC], rc[R][NC];
+    const uint32_t lane_off = static_cast<uint32_t>(q0) * sizeof(Real);
     auto load_row = [&](int uu, Real (&buf)[R][NC]) {
       const int j = static_cast<int>(static_cast<uint32_t>(__builtin_amdgcn_readlane(vju, uu)) >> 4);
-      const Real* src = f + static_cast<size_t>(j) * NVs + q0;
+      const Real* src = f + static_cast<size_t>(j) * NVs;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         Real tmp[R];
-        load_r<Real, R>(src + c * cs, tmp);
+        if constexpr ((R * sizeof(Real)) % 16 == 0)
+          load_rb<Real, R>(src + c * cs, lane_off, tmp);
+        else
+          load_r<Real, R>(src + c * cs + q0, tmp);
 #pragma unroll
         for (int r = 0; r < R; ++r) buf[r][c] = tmp[r];
       }
