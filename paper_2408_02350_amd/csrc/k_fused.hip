@@ -77,6 +77,8 @@ __device__ __forceinline__ double fma_t(double a, double b, double c) { return f
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ double min_t(double a, double b) { return fmin(a, b); }
 __device__ __forceinline__ float min_t(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ double abs_t(double a) { return fabs(a); }
+__device__ __forceinline__ float abs_t(float a) { return fabsf(a); }
 __device__ __forceinline__ float bf16r(float x) { return static_cast<float>(static_cast<__bf16>(x)); }
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 // (x, y) rounded to a BF16 pair (round to nearest even, one instruction)
@@ -176,7 +178,12 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   using Real = typename FPrec<MODE>::real;
   constexpr int DD = D * D;
   constexpr bool DIFF = (MODE == BGK_BF16);     // products of differences
-  constexpr int REC = DD + 2 * D;               // a_k (d*d), a_k.U (d), a_k[fast]*dvs (d)
+  // 3D (not BF16): c = g.w - sum_k |a_k.w| with g.w = sum_k a_k.w advanced
+  // by its own increment (|x| is a free source modifier: 3 adds per velocity
+  // instead of 3 mins and 2 adds); 2D keeps 2 sum_k min(0, a_k.w) (equal cost)
+  constexpr bool GW = (D == 3 && !DIFF);
+  // record: a_k (d*d), a_k.U (d), a_k[fast]*dvs (d)[, their sum]
+  constexpr int REC = DD + 2 * D + (GW ? 1 : 0);
   constexpr int KM = TP * (D + 1);              // first-pass moment sums per thread
   constexpr int KP = pow2_at_least(KM);
   constexpr int KP2 = pow2_at_least(TP);         // second pass: one sum per particle
@@ -299,6 +306,12 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
           rec[DD + k] = b;
           rec[DD + D + k] = av[k * D] * dvs;
         }
+        if constexpr (GW) {
+          Real gi = rec[DD + D];
+#pragma unroll
+          for (int k = 1; k < D; ++k) gi = gi + rec[DD + D + k];
+          rec[DD + 2 * D] = gi;
+        }
 #pragma unroll
         for (int k = 0; k < DD; ++k) rec[k] = av[k];
       }
@@ -369,15 +382,30 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
           }
 #pragma unroll
           for (int k = 0; k < D; ++k) ik[k] = rec[DD + D + k];
+          Real gw = Real(0), ig = Real(0);
+          if constexpr (GW) {
+            gw = p[0];
+#pragma unroll
+            for (int k = 1; k < D; ++k) gw = gw + p[k];
+            ig = rec[DD + 2 * D];
+          }
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             if (r > 0) {
 #pragma unroll
               for (int k = 0; k < D; ++k) p[k] = p[k] + ik[k];
+              if constexpr (GW) gw = gw + ig;
             }
-            Real cm = min_t(p[0], Real(0));
+            Real cm;
+            if constexpr (GW) {
+              cm = gw;  // = 2 sum_k min(0, p_k)
 #pragma unroll
-            for (int k = 1; k < D; ++k) cm = cm + min_t(p[k], Real(0));
+              for (int k = 0; k < D; ++k) cm = cm - abs_t(p[k]);
+            } else {
+              cm = min_t(p[0], Real(0));
+#pragma unroll
+              for (int k = 1; k < D; ++k) cm = cm + min_t(p[k], Real(0));
+            }
             if constexpr (DIFF) {
 #pragma unroll
               for (int c = 0; c < NC; ++c)
@@ -500,8 +528,9 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   }
 
   // ft = f - dt sum c (f_j - f_i) = f (1 + dt sum c) - dt sum c f_j; the
-  // factor 2 of c is folded into dt (except where BF16 rounds 2 cm)
-  const Real dtf = static_cast<Real>(DIFF ? a.dt : 2.0 * a.dt);
+  // factor 2 of c is folded into dt (except where BF16 rounds 2 cm, and in the
+  // 3D form, whose g.w - sum |a_k.w| already is c)
+  const Real dtf = static_cast<Real>((DIFF || GW) ? a.dt : 2.0 * a.dt);
   Real ft[TP][R][NC];
 #pragma unroll
   for (int t = 0; t < TP; ++t) {
