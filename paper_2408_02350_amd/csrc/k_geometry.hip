@@ -325,80 +325,76 @@ struct WlsArgs {
   int32_t* err;
 };
 
-// Row entries whose product is basis function r in the order of
-// Basis::eval (index D stands for the constant 1): r = 0 -> (D, D),
-// r = 1 + a -> (a, D), then y_a y_b for a <= b -> (a, b).
+// Sum of v over the 16 lanes of a DPP row, left in every lane of the row.
+// Each step adds a lane's value to that of its partner (xor 1, xor 2, the
+// mirrored quad, the mirrored half); IEEE addition is commutative, so every
+// lane of the row ends with the same bits.
+template <int CTRL>
+__device__ __forceinline__ double row_dpp(double v) {
+  const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v));
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(u & 0xffffffffu), CTRL, 0xF,
+                                             0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(static_cast<long long>(
+      (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+      static_cast<unsigned>(lo)));
+}
+
+__device__ __forceinline__ double row_sum16(double v) {
+  v = v + row_dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v = v + row_dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v = v + row_dpp<0x141>(v);  // row_half_mirror
+  v = v + row_dpp<0x140>(v);  // row_mirror
+  return v;
+}
+
+// Basis values of one scaled offset y for the fitted degree, zero beyond
+// the degree's B functions: degree 2 and 1 as Basis::eval, degree 0 the
+// offsets alone (first derivatives only, no constant).
 template <int D>
-__device__ __forceinline__ void basis_factors(int r, int& i0, int& i1) {
-  i0 = D;
-  i1 = D;
-  if (r == 0) return;
-  if (r <= D) {
-    i0 = r - 1;
-    return;
-  }
-  int k = D + 1;
-  for (int a = 0; a < D; ++a)
-    for (int b = a; b < D; ++b) {
-      if (k == r) {
-        i0 = a;
-        i1 = b;
-      }
-      ++k;
-    }
-}
-
-// Solve L L^T z = e_col for one column (L packed lower triangle in A).
-template <int B>
-__device__ __forceinline__ void chol_solve_col(const double* A, int col, double* z) {
-  double y[B];
+__device__ __forceinline__ void wls_basis(int deg, const double* y, double* p) {
+  constexpr int B2 = Basis<D, 2>::B;
+  if (deg == 2) {
+    Basis<D, 2>::eval(y, p);
+  } else if (deg == 1) {
+    Basis<D, 1>::eval(y, p);
 #pragma unroll
-  for (int i = 0; i < B; ++i) {
-    double s = (i == col) ? 1.0 : 0.0;
+    for (int r = D + 1; r < B2; ++r) p[r] = 0.0;
+  } else {
 #pragma unroll
-    for (int k = 0; k < i; ++k) s = s - A[tri(i, k)] * y[k];
-    y[i] = s / A[tri(i, i)];
-  }
-#pragma unroll
-  for (int i = B - 1; i >= 0; --i) {
-    double s = y[i];
-#pragma unroll
-    for (int k = i + 1; k < B; ++k) s = s - A[tri(k, i)] * z[k];
-    z[i] = s / A[tri(i, i)];
+    for (int r = 0; r < B2; ++r) p[r] = r < D ? y[r] : 0.0;
   }
 }
 
-// kWlsGroup interior particles per wavefront, 64 / kWlsGroup lanes each
-// (lane group g handles particle blockIdx.x * kWlsGroup + g).  Per
-// particle: the stencil's scaled offsets y = (x_j - x_i)/h and weights are
-// staged in LDS (one lane per neighbour); the normal matrix
-// A = sum_e W_e p(y_e) p(y_e)^T is summed over e in order (one lane per
-// packed entry, basis values formed on the fly); A = L L^T column by column
-// (one lane per row of a column); one lane per gradient column solves
-// L L^T z = e_col; then one lane per neighbour forms the gradient row
-// W_e z.p(y_e)/h, the edge frame of y_e and (P, Q[, R]).  Degree: the
-// configured one if the stencil holds at least twice as many points as
-// degree-2 basis functions, else 1 if it holds d+2 points, else
-// BGK_ESINGULAR (also on a non-positive pivot).  Degree 0 is the fit as
-// printed in Sec. 3.1: first derivatives only, the basis is the scaled
-// offsets y (no constant; the particle itself has y = 0 and drops out),
-// derivative k in column k.  Barriers sit at points
-// every lane reaches (loops run to the degree-2 sizes; groups of lower
-// degree idle through the extra columns).
+// kWlsGroup interior particles per wavefront, one 16-lane DPP row each
+// (row g handles particle blockIdx.x * kWlsGroup + g).  Per particle:
+// each lane takes the neighbours e = lane, lane + 16, ... , forms the
+// scaled offset y = (x_j - x_i)/h, the weight and the basis values, and
+// adds W_e p(y_e) p(y_e)^T to its own copy of the packed normal matrix;
+// the row's 16 partial matrices are summed with DPP moves, so that every
+// lane holds all of A.  Every lane then factors A = L L^T and solves
+// L L^T z = e_col for the gradient columns in registers (the same
+// arithmetic in every lane of the row), and forms, for its own
+// neighbours, the gradient row W_e z.p(y_e)/h, the edge frame of x_j - x_i
+// and (P, Q[, R]).  The offsets, weights and indices of a lane's own
+// neighbours wait in LDS between the two passes (no lane reads another's,
+// so there is no barrier).  Degree: the configured one if the stencil holds
+// at least twice as many points as degree-2 basis functions, else 1 if it
+// holds d+2 points, else BGK_ESINGULAR (also on a non-positive pivot).
+// Degree 0 is the fit as printed in Sec. 3.1: first derivatives only, the
+// basis is the scaled offsets y (no constant; the particle itself has
+// y = 0 and drops out), derivative k in column k.  A lower degree runs on
+// the degree-2 sizes with the unused basis values zero and a unit diagonal
+// in their rows of A, which leaves the fitted block and its solution as
+// they are and zeros the rest.
 constexpr int kWlsGroup = 4;
-
-template <int D>
-struct WlsSm {
-  static constexpr int B2 = Basis<D, 2>::B, NT2 = Basis<D, 2>::NT;
-  // doubles per group: Y [cap][D+1] (offsets, then 1.0), W [cap], A [NT2], Z [D][B2], flag
-  static __host__ __device__ int doubles(int cap) { return cap * (D + 1) + cap + NT2 + D * B2 + 1; }
-};
+constexpr int kWlsRow = kWave / kWlsGroup;
 
 template <int D>
 __global__ __launch_bounds__(64) void k_wls(const WlsArgs a) {
   extern __shared__ double wls_sm[];
-  using S = WlsSm<D>;
-  constexpr int L = kWave / kWlsGroup, B2 = S::B2, B1 = D + 1, DD = D * D;
+  constexpr int B2 = Basis<D, 2>::B, NT2 = Basis<D, 2>::NT, DD = D * D;
+  constexpr int L = kWlsRow;
   const int lane = threadIdx.x, g = lane / L, gl = lane % L;
   const int pidx = blockIdx.x * kWlsGroup + g;
   const bool valid = pidx < a.Ni;
@@ -406,98 +402,110 @@ __global__ __launch_bounds__(64) void k_wls(const WlsArgs a) {
   const int m = valid ? min(a.cnt[i], a.cap) : 0;
   int deg = a.deg_cfg;
   if (deg == 2 && m < 2 * B2) deg = 1;
-  const int Bg = (deg == 2) ? B2 : (deg == 1 ? B1 : D);
+  const int Bg = (deg == 2) ? B2 : (deg == 1 ? D + 1 : D);
   const bool enough = m >= D + 2;
-  constexpr int YS = D + 1;  // Y row: y_0 .. y_{D-1}, 1.0
-  double* Y = wls_sm + g * S::doubles(a.cap);
-  double* W = Y + a.cap * YS;
-  double* A = W + a.cap;
-  double* Z = A + S::NT2;
-  double* flag = Z + D * B2;
+  // per lane and local neighbour q: dl[D], W (doubles), j (int), stored
+  // [q][field][lane] so that a wave's accesses are consecutive
+  const int qmax = (a.cap + L - 1) / L;
+  double* DL = wls_sm;                    // [qmax][D][64]
+  double* WS = DL + qmax * D * kWave;     // [qmax][64]
+  int32_t* JS = reinterpret_cast<int32_t*>(WS + qmax * kWave);  // [qmax][64]
   const int64_t row = static_cast<int64_t>(i) * a.cap;
   double xi[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) xi[k] = a.x[static_cast<int64_t>(k) * a.N + i];
-  for (int e = gl; e < m; e += L) {
+  double A[NT2];
+#pragma unroll
+  for (int t = 0; t < NT2; ++t) A[t] = 0.0;
+  for (int q = 0, e = gl; e < m; ++q, e += L) {
     const int j = a.idx[row + e];
-    double r2 = 0.0;
+    double y[D], r2 = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      const double y = (a.x[static_cast<int64_t>(k) * a.N + j] - xi[k]) / a.h;
-      Y[e * YS + k] = y;
-      r2 = r2 + y * y;
+      const double dl = a.x[static_cast<int64_t>(k) * a.N + j] - xi[k];
+      DL[(q * D + k) * kWave + lane] = dl;
+      y[k] = dl / a.h;
+      r2 = r2 + y[k] * y[k];
     }
-    Y[e * YS + D] = 1.0;
-    W[e] = exp(-a.alpha * r2);
-  }
-  if (gl == 0) flag[0] = 0.0;
-  __syncthreads();
-  const int nt = Bg * (Bg + 1) / 2;
-  for (int l = gl; l < S::NT2; l += L) {
-    if (l < nt) {
-      int r = 0;
-      while (tri(r + 1, 0) <= l) ++r;
-      const int s2 = l - tri(r, 0);
-      // basis function k is the product Y[i0] * Y[i1] of two row entries
-      // (index D holds 1.0): 1 = 1*1, y_a = y_a*1, y_a y_b
-      // (degree 0: the basis is the offsets alone, y_r = y_r * 1)
-      int r0 = r, r1 = D, s0 = s2, s1 = D;
-      if (deg != 0) {
-        basis_factors<D>(r, r0, r1);
-        basis_factors<D>(s2, s0, s1);
-      }
-      double acc = 0.0;
-      for (int e = 0; e < m; ++e) {
-        const double* y = Y + e * YS;
-        acc = acc + (W[e] * (y[r0] * y[r1])) * (y[s0] * y[s1]);
-      }
-      A[l] = acc;
-    }
-  }
-  __syncthreads();
-  for (int jc = 0; jc < B2; ++jc) {
-    if (jc < Bg && gl == 0) {
-      double s = A[tri(jc, jc)];
-      for (int k = 0; k < jc; ++k) s = s - A[tri(jc, k)] * A[tri(jc, k)];
-      if (!(s > 0.0)) flag[0] = 1.0;
-      A[tri(jc, jc)] = sqrt(s);
-    }
-    __syncthreads();
-    if (jc < Bg && gl > jc && gl < Bg) {
-      double t = A[tri(gl, jc)];
-      for (int k = 0; k < jc; ++k) t = t - A[tri(gl, k)] * A[tri(jc, k)];
-      A[tri(gl, jc)] = t / A[tri(jc, jc)];
-    }
-    __syncthreads();
-  }
-  const bool ok = valid && enough && flag[0] == 0.0;
-  if (ok && gl < D) {
-    if (deg == 2) chol_solve_col<B2>(A, 1 + gl, Z + gl * B2);
-    else if (deg == 1) chol_solve_col<B1>(A, 1 + gl, Z + gl * B2);
-    else chol_solve_col<D>(A, gl, Z + gl * B2);  // derivative k is column k
-  }
-  __syncthreads();
-  if (ok) {
-    for (int e = gl; e < m; e += L) {
-      const int j = a.idx[row + e];
-      const double* y = Y + e * YS;
-      double pv[B2];
-      if (deg == 2) {
-        Basis<D, 2>::eval(y, pv);
-      } else if (deg == 1) {
-        Basis<D, 1>::eval(y, pv);
-      } else {
+    const double w = exp(-a.alpha * r2);
+    WS[q * kWave + lane] = w;
+    JS[q * kWave + lane] = j;
+    double p[B2];
+    wls_basis<D>(deg, y, p);
 #pragma unroll
-        for (int r = 0; r < B2; ++r) pv[r] = r < D ? y[r] : 0.0;
+    for (int r = 0; r < B2; ++r) {
+      const double wp = w * p[r];
+#pragma unroll
+      for (int s = 0; s <= r; ++s) A[tri(r, s)] = A[tri(r, s)] + wp * p[s];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT2; ++t) A[t] = row_sum16(A[t]);
+#pragma unroll
+  for (int r = 0; r < B2; ++r)
+    if (r >= Bg) A[tri(r, r)] = 1.0;
+  // A = L L^T in place, with the reciprocals of the diagonal kept
+  bool bad = false;
+  double inv[B2];
+#pragma unroll
+  for (int jc = 0; jc < B2; ++jc) {
+    double s = A[tri(jc, jc)];
+#pragma unroll
+    for (int k = 0; k < jc; ++k) s = s - A[tri(jc, k)] * A[tri(jc, k)];
+    bad = bad || !(s > 0.0);
+    const double l = sqrt(s);
+    A[tri(jc, jc)] = l;
+    inv[jc] = 1.0 / l;
+#pragma unroll
+    for (int r = jc + 1; r < B2; ++r) {
+      double t = A[tri(r, jc)];
+#pragma unroll
+      for (int k = 0; k < jc; ++k) t = t - A[tri(r, k)] * A[tri(jc, k)];
+      A[tri(r, jc)] = t * inv[jc];
+    }
+  }
+  const bool ok = valid && enough && !bad;
+  // z_k = A^{-1} e_col(k): derivative k is column 1 + k (degree 1 and 2) or
+  // k (degree 0)
+  double z[D][B2];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const int col = deg == 0 ? k : 1 + k;
+    double yv[B2];
+#pragma unroll
+    for (int r = 0; r < B2; ++r) {
+      double s = (r == col) ? 1.0 : 0.0;
+#pragma unroll
+      for (int c = 0; c < r; ++c) s = s - A[tri(r, c)] * yv[c];
+      yv[r] = s * inv[r];
+    }
+#pragma unroll
+    for (int r = B2 - 1; r >= 0; --r) {
+      double s = yv[r];
+#pragma unroll
+      for (int c = r + 1; c < B2; ++c) s = s - A[tri(c, r)] * z[k][c];
+      z[k][r] = s * inv[r];
+    }
+  }
+  if (ok) {
+    for (int q = 0, e = gl; e < m; ++q, e += L) {
+      const int j = JS[q * kWave + lane];
+      const double w = WS[q * kWave + lane];
+      double dl[D], y[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        dl[k] = DL[(q * D + k) * kWave + lane];
+        y[k] = dl[k] / a.h;
       }
+      double p[B2];
+      wls_basis<D>(deg, y, p);
       double gk[D];
 #pragma unroll
       for (int k = 0; k < D; ++k) {
         double s = 0.0;
 #pragma unroll
-        for (int r = 0; r < B2; ++r)
-          if (r < Bg) s = s + Z[k * B2 + r] * pv[r];
-        gk[k] = W[e] * s / a.h;
+        for (int r = 0; r < B2; ++r) s = s + z[k][r] * p[r];
+        gk[k] = w * s / a.h;
       }
       if (a.grad) {
 #pragma unroll
@@ -508,9 +516,6 @@ __global__ __launch_bounds__(64) void k_wls(const WlsArgs a) {
 #pragma unroll
         for (int k = 0; k < DD; ++k) o[k] = 0.0;
       } else {
-        double dl[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) dl[k] = a.x[static_cast<int64_t>(k) * a.N + j] - xi[k];
         double n[3], t[3], b[3];
         edge_frame<D>(dl, n, t, b);
         double ab = 0.0, bb = 0.0, gb = 0.0;
@@ -544,8 +549,8 @@ __global__ __launch_bounds__(64) void k_wls(const WlsArgs a) {
 }
 
 static size_t wls_smem(int D, int cap) {
-  const int per = D == 2 ? WlsSm<2>::doubles(cap) : WlsSm<3>::doubles(cap);
-  return static_cast<size_t>(kWlsGroup) * per * sizeof(double);
+  const size_t qmax = static_cast<size_t>((cap + kWlsRow - 1) / kWlsRow);
+  return qmax * kWave * ((D + 1) * sizeof(double) + sizeof(int32_t));
 }
 
 hipError_t launch_wls(const Ctx& c, const double* x, const int32_t* cnt, const int32_t* idx,
