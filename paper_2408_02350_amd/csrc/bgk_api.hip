@@ -106,6 +106,11 @@ size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj, Pm*
   t.uj = reinterpret_cast<int32_t*>(take((N + 3) * cap * 4));
   t.ue = reinterpret_cast<uint32_t*>(take((N + 3) * cap * 4));
   t.jpart = reinterpret_cast<double*>(take(N * 8));
+  const int64_t npw = wall_patches_max(N, cfg.dim);
+  t.wpl = reinterpret_cast<int32_t*>(take(npw * kWallPatch * 4));
+  t.wucount = reinterpret_cast<int32_t*>(take(npw * 4));
+  t.wuj = reinterpret_cast<int32_t*>(take(npw * kWallPatch * cap * 4));
+  t.wue = reinterpret_cast<uint32_t*>(take(npw * kWallPatch * cap * 4));
   if (d) *d = t;
   if (cfg.flags & BGK_FLAG_ADJOINT) {
     // The reverse step reads the wall rows of f^{n+1} before it writes the
@@ -235,11 +240,27 @@ int bgk_init(const bgk_config* cfg, const int32_t* wall_id, void* workspace, siz
   c.tp = bgk::choose_patch(c.D, cfg->precision, c.NV, c.Ni);
   c.npatch = (c.Ni + c.tp - 1) / c.tp;
   c.ucap = c.tp * c.cap;
+  // 3D wall patches: runs of kWallPatch consecutive entries of one face
+  std::vector<int32_t> wp;
+  if (c.D == 3) {
+    for (int s0 = 0; s0 < c.Nw;) {
+      int s1 = s0;
+      while (s1 < c.Nw && wid[wl[s1]] == wid[wl[s0]]) ++s1;
+      for (int q = s0; q < s1; q += bgk::kWallPatch)
+        for (int t = 0; t < bgk::kWallPatch; ++t) wp.push_back(q + t < s1 ? q + t : -1);
+      s0 = s1;
+    }
+  }
+  c.npw = static_cast<int>(wp.size()) / bgk::kWallPatch;
+  c.wucap = bgk::kWallPatch * c.cap;
   int32_t zeros[bgk::kErrWords] = {0};
   e = hipMemcpyAsync(c.d.wall_id, wid.data(), sizeof(int32_t) * c.N, hipMemcpyHostToDevice,
                      c.stream);
   if (e == hipSuccess && c.Nw > 0)
     e = hipMemcpyAsync(c.d.wall_list, wl.data(), sizeof(int32_t) * c.Nw, hipMemcpyHostToDevice,
+                       c.stream);
+  if (e == hipSuccess && c.npw > 0)
+    e = hipMemcpyAsync(c.d.wpl, wp.data(), sizeof(int32_t) * wp.size(), hipMemcpyHostToDevice,
                        c.stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c.d.err, zeros, sizeof(zeros), hipMemcpyHostToDevice, c.stream);

@@ -22,6 +22,10 @@ namespace bgk {
 // otherwise runs 2-particle patches with 4 velocities per lane (256-lane
 // blocks), which fill ragged grids and small clouds better.
 constexpr int kPatchMax = 4;
+// Wall particles per wall patch: consecutive wall-list entries of one face
+// whose interpolation rows share most interior particles (3D).
+constexpr int kWallPatch = 4;
+inline int64_t wall_patches_max(int64_t N, int dim) { return N / kWallPatch + 2 * dim + 1; }
 inline int choose_patch(int dim, int precision, int NV, int Ni) {
   if (dim != 2 || precision != BGK_FP64) return 4;
   const int lanes = NV / 2;
@@ -59,6 +63,10 @@ struct Dev {
   int32_t* ucount;       // [npatch]
   int32_t* uj;           // [npatch][ucap]
   uint32_t* ue;          // [npatch][ucap] packed 8-bit slot of each patch particle
+  int32_t* wpl;          // [npw][kWallPatch] wall-list slots of each wall patch (-1: empty)
+  int32_t* wucount;      // [npw]
+  int32_t* wuj;          // [npw][kWallPatch*cap] union of the patch's wall rows
+  uint32_t* wue;         // [npw][kWallPatch*cap] packed 8-bit slot in each wall row
   double* jpart;         // [N]   per-particle terms of the objective
 };
 
@@ -115,6 +123,7 @@ struct Ctx {
   int device = 0;
   int N = 0, D = 0, NC = 0, NV = 0, cap = 0, DD = 0;
   int Ni = 0, Nw = 0, npatch = 0, ucap = 0, tp = 4;  // tp: particles per patch
+  int npw = 0, wucap = 0;   // wall patches (0: the wall condition runs per wall particle)
   int nca = 0, ncell = 0;
   double lid = 0.0;
   Dev d{};
@@ -151,6 +160,7 @@ hipError_t launch_wls(const Ctx& c, const double* x, const int32_t* cnt, const i
                       double* grad, double* ops, float* ops32, int32_t* degree);
 hipError_t launch_wall_stencil(const Ctx& c, const double* x);
 hipError_t launch_patches(const Ctx& c);
+hipError_t launch_wall_unions(const Ctx& c);
 
 hipError_t launch_transport(const Ctx& c, const void* f_in, void* f_out, const double* U);
 hipError_t launch_copy_wall_rows(const Ctx& c, const void* f_in, void* f_out);

@@ -227,8 +227,8 @@ struct ValueRowSm {
 
 // Value row at the point xq (one wave, all 64 lanes): the interior
 // particles within hb, the first of h, 1.5h, 2h holding at least d+2 of
-// them (the candidate cells within +-2 cells, interior ranges, scanned once
-// per radius tried), ascending in sm.srt[0..m); their degree-1
+// them (interior ranges of the candidate cells within +-1 cell for h, within
+// +-2 cells for the wider radii, scanned once per radius tried), ascending in sm.srt[0..m); their degree-1
 // least-squares value weights at xq (weights exp(-alpha r^2/hb^2)) are
 // value_weight(sm, e).  Returns m, or -1 (fewer than d+2 points or a
 // non-positive pivot: BGK_ESINGULAR) or -2 (more than cap points:
@@ -240,11 +240,18 @@ __device__ int value_row(const CloudView& a, const double* xq, ValueRowSm<D>& sm
   int cb[D];
 #pragma unroll
   for (int q = 0; q < D; ++q) cb[q] = cell_coord(xq[q], a.nca);
-  const int nr = cell_ranges<D, 2>(cb, a.nca, a.ncell, false, a.cstart, sm.rb, sm.rpre);
-  const int total = sm.rpre[nr];
+  // cells are at least h wide: the first radius needs the 3^D cells around
+  // xq, the wider ones the 5^D
+  int nr = cell_ranges<D, 1>(cb, a.nca, a.ncell, false, a.cstart, sm.rb, sm.rpre);
+  int total = sm.rpre[nr];
   const double mults[3] = {1.0, 1.5, 2.0};
   int m = 0;
   for (int t = 0; t < 3; ++t) {
+    if (t == 1) {
+      __syncthreads();
+      nr = cell_ranges<D, 2>(cb, a.nca, a.ncell, false, a.cstart, sm.rb, sm.rpre);
+      total = sm.rpre[nr];
+    }
     hb = mults[t] * a.h;
     const double hb2 = hb * hb;
     m = 0;

@@ -179,6 +179,13 @@ struct WallBcArgs {
   double* U;
   double* T;
   int32_t* err;
+  // wall patches (kernel instances with P > 1): slots of each patch, and the
+  // union of their interpolation rows
+  const int32_t* wpl;
+  const int32_t* wucount;
+  const int32_t* wuj;
+  const uint32_t* wue;
+  int wucap;
 };
 
 // Sum K doubles over a block of nw wavefronts in a fixed order (wavefront
@@ -237,33 +244,48 @@ __device__ __forceinline__ void store_vec(Real* __restrict__ p, const Real (&x)[
   }
 }
 
-// Diffuse reflection on wall particle b (S7; one block of up to 256 threads
-// per wall particle).  With the owner wall's inward normal s e_a, the
-// arriving velocities (s v_a <= 0) are exactly the half k_a < nv/2 (s > 0)
-// or k_a >= nv/2 (s < 0) of axis a (v_k is odd about the grid centre and nv
-// is even), and the emitted ones the other half.  Both halves are walked as
+// Diffuse reflection on wall particles (S7; one block of up to 256 threads
+// per wall particle, P = 1, or per wall patch of P wall particles of one
+// face, P > 1).  With the owner wall's inward normal s e_a, the arriving
+// velocities (s v_a <= 0) are exactly the half k_a < nv/2 (s > 0) or
+// k_a >= nv/2 (s < 0) of axis a (v_k is odd about the grid centre and nv is
+// even), and the emitted ones the other half.  Both halves are walked as
 // groups of R consecutive velocities along the fastest axis (R divides
 // nv/2), so every lane of a gather has work:
 //   arriving: f_b(v) = sum_e c0_e f_j(v) (rows four at a time), and the
 //     inflow sum_arriving (-v.n) f_b1;
 //   emitted:  f_b = rho_w M[1, U_w, T_w] (Chu: G1 and T_w G1 scaled by rho_w),
 //     rho_w = inflow / sum_emitted (v.n) M[1, U_w, T_w].
+// A wall patch walks the ascending union of its particles' rows once, each
+// row feeding every particle with its weight (0 where the row is not the
+// particle's): each particle's sum takes its own terms in its own row order
+// (adding exact zeros in between), so the result is the per-particle one
+// bit for bit, with each f_j row read once per patch.
 // The Maxwellian is a product of per-axis exponentials held in LDS, and the
 // emitted outflow sum factorises into per-axis sums.  The particle's moments
 // follow in two passes (U first, then the centred second moment).  A thread
 // re-reads only velocities it wrote itself.
-template <int D, int NC, typename Real, int R>
+template <int D, int NC, typename Real, int R, int P>
 __global__ __launch_bounds__(kThreads) void k_wall_bc(const WallBcArgs a) {
-  extern __shared__ double wtab[];  // v_k [nv], then exp(-(v_k - Uw_a)^2 / (2 T_w)) [D][nv]
-  __shared__ double sh[16 * (D + 1)];
+  // v_k [nv], exp(-(v_k - Uw_a)^2 / (2 T_w)) [D][nv]; wall patches then
+  // hold the union's weights [wucap][P] and rows [wucap]
+  extern __shared__ double wtab[];
+  __shared__ double sh[16 * P * (D + 1)];
   __shared__ double axsum[D];
   const int nv = a.nv, hv = nv / 2;
   double* vtab = wtab;
   double* etab = wtab + nv;
+  double* uw = etab + D * nv;
+  int32_t* ur = reinterpret_cast<int32_t*>(uw + (P > 1 ? a.wucap * P : 0));
   const int k = xcd_logical_block(blockIdx.x, gridDim.x);  // neighbouring walls share an L2
   const int nw = blockDim.x >> 6;
-  const int b = a.wall_list[k];
-  const int w = a.wall_id[b];
+  int kt[P], bt[P];  // wall-list slot and particle of each patch entry (-1: empty)
+#pragma unroll
+  for (int t = 0; t < P; ++t) {
+    kt[t] = P == 1 ? k : a.wpl[static_cast<size_t>(k) * P + t];
+    bt[t] = kt[t] >= 0 ? a.wall_list[kt[t]] : -1;
+  }
+  const int w = a.wall_id[bt[0]];  // entry 0 always holds a particle
   const int axis = (w - 1) / 2;
   const double sgn = ((w - 1) % 2 == 0) ? 1.0 : -1.0;
   const bool is_lid = (w == 2 * D);
@@ -275,6 +297,21 @@ __global__ __launch_bounds__(kThreads) void k_wall_bc(const WallBcArgs a) {
     if (ax == 0) vtab[kk] = v;
     const double dv = v - Uw[ax];
     etab[i] = exp(-(dv * dv) / (2.0 * Tw));
+  }
+  int nu = 0;
+  if (P > 1) {
+    nu = a.wucount[k];
+    const size_t ub = static_cast<size_t>(k) * a.wucap;
+    for (int u = threadIdx.x; u < nu; u += blockDim.x) {
+      const uint32_t pe = a.wue[ub + u];
+      ur[u] = a.wuj[ub + u];
+#pragma unroll
+      for (int t = 0; t < P; ++t) {
+        const int e = (pe >> (8 * t)) & 0xFF;
+        uw[u * P + t] = (kt[t] >= 0 && e != 0xFF)
+                            ? a.wc0[static_cast<size_t>(kt[t]) * a.cap + e] : 0.0;
+      }
+    }
   }
   __syncthreads();
   if (threadIdx.x < D) {
@@ -295,12 +332,13 @@ __global__ __launch_bounds__(kThreads) void k_wall_bc(const WallBcArgs a) {
   const double tp = 2.0 * kPi * Tw;
   const double norm = D == 3 ? 1.0 / (tp * sqrt(tp)) : 1.0 / tp;
 
-  const int m = a.wcnt[k];
+  int m[P];
+#pragma unroll
+  for (int t = 0; t < P; ++t) m[t] = kt[t] >= 0 ? a.wcnt[kt[t]] : 0;
   const int32_t* row = a.widx + static_cast<size_t>(k) * a.cap;
   const double* c0 = a.wc0 + static_cast<size_t>(k) * a.cap;
   const size_t NVs = a.NV, cs = static_cast<size_t>(a.N) * NVs;
   Real* f = static_cast<Real*>(a.f);
-  Real* fb = f + static_cast<size_t>(b) * NVs;
   const int G = a.NV / (2 * R);  // groups per half
   const int off_in = sgn > 0.0 ? 0 : hv, off_out = hv - off_in;
   // group g of the half whose axis-a indices start at offa: first velocity
@@ -321,136 +359,195 @@ __global__ __launch_bounds__(kThreads) void k_wall_bc(const WallBcArgs a) {
     return q;
   };
 
-  double inflow[1] = {0.0};
-  double sm[D + 1];
+  double inflow[P];
+  double sm[P * (D + 1)];
 #pragma unroll
-  for (int kk = 0; kk < D + 1; ++kk) sm[kk] = 0.0;
+  for (int t = 0; t < P; ++t) inflow[t] = 0.0;
+#pragma unroll
+  for (int kk = 0; kk < P * (D + 1); ++kk) sm[kk] = 0.0;
   for (int g = threadIdx.x; g < G; g += blockDim.x) {
     int kq[3] = {0, 0, 0};
     const int q0 = group_q(g, off_in, kq);
-    double s[NC][R];
+    double s[P][NC][R];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int t = 0; t < P; ++t)
 #pragma unroll
-      for (int r = 0; r < R; ++r) s[c][r] = 0.0;
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[t][c][r] = 0.0;
+    const int n = P == 1 ? m[0] : nu;
     int e = 0;
-    for (; e + 4 <= m; e += 4) {
+    for (; e + 4 <= n; e += 4) {
       Real x[4][NC][R];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 4; ++u) {
+        const int j = P == 1 ? row[e + u] : ur[e + u];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-          load_vec<Real, R>(f + c * cs + static_cast<size_t>(row[e + u]) * NVs + q0, x[u][c]);
+          load_vec<Real, R>(f + c * cs + static_cast<size_t>(j) * NVs + q0, x[u][c]);
+      }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const double wu = c0[e + u];
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+          const double wu = P == 1 ? c0[e + u] : uw[(e + u) * P + t];
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+              s[t][c][r] = s[t][c][r] + wu * static_cast<double>(x[u][c][r]);
+        }
+      }
+    }
+    for (; e < n; ++e) {
+      Real x[NC][R];
+      const int j = P == 1 ? row[e] : ur[e];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        load_vec<Real, R>(f + c * cs + static_cast<size_t>(j) * NVs + q0, x[c]);
+#pragma unroll
+      for (int t = 0; t < P; ++t) {
+        const double wu = P == 1 ? c0[e] : uw[e * P + t];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
-          for (int r = 0; r < R; ++r) s[c][r] = s[c][r] + wu * static_cast<double>(x[u][c][r]);
+          for (int r = 0; r < R; ++r) s[t][c][r] = s[t][c][r] + wu * static_cast<double>(x[c][r]);
       }
-    }
-    for (; e < m; ++e) {
-      Real x[NC][R];
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-        load_vec<Real, R>(f + c * cs + static_cast<size_t>(row[e]) * NVs + q0, x[c]);
-      const double wu = c0[e];
-#pragma unroll
-      for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int r = 0; r < R; ++r) s[c][r] = s[c][r] + wu * static_cast<double>(x[c][r]);
     }
     double v[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int ax = 1; ax < D; ++ax) v[ax] = vtab[kq[ax]];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      Real y[R];
+    for (int t = 0; t < P; ++t) {
+      if (bt[t] < 0) continue;
+      Real* fb = f + static_cast<size_t>(bt[t]) * NVs;
 #pragma unroll
-      for (int r = 0; r < R; ++r) y[r] = static_cast<Real>(s[c][r]);
-      store_vec<Real, R>(fb + c * cs + q0, y);
-      if (c == 0) {
+      for (int c = 0; c < NC; ++c) {
+        Real y[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          v[0] = vtab[kq[0] + r];
-          const double x0 = static_cast<double>(y[r]);
-          inflow[0] = inflow[0] + (-sgn * v[axis]) * x0;
-          sm[0] = sm[0] + x0;
+        for (int r = 0; r < R; ++r) y[r] = static_cast<Real>(s[t][c][r]);
+        store_vec<Real, R>(fb + c * cs + q0, y);
+        if (c == 0) {
 #pragma unroll
-          for (int ax = 0; ax < D; ++ax) sm[1 + ax] = sm[1 + ax] + v[ax] * x0;
+          for (int r = 0; r < R; ++r) {
+            v[0] = vtab[kq[0] + r];
+            const double x0 = static_cast<double>(y[r]);
+            inflow[t] = inflow[t] + (-sgn * v[axis]) * x0;
+            sm[t * (D + 1)] = sm[t * (D + 1)] + x0;
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax)
+              sm[t * (D + 1) + 1 + ax] = sm[t * (D + 1) + 1 + ax] + v[ax] * x0;
+          }
         }
       }
     }
   }
-  block_sum_n<1>(inflow, sh, nw);  // its barriers also publish axsum
+  block_sum_n<P>(inflow, sh, nw);  // its barriers also publish axsum
   double outflow = norm;
 #pragma unroll
   for (int ax = 0; ax < D; ++ax) outflow = outflow * axsum[ax];
-  const double rho_w = inflow[0] / outflow;
-  const double cw = rho_w * norm;
+  double cw[P];
+#pragma unroll
+  for (int t = 0; t < P; ++t) {
+    const double rho_w = inflow[t] / outflow;
+    cw[t] = rho_w * norm;
+  }
   for (int g = threadIdx.x; g < G; g += blockDim.x) {
     int kq[3] = {0, 0, 0};
     const int q0 = group_q(g, off_out, kq);
-    double efix = cw;
     double v[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int ax = 1; ax < D; ++ax) {
-      efix = efix * etab[ax * nv + kq[ax]];
-      v[ax] = vtab[kq[ax]];
+    for (int ax = 1; ax < D; ++ax) v[ax] = vtab[kq[ax]];
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      if (bt[t] < 0) continue;
+      double efix = cw[t];
+#pragma unroll
+      for (int ax = 1; ax < D; ++ax) efix = efix * etab[ax * nv + kq[ax]];
+      Real y[NC][R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double g1 = efix * etab[kq[0] + r];
+        y[0][r] = static_cast<Real>(g1);
+        if (NC == 2) y[NC - 1][r] = static_cast<Real>(Tw * g1);
+        v[0] = vtab[kq[0] + r];
+        const double x0 = static_cast<double>(y[0][r]);
+        sm[t * (D + 1)] = sm[t * (D + 1)] + x0;
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax)
+          sm[t * (D + 1) + 1 + ax] = sm[t * (D + 1) + 1 + ax] + v[ax] * x0;
+      }
+      Real* fb = f + static_cast<size_t>(bt[t]) * NVs;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) store_vec<Real, R>(fb + c * cs + q0, y[c]);
     }
-    Real y[NC][R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const double g1 = efix * etab[kq[0] + r];
-      y[0][r] = static_cast<Real>(g1);
-      if (NC == 2) y[NC - 1][r] = static_cast<Real>(Tw * g1);
-      v[0] = vtab[kq[0] + r];
-      const double x0 = static_cast<double>(y[0][r]);
-      sm[0] = sm[0] + x0;
-#pragma unroll
-      for (int ax = 0; ax < D; ++ax) sm[1 + ax] = sm[1 + ax] + v[ax] * x0;
-    }
-#pragma unroll
-    for (int c = 0; c < NC; ++c) store_vec<Real, R>(fb + c * cs + q0, y[c]);
   }
-  block_sum_n<D + 1>(sm, sh, nw);
-  const double s0 = sm[0];
-  double U[3] = {0.0, 0.0, 0.0};
+  block_sum_n<P * (D + 1)>(sm, sh, nw);
+  double U[P][3];
 #pragma unroll
-  for (int ax = 0; ax < D; ++ax) U[ax] = sm[1 + ax] / s0;
-  double e2[1] = {0.0};
+  for (int t = 0; t < P; ++t) {
+    U[t][0] = U[t][1] = U[t][2] = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) U[t][ax] = sm[t * (D + 1) + 1 + ax] / sm[t * (D + 1)];
+  }
+  double e2[P];
+#pragma unroll
+  for (int t = 0; t < P; ++t) e2[t] = 0.0;
   for (int half = 0; half < 2; ++half) {
     for (int g = threadIdx.x; g < G; g += blockDim.x) {
       int kq[3] = {0, 0, 0};
       const int q0 = group_q(g, half == 0 ? off_in : off_out, kq);
-      double wfix = 0.0;
 #pragma unroll
-      for (int ax = 1; ax < D; ++ax) {
-        const double wk = vtab[kq[ax]] - U[ax];
-        wfix = wfix + wk * wk;
-      }
-      Real x[NC][R];
+      for (int t = 0; t < P; ++t) {
+        if (bt[t] < 0) continue;
+        double wfix = 0.0;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) load_vec<Real, R>(fb + c * cs + q0, x[c]);
+        for (int ax = 1; ax < D; ++ax) {
+          const double wk = vtab[kq[ax]] - U[t][ax];
+          wfix = wfix + wk * wk;
+        }
+        const Real* fb = f + static_cast<size_t>(bt[t]) * NVs;
+        Real x[NC][R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const double w0 = vtab[kq[0] + r] - U[0];
-        e2[0] = e2[0] + (w0 * w0 + wfix) * static_cast<double>(x[0][r]);
-        if (NC == 2) e2[0] = e2[0] + static_cast<double>(x[NC - 1][r]);
+        for (int c = 0; c < NC; ++c) load_vec<Real, R>(fb + c * cs + q0, x[c]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double w0 = vtab[kq[0] + r] - U[t][0];
+          e2[t] = e2[t] + (w0 * w0 + wfix) * static_cast<double>(x[0][r]);
+          if (NC == 2) e2[t] = e2[t] + static_cast<double>(x[NC - 1][r]);
+        }
       }
     }
   }
-  block_sum_n<1>(e2, sh, nw);
+  block_sum_n<P>(e2, sh, nw);
   if (threadIdx.x == 0) {
-    const double rho = a.omega * s0;
-    const double T = e2[0] / (3.0 * s0);
-    a.rho[b] = rho;
-    a.T[b] = T;
 #pragma unroll
-    for (int ax = 0; ax < D; ++ax) a.U[static_cast<size_t>(ax) * a.N + b] = U[ax];
-    if (!(rho > 0.0) || !(T > 0.0) || m == 0) raise_error(a.err, BGK_ENONPHYS);
+    for (int t = 0; t < P; ++t) {
+      if (bt[t] < 0) continue;
+      const int b = bt[t];
+      const double s0 = sm[t * (D + 1)];
+      const double rho = a.omega * s0;
+      const double T = e2[t] / (3.0 * s0);
+      a.rho[b] = rho;
+      a.T[b] = T;
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) a.U[static_cast<size_t>(ax) * a.N + b] = U[t][ax];
+      if (!(rho > 0.0) || !(T > 0.0) || m[t] == 0) raise_error(a.err, BGK_ENONPHYS);
+    }
   }
+}
+
+template <int D, int NC, typename Real, int R>
+static void wall_bc_r(const Ctx& c, const WallBcArgs& a, dim3 t, size_t lds) {
+  if constexpr (D == 3) {  // wall patches are formed in 3D only
+    if (c.npw > 0) {
+      const size_t ul = static_cast<size_t>(c.wucap) * (kWallPatch * sizeof(double) + sizeof(int32_t));
+      hipLaunchKernelGGL((k_wall_bc<D, NC, Real, R, kWallPatch>), dim3(c.npw), t, lds + ul,
+                         c.stream, a);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_wall_bc<D, NC, Real, R, 1>), dim3(c.Nw), t, lds, c.stream, a);
 }
 
 template <int D, int NC, typename Real>
@@ -458,18 +555,19 @@ static void wall_bc_t(const Ctx& c, const WallBcArgs& a) {
   const int hv = c.cfg.nv / 2;  // nv is even
   const int R = hv % 4 == 0 ? 4 : (hv % 2 == 0 ? 2 : 1);
   const int groups = c.NV / (2 * R);
-  dim3 g(c.Nw), t(std::min(kThreads, (groups + 63) / 64 * 64));
+  const dim3 t(std::min(kThreads, (groups + 63) / 64 * 64));
   const size_t lds = static_cast<size_t>(D + 1) * c.cfg.nv * sizeof(double);
-  if (R == 4) hipLaunchKernelGGL((k_wall_bc<D, NC, Real, 4>), g, t, lds, c.stream, a);
-  else if (R == 2) hipLaunchKernelGGL((k_wall_bc<D, NC, Real, 2>), g, t, lds, c.stream, a);
-  else hipLaunchKernelGGL((k_wall_bc<D, NC, Real, 1>), g, t, lds, c.stream, a);
+  if (R == 4) wall_bc_r<D, NC, Real, 4>(c, a, t, lds);
+  else if (R == 2) wall_bc_r<D, NC, Real, 2>(c, a, t, lds);
+  else wall_bc_r<D, NC, Real, 1>(c, a, t, lds);
 }
 
 hipError_t launch_wall_bc(const Ctx& c, void* f, double* rho, double* U, double* T) {
   if (c.Nw == 0) return hipSuccess;
   WallBcArgs a{c.N,          c.NV,      c.cfg.nv,      c.cap,  c.Nw,   c.D,    c.cfg.vmax,
                omega_of(c.cfg), c.lid,  c.cfg.wall_T,  c.d.wall_list, c.d.wall_id, c.d.wcnt,
-               c.d.widx,     c.d.wc0,   f,             rho,    U,      T,      c.d.err};
+               c.d.widx,     c.d.wc0,   f,             rho,    U,      T,      c.d.err,
+               c.d.wpl,      c.d.wucount, c.d.wuj,     c.d.wue, c.wucap};
   const bool f64 = c.cfg.precision == BGK_FP64;
   if (c.D == 2) {
     if (f64) wall_bc_t<2, 2, double>(c, a); else wall_bc_t<2, 2, float>(c, a);

@@ -619,7 +619,8 @@ hipError_t launch_wall_stencil(const Ctx& c, const double* x) {
     hipLaunchKernelGGL(k_wall_stencil<2>, dim3(c.Nw), dim3(kWave), 0, c.stream, a);
   else
     hipLaunchKernelGGL(k_wall_stencil<3>, dim3(c.Nw), dim3(kWave), 0, c.stream, a);
-  return hipGetLastError();
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? launch_wall_unions(c) : e;
 }
 
 // Expand the compact wall rows to per-particle output arrays.
@@ -660,7 +661,9 @@ hipError_t launch_scatter_wall_rows(const Ctx& c, int32_t* cnt_out, int32_t* idx
 // (0xFF: j is not a neighbour of slot t).
 // One wave per patch: the slot rows are merged by rank (position of each
 // entry = entries smaller than it in every row, ties ordered by slot),
-// equal indices are grouped, and each group becomes one union entry.
+// equal indices are grouped, and each group becomes one union entry.  The
+// same kernel merges the interpolation rows of wall patches (rows indexed
+// by wall-list slot, no self entry to drop: drop_self = 0).
 __device__ __forceinline__ int lower_bound_i(const int32_t* v, int n, int x) {
   int lo = 0, hi = n;
   while (lo < hi) {
@@ -670,7 +673,7 @@ __device__ __forceinline__ int lower_bound_i(const int32_t* v, int n, int x) {
   return lo;
 }
 
-__global__ __launch_bounds__(64) void k_patches(int Ni, int P, int cap, int ucap,
+__global__ __launch_bounds__(64) void k_patches(int Ni, int P, int cap, int ucap, int drop_self,
                                                 const int32_t* __restrict__ plist,
                                                 const int32_t* __restrict__ cnt,
                                                 const int32_t* __restrict__ idx,
@@ -696,7 +699,8 @@ __global__ __launch_bounds__(64) void k_patches(int Ni, int P, int cap, int ucap
   // find it in all rows at once, then copy the rows without it
   for (int w = lane; w < P * cap; w += kWave) {
     const int t = w / cap, e = w - t * cap;
-    if (e < sm_[t] && idx[static_cast<int64_t>(spt[t]) * cap + e] == spt[t]) sself[t] = e + 1;
+    if (drop_self && e < sm_[t] && idx[static_cast<int64_t>(spt[t]) * cap + e] == spt[t])
+      sself[t] = e + 1;
   }
   __syncthreads();
   for (int w = lane; w < P * cap; w += kWave) {
@@ -759,7 +763,16 @@ hipError_t launch_patches(const Ctx& c) {
   if (c.npatch == 0) return hipSuccess;
   const size_t sm = static_cast<size_t>(4) * c.tp * c.cap * sizeof(int32_t);
   hipLaunchKernelGGL(k_patches, dim3(c.npatch), dim3(kWave), sm, c.stream, c.Ni, c.tp, c.cap, c.ucap,
-                     c.d.cperm, c.d.ncnt, c.d.nidx, c.d.ucount, c.d.uj, c.d.ue, c.d.err);
+                     1, c.d.cperm, c.d.ncnt, c.d.nidx, c.d.ucount, c.d.uj, c.d.ue, c.d.err);
+  return hipGetLastError();
+}
+
+hipError_t launch_wall_unions(const Ctx& c) {
+  if (c.npw == 0) return hipSuccess;
+  const size_t sm = static_cast<size_t>(4) * kWallPatch * c.cap * sizeof(int32_t);
+  hipLaunchKernelGGL(k_patches, dim3(c.npw), dim3(kWave), sm, c.stream, c.npw * kWallPatch,
+                     kWallPatch, c.cap, c.wucap, 0, c.d.wpl, c.d.wcnt, c.d.widx, c.d.wucount,
+                     c.d.wuj, c.d.wue, c.d.err);
   return hipGetLastError();
 }
 
