@@ -132,6 +132,9 @@ size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj, Pm*
     a.larr = take(F * fs);
     a.lidpart = reinterpret_cast<double*>(take(N * 8));
     a.gpart = reinterpret_cast<double*>(take(adj_tiles(cfg) * D * N * 8));
+    a.ucount = reinterpret_cast<int32_t*>(take((N + 1) / 2 * 4));
+    a.uj = reinterpret_cast<int32_t*>(take((N + 1) / 2 * kAdjPatch * cap * 4));
+    a.ue = reinterpret_cast<uint32_t*>(take((N + 1) / 2 * kAdjPatch * cap * 4));
     if (adj) *adj = a;
   }
   if (cfg.flags & BGK_FLAG_PARTICLES) {

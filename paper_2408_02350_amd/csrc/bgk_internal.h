@@ -85,6 +85,9 @@ struct Adj {
   void* larr;         // [Nw][n_c][N_v] adjoint reaching the interpolated wall values
   double* lidpart;    // [max(Nw,1)]
   double* gpart;      // [tiles][d][N] per-tile parts of lam_U (reverse transport)
+  int32_t* ucount;    // [(N+1)/2]   unions of the reverse transport's 2-particle patches
+  int32_t* uj;        // [(N+1)/2][2*cap]
+  uint32_t* ue;       // [(N+1)/2][2*cap]
 };
 
 // Workspace of the particle management (BGK_FLAG_PARTICLES).
@@ -161,6 +164,12 @@ hipError_t launch_wls(const Ctx& c, const double* x, const int32_t* cnt, const i
 hipError_t launch_wall_stencil(const Ctx& c, const double* x);
 hipError_t launch_patches(const Ctx& c);
 hipError_t launch_wall_unions(const Ctx& c);
+// sorted unions of the rows of patches of P entries of plist (n entries,
+// -1 = empty); one wavefront per patch
+hipError_t launch_unions(const Ctx& c, int P, int n, const int32_t* plist, const int32_t* cnt,
+                         const int32_t* idx, int drop_self, int ucap, int32_t* ucount,
+                         int32_t* uj, uint32_t* ue);
+constexpr int kAdjPatch = 2;  // interior particles per patch of the reverse transport
 
 hipError_t launch_transport(const Ctx& c, const void* f_in, void* f_out, const double* U);
 hipError_t launch_copy_wall_rows(const Ctx& c, const void* f_in, void* f_out);

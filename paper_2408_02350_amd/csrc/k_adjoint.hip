@@ -136,6 +136,13 @@ struct AdjArgs {  // Real: storage of f-sized arrays and operators (FP64 or FP32
   double* lidpart;         // [Nw] dJ/dlid contributions
   double* gpart;           // [tiles][D][N] per-tile parts of lam_U
   int tiles;
+  // reverse transport over the forward's patch unions: the per-particle
+  // kernel then runs over jlist (the wall particles) only
+  const int32_t* jlist;    // [njl] particles of the per-particle kernel (null: all N)
+  const int32_t* ucount;   // [npatch]
+  const int32_t* uj;       // [npatch][ucap]
+  const uint32_t* ue;      // [npatch][ucap]
+  int ucap;
 };
 
 // ------------------------------------------------------------ S7 adjoint
@@ -342,7 +349,8 @@ __global__ __launch_bounds__(64) void k_adj_transport(const AdjArgs<Real> a) {
   constexpr int DD = D * D, REC = DD + 2 * D;  // a (d*d), a.U (d), a[fast]*dv (d)
   __shared__ double rown[kAdjChunk][REC], rtr[kAdjChunk][REC];
   __shared__ int32_t ri[kAdjChunk], rfl[kAdjChunk];
-  const int j = blockIdx.x / a.tiles, tile = blockIdx.x - j * a.tiles;
+  const int jb = blockIdx.x / a.tiles, tile = blockIdx.x - jb * a.tiles;
+  const int j = a.jlist ? a.jlist[jb] : jb;
   const int tid = threadIdx.x, nt = blockDim.x;
   const bool inner = a.wall_id[j] == 0;
   const size_t NVs = a.NV, cs = static_cast<size_t>(a.N) * NVs;
@@ -546,6 +554,244 @@ __global__ __launch_bounds__(64) void k_adj_transport(const AdjArgs<Real> a) {
   }
 }
 
+// The same reverse transport for the interior particles, taken P at a time
+// in cell order (P = kAdjPatch; the unions are merged once per frozen
+// cloud): one wavefront per (patch, tile) walks the sorted union of the
+// patch's neighbour lists once and loads each neighbour's f^n and lam_ft
+// rows once for all P particles (four particles per patch were slower: the
+// register footprint halves the waves per SIMD).
+// The own and transposed edge records of every (union entry, particle) are
+// staged in LDS per chunk; each particle takes its own edges in its row
+// order, so its sums are those of the per-particle kernel bit for bit.
+constexpr int kAdjUChunk = 16;
+
+template <int D, int NC, typename Real, int R, int P>
+__global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> a) {
+  constexpr int DD = D * D, REC = DD + 2 * D, CH = kAdjUChunk;
+  __shared__ double rown[CH][P][REC], rtr[CH][P][REC];
+  __shared__ int32_t ri[CH], rfl[CH][P];
+  const int pb = blockIdx.x / a.tiles, tile = blockIdx.x - pb * a.tiles;
+  const int tid = threadIdx.x;
+  const size_t NVs = a.NV, cs = static_cast<size_t>(a.N) * NVs;
+  const double dv = 2.0 * a.vmax / static_cast<double>(a.nv - 1);
+  int jt[P];
+#pragma unroll
+  for (int t = 0; t < P; ++t) {
+    const int gp = pb * P + t;
+    jt[t] = gp < a.Ni ? a.plist[gp] : -1;
+  }
+  const int nu = a.ucount[pb];
+  const size_t ub = static_cast<size_t>(pb) * a.ucap;
+  double gU[P][3];
+#pragma unroll
+  for (int t = 0; t < P; ++t) gU[t][0] = gU[t][1] = gU[t][2] = 0.0;
+  const int ngroups = a.NV / R;
+  const int g = tile * 64 + tid;
+  const bool on = g < ngroups;
+  const int q0 = on ? g * R : 0;
+  double v0[D];
+  {
+    int q = q0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      v0[k] = vnode(q % a.nv, a.nv, a.vmax);
+      q /= a.nv;
+    }
+  }
+  double lf[P][R][NC], lj[P][R][NC], fj[P][R][NC], csum[P][R];
+#pragma unroll
+  for (int t = 0; t < P; ++t) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double t1[R], t2[R];
+      if (jt[t] >= 0) {
+        load_rr<Real, R>(a.lam_ft + c * cs + static_cast<size_t>(jt[t]) * NVs + q0, t1);
+        load_rr<Real, R>(a.f_n + c * cs + static_cast<size_t>(jt[t]) * NVs + q0, t2);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) t1[r] = t2[r] = 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        lf[t][r][c] = 0.0;
+        lj[t][r][c] = t1[r];
+        fj[t][r][c] = t2[r];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) csum[t][r] = 0.0;
+  }
+
+  for (int c0 = 0; c0 < nu; c0 += CH) {
+    const int cn = min(CH, nu - c0);
+    __syncthreads();
+    for (int x = tid; x < cn * P; x += 64) {
+      const int w = x / P, t = x - w * P;
+      const size_t u = ub + c0 + w;
+      const int i = a.uj[u];
+      const int e = (a.ue[u] >> (8 * t)) & 0xFF;
+      if (t == 0) ri[w] = i;
+      int fl = 0;
+      if (e != 0xFF) {
+        // slot t's particle; the union holds no self entry
+        const int j = a.plist[pb * P + t];
+        const int64_t rj = static_cast<int64_t>(j) * a.cap + e;
+        const int te = a.tidx[rj];
+        fl = 1 | (te >= 0 ? 2 : 0);
+        const Real* o = a.ops + rj * DD;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          double b = 0.0;
+#pragma unroll
+          for (int mm = 0; mm < D; ++mm) {
+            const double xo = static_cast<double>(o[k * D + mm]);
+            rown[w][t][k * D + mm] = xo;
+            b = b + xo * a.U_n[static_cast<size_t>(mm) * a.N + j];
+          }
+          rown[w][t][DD + k] = b;
+          rown[w][t][DD + D + k] = static_cast<double>(o[k * D]) * dv;
+        }
+        if (te >= 0) {
+          const Real* ot = a.ops + (static_cast<int64_t>(i) * a.cap + te) * DD;
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            double b = 0.0;
+#pragma unroll
+            for (int mm = 0; mm < D; ++mm) {
+              const double xo = static_cast<double>(ot[k * D + mm]);
+              rtr[w][t][k * D + mm] = xo;
+              b = b + xo * a.U_n[static_cast<size_t>(mm) * a.N + i];
+            }
+            rtr[w][t][DD + k] = b;
+            rtr[w][t][DD + D + k] = static_cast<double>(ot[k * D]) * dv;
+          }
+        }
+      }
+      rfl[w][t] = fl;
+    }
+    __syncthreads();
+    // rows of union entry w: f^n_i and lam_ft_i
+    double fa[R][NC], la[R][NC], fb[R][NC], lb[R][NC];
+    auto load_entry = [&](int w, double (&fi)[R][NC], double (&li)[R][NC]) {
+      const int i = ri[w];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        double t1[R], t2[R];
+        load_rr<Real, R>(a.f_n + c * cs + static_cast<size_t>(i) * NVs + q0, t1);
+        load_rr<Real, R>(a.lam_ft + c * cs + static_cast<size_t>(i) * NVs + q0, t2);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          fi[r][c] = t1[r];
+          li[r][c] = t2[r];
+        }
+      }
+      asm volatile("" ::: "memory");
+    };
+    auto entry = [&](int w, const double (&fi)[R][NC], const double (&li)[R][NC]) {
+#pragma unroll
+      for (int t = 0; t < P; ++t) {
+        const int fl = rfl[w][t];
+        if (fl & 1) {
+          const double* rc = rown[w][t];
+          double p[D], S[D];
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            double s1 = -rc[DD + k];
+#pragma unroll
+            for (int mm = 0; mm < D; ++mm) s1 = s1 + rc[k * D + mm] * v0[mm];
+            p[k] = s1;
+            S[k] = 0.0;
+          }
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if (r > 0) {
+#pragma unroll
+              for (int k = 0; k < D; ++k) p[k] = p[k] + rc[DD + D + k];
+            }
+            double cm = fmin(p[0], 0.0);
+#pragma unroll
+            for (int k = 1; k < D; ++k) cm = cm + fmin(p[k], 0.0);
+            csum[t][r] = csum[t][r] + 2.0 * cm;
+            double sdf = 0.0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sdf = sdf + lj[t][r][c] * (fi[r][c] - fj[t][r][c]);
+#pragma unroll
+            for (int k = 0; k < D; ++k) S[k] = S[k] + (p[k] < 0.0 ? sdf : 0.0);
+          }
+          if (on) {
+#pragma unroll
+            for (int mm = 0; mm < D; ++mm) {
+              double tt = 0.0;
+#pragma unroll
+              for (int k = 0; k < D; ++k) tt = tt + rc[k * D + mm] * S[k];
+              gU[t][mm] = gU[t][mm] - 2.0 * tt;
+            }
+          }
+        }
+        if (fl & 2) {
+          const double* rc = rtr[w][t];
+          double p[D];
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            double s1 = -rc[DD + k];
+#pragma unroll
+            for (int mm = 0; mm < D; ++mm) s1 = s1 + rc[k * D + mm] * v0[mm];
+            p[k] = s1;
+          }
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if (r > 0) {
+#pragma unroll
+              for (int k = 0; k < D; ++k) p[k] = p[k] + rc[DD + D + k];
+            }
+            double cm = fmin(p[0], 0.0);
+#pragma unroll
+            for (int k = 1; k < D; ++k) cm = cm + fmin(p[k], 0.0);
+            const double dc = a.dt * (2.0 * cm);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) lf[t][r][c] = lf[t][r][c] - dc * li[r][c];
+          }
+        }
+      }
+    };
+    load_entry(0, fa, la);
+    for (int w = 0; w < cn; w += 2) {
+      if (w + 1 < cn) load_entry(w + 1, fb, lb);
+      entry(w, fa, la);
+      if (w + 1 < cn) {
+        if (w + 2 < cn) load_entry(w + 2, fa, la);
+        entry(w + 1, fb, lb);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < P; ++t) {
+    if (jt[t] < 0) continue;
+    if (on) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        Real out[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          out[r] = static_cast<Real>(lf[t][r][c] + lj[t][r][c] * (1.0 + a.dt * csum[t][r]));
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          a.lam_f[c * cs + static_cast<size_t>(jt[t]) * NVs + q0 + r] = out[r];
+      }
+    }
+#pragma unroll
+    for (int mm = 0; mm < D; ++mm) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) gU[t][mm] += __shfl_xor(gU[t][mm], o, 64);
+    }
+    if (tid == 0) {
+#pragma unroll
+      for (int mm = 0; mm < D; ++mm)
+        a.gpart[(static_cast<size_t>(tile) * D + mm) * a.N + jt[t]] = gU[t][mm];
+    }
+  }
+}
+
 // lam_U_j = -dt * (sum over the tiles of j, in tile order)  (interior j)
 __global__ void k_adj_sum_tiles(int N, int D, int tiles, double dt,
                                 const int32_t* __restrict__ wall_id,
@@ -692,7 +938,10 @@ hipError_t launch_adjoint_transposes(const Ctx& c) {
                        c.d.widx, j.wtcursor, j.wt);
   hipLaunchKernelGGL(k_wt_sort, dim3((c.N + 127) / 128), dim3(128), 0, c.stream, c.N, j.wtstart,
                      j.wt);
-  return hipGetLastError();
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_unions(c, kAdjPatch, c.Ni, c.d.cperm, c.d.ncnt, c.d.nidx, 1, kAdjPatch * c.cap,
+                       j.ucount, j.uj, j.ue);
 }
 
 template <typename Real>
@@ -711,22 +960,32 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
                   static_cast<const Real*>(j.ft), static_cast<const Real*>(j.f1), j.rho1, j.U1,
                   j.T1,       lam_f1,     lam_U1,     lam_rho1,    lam_T1,
                   static_cast<Real*>(j.larr), static_cast<Real*>(j.lam_ft), lam_f, lam_U,
-                  j.lidpart, j.gpart, static_cast<int>(adj_tiles(c.cfg))};
+                  j.lidpart, j.gpart, static_cast<int>(adj_tiles(c.cfg)),
+                  nullptr,    j.ucount,   j.uj,       j.ue,        kAdjPatch * c.cap};
   dim3 t(kThreads);
   const size_t lds = static_cast<size_t>(c.D + 1) * c.cfg.nv * sizeof(double);
-  // reverse transport: one wavefront per (particle, tile of 64 groups of 2
-  // velocities), then the tile parts of lam_U summed in tile order
-  const int64_t nblk = static_cast<int64_t>(c.N) * a.tiles;
-  if (nblk > INT32_MAX) return hipErrorInvalidValue;
-  const dim3 tg(static_cast<unsigned>(nblk)), tt(64);
+  // reverse transport: one wavefront per (patch of interior particles, tile
+  // of 64 groups of 2 velocities) and per (wall particle, tile), then the
+  // tile parts of lam_U summed in tile order
+  const int npa = (c.Ni + kAdjPatch - 1) / kAdjPatch;
+  const int64_t nbp = static_cast<int64_t>(npa) * a.tiles;
+  const int64_t nbw = static_cast<int64_t>(c.Nw) * a.tiles;
+  if (nbp > INT32_MAX || nbw > INT32_MAX) return hipErrorInvalidValue;
+  const dim3 tp(static_cast<unsigned>(nbp)), tw(static_cast<unsigned>(nbw)), tt(64);
+  AdjArgs<Real> aw = a;
+  aw.jlist = c.d.wall_list;
   if (c.D == 2) {
     if (c.Nw) hipLaunchKernelGGL((k_adj_wall<2, 2, Real>), dim3(c.Nw), t, 0, c.stream, a);
     if (c.Ni) hipLaunchKernelGGL((k_adj_collide<2, 2, Real>), dim3(c.Ni), t, lds, c.stream, a);
-    hipLaunchKernelGGL((k_adj_transport<2, 2, Real, 2>), tg, tt, 0, c.stream, a);
+    if (npa)
+      hipLaunchKernelGGL((k_adj_transport_patch<2, 2, Real, 2, kAdjPatch>), tp, tt, 0, c.stream, a);
+    if (c.Nw) hipLaunchKernelGGL((k_adj_transport<2, 2, Real, 2>), tw, tt, 0, c.stream, aw);
   } else {
     if (c.Nw) hipLaunchKernelGGL((k_adj_wall<3, 1, Real>), dim3(c.Nw), t, 0, c.stream, a);
     if (c.Ni) hipLaunchKernelGGL((k_adj_collide<3, 1, Real>), dim3(c.Ni), t, lds, c.stream, a);
-    hipLaunchKernelGGL((k_adj_transport<3, 1, Real, 2>), tg, tt, 0, c.stream, a);
+    if (npa)
+      hipLaunchKernelGGL((k_adj_transport_patch<3, 1, Real, 2, kAdjPatch>), tp, tt, 0, c.stream, a);
+    if (c.Nw) hipLaunchKernelGGL((k_adj_transport<3, 1, Real, 2>), tw, tt, 0, c.stream, aw);
   }
   const int64_t nu = static_cast<int64_t>(c.N) * c.D;
   hipLaunchKernelGGL(k_adj_sum_tiles, dim3(static_cast<unsigned>((nu + 255) / 256)), dim3(256), 0,

@@ -759,21 +759,25 @@ __global__ __launch_bounds__(64) void k_patches(int Ni, int P, int cap, int ucap
   if (lane == 0) ucount[p] = min(nu, ucap);
 }
 
-hipError_t launch_patches(const Ctx& c) {
-  if (c.npatch == 0) return hipSuccess;
-  const size_t sm = static_cast<size_t>(4) * c.tp * c.cap * sizeof(int32_t);
-  hipLaunchKernelGGL(k_patches, dim3(c.npatch), dim3(kWave), sm, c.stream, c.Ni, c.tp, c.cap, c.ucap,
-                     1, c.d.cperm, c.d.ncnt, c.d.nidx, c.d.ucount, c.d.uj, c.d.ue, c.d.err);
+hipError_t launch_unions(const Ctx& c, int P, int n, const int32_t* plist, const int32_t* cnt,
+                         const int32_t* idx, int drop_self, int ucap, int32_t* ucount,
+                         int32_t* uj, uint32_t* ue) {
+  if (n == 0) return hipSuccess;
+  if (P < 1 || P > kPatchMax || ucap < P * c.cap) return hipErrorInvalidValue;
+  const size_t sm = static_cast<size_t>(4) * P * c.cap * sizeof(int32_t);
+  hipLaunchKernelGGL(k_patches, dim3((n + P - 1) / P), dim3(kWave), sm, c.stream, n, P, c.cap,
+                     ucap, drop_self, plist, cnt, idx, ucount, uj, ue, c.d.err);
   return hipGetLastError();
 }
 
+hipError_t launch_patches(const Ctx& c) {
+  return launch_unions(c, c.tp, c.Ni, c.d.cperm, c.d.ncnt, c.d.nidx, 1, c.ucap, c.d.ucount,
+                       c.d.uj, c.d.ue);
+}
+
 hipError_t launch_wall_unions(const Ctx& c) {
-  if (c.npw == 0) return hipSuccess;
-  const size_t sm = static_cast<size_t>(4) * kWallPatch * c.cap * sizeof(int32_t);
-  hipLaunchKernelGGL(k_patches, dim3(c.npw), dim3(kWave), sm, c.stream, c.npw * kWallPatch,
-                     kWallPatch, c.cap, c.wucap, 0, c.d.wpl, c.d.wcnt, c.d.widx, c.d.wucount,
-                     c.d.wuj, c.d.wue, c.d.err);
-  return hipGetLastError();
+  return launch_unions(c, kWallPatch, c.npw * kWallPatch, c.d.wpl, c.d.wcnt, c.d.widx, 0,
+                       c.wucap, c.d.wucount, c.d.wuj, c.d.wue);
 }
 
 }  // namespace bgk
