@@ -349,7 +349,10 @@ __global__ __launch_bounds__(64) void k_adj_transport(const AdjArgs<Real> a) {
   constexpr int DD = D * D, REC = DD + 2 * D;  // a (d*d), a.U (d), a[fast]*dv (d)
   __shared__ double rown[kAdjChunk][REC], rtr[kAdjChunk][REC];
   __shared__ int32_t ri[kAdjChunk], rfl[kAdjChunk];
-  const int jb = blockIdx.x / a.tiles, tile = blockIdx.x - jb * a.tiles;
+  // tile-major logical order, each XCD on one contiguous range: the
+  // neighbouring particles one XCD runs together read the same row slices
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x), nj = gridDim.x / a.tiles;
+  const int tile = lb / nj, jb = lb - tile * nj;
   const int j = a.jlist ? a.jlist[jb] : jb;
   const int tid = threadIdx.x, nt = blockDim.x;
   const bool inner = a.wall_id[j] == 0;
@@ -570,7 +573,9 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
   constexpr int DD = D * D, REC = DD + 2 * D, CH = kAdjUChunk;
   __shared__ double rown[CH][P][REC], rtr[CH][P][REC];
   __shared__ int32_t ri[CH], rfl[CH][P];
-  const int pb = blockIdx.x / a.tiles, tile = blockIdx.x - pb * a.tiles;
+  // tile-major logical order, each XCD on one contiguous range of patches
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x), np = gridDim.x / a.tiles;
+  const int tile = lb / np, pb = lb - tile * np;
   const int tid = threadIdx.x;
   const size_t NVs = a.NV, cs = static_cast<size_t>(a.N) * NVs;
   const double dv = 2.0 * a.vmax / static_cast<double>(a.nv - 1);
