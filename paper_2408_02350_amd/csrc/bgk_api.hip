@@ -545,10 +545,14 @@ int bgk_adjoint_step(bgk_ctx* ctx, const void* f_n, const double* U_n, const dou
   }
   // recompute S4-S7 from (f_n, U_n), keeping f-tilde and the new moments
   const bgk::Adj& a = c.adj;
-  // f-tilde by the fused kernel without its relaxation (or the generic one)
-  e = bgk::use_fused(c) ? bgk::launch_fused(c, f_n, a.ft, U_n, nullptr, nullptr, nullptr, false)
-                        : bgk::launch_transport(c, f_n, a.ft, U_n);
-  if (e == hipSuccess) e = bgk::launch_collide(c, a.ft, a.f1, a.rho1, a.U1, a.T1);
+  // the fused kernel relaxes and keeps a copy of f-tilde (the generic path
+  // transports, then relaxes)
+  if (bgk::use_fused(c)) {
+    e = bgk::launch_fused(c, f_n, a.f1, U_n, a.rho1, a.U1, a.T1, true, a.ft);
+  } else {
+    e = bgk::launch_transport(c, f_n, a.ft, U_n);
+    if (e == hipSuccess) e = bgk::launch_collide(c, a.ft, a.f1, a.rho1, a.U1, a.T1);
+  }
   if (e == hipSuccess) e = bgk::launch_wall_bc(c, a.f1, a.rho1, a.U1, a.T1);
   if (e == hipSuccess)
     e = bgk::launch_adjoint_step(c, f_n, U_n, lam_f1, lam_U1, lam_rho1, lam_T1, lam_f, lam_U,

@@ -174,10 +174,13 @@ constexpr int kAdjPatch = 2;  // interior particles per patch of the reverse tra
 hipError_t launch_transport(const Ctx& c, const void* f_in, void* f_out, const double* U);
 hipError_t launch_copy_wall_rows(const Ctx& c, const void* f_in, void* f_out);
 // Fused S4-S6 (or S4 alone with fuse = false) over patches x all velocities.
+// With fuse and f_tilde non-null, f-tilde's interior rows are also stored
+// there (the reverse step's recompute).
 bool fused_supported(const Ctx& c);
 bool use_fused(const Ctx& c);
 hipError_t launch_fused(const Ctx& c, const void* f_in, void* f_out, const double* U_in,
-                        double* rho, double* U_out, double* T, bool fuse);
+                        double* rho, double* U_out, double* T, bool fuse,
+                        void* f_tilde = nullptr);
 hipError_t launch_collide(const Ctx& c, const void* ft, void* fout, double* rho, double* U,
                           double* T);
 hipError_t launch_wall_bc(const Ctx& c, void* f, double* rho, double* U, double* T);

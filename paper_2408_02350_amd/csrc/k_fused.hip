@@ -71,6 +71,7 @@ struct FusedArgs {
   double* Unew;
   double* T;
   int32_t* err;
+  void* fto;         // fused: f-tilde's interior rows as well (may be null)
 };
 
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
@@ -566,6 +567,19 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
         }
     return;
   } else {
+    if (a.fto != nullptr) {
+      Real* __restrict__ fto = static_cast<Real*>(a.fto);
+#pragma unroll
+      for (int t = 0; t < TP; ++t)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          if (pt[t] >= 0 && lane_on) {
+            Real tmp[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) tmp[r] = ft[t][r][c];
+            store_r<Real, R>(fto + c * cs + static_cast<size_t>(pt[t]) * NVs + q0, tmp);
+          }
+    }
     const int lane = tid & 63, wid = tid >> 6, nw = nthreads >> 6;
     // ---- S5 pass 1 (FP64): s0 = sum f1, s1 = sum v f1
     double sm[KP];
@@ -810,7 +824,7 @@ static double omega_fused(const bgk_config& cfg) {
 }
 
 hipError_t launch_fused(const Ctx& c, const void* f_in, void* f_out, const double* U_in,
-                        double* rho, double* U_out, double* T, bool fuse) {
+                        double* rho, double* U_out, double* T, bool fuse, void* f_tilde) {
   if (c.npatch == 0) return hipSuccess;
   const FusedPlan p = plan_fused(c);
   if (p.R == 0) return hipErrorInvalidValue;
@@ -819,11 +833,16 @@ hipError_t launch_fused(const Ctx& c, const void* f_in, void* f_out, const doubl
               f_in, f_out, U_in,
               c.cfg.precision == BGK_FP64 ? static_cast<const void*>(c.d.ops64)
                                           : static_cast<const void*>(c.d.ops32),
-              c.d.cperm, c.d.ucount, c.d.uj, c.d.ue, rho, U_out, T, c.d.err};
+              c.d.cperm, c.d.ucount, c.d.uj, c.d.ue, rho, U_out, T, c.d.err,
+              fuse ? f_tilde : nullptr};
   if (fuse && p.tiles == 1) return launch_fused_any<true>(c, a, p);
+  // several velocity tiles: f-tilde first (into f_tilde if given, else
+  // f_out), then relaxed into f_out
+  void* ft = (fuse && f_tilde) ? f_tilde : f_out;
+  a.fo = ft;
+  a.fto = nullptr;
   hipError_t e = launch_fused_any<false>(c, a, p);
-  // several velocity tiles: f_out holds f-tilde; relax it in place
-  if (e == hipSuccess && fuse) e = launch_collide(c, f_out, f_out, rho, U_out, T);
+  if (e == hipSuccess && fuse) e = launch_collide(c, ft, f_out, rho, U_out, T);
   return e;
 }
 
