@@ -221,6 +221,8 @@ __global__ __launch_bounds__(kThreads) void k_adj_wall(const AdjArgs<Real> a) {
 // The velocity nodes and the per-axis factors exp(-(v_k - U_a)^2 / (2T)) of
 // the particle's Maxwellian are tabulated in LDS (dynamic, (D+1)*nv doubles):
 // M = norm * prod_a e_a[k_a], Chu G2 = T G1.
+constexpr int kAdjKeep = 4;
+
 template <int D, int NC, typename Real>
 __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a) {
   __shared__ double sh[4 * (D + 4)];
@@ -277,7 +279,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
   double s[D + 3];  // A1 = sum l M, A2 = sum l (ft - M), AU[d], AT
 #pragma unroll
   for (int k = 0; k < D + 3; ++k) s[k] = 0.0;
-  for (int q = threadIdx.x; q < a.NV; q += kThreads) {
+  auto sums = [&](int q, double (&lq)[NC]) {
     double v[3], M1;
     vel(q, v, M1);
     double w2 = 0.0;
@@ -287,6 +289,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
     for (int c = 0; c < NC; ++c) {
       const double M = c == 0 ? M1 : T * M1;
       const double l = lam_fp(c, q);
+      lq[c] = l;
       const double x = a.ft[c * cs + static_cast<size_t>(i) * NVs + q];
       s[0] = s[0] + l * M;
       s[1] = s[1] + l * (x - M);
@@ -295,6 +298,18 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
       const double kap = (c == 1) ? 0.0 : kap0;
       s[2 + D] = s[2 + D] + l * M * (-kap / T + w2 / (2.0 * T * T));
     }
+  };
+  // the adjoint of f' at a thread's first kAdjKeep velocities is kept in
+  // registers for the second pass (the rest is gathered again)
+  double lk[kAdjKeep][NC];
+#pragma unroll
+  for (int k = 0; k < kAdjKeep; ++k) {
+    const int q = threadIdx.x + k * kThreads;
+    if (q < a.NV) sums(q, lk[k]);
+  }
+  for (int q = threadIdx.x + kAdjKeep * kThreads; q < a.NV; q += kThreads) {
+    double lq[NC];
+    sums(q, lq);
   }
   block_sum<D + 3>(s, sh);
   const double g_rho = lr + cb * s[0] / rho + s[1] * dtau * (-tau / rho);
@@ -302,14 +317,25 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
 #pragma unroll
   for (int k = 0; k < D; ++k) gU[k] = lU[k] + cb * s[2 + k] / T;
   const double g_T = lT + cb * s[2 + D] + s[1] * dtau * (-tau / (2.0 * T));
-  for (int q = threadIdx.x; q < a.NV; q += kThreads) {
+  auto write = [&](int q, const double (&lq)[NC]) {
     double v[3], M1;
     vel(q, v, M1);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const double l = ca * lam_fp(c, q) + mom_adj<D, NC>(c, v, a.omega, s0, U, T, g_rho, gU, g_T);
+      const double l = ca * lq[c] + mom_adj<D, NC>(c, v, a.omega, s0, U, T, g_rho, gU, g_T);
       a.lam_ft[c * cs + static_cast<size_t>(i) * NVs + q] = static_cast<Real>(l);
     }
+  };
+#pragma unroll
+  for (int k = 0; k < kAdjKeep; ++k) {
+    const int q = threadIdx.x + k * kThreads;
+    if (q < a.NV) write(q, lk[k]);
+  }
+  for (int q = threadIdx.x + kAdjKeep * kThreads; q < a.NV; q += kThreads) {
+    double lq[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) lq[c] = lam_fp(c, q);
+    write(q, lq);
   }
 }
 
