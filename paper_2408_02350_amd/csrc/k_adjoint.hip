@@ -991,13 +991,18 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
                   static_cast<const Real*>(j.ft), static_cast<const Real*>(j.f1), j.rho1, j.U1,
                   j.T1,       lam_f1,     lam_U1,     lam_rho1,    lam_T1,
                   static_cast<Real*>(j.larr), static_cast<Real*>(j.lam_ft), lam_f, lam_U,
-                  j.lidpart, j.gpart, static_cast<int>(adj_tiles(c.cfg)),
+                  j.lidpart, j.gpart, 0,
                   nullptr,    j.ucount,   j.uj,       j.ue,        kAdjPatch * c.cap};
   dim3 t(kThreads);
   const size_t lds = static_cast<size_t>(c.D + 1) * c.cfg.nv * sizeof(double);
   // reverse transport: one wavefront per (patch of interior particles, tile
   // of 64 groups of 2 velocities) and per (wall particle, tile), then the
   // tile parts of lam_U summed in tile order
+  // velocities per lane: 4 in 3D when 4 divides nv (the per-edge set-up is
+  // shared by more velocities: the 3D kernel issues VALU work most of the
+  // time), else 2
+  const int R = (c.D == 3 && c.cfg.nv % 4 == 0) ? 4 : 2;
+  a.tiles = static_cast<int>((c.NV / R + 63) / 64);
   const int npa = (c.Ni + kAdjPatch - 1) / kAdjPatch;
   const int64_t nbp = static_cast<int64_t>(npa) * a.tiles;
   const int64_t nbw = static_cast<int64_t>(c.Nw) * a.tiles;
@@ -1014,9 +1019,17 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
   } else {
     if (c.Nw) hipLaunchKernelGGL((k_adj_wall<3, 1, Real>), dim3(c.Nw), t, 0, c.stream, a);
     if (c.Ni) hipLaunchKernelGGL((k_adj_collide<3, 1, Real>), dim3(c.Ni), t, lds, c.stream, a);
-    if (npa)
-      hipLaunchKernelGGL((k_adj_transport_patch<3, 1, Real, 2, kAdjPatch>), tp, tt, 0, c.stream, a);
-    if (c.Nw) hipLaunchKernelGGL((k_adj_transport<3, 1, Real, 2>), tw, tt, 0, c.stream, aw);
+    if (R == 4) {
+      if (npa)
+        hipLaunchKernelGGL((k_adj_transport_patch<3, 1, Real, 4, kAdjPatch>), tp, tt, 0, c.stream,
+                           a);
+      if (c.Nw) hipLaunchKernelGGL((k_adj_transport<3, 1, Real, 4>), tw, tt, 0, c.stream, aw);
+    } else {
+      if (npa)
+        hipLaunchKernelGGL((k_adj_transport_patch<3, 1, Real, 2, kAdjPatch>), tp, tt, 0, c.stream,
+                           a);
+      if (c.Nw) hipLaunchKernelGGL((k_adj_transport<3, 1, Real, 2>), tw, tt, 0, c.stream, aw);
+    }
   }
   const int64_t nu = static_cast<int64_t>(c.N) * c.D;
   hipLaunchKernelGGL(k_adj_sum_tiles, dim3(static_cast<unsigned>((nu + 255) / 256)), dim3(256), 0,
