@@ -718,6 +718,26 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
       }
       asm volatile("" ::: "memory");
     };
+    // 2 sum_k min(p_k, 0), the flux coefficient of an edge at one velocity:
+    // in 3D as g.w - |p_0| - |p_1| - |p_2| with g.w = sum_k p_k advanced by
+    // its own increment (absolute values are free source modifiers), in 2D
+    // from the minima
+    auto gw_init = [&](const double (&p)[D], const double* rc, double& gw, double& dgw) {
+      if constexpr (D == 3) {
+        gw = (p[0] + p[1]) + p[2];
+        dgw = (rc[DD + D] + rc[DD + D + 1]) + rc[DD + D + 2];
+      }
+    };
+    auto two_cm = [&](const double (&p)[D], double gw) {
+      if constexpr (D == 3) {
+        return ((gw - fabs(p[0])) - fabs(p[1])) - fabs(p[2]);
+      } else {
+        double cm = fmin(p[0], 0.0);
+#pragma unroll
+        for (int k = 1; k < D; ++k) cm = cm + fmin(p[k], 0.0);
+        return 2.0 * cm;
+      }
+    };
     auto entry = [&](int w, const double (&fi)[R][NC], const double (&li)[R][NC]) {
 #pragma unroll
       for (int t = 0; t < P; ++t) {
@@ -733,16 +753,16 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
             p[k] = s1;
             S[k] = 0.0;
           }
+          double gw = 0.0, dgw = 0.0;
+          gw_init(p, rc, gw, dgw);
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             if (r > 0) {
 #pragma unroll
               for (int k = 0; k < D; ++k) p[k] = p[k] + rc[DD + D + k];
+              gw = gw + dgw;
             }
-            double cm = fmin(p[0], 0.0);
-#pragma unroll
-            for (int k = 1; k < D; ++k) cm = cm + fmin(p[k], 0.0);
-            csum[t][r] = csum[t][r] + 2.0 * cm;
+            csum[t][r] = csum[t][r] + two_cm(p, gw);
             double sdf = 0.0;
 #pragma unroll
             for (int c = 0; c < NC; ++c) sdf = sdf + lj[t][r][c] * (fi[r][c] - fj[t][r][c]);
@@ -769,16 +789,16 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
             for (int mm = 0; mm < D; ++mm) s1 = s1 + rc[k * D + mm] * v0[mm];
             p[k] = s1;
           }
+          double gw = 0.0, dgw = 0.0;
+          gw_init(p, rc, gw, dgw);
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             if (r > 0) {
 #pragma unroll
               for (int k = 0; k < D; ++k) p[k] = p[k] + rc[DD + D + k];
+              gw = gw + dgw;
             }
-            double cm = fmin(p[0], 0.0);
-#pragma unroll
-            for (int k = 1; k < D; ++k) cm = cm + fmin(p[k], 0.0);
-            const double dc = a.dt * (2.0 * cm);
+            const double dc = a.dt * two_cm(p, gw);
 #pragma unroll
             for (int c = 0; c < NC; ++c) lf[t][r][c] = lf[t][r][c] - dc * li[r][c];
           }
