@@ -753,7 +753,7 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
             p[k] = s1;
             S[k] = 0.0;
           }
-          double gw = 0.0, dgw = 0.0;
+          double gw = 0.0, dgw = 0.0, sd = 0.0;
           gw_init(p, rc, gw, dgw);
 #pragma unroll
           for (int r = 0; r < R; ++r) {
@@ -766,16 +766,26 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
             double sdf = 0.0;
 #pragma unroll
             for (int c = 0; c < NC; ++c) sdf = sdf + lj[t][r][c] * (fi[r][c] - fj[t][r][c]);
+            if constexpr (D == 3) {
+              // sum over the group of [p_k < 0] sdf as (sum sdf - sum sign(p_k) sdf) / 2
+              sd = sd + sdf;
 #pragma unroll
-            for (int k = 0; k < D; ++k) S[k] = S[k] + (p[k] < 0.0 ? sdf : 0.0);
+              for (int k = 0; k < D; ++k) S[k] = fma(copysign(1.0, p[k]), sdf, S[k]);
+            } else {
+#pragma unroll
+              for (int k = 0; k < D; ++k) S[k] = S[k] + (p[k] < 0.0 ? sdf : 0.0);
+            }
           }
           if (on) {
+            double S2[D];  // 2 x the sums of [p_k < 0] sdf
+#pragma unroll
+            for (int k = 0; k < D; ++k) S2[k] = D == 3 ? sd - S[k] : 2.0 * S[k];
 #pragma unroll
             for (int mm = 0; mm < D; ++mm) {
               double tt = 0.0;
 #pragma unroll
-              for (int k = 0; k < D; ++k) tt = tt + rc[k * D + mm] * S[k];
-              gU[t][mm] = gU[t][mm] - 2.0 * tt;
+              for (int k = 0; k < D; ++k) tt = tt + rc[k * D + mm] * S2[k];
+              gU[t][mm] = gU[t][mm] - tt;
             }
           }
         }
