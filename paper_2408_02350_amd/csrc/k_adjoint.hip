@@ -718,25 +718,23 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
       }
       asm volatile("" ::: "memory");
     };
-    // 2 sum_k min(p_k, 0), the flux coefficient of an edge at one velocity:
-    // in 3D as g.w - |p_0| - |p_1| - |p_2| with g.w = sum_k p_k advanced by
-    // its own increment (absolute values are free source modifiers), in 2D
-    // from the minima
+    // 2 sum_k min(p_k, 0), the flux coefficient of an edge at one velocity,
+    // as g.w - sum_k |p_k| with g.w = sum_k p_k advanced by its own increment
+    // (absolute values are free source modifiers)
     auto gw_init = [&](const double (&p)[D], const double* rc, double& gw, double& dgw) {
-      if constexpr (D == 3) {
-        gw = (p[0] + p[1]) + p[2];
-        dgw = (rc[DD + D] + rc[DD + D + 1]) + rc[DD + D + 2];
+      gw = p[0];
+      dgw = rc[DD + D];
+#pragma unroll
+      for (int k = 1; k < D; ++k) {
+        gw = gw + p[k];
+        dgw = dgw + rc[DD + D + k];
       }
     };
     auto two_cm = [&](const double (&p)[D], double gw) {
-      if constexpr (D == 3) {
-        return ((gw - fabs(p[0])) - fabs(p[1])) - fabs(p[2]);
-      } else {
-        double cm = fmin(p[0], 0.0);
+      double c = gw;
 #pragma unroll
-        for (int k = 1; k < D; ++k) cm = cm + fmin(p[k], 0.0);
-        return 2.0 * cm;
-      }
+      for (int k = 0; k < D; ++k) c = c - fabs(p[k]);
+      return c;
     };
     auto entry = [&](int w, const double (&fi)[R][NC], const double (&li)[R][NC]) {
 #pragma unroll
@@ -766,20 +764,15 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
             double sdf = 0.0;
 #pragma unroll
             for (int c = 0; c < NC; ++c) sdf = sdf + lj[t][r][c] * (fi[r][c] - fj[t][r][c]);
-            if constexpr (D == 3) {
-              // sum over the group of [p_k < 0] sdf as (sum sdf - sum sign(p_k) sdf) / 2
-              sd = sd + sdf;
+            // sum over the group of [p_k < 0] sdf as (sum sdf - sum sign(p_k) sdf) / 2
+            sd = sd + sdf;
 #pragma unroll
-              for (int k = 0; k < D; ++k) S[k] = fma(copysign(1.0, p[k]), sdf, S[k]);
-            } else {
-#pragma unroll
-              for (int k = 0; k < D; ++k) S[k] = S[k] + (p[k] < 0.0 ? sdf : 0.0);
-            }
+            for (int k = 0; k < D; ++k) S[k] = fma(copysign(1.0, p[k]), sdf, S[k]);
           }
           if (on) {
             double S2[D];  // 2 x the sums of [p_k < 0] sdf
 #pragma unroll
-            for (int k = 0; k < D; ++k) S2[k] = D == 3 ? sd - S[k] : 2.0 * S[k];
+            for (int k = 0; k < D; ++k) S2[k] = sd - S[k];
 #pragma unroll
             for (int mm = 0; mm < D; ++mm) {
               double tt = 0.0;
