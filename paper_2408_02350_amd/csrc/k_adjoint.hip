@@ -591,7 +591,11 @@ __global__ __launch_bounds__(64) void k_adj_transport(const AdjArgs<Real> a) {
 // register footprint halves the waves per SIMD).
 // The own and transposed edge records of every (union entry, particle) are
 // staged in LDS per chunk; each particle takes its own edges in its row
-// order, so its sums are those of the per-particle kernel bit for bit.
+// order.  The flux coefficient is formed as g.w - sum_k |a_k.w| and the
+// U-derivative sums from the signs of the projections (fewer VALU
+// operations than the minima and selects of the per-particle kernel; the
+// same values up to rounding, and the same derivative convention except at
+// a projection of exactly -0).
 constexpr int kAdjUChunk = 16;
 
 template <int D, int NC, typename Real, int R, int P>
