@@ -5,15 +5,15 @@
  * for the BGK model of the Boltzmann equation with a meshfree ALE method"),
  * implemented as HIP kernels for AMD Instinct MI355X (gfx950).
  *
- * One time step (Sections 3.1-3.5):
+ * One time step (Sections 3.2-3.5):
  *   S1  neighbour search in a cell list over the moving cloud     (Sec. 3.5.1)
  *   S2  weighted least-squares (WLS) gradient operators           (Sec. 3.4.1)
  *   S3  edge frames and positive-upwind vectors                   (Sec. 3.4.2)
- *   S4  explicit transport  ft = f - dt (v-U^n).grad f            (Sec. 3.1, eq. explicit)
+ *   S4  explicit transport  ft = f - dt (v-U^n).grad f            (Sec. 3.2.1, eq. explicit)
  *   S5  moments of ft: rho, U, T                                  (eqs. fullmoment1a / moment1a, moment1b)
- *   S6  implicit BGK relaxation f = (tau ft + dt M)/(tau + dt)    (Sec. 3.1, closed form after implicitfull_1)
+ *   S6  implicit BGK relaxation f = (tau ft + dt M)/(tau + dt)    (Sec. 3.2.1, closed form after implicitfull_1)
  *   S7  diffuse-reflection walls with a moving lid                (Sec. 5; Table 3)
- *   S8  ALE motion  x^{n+1} = x^n + dt U^{n+1}                    (Sec. 3.1)
+ *   S8  ALE motion  x^{n+1} = x^n + dt U^{n+1}                    (Sec. 3.2.1)
  *
  * Conventions (all entry points):
  *   - Every function returns an int: BGK_OK (0) or a positive bgk_status.
@@ -38,7 +38,7 @@
  *       grad      double [N][max_neighbors][d]
  *       ops       double [N][max_neighbors][d*d]: P (d values), Q (d)
  *                 [, R (d)] per neighbour slot
- *   - Velocity grid (Sec. 3.2, read as nv points per axis including both
+ *   - Velocity grid (Sec. 3.3, read as nv points per axis including both
  *     ends): v_k = vmax*(2k-(nv-1))/(nv-1), k = 0..nv-1; every node has the
  *     weight omega = (2 vmax/(nv-1))^d.
  *   - Particles: wall_id[i] = 0 for interior particles, else the owner wall
@@ -76,7 +76,7 @@ typedef struct {
   int32_t n_particles;   /* N, interior + wall                                           */
   int32_t nv;            /* velocity points per axis, even, 2..1024                      */
   int32_t wls_degree;    /* 1 or 2: degree of the full-basis least-squares fit;          *
-                          * 0: first-derivative fit as printed in Sec. 3.1              */
+                          * 0: first-derivative fit as printed in Sec. 3.4.1            */
   int32_t max_neighbors; /* neighbour slots per particle (self included), <= 255         */
   int32_t move;          /* 1: ALE motion (S8); 0: frozen cloud (geometry reused)        */
   int32_t precision;     /* BGK_FP64, BGK_FP32 (FP32 f and transport arithmetic) or
@@ -105,8 +105,11 @@ typedef struct bgk_ctx bgk_ctx;
 /* Device workspace needed by bgk_init for this configuration (bytes, host). */
 int bgk_workspace_bytes(const bgk_config* cfg, size_t* bytes);
 
-/* Create a context.  cfg is copied.  wall_id: device int32 [N] (read once,
- * synchronously, at init).  workspace: device buffer of ws_bytes bytes that
+/* Create a context for one point cloud (Sec. 3.4.1: boundary and interior
+ * particles of the moving cloud; Sec. 3.3: the velocity grid; Sec. 5: the
+ * cavity's walls and lid).  cfg is copied.  wall_id: device int32 [N] (read
+ * once, synchronously, at init), 0 for interior particles, else the owner
+ * wall.  workspace: device buffer of ws_bytes bytes that
  * the caller keeps alive until bgk_destroy.  hip_stream: hipStream_t or NULL.
  * *out receives the context (host).  Errors: BGK_EINVAL (dim not 2/3, odd nv
  * or nv > 1024, N <= 0, dt <= 0, bad degree or capacity), BGK_ENOMEM (ws_bytes too small),
@@ -161,7 +164,7 @@ int bgk_wall_stencil(bgk_ctx* ctx, const double* x, int32_t* wall_cnt, int32_t* 
  * first); used by the staged calls below. */
 int bgk_geometry(bgk_ctx* ctx, const double* x);
 
-/* S4 (Sec. 3.1 eq. explicit; Sec. 3.4.2 eq. flux and its 3D form), with the
+/* S4 (Sec. 3.2.1 eq. explicit, Sec. 3.2.2 for Chu; Sec. 3.4.2 eq. flux and its 3D form), with the
  * geometry of the last bgk_geometry/bgk_step: for interior i and every v,
  *   ft_i(v) = f_i(v) - dt sum_{j != i} c_ij(v) (f_j(v) - f_i(v)),
  *   c_ij(v) = g_ij.w - |P_ij.w| - |Q_ij.w| - |R_ij.w|,  w = v - U_i,
@@ -169,7 +172,7 @@ int bgk_geometry(bgk_ctx* ctx, const double* x);
  * Wall rows of f_tilde are copies of f_in.  f_in and f_tilde must differ. */
 int bgk_transport(bgk_ctx* ctx, const void* f_in, void* f_tilde, const double* U);
 
-/* S5-S6 for interior particles: rho, U, T of ft (Chu: 3 rho T from g1 and g2,
+/* S5-S6 (Sec. 3.2.1, Sec. 3.2.2) for interior particles: rho, U, T of ft (Chu: 3 rho T from g1 and g2,
  * eq. moment1b; two passes, U first), tau = kn sqrt(2/pi)/(rho sqrt T), and
  * f_out = (tau ft + dt M[rho,U,T])/(tau + dt) (Chu: G1 = rho/(2 pi T)
  * exp(-|v-U|^2/(2T)), G2 = T G1).  f_out may equal f_tilde.  Wall rows of
@@ -184,7 +187,7 @@ int bgk_collide(bgk_ctx* ctx, const void* f_tilde, void* f_out, double* rho, dou
  * the wall particles' rho, U, T are the moments of their f. */
 int bgk_wall_bc(bgk_ctx* ctx, void* f, double* rho, double* U, double* T);
 
-/* S8 (Sec. 3.1): x_i += dt U_i for interior particles, clamped to
+/* S8 (Sec. 3.2.1, position update): x_i += dt U_i for interior particles, clamped to
  * [0.1 dx, 1 - 0.1 dx]^d (clamped coordinates are counted, bgk_diagnostics). */
 int bgk_move(bgk_ctx* ctx, double* x, const double* U);
 
@@ -195,7 +198,7 @@ int bgk_move(bgk_ctx* ctx, double* x, const double* U);
 int bgk_step(bgk_ctx* ctx, const void* f_in, void* f_out, double* x, double* U, double* rho,
              double* T);
 
-/* Particle management (Sec. 4.1.2, adding and removing points), plan.  The
+/* Particle management (Sec. 3.5.2, adding and removing points), plan.  The
  * paper replaces two points that come too close by one at their midpoint
  * and adds points where holes open, filling f there by least squares; it
  * states no thresholds.  The rule taken: interior particles i < j that are
@@ -262,7 +265,7 @@ int bgk_objective(bgk_ctx* ctx, const void* f, const double* rho, const double* 
                   double ke_weight, double* J, void* dJ_df, double* dJ_drho, double* dJ_dU);
 
 /* Reverse mode of one frozen-cloud step (S4-S7 with the operators of the
- * fixed cloud; Sec. 3.1 and Sec. 5).  The step maps the state (f^n, U^n) and
+ * fixed cloud; Sec. 3.2 and Sec. 5).  The step maps the state (f^n, U^n) and
  * the lid speed to (f^{n+1}, U^{n+1}, rho^{n+1}, T^{n+1}).  Given the
  * adjoints lam_* of those outputs, this returns
  *   lam_f = (d f^{n+1}/d f^n)^T lam_f1 + ... (every output's term),

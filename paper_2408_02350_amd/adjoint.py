@@ -1,7 +1,7 @@
 """Gradients of a cavity rollout by the hand-written reverse step.
 
 The rollout is the frozen-cloud map (S4-S7 of every step with the operators
-of the fixed cloud, Sec. 3.1 and Sec. 5): (rho, U, T)^0 are the moments of
+of the fixed cloud, Sec. 3.2 and Sec. 5): (rho, U, T)^0 are the moments of
 f^0, then ``nsteps`` steps, then the objective J(f, rho, U) of the final
 state (lid heat flux plus weighted kinetic energy, see ``bgk_objective``).
 

@@ -16,7 +16,7 @@ namespace bgk {
 constexpr double kPi = 3.14159265358979323846;
 
 // Velocity node k of an axis with nv points on [-vmax, vmax], both ends
-// included (Sec. 3.2): v_k = vmax (2k - (nv-1)) / (nv-1).
+// included (Sec. 3.3): v_k = vmax (2k - (nv-1)) / (nv-1).
 __device__ __forceinline__ double vnode(int k, int nv, double vmax) {
   return vmax * static_cast<double>(2 * k - (nv - 1)) / static_cast<double>(nv - 1);
 }

@@ -381,7 +381,7 @@ __device__ __forceinline__ void wls_basis(int deg, const double* y, double* p) {
 // so there is no barrier).  Degree: the configured one if the stencil holds
 // at least twice as many points as degree-2 basis functions, else 1 if it
 // holds d+2 points, else BGK_ESINGULAR (also on a non-positive pivot).
-// Degree 0 is the fit as printed in Sec. 3.1: first derivatives only, the
+// Degree 0 is the fit as printed in Sec. 3.4.1: first derivatives only, the
 // basis is the scaled offsets y (no constant; the particle itself has
 // y = 0 and drops out), derivative k in column k.  A lower degree runs on
 // the degree-2 sizes with the unused basis values zero and a unit diagonal

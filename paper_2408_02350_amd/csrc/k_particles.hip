@@ -1,4 +1,4 @@
-// Particle management (Sec. 4.1.2, adding and removing points): two
+// Particle management (Sec. 3.5.2, adding and removing points): two
 // interior particles that come too close are replaced by one at their
 // midpoint, particles are added where holes open, and f at every new
 // particle is filled by least squares from the old cloud.

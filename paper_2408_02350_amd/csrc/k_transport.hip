@@ -1,4 +1,4 @@
-// S4: explicit transport with the positive upwind flux (Sec. 3.1 eq.
+// S4: explicit transport with the positive upwind flux (Sec. 3.2.1 eq.
 // explicit; Sec. 3.4.2 eq. flux and its 3D form):
 //
 //   ft_i(v) = f_i(v) - dt sum_{j != i} c_ij(v) (f_j(v) - f_i(v)),

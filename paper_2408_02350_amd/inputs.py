@@ -108,7 +108,7 @@ CONFIGS = {
 # The paper's own cavity scales (Sec. 5, Tables 1 and 2): 20 velocity points
 # per axis, 200^2..500^2 particles in 2D and 20^3..40^3 in 3D, support
 # h = 3.1 dx and the first-derivative least-squares fit as printed
-# (Sec. 3.1).  v_max is not given there; 4 is taken as for the other
+# (Sec. 3.4.1).  v_max is not given there; 4 is taken as for the other
 # 20-point grid.  The paper reports whole runs in minutes without the step
 # count, so these are timed per step only.
 PAPER_SCALES = {

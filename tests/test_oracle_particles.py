@@ -1,4 +1,4 @@
-"""Pins of the oracle's particle management (Sec. 4.1.2, adding and removing
+"""Pins of the oracle's particle management (Sec. 3.5.2, adding and removing
 points): planted clusters and holes with known outcomes, the merge rule on a
 three-point cluster, and exact reproduction of linear fields at new points
 (the degree-1 least-squares value fit reproduces them)."""

@@ -205,7 +205,7 @@ def test_wls_matches_dense_weighted_lstsq(dim, n):
         assert np.allclose(est, ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
 
 
-# Degree 0: the least-squares fit as printed in Sec. 3.1 (eqs. taylor,
+# Degree 0: the least-squares fit as printed in Sec. 3.4.1 (eqs. taylor,
 # solution, x/y/z_derivative): unknowns are the first derivatives only, the
 # rows of M are the offsets x_j - x_i, b_j = f_j - f_i, no constant column.
 @pytest.mark.parametrize("dim,n", [(2, 30), (3, 10)])
@@ -472,6 +472,72 @@ def test_wall_bc_zero_net_mass_flux_and_rest_density():
     fb0, rho0, U0, T0 = oracle.wall_bc(c0, wid, wcnt, widx, wc0, f0, np.ones(N),
                                        np.zeros((2, N)), np.ones(N))
     assert np.allclose(fb0, f0, rtol=1e-12, atol=1e-16)
+
+
+@pytest.mark.parametrize("dim,n,nv", [(2, 12, 16), (3, 6, 8)])
+def test_walls_reproduce_a_rest_maxwellian_at_the_wall_temperature(dim, n, nv):
+    """Resting lid, wall temperature T_w = 1.3, interior at M[1, 0, T_w]: the
+    arriving half interpolates rows that all hold the same values, the
+    zero-mass-flux density of the emitted half is 1 on the symmetric grid,
+    and the emitted half is M[1, 0, T_w] (Chu: g2 = T_w g1).  A wall
+    Maxwellian taken at T = 1, or a Chu g2 without its factor T_w, fails."""
+    Tw = 1.3
+    x, wid = make_cloud(dim, n, 3)
+    c = cfg(dim, n, nv, 4.0, lid=0.0, wall_T=Tw)
+    N = c.n_particles
+    walls = wid != 0
+    wcnt, widx, wc0, hb = oracle.wall_stencil(c, x, wid)
+    fM = oracle.maxwellian(c, np.ones(N), np.zeros((dim, N)), np.full(N, Tw))
+    f = fM.copy()
+    f[:, walls] = 0.0
+    fb, rho, U, T = oracle.wall_bc(c, wid, wcnt, widx, wc0, f, np.ones(N), np.zeros((dim, N)),
+                                   np.ones(N))
+    assert np.max(np.abs(fb - fM)) <= 1e-13 * fM.max()
+    if dim == 2:
+        assert np.allclose(fb[1, walls], Tw * fb[0, walls], rtol=1e-13, atol=0)
+    rM, UM, TM = oracle.moments(c, fM)
+    assert np.allclose(rho[walls], rM[walls], rtol=1e-12, atol=0)
+    assert np.allclose(T[walls], TM[walls], rtol=1e-12, atol=0)
+    assert np.max(np.abs(U[:, walls])) < 1e-13
+    # the discrete moments sit within the quadrature defect of (1, 0, T_w)
+    assert np.max(np.abs(T[walls] - Tw)) < 5e-3 and np.max(np.abs(rho[walls] - 1)) < 5e-3
+    # the same walls at T_w = 1 give a different emitted half
+    c1 = cfg(dim, n, nv, 4.0, lid=0.0, wall_T=1.0)
+    fb1, *_ = oracle.wall_bc(c1, wid, wcnt, widx, wc0, f, np.ones(N), np.zeros((dim, N)),
+                             np.ones(N))
+    assert np.max(np.abs(fb1 - fM)) > 1e-3 * fM.max()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_motion_clamps_interior_particles_and_never_moves_walls(dim):
+    """S8: an interior particle pushed past 1 - 0.1 dx (or below 0.1 dx) ends
+    exactly on the bound and is counted once per clamped coordinate; every
+    other interior coordinate moves by exactly dt U; wall particles do not
+    move whatever their U."""
+    n = 8
+    x, wid = make_cloud(dim, n, 4)
+    c = cfg(dim, n, 4, 4.0)
+    N = c.n_particles
+    lo, hi = 0.1 * c.dx, 1.0 - 0.1 * c.dx
+    rng = np.random.default_rng(5)
+    U = rng.uniform(-0.2, 0.2, (dim, N))
+    inner = np.nonzero(wid == 0)[0]
+    up, down, both = inner[0], inner[-1], inner[len(inner) // 2]
+    U[0, up] = (hi + 0.5 * c.dx - x[0, up]) / c.dt
+    U[dim - 1, down] = (lo - 0.5 * c.dx - x[dim - 1, down]) / c.dt
+    U[0, both] = (lo - 2.0 * c.dx - x[0, both]) / c.dt
+    U[1, both] = (hi + 2.0 * c.dx - x[1, both]) / c.dt
+    U[:, wid != 0] = 1e3
+    x1, k = oracle.move(c, wid, U, x)
+    assert k == 4
+    assert x1[0, up] == hi and x1[dim - 1, down] == lo
+    assert x1[0, both] == lo and x1[1, both] == hi
+    assert np.array_equal(x1[:, wid != 0], x[:, wid != 0])
+    free = np.zeros((dim, N), bool)
+    free[:, inner] = True
+    free[0, up] = free[dim - 1, down] = free[0, both] = free[1, both] = False
+    assert np.array_equal(x1[free], (x + c.dt * U)[free])
+    assert np.all(x1[:, inner] >= lo) and np.all(x1[:, inner] <= hi)
 
 
 @pytest.mark.parametrize("dim,n", [(2, 16), (3, 8)])
