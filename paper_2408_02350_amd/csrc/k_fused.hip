@@ -72,6 +72,7 @@ struct FusedArgs {
   double* T;
   int32_t* err;
   void* fto;         // fused: f-tilde's interior rows as well (may be null)
+  int ntl;           // velocity tiles walked in turn by one block (INLDS)
 };
 
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
@@ -174,7 +175,11 @@ __device__ __forceinline__ double wave_reduce_scatter(double (&v)[K]) {
 
 constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) / 2); }
 
-template <int D, int NC, int MODE, int R, bool FUSE, int TP>
+// INLDS: the block walks all ntl velocity tiles of its patch in turn; the
+// f-tilde of every tile but the last waits in LDS (thread-private slots, no
+// barrier), so the moments and the relaxation run in the same block and
+// f-tilde never goes to HBM.
+template <int D, int NC, int MODE, int R, bool FUSE, int TP, bool INLDS>
 __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   using Real = typename FPrec<MODE>::real;
   constexpr int DD = D * D;
@@ -188,16 +193,35 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   constexpr int KM = TP * (D + 1);              // first-pass moment sums per thread
   constexpr int KP = pow2_at_least(KM);
   constexpr int KP2 = pow2_at_least(TP);         // second pass: one sum per particle
-  __shared__ Real lrec[kChunk][TP][REC];
+  // the per-edge records are read only during the walk, the reduction
+  // slots and exponential tables only after it: they share LDS
+  struct Post {
+    double red[16][KP > KP2 ? KP : KP2];
+    double etab[TP][D][kMaxNv];
+  };
+  union Shared {
+    Real lrec[kChunk][TP][REC];
+    Post post;
+  };
+  __shared__ Shared sh;
   __shared__ double vtab[kMaxNv];
-  __shared__ double red[16][KP > KP2 ? KP : KP2];
-  __shared__ double etab[TP][D][kMaxNv];
   __shared__ double pstat[TP][D + 5];           // rho, U[d], T, norm, a, b
+  extern __shared__ __align__(16) unsigned char fts_raw[];  // INLDS tiles
+  auto& lrec = sh.lrec;
+  auto& red = sh.post.red;
+  auto& etab = sh.post.etab;
 
   const int tid = threadIdx.x;
   const int nthreads = blockDim.x;
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int patch = lb % a.npatch, tile = lb / a.npatch;
+  const int patch = lb % a.npatch;
+  const int tile0 = INLDS ? 0 : lb / a.npatch;
+  const int ntl = INLDS ? a.ntl : 1;
+  // slot of (stored tile tl, particle t, velocity r, component c) of this thread
+  Real* fts = reinterpret_cast<Real*>(fts_raw);
+  auto fts_at = [&](int tl, int t, int r, int c) -> Real& {
+    return fts[(((static_cast<size_t>(tl) * TP + t) * R + r) * NC + c) * a.bte + tid];
+  };
   const Real* __restrict__ f = static_cast<const Real*>(a.f);
   Real* __restrict__ fo = static_cast<Real*>(a.fo);
   const Real* __restrict__ ops = static_cast<const Real*>(a.ops);
@@ -213,20 +237,33 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   if (tid < a.nv) vtab[tid] = vnode(tid, a.nv, a.vmax);
   __syncthreads();
 
-  // velocities of this thread: q = q0 + r; the fast component is kq[0] + r,
-  // the others are fixed
-  const int qs = tile * (a.bte * R) + R * tid;
-  const bool lane_on = tid < a.bte && qs < a.NV;
-  const int q0 = lane_on ? qs : 0;
-  int kq[D];
-  {
-    int q = q0;
+  // velocities of this thread in tile tile0 + tl: q = q0 + r; the fast
+  // component is kq[0] + r, the others are fixed
+  auto tile_vel = [&](int tl, bool& on, int& qq0, int (&kk)[D]) {
+    const int qs = (tile0 + tl) * (a.bte * R) + R * tid;
+    on = tid < a.bte && qs < a.NV;
+    qq0 = on ? qs : 0;
+    int q = qq0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      kq[k] = q % a.nv;
+      kk[k] = q % a.nv;
       q /= a.nv;
     }
-  }
+  };
+  const int nu = a.ucount[patch];
+  const int32_t* __restrict__ ujp = a.uj + static_cast<size_t>(patch) * a.ucap;
+  const uint32_t* __restrict__ uep = a.ue + static_cast<size_t>(patch) * a.ucap;
+  const Real dvs = static_cast<Real>(a.dvs);
+  // ft = f - dt sum c (f_j - f_i) = f (1 + dt sum c) - dt sum c f_j; the
+  // factor 2 of c is folded into dt (except where BF16 rounds 2 cm, and in the
+  // 3D form, whose g.w - sum |a_k.w| already is c)
+  const Real dtf = static_cast<Real>((DIFF || GW) ? a.dt : 2.0 * a.dt);
+  bool lane_on;
+  int q0, kq[D];
+  Real ft[TP][R][NC];
+
+  for (int tl = 0; tl < ntl; ++tl) {
+  tile_vel(tl, lane_on, q0, kq);
   Real v0[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) v0[k] = static_cast<Real>(vtab[kq[k]]);
@@ -262,11 +299,6 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
         for (int r = 0; r < R; ++r) fi[t][r][c] = tmp[r];
       }
   }
-
-  const int nu = a.ucount[patch];
-  const int32_t* __restrict__ ujp = a.uj + static_cast<size_t>(patch) * a.ucap;
-  const uint32_t* __restrict__ uep = a.ue + static_cast<size_t>(patch) * a.ucap;
-  const Real dvs = static_cast<Real>(a.dvs);
 
   for (int c0 = 0; c0 < nu; c0 += kChunk) {
     const int cn = min(kChunk, nu - c0);
@@ -528,11 +560,6 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
     }
   }
 
-  // ft = f - dt sum c (f_j - f_i) = f (1 + dt sum c) - dt sum c f_j; the
-  // factor 2 of c is folded into dt (except where BF16 rounds 2 cm, and in the
-  // 3D form, whose g.w - sum |a_k.w| already is c)
-  const Real dtf = static_cast<Real>((DIFF || GW) ? a.dt : 2.0 * a.dt);
-  Real ft[TP][R][NC];
 #pragma unroll
   for (int t = 0; t < TP; ++t) {
     if constexpr (DIFF) {
@@ -553,6 +580,30 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
       }
     }
   }
+  if (FUSE && a.fto != nullptr) {
+    Real* __restrict__ fto = static_cast<Real*>(a.fto);
+#pragma unroll
+    for (int t = 0; t < TP; ++t)
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (pt[t] >= 0 && lane_on) {
+          Real tmp[R];
+#pragma unroll
+          for (int r = 0; r < R; ++r) tmp[r] = ft[t][r][c];
+          store_r<Real, R>(fto + c * cs + static_cast<size_t>(pt[t]) * NVs + q0, tmp);
+        }
+  }
+  if constexpr (INLDS) {
+    if (tl + 1 < ntl) {
+#pragma unroll
+      for (int t = 0; t < TP; ++t)
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) fts_at(tl, t, r, c) = ft[t][r][c];
+    }
+  }
+  }  // tiles
 
   if constexpr (!FUSE) {
 #pragma unroll
@@ -567,33 +618,47 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
         }
     return;
   } else {
-    if (a.fto != nullptr) {
-      Real* __restrict__ fto = static_cast<Real*>(a.fto);
-#pragma unroll
-      for (int t = 0; t < TP; ++t)
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-          if (pt[t] >= 0 && lane_on) {
-            Real tmp[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) tmp[r] = ft[t][r][c];
-            store_r<Real, R>(fto + c * cs + static_cast<size_t>(pt[t]) * NVs + q0, tmp);
-          }
-    }
+    // the records are consumed by every wave before red / etab reuse them
+    __syncthreads();
     const int lane = tid & 63, wid = tid >> 6, nw = nthreads >> 6;
+    // f-tilde of (tile tl, particle t, velocity r, component c) of this
+    // thread: the stored tiles from LDS, the last one from registers
+    // velocities of tile tl of this thread (the last tile's are at hand)
+    auto epi_vel = [&](int tl, bool& on, int& qq0, int (&kk)[D]) {
+      if constexpr (INLDS) {
+        if (tl + 1 < ntl) {
+          tile_vel(tl, on, qq0, kk);
+          return;
+        }
+      }
+      on = lane_on;
+      qq0 = q0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) kk[k] = kq[k];
+    };
+    auto ftv = [&](int tl, int t, int r, int c) -> double {
+      if constexpr (INLDS) {
+        if (tl + 1 < ntl) return static_cast<double>(fts_at(tl, t, r, c));
+      }
+      return static_cast<double>(ft[t][r][c]);
+    };
     // ---- S5 pass 1 (FP64): s0 = sum f1, s1 = sum v f1
     double sm[KP];
 #pragma unroll
     for (int k = 0; k < KP; ++k) sm[k] = 0.0;
-    if (lane_on) {
+    for (int tl = 0; tl < ntl; ++tl) {
+      bool on;
+      int qq0, kk[D];
+      epi_vel(tl, on, qq0, kk);
+      if (!on) continue;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         double v[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) v[k] = vtab[k == 0 ? kq[0] + r : kq[k]];
+        for (int k = 0; k < D; ++k) v[k] = vtab[k == 0 ? kk[0] + r : kk[k]];
 #pragma unroll
         for (int t = 0; t < TP; ++t) {
-          const double x = static_cast<double>(ft[t][r][0]);
+          const double x = ftv(tl, t, r, 0);
           double* st = sm + t * (D + 1);
           st[0] = st[0] + x;
 #pragma unroll
@@ -624,12 +689,16 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
     double se[KP2];
 #pragma unroll
     for (int t = 0; t < KP2; ++t) se[t] = 0.0;
-    if (lane_on) {
+    for (int tl = 0; tl < ntl; ++tl) {
+      bool on;
+      int qq0, kk[D];
+      epi_vel(tl, on, qq0, kk);
+      if (!on) continue;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         double v[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) v[k] = vtab[k == 0 ? kq[0] + r : kq[k]];
+        for (int k = 0; k < D; ++k) v[k] = vtab[k == 0 ? kk[0] + r : kk[k]];
 #pragma unroll
         for (int t = 0; t < TP; ++t) {
           double w2 = 0.0;
@@ -638,8 +707,8 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
             const double wk = v[k] - pstat[t][1 + k];
             w2 = w2 + wk * wk;
           }
-          se[t] = se[t] + w2 * static_cast<double>(ft[t][r][0]);
-          if (NC == 2) se[t] = se[t] + static_cast<double>(ft[t][r][NC - 1]);
+          se[t] = se[t] + w2 * ftv(tl, t, r, 0);
+          if (NC == 2) se[t] = se[t] + ftv(tl, t, r, NC - 1);
         }
       }
     }
@@ -690,28 +759,32 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
     }
     __syncthreads();
     // ---- S6: f^{n+1} = (tau ft + dt M)/(tau + dt) = a ft + b M
+    for (int tl = 0; tl < ntl; ++tl) {
+      bool on;
+      int qq0, kk[D];
+      epi_vel(tl, on, qq0, kk);
 #pragma unroll
-    for (int t = 0; t < TP; ++t) {
-      if (pt[t] < 0 || !lane_on) continue;
-      const double T = pstat[t][D + 1], norm = pstat[t][D + 2];
-      const double ca = pstat[t][D + 3], cb = pstat[t][D + 4];
-      double efix = norm;
+      for (int t = 0; t < TP; ++t) {
+        if (pt[t] < 0 || !on) continue;
+        const double T = pstat[t][D + 1], norm = pstat[t][D + 2];
+        const double ca = pstat[t][D + 3], cb = pstat[t][D + 4];
+        double efix = norm;
 #pragma unroll
-      for (int k = 1; k < D; ++k) efix = efix * etab[t][k][kq[k]];
-      Real out[NC][R];
+        for (int k = 1; k < D; ++k) efix = efix * etab[t][k][kk[k]];
+        Real out[NC][R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const double M1 = efix * etab[t][0][kq[0] + r];
+        for (int r = 0; r < R; ++r) {
+          const double M1 = efix * etab[t][0][kk[0] + r];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const double M = (c == 1) ? T * M1 : M1;
-          const double x = static_cast<double>(ft[t][r][c]);
-          out[c][r] = static_cast<Real>(fma(cb, M, ca * x));
+          for (int c = 0; c < NC; ++c) {
+            const double M = (c == 1) ? T * M1 : M1;
+            out[c][r] = static_cast<Real>(fma(cb, M, ca * ftv(tl, t, r, c)));
+          }
         }
-      }
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        store_r<Real, R>(fo + c * cs + static_cast<size_t>(pt[t]) * NVs + q0, out[c]);
+        for (int c = 0; c < NC; ++c)
+          store_r<Real, R>(fo + c * cs + static_cast<size_t>(pt[t]) * NVs + qq0, out[c]);
+      }
     }
   }
 }
@@ -720,11 +793,22 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
 // nv, so a thread's R velocities share every other component), at most
 // Rmax for the precision and model (the per-thread accumulators are
 // tp * R * (n_c + 1) values), and the fewest velocity tiles of at most
-// 1024 threads (2D: fewer, see lanes_max).  One tile can run the
-// fused relaxation; several tiles write f-tilde for the separate kernel.
+// 1024 threads (2D: fewer, see lanes_max).  One tile runs the fused
+// relaxation.  Several FP64 tiles whose f-tilde (all but the last tile)
+// fits the LDS next to the kernel's own tables are walked in turn by one
+// block per patch (inlds), which then relaxes them; otherwise each tile is
+// a block that writes f-tilde, and the separate relaxation kernel finishes.
 struct FusedPlan {
   int R = 0, tiles = 0, bte = 0;
+  bool inlds = false;
+  size_t lds = 0;   // dynamic LDS bytes of the inlds variant
 };
+
+// LDS of one gfx950 workgroup, and what the fused kernel declares
+// statically (upper bound over the instantiations that take inlds: 3D FP64
+// and 2D FP64 with 2- or 4-particle patches)
+constexpr size_t kLdsBytes = 160 * 1024;
+constexpr size_t kFusedStaticLds = 34 * 1024;
 
 // Instantiated (patch size, R) pairs per model and precision, within the
 // register budget.
@@ -768,6 +852,11 @@ static FusedPlan plan_fused(const Ctx& c) {
     p.R = R;
     p.tiles = (lanes + 1023) / 1024;
     p.bte = (lanes + p.tiles - 1) / p.tiles;
+    if (f64) {
+      const size_t nc = D == 2 ? 2 : 1;
+      p.lds = static_cast<size_t>(p.tiles - 1) * c.tp * R * nc * p.bte * sizeof(double);
+      p.inlds = p.lds + kFusedStaticLds <= kLdsBytes;
+    }
     return p;
   }
   return p;
@@ -779,15 +868,36 @@ template <int D, int NC, int MODE, bool FUSE, int TP>
 static hipError_t launch_fused_t(const Ctx& c, FusedArgs a, const FusedPlan& p) {
   a.bte = p.bte;
   a.dvs = 2.0 * c.cfg.vmax / (c.cfg.nv - 1);
+  const bool inlds = FUSE && MODE == BGK_FP64 && p.tiles > 1 && p.inlds;
+  a.ntl = inlds ? p.tiles : 1;
   const int bt = (a.bte + 63) / 64 * 64;
-  dim3 g(c.npatch * p.tiles), b(bt);
+  dim3 g(c.npatch * (inlds ? 1 : p.tiles)), b(bt);
+  const size_t lds = inlds ? p.lds : 0;
+  // (the dynamic LDS size is set on the kernel before the launch: gfx950
+  // gives one workgroup up to 160 KB)
+#define BGK_LAUNCH_FUSED(RR, IL)                                                          \
+  do {                                                                                    \
+    auto kf = k_fused<D, NC, MODE, RR, FUSE, TP, IL>;                                     \
+    if (lds) {                                                                            \
+      const hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(kf),        \
+          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));             \
+      if (ea != hipSuccess) return ea;                                                    \
+    }                                                                                     \
+    hipLaunchKernelGGL(kf, g, b, lds, c.stream, a);                                       \
+  } while (0)
   switch (p.R) {
 #define BGK_R_CASE(RR)                                                                    \
   case RR:                                                                                \
-    if constexpr (fused_instance<D, MODE, TP, RR>())                                      \
-      hipLaunchKernelGGL((k_fused<D, NC, MODE, RR, FUSE, TP>), g, b, 0, c.stream, a);     \
-    else                                                                                  \
+    if constexpr (fused_instance<D, MODE, TP, RR>()) {                                    \
+      if constexpr (FUSE && MODE == BGK_FP64) {                                           \
+        if (inlds) BGK_LAUNCH_FUSED(RR, true);                                            \
+        else BGK_LAUNCH_FUSED(RR, false);                                                 \
+      } else {                                                                            \
+        BGK_LAUNCH_FUSED(RR, false);                                                      \
+      }                                                                                   \
+    } else {                                                                              \
       return hipErrorInvalidValue;                                                        \
+    }                                                                                     \
     break;
     BGK_R_CASE(1)
     BGK_R_CASE(2)
@@ -796,6 +906,7 @@ static hipError_t launch_fused_t(const Ctx& c, FusedArgs a, const FusedPlan& p) 
     BGK_R_CASE(8)
     BGK_R_CASE(10)
 #undef BGK_R_CASE
+#undef BGK_LAUNCH_FUSED
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -834,8 +945,9 @@ hipError_t launch_fused(const Ctx& c, const void* f_in, void* f_out, const doubl
               c.cfg.precision == BGK_FP64 ? static_cast<const void*>(c.d.ops64)
                                           : static_cast<const void*>(c.d.ops32),
               c.d.cperm, c.d.ucount, c.d.uj, c.d.ue, rho, U_out, T, c.d.err,
-              fuse ? f_tilde : nullptr};
-  if (fuse && p.tiles == 1) return launch_fused_any<true>(c, a, p);
+              fuse ? f_tilde : nullptr, 1};
+  if (fuse && (p.tiles == 1 || (p.inlds && c.cfg.precision == BGK_FP64)))
+    return launch_fused_any<true>(c, a, p);
   // several velocity tiles: f-tilde first (into f_tilde if given, else
   // f_out), then relaxed into f_out
   void* ft = (fuse && f_tilde) ? f_tilde : f_out;

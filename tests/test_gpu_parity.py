@@ -304,10 +304,10 @@ def run_both(cav, steps, seed=0, init="rest", **over):
         (rf, rx, rU, rrho, rT)
 
 
-def assert_state_close(g, r, rtol=RTOL):
+def assert_state_close(g, r, rtol=RTOL, floor=1e-10):
     f, x, U, rho, T = g
     rf, rx, rU, rrho, rT = r
-    ef = rel(f, rf)
+    ef = rel(f, rf, floor)
     say(f"  step parity: f {ef:.2e}  x {np.max(np.abs(x - rx)):.2e}  "
         f"U {np.max(np.abs(U - rU)):.2e}  rho {rel(rho, rrho):.2e}  T {rel(T, rT):.2e}")
     assert ef <= rtol
@@ -340,11 +340,14 @@ def test_step_parity_first_order_fit(dim, n, nv, steps, flags):
     assert_state_close(g, r)
 
 
-@pytest.mark.parametrize("dim,n,nv", [(3, 6, 18), (2, 8, 46)])
+@pytest.mark.parametrize("dim,n,nv", [(3, 6, 18), (2, 8, 46), (3, 6, 24)])
 def test_step_parity_velocity_tiles(dim, n, nv):
-    """Velocity grids too large for one block at the FP64 register budget
-    (18^3 in 3D, 46^2 in 2D): the transport runs over several velocity
-    tiles and the relaxation kernel finishes the step."""
+    """Velocity grids too large for one block at the FP64 register budget:
+    18^3 (3 tiles) in 3D and 46^2 (2 tiles) in 2D are walked in turn by one
+    block per patch, the f-tilde of all but the last tile waiting in LDS;
+    24^3 (4 tiles of 864 lanes x 4 velocities) does not fit the LDS, so its
+    tiles run as separate blocks that write f-tilde, and the relaxation
+    kernel finishes the step."""
     k, g, r = run_both(cavity(dim, n, nv), 2, 5)
     assert_state_close(g, r)
 
@@ -417,9 +420,17 @@ def test_step_parity_3d_fp64_two_velocity_tiles(n, nv, steps):
 @pytest.mark.parametrize("dim,n,nv", [(2, 12, 16), (3, 7, 8)])
 def test_step_parity_hot_walls(dim, n, nv):
     """Walls at T_w = 1.3 (the emitted Maxwellian's temperature and, in 2D,
-    g2 = T_w g1 on the emitted half): full steps against the oracle's."""
+    g2 = T_w g1 on the emitted half): full steps against the oracle's.
+
+    On the coarse 8^3 grid the hot walls drive the linearly extrapolated
+    arriving half of some wall rows down to ~2e-10 of the field's maximum
+    (and below zero) by cancellation between terms ~100x larger: there the
+    oracle itself moves by 3.9e-12 relative when only the rounding of its
+    velocity sums changes (compensated against plain left-to-right sums),
+    so f is compared with values below 1e-8 of the maximum measured
+    against 1e-8 of it; x, U, rho and T keep the 1e-12 bar."""
     k, g, r = run_both(cavity(dim, n, nv, wall_T=1.3), 3, 1, init="smooth")
-    assert_state_close(g, r)
+    assert_state_close(g, r, floor=1e-8)
 
 
 @pytest.mark.parametrize("dim", [2, 3])
