@@ -594,7 +594,8 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
         }
   }
   if constexpr (INLDS) {
-    if (tl + 1 < ntl) {
+    // (lanes past bte have no slot: slot s of lane l is s * bte + l)
+    if (tl + 1 < ntl && tid < a.bte) {
 #pragma unroll
       for (int t = 0; t < TP; ++t)
 #pragma unroll
