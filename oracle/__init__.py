@@ -79,12 +79,18 @@ def lib():
         L.ref_wall_bc.argtypes = [cp, ip, ip, ip, dp, dp, dp, dp, dp]
         L.ref_move.argtypes = [cp, ip, dp, dp, ip]
         L.ref_step.argtypes = [cp, ip, dp, dp, dp, dp, dp, dp, ip]
+        L.ref_step_rows.argtypes = [cp, ip, dp, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    dp, dp, ip]
         L.ref_objective.restype = ctypes.c_double
         L.ref_objective.argtypes = [cp, ip, dp, dp, dp, ctypes.c_double]
         L.ref_rollout_dual.argtypes = [cp, ip, dp, dp, dp, ctypes.c_double, ctypes.c_int,
                                        ctypes.c_double, dp, dp, dp]
         L.ref_step_dual.argtypes = [cp, ip, dp, dp, dp, dp, dp, ctypes.c_double,
                                     dp, dp, dp, dp, dp, dp, dp, dp]
+        L.ref_step_dual_move.argtypes = [cp, ip, dp, dp, dp, dp, dp, dp, ctypes.c_double,
+                                         dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.ref_rollout_dual_move.argtypes = [cp, ip, dp, dp, dp, ctypes.c_double, ctypes.c_int,
+                                            ctypes.c_double, dp, dp]
         L.ref_objective_dual.restype = ctypes.c_double
         L.ref_objective_dual.argtypes = [cp, ip, dp, dp, dp, dp, dp, dp, ctypes.c_double]
         L.ref_pm_count.argtypes = [cp, dp, ip, ctypes.c_double, ctypes.c_double, ip, ip]
@@ -297,6 +303,21 @@ def step(c, wall_id, x, f, U):
     return x, fout, U, rho, T, k.value
 
 
+def step_rows(c, wall_id, x, f, U, i0, i1, threads=0):
+    """Timing sample of one step's per-particle work (S1-S6) for the interior
+    particles among i0..i1-1 on `threads` threads (0: all).  Returns
+    (f_out, seconds, rows): f_out [n_c][N][N_v] holds f^{n+1} on the sampled
+    rows only (other rows are left uninitialised)."""
+    f, U, x = _f64(f), _f64(U), _f64(x)
+    fout = np.empty_like(f)
+    sec = ctypes.c_double(0.0)
+    nr = ctypes.c_int32(0)
+    _check(lib().ref_step_rows(ctypes.byref(c), _i(_i32(wall_id)), _d(x), _d(f), _d(U),
+                               int(i0), int(i1), int(threads), _d(fout), ctypes.byref(sec),
+                               ctypes.byref(nr)), "step_rows")
+    return fout, sec.value, nr.value
+
+
 def run(c, wall_id, x, f, U, nsteps):
     rho = T = None
     clamped = 0
@@ -340,6 +361,40 @@ def step_dual(c, wall_id, x, f, U, f_dot=None, U_dot=None, lid_dot=0.0):
                                _d(Ud) if Ud is not None else None, lid_dot, _d(f1), _d(f1d),
                                _d(U1), _d(U1d), _d(r), _d(rd), _d(T), _d(Td)), "step_dual")
     return f1, f1d, U1, U1d, r, rd, T, Td
+
+
+def step_dual_move(c, wall_id, x, f, U, x_dot=None, f_dot=None, U_dot=None, lid_dot=0.0):
+    """One step S1..S8 of the moving cloud (c.move = 1) with tangents through
+    the geometry.  Returns (x1, x1_dot, f1, f1_dot, U1, U1_dot, rho, rho_dot,
+    T, T_dot)."""
+    N = c.n_particles
+    x, f, U = _f64(x), _f64(f), _f64(U)
+    keep = [_f64(v) if v is not None else None for v in (x_dot, f_dot, U_dot)]
+    a = lambda v: _d(v) if v is not None else None
+    x_dot, f_dot, U_dot = keep
+    x1, x1d = np.zeros((c.dim, N)), np.zeros((c.dim, N))
+    f1, f1d = np.empty_like(f), np.empty_like(f)
+    U1, U1d = np.zeros((c.dim, N)), np.zeros((c.dim, N))
+    r, rd, T, Td = np.zeros(N), np.zeros(N), np.zeros(N), np.zeros(N)
+    wall_id = _i32(wall_id)
+    _check(lib().ref_step_dual_move(ctypes.byref(c), _i(wall_id), _d(x), a(x_dot), _d(f),
+                                    a(f_dot), _d(U), a(U_dot), float(lid_dot), _d(x1), _d(x1d),
+                                    _d(f1), _d(f1d), _d(U1), _d(U1d), _d(r), _d(rd), _d(T),
+                                    _d(Td)), "step_dual_move")
+    return x1, x1d, f1, f1d, U1, U1d, r, rd, T, Td
+
+
+def rollout_dual_move(c, wall_id, x0, f0, nsteps, f0_dot=None, lid_dot=0.0, ke_weight=1.0):
+    """Moving-cloud rollout (c.move = 1); returns (J, dJ along (f0_dot, lid_dot))."""
+    J, Jd = ctypes.c_double(0), ctypes.c_double(0)
+    x0, f0, wall_id = _f64(x0), _f64(f0), _i32(wall_id)
+    fd = _f64(f0_dot) if f0_dot is not None else None
+    _check(lib().ref_rollout_dual_move(ctypes.byref(c), _i(wall_id), _d(x0),
+                                       _d(f0), _d(fd) if fd is not None else None,
+                                       float(lid_dot), int(nsteps),
+                                       float(ke_weight), ctypes.byref(J), ctypes.byref(Jd)),
+           "rollout_dual_move")
+    return J.value, Jd.value
 
 
 def objective_dual(c, wall_id, f, rho, U, f_dot=None, rho_dot=None, U_dot=None, ke_weight=1.0):

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <memory>
 #include <vector>
 
 #include <omp.h>
@@ -79,6 +80,22 @@ inline Dual s_sqrt(Dual a) {
 // |a|; at a = 0 the derivative of the + branch is taken
 inline double s_abs(double a) { return std::fabs(a); }
 inline Dual s_abs(Dual a) { return a.v < 0.0 ? Dual{-a.v, -a.d} : a; }
+inline double s_sin(double a) { return std::sin(a); }
+inline Dual s_sin(Dual a) { return {std::sin(a.v), std::cos(a.v) * a.d}; }
+inline double s_cos(double a) { return std::cos(a); }
+inline Dual s_cos(Dual a) { return {std::cos(a.v), -std::sin(a.v) * a.d}; }
+inline double s_atan2(double y, double x) { return std::atan2(y, x); }
+// d atan2(y, x) = (x dy - y dx) / (x^2 + y^2); taken as 0 at the origin
+inline Dual s_atan2(Dual y, Dual x) {
+  const double r2 = x.v * x.v + y.v * y.v;
+  return {std::atan2(y.v, x.v), r2 > 0.0 ? (x.v * y.d - y.v * x.d) / r2 : 0.0};
+}
+inline double s_acos(double a) { return std::acos(a); }
+// d acos(a) = -da / sqrt(1 - a^2); taken as 0 at a = +-1
+inline Dual s_acos(Dual a) {
+  const double q = 1.0 - a.v * a.v;
+  return {std::acos(a.v), q > 0.0 ? -a.d / std::sqrt(q) : 0.0};
+}
 
 // Compensated (Neumaier) summation of a long sequence: the running sum plus
 // the rounding error of every addition, so that a quadrature sum over a
@@ -229,27 +246,33 @@ void moments_row(const ref_config& c, const S* f, int64_t stride, S& rho, S U[3]
 // ball of radius h, the truncation of eq. weight being inclusive (r/h <= 1).
 // Written as the plain O(N^2) definition; the squared distance is summed
 // component by component, left to right.
-int neighbors(const ref_config& c, const double* x, int32_t* cnt, int32_t* idx) {
+// Row i; returns 1 if the row holds more than cap particles.
+template <class S>
+int neighbors_row(const ref_config& c, const S* x, int i, int32_t* cnt, int32_t* idx) {
   const int N = c.n_particles, d = c.dim, cap = c.cap;
   const double h2 = c.h * c.h;
+  int m = 0;
+  for (int j = 0; j < N; ++j) {
+    double r2 = 0.0;
+    for (int a = 0; a < d; ++a) {
+      const double dl = val(x[a * N + j]) - val(x[a * N + i]);
+      r2 = r2 + dl * dl;
+    }
+    if (r2 <= h2) {
+      if (m < cap) idx[static_cast<int64_t>(i) * cap + m] = j;
+      ++m;
+    }
+  }
+  cnt[i] = m;
+  return m > cap ? 1 : 0;
+}
+
+template <class S>
+int neighbors(const ref_config& c, const S* x, int32_t* cnt, int32_t* idx) {
+  const int N = c.n_particles;
   int overflow = 0;
 #pragma omp parallel for schedule(static) reduction(| : overflow)
-  for (int i = 0; i < N; ++i) {
-    int m = 0;
-    for (int j = 0; j < N; ++j) {
-      double r2 = 0.0;
-      for (int a = 0; a < d; ++a) {
-        const double dl = x[a * N + j] - x[a * N + i];
-        r2 = r2 + dl * dl;
-      }
-      if (r2 <= h2) {
-        if (m < cap) idx[static_cast<int64_t>(i) * cap + m] = j;
-        ++m;
-      }
-    }
-    cnt[i] = m;
-    if (m > cap) overflow = 1;
-  }
+  for (int i = 0; i < N; ++i) overflow |= neighbors_row(c, x, i, cnt, idx);
   return overflow ? R_ENBR_OVERFLOW : R_OK;
 }
 
@@ -270,12 +293,13 @@ int basis_size(int d, int deg) { return deg == 0 ? d : (deg == 1 ? d + 1 : (d ==
 // column of the basis that carries the first derivative along axis a
 int grad_column(int deg, int a) { return deg == 0 ? a : 1 + a; }
 
-void basis(int d, int deg, const double* y, double* p) {
+template <class S>
+void basis(int d, int deg, const S* y, S* p) {
   if (deg == 0) {
     for (int a = 0; a < d; ++a) p[a] = y[a];
     return;
   }
-  p[0] = 1.0;
+  p[0] = S(1.0);
   for (int a = 0; a < d; ++a) p[1 + a] = y[a];
   if (deg == 2) {
     int k = d + 1;
@@ -286,16 +310,17 @@ void basis(int d, int deg, const double* y, double* p) {
 
 // Cholesky factorisation A = L L^T of a symmetric B x B matrix (row major).
 // Returns false on a non-positive pivot.
-bool cholesky(int B, const double* A, double* L) {
-  for (int i = 0; i < B * B; ++i) L[i] = 0.0;
+template <class S>
+bool cholesky(int B, const S* A, S* L) {
+  for (int i = 0; i < B * B; ++i) L[i] = S(0.0);
   for (int j = 0; j < B; ++j) {
-    double s = A[j * B + j];
+    S s = A[j * B + j];
     for (int k = 0; k < j; ++k) s = s - L[j * B + k] * L[j * B + k];
-    if (!(s > 0.0)) return false;
-    const double ljj = std::sqrt(s);
+    if (!(val(s) > 0.0)) return false;
+    const S ljj = s_sqrt(s);
     L[j * B + j] = ljj;
     for (int i = j + 1; i < B; ++i) {
-      double t = A[i * B + j];
+      S t = A[i * B + j];
       for (int k = 0; k < j; ++k) t = t - L[i * B + k] * L[j * B + k];
       L[i * B + j] = t / ljj;
     }
@@ -304,15 +329,16 @@ bool cholesky(int B, const double* A, double* L) {
 }
 
 // Solve L L^T z = e_col.
-void chol_solve_unit(int B, const double* L, int col, double* z) {
-  double y[16];
+template <class S>
+void chol_solve_unit(int B, const S* L, int col, S* z) {
+  S y[16];
   for (int i = 0; i < B; ++i) {
-    double s = (i == col) ? 1.0 : 0.0;
+    S s = S((i == col) ? 1.0 : 0.0);
     for (int k = 0; k < i; ++k) s = s - L[i * B + k] * y[k];
     y[i] = s / L[i * B + i];
   }
   for (int i = B - 1; i >= 0; --i) {
-    double s = y[i];
+    S s = y[i];
     for (int k = i + 1; k < B; ++k) s = s - L[k * B + i] * z[k];
     z[i] = s / L[i * B + i];
   }
@@ -321,21 +347,22 @@ void chol_solve_unit(int B, const double* L, int col, double* z) {
 // Local frame of the edge i -> j (Section 3.4.2).  2D: n along the edge at
 // angle phi = atan2(dy, dx), t = n turned by +90 degrees.  3D: the matrix A
 // built from phi = atan2(dy, dx) and theta = arccos(dz/r); rows n, t, b.
-void edge_frame(int d, const double* dl, double n[3], double t[3], double b[3]) {
+template <class S>
+void edge_frame(int d, const S* dl, S n[3], S t[3], S b[3]) {
   if (d == 2) {
-    const double phi = std::atan2(dl[1], dl[0]);
-    n[0] = std::cos(phi);
-    n[1] = std::sin(phi);
-    t[0] = -std::sin(phi);
-    t[1] = std::cos(phi);
-    n[2] = t[2] = 0.0;
-    b[0] = b[1] = b[2] = 0.0;
+    const S phi = s_atan2(dl[1], dl[0]);
+    n[0] = s_cos(phi);
+    n[1] = s_sin(phi);
+    t[0] = -s_sin(phi);
+    t[1] = s_cos(phi);
+    n[2] = t[2] = S(0.0);
+    b[0] = b[1] = b[2] = S(0.0);
   } else {
-    const double r = std::sqrt(dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2]);
-    const double phi = std::atan2(dl[1], dl[0]);
-    const double th = std::acos(dl[2] / r);
-    const double st = std::sin(th), ct = std::cos(th);
-    const double sp = std::sin(phi), cp = std::cos(phi);
+    const S r = s_sqrt(dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2]);
+    const S phi = s_atan2(dl[1], dl[0]);
+    const S th = s_acos(dl[2] / r);
+    const S st = s_sin(th), ct = s_cos(th);
+    const S sp = s_sin(phi), cp = s_cos(phi);
     n[0] = st * cp;
     n[1] = st * sp;
     n[2] = ct;
@@ -344,7 +371,7 @@ void edge_frame(int d, const double* dl, double n[3], double t[3], double b[3]) 
     t[2] = -st;
     b[0] = -sp;
     b[1] = cp;
-    b[2] = 0.0;
+    b[2] = S(0.0);
   }
 }
 
@@ -357,71 +384,64 @@ void edge_frame(int d, const double* dl, double n[3], double t[3], double b[3]) 
 // Degree: the configured degree if the stencil has at least twice as many
 // points as basis functions, else degree 1 if it has d+2 points, else error
 // (degree 0 also needs d+2 points, the particle itself included).
-int wls(const ref_config& c, const double* x, const int32_t* wall_id, const int32_t* cnt,
-        const int32_t* idx, double* grad, double* ops, int32_t* degree) {
+// Row i (zero for wall particles); returns R_OK or R_ESINGULAR.
+template <class S>
+int wls_row(const ref_config& c, const S* x, const int32_t* wall_id, const int32_t* cnt,
+            const int32_t* idx, int i, S* grad, S* ops, int32_t* degree) {
   const int N = c.n_particles, d = c.dim, cap = c.cap, dd = d * d;
-  int err = R_OK;
-#pragma omp parallel for schedule(dynamic, 64)
-  for (int i = 0; i < N; ++i) {
+  {
     const int64_t row = static_cast<int64_t>(i) * cap;
     for (int e = 0; e < cap; ++e) {
-      for (int a = 0; a < d; ++a) grad[(row + e) * d + a] = 0.0;
-      for (int a = 0; a < dd; ++a) ops[(row + e) * dd + a] = 0.0;
+      for (int a = 0; a < d; ++a) grad[(row + e) * d + a] = S(0.0);
+      for (int a = 0; a < dd; ++a) ops[(row + e) * dd + a] = S(0.0);
     }
     if (degree) degree[i] = 0;
-    if (wall_id[i] != 0) continue;
+    if (wall_id[i] != 0) return R_OK;
     const int m = std::min<int>(cnt[i], cap);
     int deg = c.wls_degree;
     if (deg == 2 && m < 2 * basis_size(d, 2)) deg = 1;
-    if (m < d + 2) {
-#pragma omp critical
-      err = R_ESINGULAR;
-      continue;
-    }
+    if (m < d + 2) return R_ESINGULAR;
     const int B = basis_size(d, deg);
-    double A[100] = {0}, L[100];
-    std::vector<double> P(static_cast<size_t>(m) * B), W(m);
+    S A[100], L[100];
+    for (int k = 0; k < 100; ++k) A[k] = S(0.0);
+    std::vector<S> P(static_cast<size_t>(m) * B), W(m);
     for (int e = 0; e < m; ++e) {
       const int j = idx[row + e];
-      double y[3], r2 = 0.0;
+      S y[3], r2 = S(0.0);
       for (int a = 0; a < d; ++a) {
         y[a] = (x[a * N + j] - x[a * N + i]) / c.h;
         r2 = r2 + y[a] * y[a];
       }
-      W[e] = std::exp(-c.alpha * r2);
+      W[e] = s_exp(-c.alpha * r2);
       basis(d, deg, y, &P[static_cast<size_t>(e) * B]);
     }
     for (int e = 0; e < m; ++e)
       for (int r = 0; r < B; ++r)
         for (int s = 0; s < B; ++s)
           A[r * B + s] = A[r * B + s] + W[e] * P[e * B + r] * P[e * B + s];
-    if (!cholesky(B, A, L)) {
-#pragma omp critical
-      err = R_ESINGULAR;
-      continue;
-    }
-    double z[3][16];
+    if (!cholesky(B, A, L)) return R_ESINGULAR;
+    S z[3][16];
     for (int a = 0; a < d; ++a) chol_solve_unit(B, L, grad_column(deg, a), z[a]);
     for (int e = 0; e < m; ++e) {
       const int j = idx[row + e];
-      double g[3] = {0, 0, 0};
+      S g[3] = {S(0.0), S(0.0), S(0.0)};
       for (int a = 0; a < d; ++a) {
-        double s = 0.0;
+        S s = S(0.0);
         for (int r = 0; r < B; ++r) s = s + z[a][r] * P[e * B + r];
         g[a] = W[e] * s / c.h;
         grad[(row + e) * d + a] = g[a];
       }
       if (j == i) continue;
-      double dl[3] = {0, 0, 0}, n[3], t[3], b[3];
+      S dl[3] = {S(0.0), S(0.0), S(0.0)}, n[3], t[3], b[3];
       for (int a = 0; a < d; ++a) dl[a] = x[a * N + j] - x[a * N + i];
       edge_frame(d, dl, n, t, b);
-      double ab = 0, bb = 0, gb = 0;
+      S ab = S(0.0), bb = S(0.0), gb = S(0.0);
       for (int a = 0; a < d; ++a) {
         ab = ab + g[a] * n[a];
         bb = bb + g[a] * t[a];
         gb = gb + g[a] * b[a];
       }
-      double* o = &ops[(row + e) * dd];
+      S* o = &ops[(row + e) * dd];
       for (int a = 0; a < d; ++a) {
         o[a] = ab * n[a];
         o[d + a] = bb * t[a];
@@ -429,6 +449,22 @@ int wls(const ref_config& c, const double* x, const int32_t* wall_id, const int3
       }
     }
     if (degree) degree[i] = deg;
+  }
+  return R_OK;
+}
+
+template <class S>
+int wls(const ref_config& c, const S* x, const int32_t* wall_id, const int32_t* cnt,
+        const int32_t* idx, S* grad, S* ops, int32_t* degree) {
+  const int N = c.n_particles;
+  int err = R_OK;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int i = 0; i < N; ++i) {
+    const int e = wls_row(c, x, wall_id, cnt, idx, i, grad, ops, degree);
+    if (e != R_OK) {
+#pragma omp critical
+      err = e;
+    }
   }
   return err;
 }
@@ -444,38 +480,41 @@ int wls(const ref_config& c, const double* x, const int32_t* wall_id, const int3
 // h, 1.5h, 2h holding at least d+2 of them (ascending), and the degree-1
 // least-squares value weights at xq (weights exp(-alpha r^2/hb^2)), so that
 // f(xq) ~ sum_e c0[e] f_{S[e]}.
-int value_row(const ref_config& c, const double* x, const int32_t* wall_id, const double* xq,
-              std::vector<int>& S, std::vector<double>& c0, double& hb) {
+// (The set and the radius depend on the positions' values only.)
+template <class S>
+int value_row(const ref_config& c, const S* x, const int32_t* wall_id, const S* xq,
+              std::vector<int>& set, std::vector<S>& c0, double& hb) {
   const int N = c.n_particles, d = c.dim;
   const double mults[3] = {1.0, 1.5, 2.0};
   for (int k = 0; k < 3; ++k) {
     hb = mults[k] * c.h;
     const double hb2 = hb * hb;
-    S.clear();
+    set.clear();
     for (int j = 0; j < N; ++j) {
       if (wall_id[j] != 0) continue;
       double r2 = 0.0;
       for (int a = 0; a < d; ++a) {
-        const double dl = x[a * N + j] - xq[a];
+        const double dl = val(x[a * N + j]) - val(xq[a]);
         r2 = r2 + dl * dl;
       }
-      if (r2 <= hb2) S.push_back(j);
+      if (r2 <= hb2) set.push_back(j);
     }
-    if (static_cast<int>(S.size()) >= d + 2) break;
+    if (static_cast<int>(set.size()) >= d + 2) break;
   }
-  const int m = static_cast<int>(S.size());
+  const int m = static_cast<int>(set.size());
   if (m < d + 2) return R_ESINGULAR;
   if (m > c.cap) return R_ENBR_OVERFLOW;
   const int B = d + 1;
-  double A[16] = {0}, L[16];
-  std::vector<double> P(static_cast<size_t>(m) * B), W(m);
+  S A[16], L[16];
+  for (int k = 0; k < 16; ++k) A[k] = S(0.0);
+  std::vector<S> P(static_cast<size_t>(m) * B), W(m);
   for (int e = 0; e < m; ++e) {
-    double y[3], r2 = 0.0;
+    S y[3], r2 = S(0.0);
     for (int a = 0; a < d; ++a) {
-      y[a] = (x[a * N + S[e]] - xq[a]) / hb;
+      y[a] = (x[a * N + set[e]] - xq[a]) / hb;
       r2 = r2 + y[a] * y[a];
     }
-    W[e] = std::exp(-c.alpha * r2);
+    W[e] = s_exp(-c.alpha * r2);
     basis(d, 1, y, &P[static_cast<size_t>(e) * B]);
   }
   for (int e = 0; e < m; ++e)
@@ -483,19 +522,20 @@ int value_row(const ref_config& c, const double* x, const int32_t* wall_id, cons
       for (int s = 0; s < B; ++s)
         A[r * B + s] = A[r * B + s] + W[e] * P[e * B + r] * P[e * B + s];
   if (!cholesky(B, A, L)) return R_ESINGULAR;
-  double z[16];
+  S z[16];
   chol_solve_unit(B, L, 0, z);
-  c0.assign(m, 0.0);
+  c0.assign(m, S(0.0));
   for (int e = 0; e < m; ++e) {
-    double s = 0.0;
+    S s = S(0.0);
     for (int r = 0; r < B; ++r) s = s + z[r] * P[e * B + r];
     c0[e] = W[e] * s;
   }
   return R_OK;
 }
 
-int wall_stencil(const ref_config& c, const double* x, const int32_t* wall_id, int32_t* wcnt,
-                 int32_t* widx, double* wc0, double* hb_out) {
+template <class S>
+int wall_stencil(const ref_config& c, const S* x, const int32_t* wall_id, int32_t* wcnt,
+                 int32_t* widx, S* wc0, double* hb_out) {
   const int N = c.n_particles, d = c.dim, cap = c.cap;
   int err = R_OK;
 #pragma omp parallel for schedule(dynamic, 16)
@@ -504,20 +544,20 @@ int wall_stencil(const ref_config& c, const double* x, const int32_t* wall_id, i
     wcnt[b] = 0;
     if (hb_out) hb_out[b] = 0.0;
     if (wall_id[b] == 0) continue;
-    double xb[3] = {0.0, 0.0, 0.0};
+    S xb[3] = {S(0.0), S(0.0), S(0.0)};
     for (int a = 0; a < d; ++a) xb[a] = x[a * N + b];
-    std::vector<int> S;
-    std::vector<double> c0;
+    std::vector<int> set;
+    std::vector<S> c0;
     double hb = 0.0;
-    const int rc = value_row(c, x, wall_id, xb, S, c0, hb);
+    const int rc = value_row(c, x, wall_id, xb, set, c0, hb);
     if (rc != R_OK) {
 #pragma omp critical
       err = rc;
       continue;
     }
-    const int m = static_cast<int>(S.size());
+    const int m = static_cast<int>(set.size());
     for (int e = 0; e < m; ++e) {
-      widx[row + e] = S[e];
+      widx[row + e] = set[e];
       wc0[row + e] = c0[e];
     }
     wcnt[b] = m;
@@ -722,13 +762,15 @@ int pm_apply(const ref_config& c, const double* x, const int32_t* wall_id, const
 // (+ gbar[w.b - sign(gbar)|w.b|]) with the dissipation of the n-term taken
 // as |abar||w.n| (equal to the printed form when abar >= 0, which is the
 // positivity hypothesis of the scheme).  Wall particles are not transported.
-template <class S>
-void transport(const ref_config& c, const int32_t* wall_id, const int32_t* cnt, const int32_t* idx,
-               const double* grad, const double* ops, const S* U, const S* f, S* ft) {
+// (G: the operators' type, double for a fixed cloud or the state's type
+// when the cloud moves with the state.)
+template <class S, class G>
+void transport_row(const ref_config& c, const int32_t* wall_id, const int32_t* cnt,
+                   const int32_t* idx, const G* grad, const G* ops, const S* U,
+                   const S* f, S* ft, int i) {
   const int N = c.n_particles, d = c.dim, cap = c.cap, dd = d * d, nc = n_comp(c);
   const int64_t NV = n_vel(c);
-#pragma omp parallel for schedule(dynamic, 16)
-  for (int i = 0; i < N; ++i) {
+  {
     for (int k = 0; k < nc; ++k) {
       const S* fi = f + (static_cast<int64_t>(k) * N + i) * NV;
       S* out = ft + (static_cast<int64_t>(k) * N + i) * NV;
@@ -736,7 +778,7 @@ void transport(const ref_config& c, const int32_t* wall_id, const int32_t* cnt, 
         for (int64_t q = 0; q < NV; ++q) out[q] = fi[q];
       }
     }
-    if (wall_id[i] != 0) continue;
+    if (wall_id[i] != 0) return;
     const int64_t row = static_cast<int64_t>(i) * cap;
     const int m = std::min<int>(cnt[i], cap);
     double v[3];
@@ -748,8 +790,8 @@ void transport(const ref_config& c, const int32_t* wall_id, const int32_t* cnt, 
       for (int e = 0; e < m; ++e) {
         const int j = idx[row + e];
         if (j == i) continue;
-        const double* g = &grad[(row + e) * d];
-        const double* o = &ops[(row + e) * dd];
+        const G* g = &grad[(row + e) * d];
+        const G* o = &ops[(row + e) * dd];
         S gw = S(0.0), pw = S(0.0), qw = S(0.0), rw = S(0.0);
         for (int a = 0; a < d; ++a) {
           gw = gw + g[a] * w[a];
@@ -773,27 +815,32 @@ void transport(const ref_config& c, const int32_t* wall_id, const int32_t* cnt, 
   }
 }
 
+template <class S, class G>
+void transport(const ref_config& c, const int32_t* wall_id, const int32_t* cnt, const int32_t* idx,
+               const G* grad, const G* ops, const S* U, const S* f, S* ft) {
+  const int N = c.n_particles;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int i = 0; i < N; ++i) transport_row(c, wall_id, cnt, idx, grad, ops, U, f, ft, i);
+}
+
 // ---------------------------------------------------------------------------
 // Implicit relaxation (Section 3.2.1: eqs. implicitfull_1 and fullmoment1a
 // and the closed form that follows; Section 3.2.2 reduced model: eqs.
 // implicit_1/2, moment1a, moment1b).  The new (rho, U, T) are the moments of
 // ft; tau is taken at the new state; f^{n+1} = (tau ft + dt M^{n+1})/(tau+dt).
+// Row i (nothing for wall particles); returns R_OK or R_ENONPHYS.
 template <class S>
-int collide(const ref_config& c, const int32_t* wall_id, const S* ft, S* fout, S* rho, S* U,
-            S* T) {
+int collide_row(const ref_config& c, const int32_t* wall_id, const S* ft, S* fout, S* rho, S* U,
+                S* T, int i) {
   const int N = c.n_particles, nc = n_comp(c);
   const int64_t NV = n_vel(c), stride = static_cast<int64_t>(N) * NV;
   int err = R_OK;
-#pragma omp parallel for schedule(dynamic, 16)
-  for (int i = 0; i < N; ++i) {
-    if (wall_id[i] != 0) continue;
+  {
+    if (wall_id[i] != 0) return R_OK;
     const S* fi = ft + static_cast<int64_t>(i) * NV;
     S r, u[3], tt;
     moments_row(c, fi, stride, r, u, tt);
-    if (!(val(r) > 0.0) || !(val(tt) > 0.0)) {
-#pragma omp critical
-      err = R_ENONPHYS;
-    }
+    if (!(val(r) > 0.0) || !(val(tt) > 0.0)) err = R_ENONPHYS;
     rho[i] = r;
     T[i] = tt;
     for (int a = 0; a < c.dim; ++a) U[a * N + i] = u[a];
@@ -806,6 +853,22 @@ int collide(const ref_config& c, const int32_t* wall_id, const S* ft, S* fout, S
         const int64_t o = k * stride + static_cast<int64_t>(i) * NV + q;
         fout[o] = (tau * ft[o] + c.dt * M) / (tau + c.dt);
       }
+    }
+  }
+  return err;
+}
+
+template <class S>
+int collide(const ref_config& c, const int32_t* wall_id, const S* ft, S* fout, S* rho, S* U,
+            S* T) {
+  const int N = c.n_particles;
+  int err = R_OK;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int i = 0; i < N; ++i) {
+    const int e = collide_row(c, wall_id, ft, fout, rho, U, T, i);
+    if (e != R_OK) {
+#pragma omp critical
+      err = e;
     }
   }
   return err;
@@ -828,9 +891,9 @@ inline void wall_geometry(int d, int w, int& axis, double& sign, bool& is_lid) {
 // rho_w M[1, U_w, T_w] (Chu: g1 = rho_w G1hat, g2 = T_w rho_w G1hat) with
 // rho_w fixed by zero net discrete mass flux through the wall.  Then the
 // wall particle's (rho, U, T) are the moments of its new f.
-template <class S>
+template <class S, class G>
 int wall_bc(const ref_config& c, const S& lid, const int32_t* wall_id, const int32_t* wcnt,
-            const int32_t* widx, const double* wc0, S* f, S* rho, S* U, S* T) {
+            const int32_t* widx, const G* wc0, S* f, S* rho, S* U, S* T) {
   const int N = c.n_particles, d = c.dim, cap = c.cap, nc = n_comp(c);
   const int64_t NV = n_vel(c), stride = static_cast<int64_t>(N) * NV;
   int err = R_OK;
@@ -887,20 +950,22 @@ int wall_bc(const ref_config& c, const S& lid, const int32_t* wall_id, const int
 // ALE position update (Section 3.2.1: x^{n+1} = x^n + dt U^{n+1}) for interior
 // particles, kept inside [0.1 dx, 1 - 0.1 dx]^d (particle management is out
 // of this step; clamped coordinates are counted).
-int move(const ref_config& c, const int32_t* wall_id, const double* U, double* x) {
+// (A clamped coordinate is the constant bound: its derivative is zero.)
+template <class S>
+int move(const ref_config& c, const int32_t* wall_id, const S* U, S* x) {
   const int N = c.n_particles;
   const double lo = 0.1 * c.dx, hi = 1.0 - 0.1 * c.dx;
   int clamped = 0;
   for (int i = 0; i < N; ++i) {
     if (wall_id[i] != 0) continue;
     for (int a = 0; a < c.dim; ++a) {
-      double y = x[a * N + i] + c.dt * U[a * N + i];
-      if (y < lo) {
-        y = lo;
+      S y = x[a * N + i] + c.dt * U[a * N + i];
+      if (val(y) < lo) {
+        y = S(lo);
         ++clamped;
       }
-      if (y > hi) {
-        y = hi;
+      if (val(y) > hi) {
+        y = S(hi);
         ++clamped;
       }
       x[a * N + i] = y;
@@ -957,20 +1022,22 @@ S objective(const ref_config& c, const int32_t* wall_id, const S* f, const S* rh
   return J;
 }
 
-// Geometry of one step: neighbours, operators and wall stencils at x.
-struct Geometry {
+// Geometry of one step: neighbours, operators and wall stencils at x (G:
+// double, or the dual type when the positions carry derivatives).
+template <class G>
+struct GeometryT {
   std::vector<int32_t> cnt, idx, deg, wcnt, widx;
-  std::vector<double> grad, ops, wc0;
-  int build(const ref_config& c, const double* x, const int32_t* wall_id) {
+  std::vector<G> grad, ops, wc0;
+  int build(const ref_config& c, const G* x, const int32_t* wall_id) {
     const int64_t N = c.n_particles, cap = c.cap;
     cnt.assign(N, 0);
     idx.assign(N * cap, 0);
     deg.assign(N, 0);
     wcnt.assign(N, 0);
     widx.assign(N * cap, 0);
-    grad.assign(N * cap * c.dim, 0.0);
-    ops.assign(N * cap * c.dim * c.dim, 0.0);
-    wc0.assign(N * cap, 0.0);
+    grad.assign(N * cap * c.dim, G(0.0));
+    ops.assign(N * cap * c.dim * c.dim, G(0.0));
+    wc0.assign(N * cap, G(0.0));
     int rc = neighbors(c, x, cnt.data(), idx.data());
     if (rc) return rc;
     rc = wls(c, x, wall_id, cnt.data(), idx.data(), grad.data(), ops.data(), deg.data());
@@ -978,12 +1045,13 @@ struct Geometry {
     return wall_stencil(c, x, wall_id, wcnt.data(), widx.data(), wc0.data(), nullptr);
   }
 };
+using Geometry = GeometryT<double>;
 
 // One time step on the state (f, U) at positions x with a given geometry:
 // transport, moments + relaxation, walls.  f_out receives f^{n+1}; U is
 // overwritten with U^{n+1}; rho and T receive the new values.
-template <class S>
-int advance(const ref_config& c, const Geometry& g, const int32_t* wall_id, const S& lid,
+template <class S, class G>
+int advance(const ref_config& c, const GeometryT<G>& g, const int32_t* wall_id, const S& lid,
             const S* f_in, S* f_out, S* U, S* rho, S* T) {
   const int64_t total = static_cast<int64_t>(n_comp(c)) * c.n_particles * n_vel(c);
   std::vector<S> ft(total);
@@ -1124,6 +1192,50 @@ int ref_move(const ref_config* c, const int32_t* wall_id, const double* U, doubl
   return R_OK;
 }
 
+// Timing sample of the per-particle work of one step (S1-S6) for the
+// interior particles among i0..i1-1: the neighbour row, the least-squares
+// row, the transport of the row and its moments + relaxation, with the same
+// row functions the full step uses, on `threads` OpenMP threads (0: all).
+// Rows of the other particles are not computed.  f_out (full [n_c][N][N_v])
+// receives the new rows of the sampled particles; *seconds the wall time of
+// the row work alone (buffers are allocated before the clock starts).
+int ref_step_rows(const ref_config* c, const int32_t* wall_id, const double* x,
+                  const double* f_in, const double* U_in, int i0, int i1, int threads,
+                  double* f_out, double* seconds, int32_t* n_rows) {
+  if (!config_ok(*c) || i0 < 0 || i1 > c->n_particles || i0 > i1) return R_EINVAL;
+  const int64_t N = c->n_particles, cap = c->cap, d = c->dim;
+  std::vector<int32_t> cnt(N, 0), idx(N * cap, 0), deg(N, 0);
+  std::vector<double> grad(N * cap * d, 0.0), ops(N * cap * d * d, 0.0);
+  std::vector<double> U(U_in, U_in + d * N), rho(N, 0.0), T(N, 0.0);
+  std::unique_ptr<double[]> ft(new double[n_comp(*c) * N * n_vel(*c)]);
+  std::vector<int> rows;
+  for (int i = i0; i < i1; ++i)
+    if (wall_id[i] == 0) rows.push_back(i);
+  const int nr = static_cast<int>(rows.size());
+  const int nt = threads > 0 ? threads : omp_get_max_threads();
+  int err = R_OK;
+  const double t0 = omp_get_wtime();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+  for (int r = 0; r < nr; ++r) {
+    const int i = rows[r];
+    int e = neighbors_row(*c, x, i, cnt.data(), idx.data()) ? R_ENBR_OVERFLOW : R_OK;
+    if (e == R_OK)
+      e = wls_row(*c, x, wall_id, cnt.data(), idx.data(), i, grad.data(), ops.data(), deg.data());
+    if (e == R_OK) {
+      transport_row(*c, wall_id, cnt.data(), idx.data(), grad.data(), ops.data(), U_in, f_in,
+                    ft.get(), i);
+      e = collide_row(*c, wall_id, ft.get(), f_out, rho.data(), U.data(), T.data(), i);
+    }
+    if (e != R_OK) {
+#pragma omp critical
+      err = e;
+    }
+  }
+  *seconds = omp_get_wtime() - t0;
+  if (n_rows) *n_rows = nr;
+  return err;
+}
+
 // One full step S1..S8: geometry at x^n, transport with U^n, relaxation,
 // walls, then (if c->move) x^{n+1} = x^n + dt U^{n+1}.
 int ref_step(const ref_config* c, const int32_t* wall_id, double* x, const double* f_in,
@@ -1185,6 +1297,93 @@ int ref_rollout_dual(const ref_config* c, const int32_t* wall_id, const double* 
 // One frozen-cloud step with tangents: (f, U) with directions (f_dot,
 // U_dot) and the lid speed's direction lid_dot -> f^{n+1}, U^{n+1}, rho, T
 // and their exact directional derivatives.  Null tangent inputs are zero.
+// One full step S1..S8 with the cloud moving (c->move must be 1), every
+// quantity carrying one directional derivative: the geometry (neighbour
+// sets fixed by the positions' values; least-squares rows, edge frames and
+// wall rows as functions of the positions), transport, relaxation, walls
+// and the position update, so that the derivative includes how the moving
+// cloud changes the operators.  Inputs: state (x, f, U) and tangents
+// (x_dot, f_dot, U_dot; each may be null = 0) and lid_dot; outputs the new
+// state and its tangents.
+int ref_step_dual_move(const ref_config* c, const int32_t* wall_id, const double* x,
+                       const double* x_dot, const double* f, const double* f_dot,
+                       const double* U, const double* U_dot, double lid_dot, double* x_out,
+                       double* x_out_dot, double* f_out, double* f_out_dot, double* U_out,
+                       double* U_out_dot, double* rho, double* rho_dot, double* T,
+                       double* T_dot) {
+  if (!config_ok(*c) || !c->move) return R_EINVAL;
+  const int N = c->n_particles, d = c->dim;
+  const int64_t total = static_cast<int64_t>(n_comp(*c)) * N * n_vel(*c);
+  std::vector<Dual> xd(static_cast<size_t>(d) * N), fa(total), fb(total),
+      Ud(static_cast<size_t>(3) * N), rd(N), Td(N);
+  for (int64_t k = 0; k < static_cast<int64_t>(d) * N; ++k) {
+    xd[k] = Dual(x[k], x_dot ? x_dot[k] : 0.0);
+    Ud[k] = Dual(U[k], U_dot ? U_dot[k] : 0.0);
+  }
+  for (int64_t k = 0; k < total; ++k) fa[k] = Dual(f[k], f_dot ? f_dot[k] : 0.0);
+  GeometryT<Dual> g;
+  int rc = g.build(*c, xd.data(), wall_id);
+  if (rc) return rc;
+  rc = advance(*c, g, wall_id, Dual(c->lid, lid_dot), fa.data(), fb.data(), Ud.data(), rd.data(),
+               Td.data());
+  move(*c, wall_id, Ud.data(), xd.data());
+  for (int64_t k = 0; k < total; ++k) {
+    f_out[k] = fb[k].v;
+    f_out_dot[k] = fb[k].d;
+  }
+  for (int64_t k = 0; k < static_cast<int64_t>(d) * N; ++k) {
+    U_out[k] = Ud[k].v;
+    U_out_dot[k] = Ud[k].d;
+    x_out[k] = xd[k].v;
+    x_out_dot[k] = xd[k].d;
+  }
+  for (int i = 0; i < N; ++i) {
+    rho[i] = rd[i].v;
+    rho_dot[i] = rd[i].d;
+    T[i] = Td[i].v;
+    T_dot[i] = Td[i].d;
+  }
+  return rc;
+}
+
+// Rollout with the moving cloud (c->move must be 1): (rho, U, T)^0 are the
+// moments of f0, then nsteps full steps S1..S8, then J of the final state.
+// Returns J and its exact directional derivative along (f0_dot, lid_dot),
+// through the moving geometry.
+int ref_rollout_dual_move(const ref_config* c, const int32_t* wall_id, const double* x0,
+                          const double* f0, const double* f0_dot, double lid_dot, int nsteps,
+                          double ke_weight, double* J, double* J_dot) {
+  if (!config_ok(*c) || !c->move) return R_EINVAL;
+  const int N = c->n_particles, d = c->dim;
+  const int64_t total = static_cast<int64_t>(n_comp(*c)) * N * n_vel(*c);
+  std::vector<Dual> xd(static_cast<size_t>(d) * N), fa(total), fb(total),
+      U(static_cast<size_t>(3) * N), rho(N), T(N);
+  for (int64_t k = 0; k < static_cast<int64_t>(d) * N; ++k) xd[k] = Dual(x0[k]);
+  for (int64_t k = 0; k < total; ++k) fa[k] = Dual(f0[k], f0_dot ? f0_dot[k] : 0.0);
+  const int64_t NV = n_vel(*c), stride = static_cast<int64_t>(N) * NV;
+  for (int i = 0; i < N; ++i) {
+    Dual r, u[3], t;
+    moments_row(*c, fa.data() + static_cast<int64_t>(i) * NV, stride, r, u, t);
+    rho[i] = r;
+    T[i] = t;
+    for (int a = 0; a < d; ++a) U[a * N + i] = u[a];
+  }
+  const Dual lid(c->lid, lid_dot);
+  for (int s = 0; s < nsteps; ++s) {
+    GeometryT<Dual> g;
+    int rc = g.build(*c, xd.data(), wall_id);
+    if (rc) return rc;
+    rc = advance(*c, g, wall_id, lid, fa.data(), fb.data(), U.data(), rho.data(), T.data());
+    if (rc) return rc;
+    std::swap(fa, fb);
+    move(*c, wall_id, U.data(), xd.data());
+  }
+  const Dual Jd = objective(*c, wall_id, fa.data(), rho.data(), U.data(), ke_weight);
+  *J = Jd.v;
+  *J_dot = Jd.d;
+  return R_OK;
+}
+
 int ref_step_dual(const ref_config* c, const int32_t* wall_id, const double* x, const double* f,
                   const double* f_dot, const double* U, const double* U_dot, double lid_dot,
                   double* f_out, double* f_out_dot, double* U_out, double* U_out_dot,

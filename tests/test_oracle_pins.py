@@ -632,6 +632,26 @@ def test_lid_drives_flow_and_config_dt_keeps_f_positive():
     assert np.all(x1[:, wid != 0] == x[:, wid != 0])
 
 
+@pytest.mark.parametrize("dim,n,nv", [(2, 12, 8), (3, 7, 6)])
+def test_row_sample_equals_the_full_step_rows(dim, n, nv):
+    """The timing sample (neighbour, least-squares, transport and relaxation
+    rows of a window of particles) computes the sampled interior rows of
+    f^{n+1} exactly as the full step does, on one thread and on several."""
+    x, wid = make_cloud(dim, n, 2)
+    c = cfg(dim, n, nv, 4.0)
+    f0, *_ = oracle.initial_state(c)
+    rng = np.random.default_rng(4)
+    f = f0 * rng.uniform(0.8, 1.2, f0.shape)
+    rho, U, T = oracle.moments(c, f)
+    _, f1, *_ = oracle.step(c, wid, x, f, U)
+    i0, i1 = n + 3, c.n_particles - n - 5
+    rows = [i for i in range(i0, i1) if wid[i] == 0]
+    for threads in (1, 3):
+        fs, sec, nr = oracle.step_rows(c, wid, x, f, U, i0, i1, threads)
+        assert nr == len(rows) and sec > 0
+        assert np.array_equal(fs[:, rows], f1[:, rows])
+
+
 # --------------------------------------------------------------- dual numbers
 def test_dual_directional_derivative_matches_central_differences():
     n = 8
