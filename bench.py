@@ -7,10 +7,12 @@ particle and velocity of the workload, with all inputs resident in HBM.  The
 metric is particle x velocity updates per second: N * N_v / t_step (a Chu
 pair g1, g2 counts once).
 
-Default workload: the 2D Chu-reduced cavity with 200 x 200 particles and
-32 x 32 velocities on [-5, 5]^2, FP64 (h = 2.5 dx, Kn = 1, lid 0.1).  The
-same run is repeated in FP32 and BF16-operand modes and their moment errors
-against the FP64 run are reported next to their rates.
+Default workload: the 3D cavity with 48^3 particles and 20^3 velocities on
+[-4, 4]^3 (full BGK, h = 2.2 dx, Kn = 1, lid 0.1, moving cloud), FP64.  The
+same run is repeated in FP32 and BF16-operand modes; each precision then
+continues untimed to the workload's 200 steps, and the errors of rho, u, T
+against the FP64 run are reported there, at Kn = 1 and (unless
+--no-kn-sweep) at Kn = 0.1 and 10.
 
 Printed: one JSON line (the benchmark contract), with the roofline of the
 dominant kernel (the transport, timed with HIP events on the library's
@@ -99,7 +101,9 @@ def cav_interior(cav):
     return (cav.n - 2) ** cav.dim
 
 
-def run_gpu(cav, precision, steps, warmup, timing=True):
+def run_gpu(cav, precision, steps, warmup, timing=True, total_steps=None):
+    """Time `steps` full steps after `warmup`; then (untimed) continue to
+    total_steps.  Returns the timing and (rho, U, T) at the last step."""
     import torch
 
     import paper_2408_02350_amd.bgk as bgk
@@ -127,8 +131,39 @@ def run_gpu(cav, precision, steps, warmup, timing=True):
     ms = (t1 - t0) * 1e3 / steps
     log(f"[bench] {precision}: {ms:.4f} ms/step, transport {ktime[0] / max(ktime[1], 1):.4f} ms "
         f"x {ktime[1]}, edges {edges}, diag {diag}")
+    done = warmup + steps
+    if total_steps is not None and total_steps > done:
+        sim.step(total_steps - done)
+        bgk.bgk_check(sim.ctx)
+        done = total_steps
+    torch.cuda.synchronize()
     state = (sim.rho.cpu().numpy(), sim.U.cpu().numpy(), sim.T.cpu().numpy())
-    return ms, ktime, edges, state, diag
+    del sim
+    torch.cuda.empty_cache()
+    return ms, ktime, edges, state, diag, done
+
+
+def follow_run(cav, precision, steps, follow=None, record=None):
+    """Untimed run of `steps` steps.  record: a list that receives the
+    positions before every step; follow: positions to take before every step
+    (another run's cloud).  Returns (rho, U, T) after the last step."""
+    import torch
+
+    import paper_2408_02350_amd.bgk as bgk
+
+    sim = bgk.Simulation(cav, precision=precision, device="cuda:0")
+    for s in range(steps):
+        if record is not None:
+            record.append(sim.x.clone())
+        if follow is not None:
+            sim.x.copy_(follow[s])
+        sim.step(1)
+    bgk.bgk_check(sim.ctx)
+    torch.cuda.synchronize()
+    state = (sim.rho.cpu().numpy(), sim.U.cpu().numpy(), sim.T.cpu().numpy())
+    del sim
+    torch.cuda.empty_cache()
+    return state
 
 
 def time_particle_management(cav, reps):
@@ -245,32 +280,78 @@ def moment_errors(state, ref, lid):
     return e_rho, e_u, e_T
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cav, budget_s):
-    """The CPU oracle on the host cores, on a bounded sample of the workload:
-    full steps of the same cloud (the first one after the initial state),
-    repeated while the budget lasts (at least one)."""
+    """The CPU oracle on the host cores, on a bounded sample of the workload.
+
+    The oracle's full step at the 3D sizes takes minutes, so the sample is
+    the per-particle work of one step (neighbour row by the oracle's O(N)
+    scan, least-squares row, transport of the row over all velocities, its
+    moments and relaxation: S1-S6, the same row functions the oracle's full
+    step runs) for a window of consecutive interior particles of the
+    workload's cloud, sized to about budget_s seconds; the rate is that
+    window's particle x velocity updates per second (walls and motion, a
+    few percent of a step, are not in the sample).  Timed once on all the
+    OpenMP threads and once on one thread."""
+    import numpy as np
+
     import oracle
     from paper_2408_02350_amd.inputs import cloud_for
 
     c = oracle.config(cav)
     x, wid = cloud_for(cav)
-    f, rho, U, T = oracle.initial_state(c)
-    n, t = 0, 0.0
-    while n == 0 or t < budget_s * 0.5:
-        t0 = time.perf_counter()
-        x, f, U, rho, T, _ = oracle.step(c, wid, x, f, U)
-        t += time.perf_counter() - t0
-        n += 1
-        log(f"[bench] oracle step {n}: {t / n:.2f} s/step")
-        if t / n > budget_s:
-            break
-    per = t / n
-    return {"value": cav.n_particles * cav.n_velocities / per,
-            "unit": "particle-velocity updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{n} full step(s) of {cav.name} ({cav.n_particles} particles x "
-                      f"{cav.n_velocities} velocities) from the rest state, FP64, "
-                      f"{per:.2f} s/step"}
+    N = cav.n_particles
+    interior = np.nonzero(wid == 0)[0]
+    start = len(interior) // 4
+    kmax = min(20000, len(interior) - 1 - start)      # window limit, interior rows
+    # timing input: a constant f and a resting gas (the row work does not
+    # depend on the values).  Only the rows a window can read are filled:
+    # the window and its neighbours, which lie within 3 lattice layers.
+    margin = 4 * cav.n ** (cav.dim - 1)
+    lo = max(0, int(interior[start]) - margin)
+    hi = min(N, int(interior[start + kmax]) + 1 + margin)
+    f = np.empty((cav.n_comp, N, cav.n_velocities))
+    f[:, lo:hi] = 0.01
+    U = np.zeros((cav.dim, N))
+
+    def sample(threads):
+        k, sec, rows = 64, 0.0, 0
+        i0 = int(interior[start])
+        while True:     # grow the window until it takes about budget_s
+            i1 = int(interior[start + k]) + 1
+            _, sec, rows = oracle.step_rows(c, wid, x, f, U, i0, i1, threads)
+            if sec >= 0.25 * budget_s or k >= kmax:
+                break
+            k = min(kmax, int(k * min(16.0, max(2.0, budget_s / max(sec, 1e-3)))))
+        if sec < 0.5 * budget_s and k < kmax:
+            k = min(kmax, int(k * budget_s / max(sec, 1e-3)))
+            i1 = int(interior[start + k]) + 1
+            _, sec, rows = oracle.step_rows(c, wid, x, f, U, i0, i1, threads)
+        log(f"[bench] oracle sample, {threads or oracle.num_threads()} thread(s): {rows} rows "
+            f"in {sec:.2f} s")
+        return rows * cav.n_velocities / sec, rows, sec
+
+    cores = oracle.num_threads()
+    v_all, r_all, s_all = sample(0)
+    v_one, r_one, s_one = sample(1)
+    return {"value": v_all, "unit": "particle-velocity updates/s", "cores": cores,
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "single_thread": {"value": v_one, "cores": 1, "rows": r_one, "seconds": s_one},
+            "sample": f"S1-S6 of {r_all} consecutive interior particles ({r_one} on one thread) "
+                      f"of {cav.name} ({cav.n_particles} particles x {cav.n_velocities} "
+                      f"velocities, FP64; the oracle's row functions: O(N) neighbour scan, "
+                      f"least-squares row, transport of the row, moments + relaxation), "
+                      f"{s_all:.1f} s on {cores} threads, {s_one:.1f} s on one thread"}
 
 
 def main():
@@ -278,11 +359,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", help="c1..c5 (default c2)")
+    ap.add_argument("--workload", default="c5", help="c1..c5 (default c5)")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/BF16 runs")
+    ap.add_argument("--no-kn-sweep", action="store_true",
+                    help="report the FP32/BF16 errors at the workload's Kn only")
+    ap.add_argument("--error-steps", type=int, default=None,
+                    help="steps after which the FP32/BF16 errors are taken (default: the "
+                         "workload's step count, at least warmup + steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="CPU seconds of each oracle sample (all threads, then one thread)")
     ap.add_argument("--paper-scales", action="store_true",
                     help="only time the paper's own cavity sizes (20 velocity points per "
                          "axis, h = 3.1 dx, first-derivative least squares) and print one "
@@ -319,7 +406,7 @@ def main():
         rows = []
         for key, pc in PAPER_SCALES.items():
             pc = pc.replace(precision=args.precision)
-            ms, ktime, edges, _, _ = run_gpu(pc, args.precision, args.steps, args.warmup)
+            ms, ktime, edges, *_ = run_gpu(pc, args.precision, args.steps, args.warmup)
             interior = cav_interior(pc)
             rows.append({"workload": pc.name, "n_particles": pc.n_particles,
                          "n_velocities": pc.n_velocities, "h_over_dx": pc.h_factor,
@@ -346,7 +433,11 @@ def main():
         return
 
     cav = CONFIGS[args.workload].replace(precision=args.precision)
-    ms, ktime, edges, state, diag = run_gpu(cav, args.precision, args.steps, args.warmup)
+    mixed_on = not args.no_mixed and args.precision == "fp64"
+    err_steps = args.error_steps if args.error_steps is not None else cav.steps
+    err_steps = max(err_steps, args.warmup + args.steps)
+    ms, ktime, edges, state, diag, _ = run_gpu(cav, args.precision, args.steps, args.warmup,
+                                               total_steps=err_steps if mixed_on else None)
     updates = cav.n_particles * cav.n_velocities
     value = updates / (ms * 1e-3)
 
@@ -389,17 +480,51 @@ def main():
         "roofline": roof,
     }
 
-    if not args.no_mixed and args.precision == "fp64":
+    if mixed_on:
+        # FP32 and BF16 operands: timed like the FP64 run.  Their errors of
+        # rho, u (over the lid speed) and T against FP64 after err_steps steps
+        # are taken along the FP64 run's cloud (the run takes the FP64 run's
+        # positions before every step: two free runs a rounding apart cross
+        # the weight's truncation r = h at different steps, a discontinuity
+        # of the method rather than an error of the arithmetic), and, as
+        # "free", from the free-running timed run continued to err_steps.
         mixed = {}
+        xs = []
+        ref = follow_run(cav, "fp64", err_steps, record=xs)
         for p in ("fp32", "bf16"):
-            ms_p, kt_p, _, st_p, _ = run_gpu(cav.replace(precision=p), p, args.steps,
-                                            args.warmup)
-            e_rho, e_u, e_T = moment_errors(st_p, state, cav.lid)
+            ms_p, kt_p, _, st_free, _, n_p = run_gpu(cav.replace(precision=p), p, args.steps,
+                                                     args.warmup, total_steps=err_steps)
+            st_p = follow_run(cav.replace(precision=p), p, err_steps, follow=xs)
+            e_rho, e_u, e_T = moment_errors(st_p, ref, cav.lid)
+            f_rho, f_u, f_T = moment_errors(st_free, state, cav.lid)
+            log(f"[bench] {p} vs fp64 after {err_steps} steps: e_rho {e_rho:.2e} e_u {e_u:.2e} "
+                f"e_T {e_T:.2e} (free-running: {f_rho:.2e} {f_u:.2e} {f_T:.2e})")
             mixed[p] = {"value": updates / (ms_p * 1e-3), "ms_per_step": ms_p,
                         "transport_ms": kt_p[0] / max(kt_p[1], 1),
                         "speedup_vs_fp64": ms / ms_p, "e_rho": e_rho, "e_u": e_u, "e_T": e_T,
-                        "after_steps": args.warmup + args.steps}
+                        "free": {"e_rho": f_rho, "e_u": f_u, "e_T": f_T},
+                        "after_steps": err_steps, "kn": cav.kn}
+        del xs
         out["mixed"] = mixed
+        if not args.no_kn_sweep:
+            # the same errors at the workload's other Knudsen numbers
+            sweep = {}
+            for kn in (0.1, 10.0):
+                if kn == cav.kn:
+                    continue
+                ck = cav.replace(kn=kn)
+                xs = []
+                ref = follow_run(ck, "fp64", err_steps, record=xs)
+                row = {}
+                for p in ("fp32", "bf16"):
+                    st_p = follow_run(ck.replace(precision=p), p, err_steps, follow=xs)
+                    e_rho, e_u, e_T = moment_errors(st_p, ref, cav.lid)
+                    log(f"[bench] Kn {kn} {p} vs fp64 after {err_steps} steps: e_rho {e_rho:.2e} "
+                        f"e_u {e_u:.2e} e_T {e_T:.2e}")
+                    row[p] = {"e_rho": e_rho, "e_u": e_u, "e_T": e_T, "after_steps": err_steps}
+                del xs
+                sweep[f"kn_{kn:g}"] = row
+            out["mixed_kn"] = sweep
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cav.replace(precision="fp64"), args.cpu_seconds)

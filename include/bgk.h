@@ -86,7 +86,8 @@ typedef struct {
   int32_t flags;         /* bit set: BGK_FLAG_GENERIC uses the separate transport and
                             relaxation kernels instead of the fused one (for testing);
                             BGK_FLAG_ADJOINT reserves the workspace of
-                            bgk_adjoint_step (needs BGK_FP64 or BGK_FP32, move = 0);
+                            bgk_adjoint_step (move = 0) or bgk_adjoint_step_move
+                            (move = 1); needs BGK_FP64 or BGK_FP32;
                             BGK_FLAG_PARTICLES reserves that of bgk_pm_plan /
                             bgk_pm_apply                                                  */
   double vmax;           /* velocity grid spans [-vmax, vmax] per axis                   */
@@ -151,9 +152,14 @@ int bgk_wls_operators(bgk_ctx* ctx, const double* x, const int32_t* nbr_cnt,
 
 /* Boundary interpolation rows (S7 part 1; the paper names the interpolation
  * of f on the boundary in Table 3): for each wall particle b, the interior
- * particles within radius hb, hb the first of h, 1.5h, 2h giving at least
- * d+2 of them (else BGK_ESINGULAR), ascending, and the value weights
- * c0[b][e] of a degree-1 weighted least-squares fit evaluated at x_b.
+ * particles within radius hb, ascending, and the value weights c0[b][e] of
+ * a degree-1 weighted least-squares fit evaluated at x_b.  hb is the first
+ * of h, 1.5h, 2h whose set holds at least d+2 particles, gives a
+ * positive-definite fit and keeps the extrapolation's amplification
+ * sum_e |c0[b][e]| at most 8 (above every row of a jittered lattice, so the
+ * bound only widens stencils that a moving cloud has made near-degenerate);
+ * the 2h row is taken without the bound, and BGK_ESINGULAR is raised when
+ * it has fewer than d+2 points or a non-positive pivot.
  * Outputs are indexed by particle: wall_cnt int32 [N] (0 on interior rows),
  * wall_idx int32 [N][max_neighbors], wall_c0 double [N][max_neighbors],
  * wall_radius double [N] (may be NULL). */
@@ -280,12 +286,35 @@ int bgk_objective(bgk_ctx* ctx, const void* f, const double* rho, const double* 
  * device double [1], accumulated (+=); may be NULL.  |.| terms take the
  * derivative of their + branch at 0.  The transposed stencils make every
  * sum a gather: results are deterministic.  Needs a context created with
- * BGK_FLAG_ADJOINT (move = 0), else BGK_ENOTSUP.  f_n, lam_f1 and lam_f
+ * BGK_FLAG_ADJOINT and move = 0, else BGK_ENOTSUP.  f_n, lam_f1 and lam_f
  * are in the f storage type (FP64, or FP32 with FP64 arithmetic and
  * reductions inside). */
 int bgk_adjoint_step(bgk_ctx* ctx, const void* f_n, const double* U_n, const double* x,
                      const void* lam_f1, const double* lam_U1, const double* lam_rho1,
                      const double* lam_T1, void* lam_f, double* lam_U, double* dJ_dlid);
+
+/* Reverse mode of one full step S1-S8 with the MOVING cloud (Sec. 3.2.1 with
+ * the position update; Sec. 3.4.1 least squares; Sec. 3.4.2 edge frames;
+ * Sec. 5 walls): the step maps (f^n, U^n, x^n, lid) to (f^{n+1}, U^{n+1},
+ * x^{n+1}, rho^{n+1}, T^{n+1}), and the operators, edge frames and wall
+ * value rows are functions of x^n.  Given the output adjoints, returns
+ * lam_f and lam_U as bgk_adjoint_step does, plus
+ *   lam_x = (d x^{n+1}/d x^n)^T lam_x1 (identity on coordinates the clamp
+ *           of S8 left alone, zero on clamped ones) + the adjoint of x^n
+ *           through the gradient rows, frames and wall rows of every edge,
+ * and lam_U1 receives dt lam_x1 of the unclamped interior coordinates
+ * (x^{n+1} = x^n + dt U^{n+1}).  Neighbour sets, stencil radii and fitted
+ * degrees are those of x^n's values (piecewise constant; the derivative is
+ * that of the smooth piece).  x_n: device double [d][N], the positions the
+ * forward step started from; lam_x1, lam_x: double [d][N]; lam_x1,
+ * lam_U1, lam_rho1, lam_T1 may be NULL (zero); lam_f may equal lam_f1,
+ * lam_U may equal lam_U1 and lam_x may equal lam_x1 (in place); no other
+ * overlap (BGK_EINVAL).  Needs a context created with BGK_FLAG_ADJOINT and
+ * move = 1 (else BGK_ENOTSUP).  Sums have a fixed order: deterministic. */
+int bgk_adjoint_step_move(bgk_ctx* ctx, const void* f_n, const double* U_n, const double* x_n,
+                          const void* lam_f1, const double* lam_U1, const double* lam_x1,
+                          const double* lam_rho1, const double* lam_T1, void* lam_f,
+                          double* lam_U, double* lam_x, double* dJ_dlid);
 
 /* Reverse mode of bgk_moments (Sec. 2 eqs. moments, internal_energy; Chu
  * eq. macroeq): lam_f += (d(rho, U, T)/d f)^T (lam_rho, lam_U, lam_T) at the

@@ -89,7 +89,7 @@ def lib():
                                     dp, dp, dp, dp, dp, dp, dp, dp]
         L.ref_step_dual_move.argtypes = [cp, ip, dp, dp, dp, dp, dp, dp, ctypes.c_double,
                                          dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
-        L.ref_rollout_dual_move.argtypes = [cp, ip, dp, dp, dp, ctypes.c_double, ctypes.c_int,
+        L.ref_rollout_dual_move.argtypes = [cp, ip, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int,
                                             ctypes.c_double, dp, dp]
         L.ref_objective_dual.restype = ctypes.c_double
         L.ref_objective_dual.argtypes = [cp, ip, dp, dp, dp, dp, dp, dp, ctypes.c_double]
@@ -384,12 +384,16 @@ def step_dual_move(c, wall_id, x, f, U, x_dot=None, f_dot=None, U_dot=None, lid_
     return x1, x1d, f1, f1d, U1, U1d, r, rd, T, Td
 
 
-def rollout_dual_move(c, wall_id, x0, f0, nsteps, f0_dot=None, lid_dot=0.0, ke_weight=1.0):
-    """Moving-cloud rollout (c.move = 1); returns (J, dJ along (f0_dot, lid_dot))."""
+def rollout_dual_move(c, wall_id, x0, f0, nsteps, f0_dot=None, lid_dot=0.0, ke_weight=1.0,
+                      x0_dot=None):
+    """Moving-cloud rollout (c.move = 1); returns (J, dJ along (x0_dot,
+    f0_dot, lid_dot))."""
     J, Jd = ctypes.c_double(0), ctypes.c_double(0)
     x0, f0, wall_id = _f64(x0), _f64(f0), _i32(wall_id)
     fd = _f64(f0_dot) if f0_dot is not None else None
+    xd = _f64(x0_dot) if x0_dot is not None else None
     _check(lib().ref_rollout_dual_move(ctypes.byref(c), _i(wall_id), _d(x0),
+                                       _d(xd) if xd is not None else None,
                                        _d(f0), _d(fd) if fd is not None else None,
                                        float(lid_dot), int(nsteps),
                                        float(ke_weight), ctypes.byref(J), ctypes.byref(Jd)),

@@ -473,20 +473,30 @@ int wls(const ref_config& c, const S* x, const int32_t* wall_id, const int32_t* 
 // Boundary stencils.  The paper only names the interpolation of f on the
 // boundary and the diffuse-reflection condition (Table 3, Section 5).
 // Taken reading: each wall particle b reconstructs f at x_b from the
-// interior particles within radius hb, the first of h, 1.5h, 2h that holds
-// at least d+2 of them, by a degree-1 weighted least-squares fit (weights
-// exp(-alpha r^2/hb^2)) evaluated at x_b: f_b = sum_j c0_bj f_j.
-// Value row at a point xq: the interior particles within hb, the first of
-// h, 1.5h, 2h holding at least d+2 of them (ascending), and the degree-1
-// least-squares value weights at xq (weights exp(-alpha r^2/hb^2)), so that
-// f(xq) ~ sum_e c0[e] f_{S[e]}.
-// (The set and the radius depend on the positions' values only.)
+// interior particles within radius hb (the rule below), by a degree-1
+// weighted least-squares fit (weights exp(-alpha r^2/hb^2)) evaluated at
+// x_b: f_b = sum_j c0_bj f_j.
+// Value row at a point xq: the interior particles within hb (ascending) and
+// the degree-1 least-squares value weights at xq (weights
+// exp(-alpha r^2/hb^2)), so that f(xq) ~ sum_e c0[e] f_{set[e]}.  hb is the
+// first of h, 1.5h, 2h whose set holds at least d+2 particles, gives a
+// positive-definite fit, and keeps the extrapolation's amplification
+// sum_e |c0_e| at most kValueRowAmp; the 2h row is taken without the bound.
+// (The bound lies above the amplification of every row of the jittered
+// initial lattices, 3.7 in 2D and 6.6 in 3D, so it acts only where a moving
+// cloud has left a wall particle a near-degenerate stencil: the plain first
+// radius with d+2 points then extrapolates with weights summing to ~100 in
+// magnitude, and the step turns non-physical.)  The set and the radius
+// depend on the positions' values only.
+constexpr double kValueRowAmp = 8.0;
+
 template <class S>
 int value_row(const ref_config& c, const S* x, const int32_t* wall_id, const S* xq,
               std::vector<int>& set, std::vector<S>& c0, double& hb) {
   const int N = c.n_particles, d = c.dim;
   const double mults[3] = {1.0, 1.5, 2.0};
   for (int k = 0; k < 3; ++k) {
+    const bool last = k == 2;
     hb = mults[k] * c.h;
     const double hb2 = hb * hb;
     set.clear();
@@ -499,38 +509,46 @@ int value_row(const ref_config& c, const S* x, const int32_t* wall_id, const S* 
       }
       if (r2 <= hb2) set.push_back(j);
     }
-    if (static_cast<int>(set.size()) >= d + 2) break;
-  }
-  const int m = static_cast<int>(set.size());
-  if (m < d + 2) return R_ESINGULAR;
-  if (m > c.cap) return R_ENBR_OVERFLOW;
-  const int B = d + 1;
-  S A[16], L[16];
-  for (int k = 0; k < 16; ++k) A[k] = S(0.0);
-  std::vector<S> P(static_cast<size_t>(m) * B), W(m);
-  for (int e = 0; e < m; ++e) {
-    S y[3], r2 = S(0.0);
-    for (int a = 0; a < d; ++a) {
-      y[a] = (x[a * N + set[e]] - xq[a]) / hb;
-      r2 = r2 + y[a] * y[a];
+    const int m = static_cast<int>(set.size());
+    if (m < d + 2) {
+      if (last) return R_ESINGULAR;
+      continue;
     }
-    W[e] = s_exp(-c.alpha * r2);
-    basis(d, 1, y, &P[static_cast<size_t>(e) * B]);
+    if (m > c.cap) return R_ENBR_OVERFLOW;
+    const int B = d + 1;
+    S A[16], L[16];
+    for (int q = 0; q < 16; ++q) A[q] = S(0.0);
+    std::vector<S> P(static_cast<size_t>(m) * B), W(m);
+    for (int e = 0; e < m; ++e) {
+      S y[3], r2 = S(0.0);
+      for (int a = 0; a < d; ++a) {
+        y[a] = (x[a * N + set[e]] - xq[a]) / hb;
+        r2 = r2 + y[a] * y[a];
+      }
+      W[e] = s_exp(-c.alpha * r2);
+      basis(d, 1, y, &P[static_cast<size_t>(e) * B]);
+    }
+    for (int e = 0; e < m; ++e)
+      for (int r = 0; r < B; ++r)
+        for (int s = 0; s < B; ++s)
+          A[r * B + s] = A[r * B + s] + W[e] * P[e * B + r] * P[e * B + s];
+    if (!cholesky(B, A, L)) {
+      if (last) return R_ESINGULAR;
+      continue;
+    }
+    S z[16];
+    chol_solve_unit(B, L, 0, z);
+    c0.assign(m, S(0.0));
+    double amp = 0.0;
+    for (int e = 0; e < m; ++e) {
+      S s = S(0.0);
+      for (int r = 0; r < B; ++r) s = s + z[r] * P[e * B + r];
+      c0[e] = W[e] * s;
+      amp = amp + std::fabs(val(c0[e]));
+    }
+    if (last || amp <= kValueRowAmp) return R_OK;
   }
-  for (int e = 0; e < m; ++e)
-    for (int r = 0; r < B; ++r)
-      for (int s = 0; s < B; ++s)
-        A[r * B + s] = A[r * B + s] + W[e] * P[e * B + r] * P[e * B + s];
-  if (!cholesky(B, A, L)) return R_ESINGULAR;
-  S z[16];
-  chol_solve_unit(B, L, 0, z);
-  c0.assign(m, S(0.0));
-  for (int e = 0; e < m; ++e) {
-    S s = S(0.0);
-    for (int r = 0; r < B; ++r) s = s + z[r] * P[e * B + r];
-    c0[e] = W[e] * s;
-  }
-  return R_OK;
+  return R_ESINGULAR;
 }
 
 template <class S>
@@ -1348,17 +1366,19 @@ int ref_step_dual_move(const ref_config* c, const int32_t* wall_id, const double
 
 // Rollout with the moving cloud (c->move must be 1): (rho, U, T)^0 are the
 // moments of f0, then nsteps full steps S1..S8, then J of the final state.
-// Returns J and its exact directional derivative along (f0_dot, lid_dot),
-// through the moving geometry.
+// Returns J and its exact directional derivative along (x0_dot, f0_dot,
+// lid_dot) (each direction may be null / 0), through the moving geometry.
 int ref_rollout_dual_move(const ref_config* c, const int32_t* wall_id, const double* x0,
-                          const double* f0, const double* f0_dot, double lid_dot, int nsteps,
-                          double ke_weight, double* J, double* J_dot) {
+                          const double* x0_dot, const double* f0, const double* f0_dot,
+                          double lid_dot, int nsteps, double ke_weight, double* J,
+                          double* J_dot) {
   if (!config_ok(*c) || !c->move) return R_EINVAL;
   const int N = c->n_particles, d = c->dim;
   const int64_t total = static_cast<int64_t>(n_comp(*c)) * N * n_vel(*c);
   std::vector<Dual> xd(static_cast<size_t>(d) * N), fa(total), fb(total),
       U(static_cast<size_t>(3) * N), rho(N), T(N);
-  for (int64_t k = 0; k < static_cast<int64_t>(d) * N; ++k) xd[k] = Dual(x0[k]);
+  for (int64_t k = 0; k < static_cast<int64_t>(d) * N; ++k)
+    xd[k] = Dual(x0[k], x0_dot ? x0_dot[k] : 0.0);
   for (int64_t k = 0; k < total; ++k) fa[k] = Dual(f0[k], f0_dot ? f0_dot[k] : 0.0);
   const int64_t NV = n_vel(*c), stride = static_cast<int64_t>(N) * NV;
   for (int i = 0; i < N; ++i) {

@@ -34,7 +34,8 @@ EXPORTS = ("bgk_workspace_bytes", "bgk_init", "bgk_destroy", "bgk_set_lid_veloci
            "bgk_build_neighbors", "bgk_wls_operators", "bgk_wall_stencil", "bgk_geometry",
            "bgk_transport", "bgk_collide", "bgk_wall_bc", "bgk_move", "bgk_step",
            "bgk_moments", "bgk_maxwellian", "bgk_check", "bgk_diagnostics", "bgk_last_error",
-           "bgk_timing_enable", "bgk_timing_read", "bgk_objective", "bgk_adjoint_step",
+           "bgk_timing_enable", "bgk_timing_read", "bgk_objective",
+           "bgk_adjoint_step", "bgk_adjoint_step_move",
            "bgk_moments_adjoint", "bgk_pm_plan", "bgk_pm_apply")
 
 
@@ -93,6 +94,7 @@ def load_library(path: str = LIB_PATH):
         "bgk_timing_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
         "bgk_objective": [vp, vp, dp, dp, ctypes.c_double, dp, vp, dp, dp],
         "bgk_adjoint_step": [vp, vp, dp, dp, vp, dp, dp, dp, vp, dp, dp],
+        "bgk_adjoint_step_move": [vp, vp, dp, dp, vp, dp, dp, dp, dp, vp, dp, dp, dp],
         "bgk_moments_adjoint": [vp, dp, dp, dp, dp, dp, dp, vp],
         "bgk_pm_plan": [vp, dp, ctypes.c_double, ctypes.c_double,
                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
@@ -336,18 +338,25 @@ def bgk_maxwellian(ctx: Context, rho, U, T, f_out=None):
 def bgk_objective(ctx: Context, f, rho, U, ke_weight=1.0, want_grad=True):
     """J (0-d float64 tensor) and, if want_grad, (dJ_df, dJ_drho, dJ_dU);
     dJ_df has the f storage type."""
+    return _objective(ctx, f, rho, U, ke_weight, want_grad, "bgk_objective")
+
+
+def _objective(ctx, f, rho, U, ke_weight, want_grad, name, out=None):
     _f(ctx, f, "f")
     _sca(ctx, rho, "rho")
     _vec(ctx, U, "U")
-    J = _empty(ctx, (), torch.float64)
-    g = None
-    if want_grad:
-        g = (_empty(ctx, (ctx.nc, ctx.N, ctx.NV), f_dtype(ctx.cfg)),
-             _empty(ctx, (ctx.N,), torch.float64), _empty(ctx, (ctx.d, ctx.N), torch.float64))
+    if out is not None:
+        J, g = out[0], (tuple(out[1:]) if want_grad else None)
+    else:
+        J = _empty(ctx, (), torch.float64)
+        g = None
+        if want_grad:
+            g = (_empty(ctx, (ctx.nc, ctx.N, ctx.NV), f_dtype(ctx.cfg)),
+                 _empty(ctx, (ctx.N,), torch.float64), _empty(ctx, (ctx.d, ctx.N), torch.float64))
     gp = g if g is not None else (None, None, None)
-    _check(ctx, load_library().bgk_objective(ctx.handle, _ptr(f), _ptr(rho), _ptr(U),
-                                             float(ke_weight), _ptr(J), _ptr(gp[0]), _ptr(gp[1]),
-                                             _ptr(gp[2])), "bgk_objective")
+    _check(ctx, getattr(load_library(), name)(ctx.handle, _ptr(f), _ptr(rho), _ptr(U),
+                                              float(ke_weight), _ptr(J), _ptr(gp[0]),
+                                              _ptr(gp[1]), _ptr(gp[2])), name)
     return (J, g) if want_grad else J
 
 
@@ -377,6 +386,39 @@ def bgk_adjoint_step(ctx: Context, f_n, U_n, x, lam_f1, lam_U1=None, lam_rho1=No
         ctx.handle, _ptr(f_n), _ptr(U_n), _ptr(x), _ptr(lam_f1), _ptr(lam_U1), _ptr(lam_rho1),
         _ptr(lam_T1), _ptr(lam_f), _ptr(lam_U), _ptr(dJ_dlid)), "bgk_adjoint_step")
     return lam_f, lam_U
+
+
+def bgk_adjoint_step_move(ctx: Context, f_n, U_n, x_n, lam_f1, lam_U1=None, lam_x1=None,
+                          lam_rho1=None, lam_T1=None, lam_f=None, lam_U=None, lam_x=None,
+                          dJ_dlid=None):
+    """Reverse of one step with the moving cloud; returns (lam_f, lam_U,
+    lam_x).  dJ_dlid, if given (float64 tensor of one element), is
+    accumulated in place."""
+    _f(ctx, f_n, "f_n")
+    _vec(ctx, U_n, "U_n")
+    _vec(ctx, x_n, "x_n")
+    _f(ctx, lam_f1, "lam_f1")
+    for t, name in ((lam_U1, "lam_U1"), (lam_x1, "lam_x1")):
+        if t is not None:
+            _vec(ctx, t, name)
+    for t, name in ((lam_rho1, "lam_rho1"), (lam_T1, "lam_T1")):
+        if t is not None:
+            _sca(ctx, t, name)
+    lam_f = torch.empty_like(lam_f1) if lam_f is None else lam_f
+    lam_U = _empty(ctx, (ctx.d, ctx.N), torch.float64) if lam_U is None else lam_U
+    lam_x = _empty(ctx, (ctx.d, ctx.N), torch.float64) if lam_x is None else lam_x
+    _f(ctx, lam_f, "lam_f")
+    _vec(ctx, lam_U, "lam_U")
+    _vec(ctx, lam_x, "lam_x")
+    if dJ_dlid is not None:
+        _expect(dJ_dlid, torch.float64, tuple(dJ_dlid.shape), "dJ_dlid", ctx.device)
+        if dJ_dlid.numel() != 1:
+            raise ValueError("dJ_dlid must hold one element")
+    _check(ctx, load_library().bgk_adjoint_step_move(
+        ctx.handle, _ptr(f_n), _ptr(U_n), _ptr(x_n), _ptr(lam_f1), _ptr(lam_U1), _ptr(lam_x1),
+        _ptr(lam_rho1), _ptr(lam_T1), _ptr(lam_f), _ptr(lam_U), _ptr(lam_x), _ptr(dJ_dlid)),
+        "bgk_adjoint_step_move")
+    return lam_f, lam_U, lam_x
 
 
 def bgk_moments_adjoint(ctx: Context, rho, U, T, lam_f, lam_rho=None, lam_U=None, lam_T=None):

@@ -64,7 +64,7 @@ bool config_ok(const bgk_config& g) {
          g.wls_degree >= 0 && g.wls_degree <= 2 && g.max_neighbors >= g.dim + 2 &&
          g.max_neighbors <= 255 && (g.move == 0 || g.move == 1) && g.precision >= BGK_FP64 &&
          g.precision <= BGK_BF16 && (g.flags & ~(BGK_FLAG_GENERIC | BGK_FLAG_ADJOINT | BGK_FLAG_PARTICLES)) == 0 &&
-         (!(g.flags & BGK_FLAG_ADJOINT) || (g.precision != BGK_BF16 && g.move == 0)) && g.vmax > 0 && g.h > 0 && g.alpha > 0 &&
+         (!(g.flags & BGK_FLAG_ADJOINT) || g.precision != BGK_BF16) && g.vmax > 0 && g.h > 0 && g.alpha > 0 &&
          g.kn > 0 && g.dt > 0 && g.wall_T > 0 && g.dx > 0 && std::isfinite(g.lid_velocity) &&
          ipow(g.nv, g.dim) <= INT32_MAX / 4 &&
          (!(g.flags & BGK_FLAG_PARTICLES) || ipow(lattice_nodes(g), g.dim) < INT32_MAX / 2) &&
@@ -73,7 +73,8 @@ bool config_ok(const bgk_config& g) {
 
 }  // namespace
 
-size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj, Pm* pm) {
+size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj, Pm* pm,
+                        MoveAdj* madj) {
   const int64_t N = cfg.n_particles, cap = cfg.max_neighbors, D = cfg.dim, DD = D * D;
   const int64_t ncell = ipow(cells_per_axis(cfg), cfg.dim);
   // patch unions for any patch size (chosen at init): at most (N+1)/2
@@ -136,6 +137,19 @@ size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj, Pm*
     a.uj = reinterpret_cast<int32_t*>(take((N + 1) / 2 * kAdjPatch * cap * 4));
     a.ue = reinterpret_cast<uint32_t*>(take((N + 1) / 2 * kAdjPatch * cap * 4));
     if (adj) *adj = a;
+    if (cfg.move) {
+      MoveAdj v{};
+      v.wpos = reinterpret_cast<int32_t*>(take(N * 4));
+      v.lamU_eff = reinterpret_cast<double*>(take(D * N * 8));
+      v.xpass = reinterpret_cast<double*>(take(D * N * 8));
+      v.lam_a = reinterpret_cast<double*>(take(N * cap * DD * 8));
+      v.lc0 = reinterpret_cast<double*>(take(N * cap * 8));
+      v.xc = reinterpret_cast<double*>(take(N * cap * D * 8));
+      v.xs = reinterpret_cast<double*>(take(N * D * 8));
+      v.wxc = reinterpret_cast<double*>(take(N * cap * D * 8));
+      v.wxs = reinterpret_cast<double*>(take(N * D * 8));
+      if (madj) *madj = v;
+    }
   }
   if (cfg.flags & BGK_FLAG_PARTICLES) {
     const int64_t nodes = ipow(lattice_nodes(cfg), cfg.dim);
@@ -213,7 +227,7 @@ int bgk_init(const bgk_config* cfg, const int32_t* wall_id, void* workspace, siz
   c.nca = bgk::cells_per_axis(*cfg);
   c.ncell = static_cast<int>(bgk::ipow(c.nca, c.D));
   c.lid = cfg->lid_velocity;
-  bgk::workspace_layout(*cfg, static_cast<char*>(workspace), &c.d, &c.adj, &c.pm);
+  bgk::workspace_layout(*cfg, static_cast<char*>(workspace), &c.d, &c.adj, &c.pm, &c.madj);
   c.nl = bgk::lattice_nodes(*cfg);
   c.nodes = bgk::ipow(c.nl, c.D);
   hipError_t e = hipGetDevice(&c.device);
@@ -265,6 +279,14 @@ int bgk_init(const bgk_config* cfg, const int32_t* wall_id, void* workspace, siz
   if (e == hipSuccess && c.npw > 0)
     e = hipMemcpyAsync(c.d.wpl, wp.data(), sizeof(int32_t) * wp.size(), hipMemcpyHostToDevice,
                        c.stream);
+  std::vector<int32_t> wpos;
+  if (c.madj.wpos) {  // wall-list index of every wall particle (moving-cloud reverse step)
+    wpos.assign(c.N, -1);
+    for (int k = 0; k < c.Nw; ++k) wpos[wl[k]] = k;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c.madj.wpos, wpos.data(), sizeof(int32_t) * c.N, hipMemcpyHostToDevice,
+                         c.stream);
+  }
   if (e == hipSuccess)
     e = hipMemcpyAsync(c.d.err, zeros, sizeof(zeros), hipMemcpyHostToDevice, c.stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
@@ -500,7 +522,8 @@ int bgk_objective(bgk_ctx* ctx, const void* f, const double* rho, const double* 
   Ctx& c = ctx->c;
   if (c.cfg.precision == BGK_BF16)
     return bgk::fail(&c, BGK_ENOTSUP, "bgk_objective needs FP64 or FP32");
-  return bgk::hip_fail(&c, bgk::launch_objective(c, f, rho, U, ke_weight, J, dJ_df, dJ_drho, dJ_dU),
+  return bgk::hip_fail(&c, bgk::launch_objective(c, f, rho, U, ke_weight, J, dJ_df, dJ_drho, dJ_dU,
+                                                c.d.jpart),
                        "bgk_objective");
 }
 
@@ -520,6 +543,10 @@ int bgk_adjoint_step(bgk_ctx* ctx, const void* f_n, const double* U_n, const dou
   Ctx& c = ctx->c;
   if (!(c.cfg.flags & BGK_FLAG_ADJOINT))
     return bgk::fail(&c, BGK_ENOTSUP, "bgk_adjoint_step needs a context with BGK_FLAG_ADJOINT");
+  if (c.cfg.move)
+    return bgk::fail(&c, BGK_ENOTSUP,
+                     "bgk_adjoint_step is the frozen-cloud reverse step (move = 0); the moving "
+                     "cloud's is bgk_adjoint_step_move");
   const size_t F = (c.cfg.precision == BGK_FP64 ? 8 : 4) * c.NC * static_cast<size_t>(c.N) * c.NV;
   const size_t DN = sizeof(double) * c.D * static_cast<size_t>(c.N), N8 = sizeof(double) * c.N;
   // outputs against every input; lam_f == lam_f1 and lam_U == lam_U1 are allowed
@@ -558,6 +585,56 @@ int bgk_adjoint_step(bgk_ctx* ctx, const void* f_n, const double* U_n, const dou
     e = bgk::launch_adjoint_step(c, f_n, U_n, lam_f1, lam_U1, lam_rho1, lam_T1, lam_f, lam_U,
                                  dJ_dlid);
   return bgk::hip_fail(&c, e, "bgk_adjoint_step");
+}
+
+int bgk_adjoint_step_move(bgk_ctx* ctx, const void* f_n, const double* U_n, const double* x_n,
+                          const void* lam_f1, const double* lam_U1, const double* lam_x1,
+                          const double* lam_rho1, const double* lam_T1, void* lam_f,
+                          double* lam_U, double* lam_x, double* dJ_dlid) {
+  if (!ctx || !f_n || !U_n || !x_n || !lam_f1 || !lam_f || !lam_U || !lam_x) return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  if (!(c.cfg.flags & BGK_FLAG_ADJOINT) || !c.cfg.move)
+    return bgk::fail(&c, BGK_ENOTSUP,
+                     "bgk_adjoint_step_move needs a context with BGK_FLAG_ADJOINT and move = 1");
+  const size_t F = (c.cfg.precision == BGK_FP64 ? 8 : 4) * c.NC * static_cast<size_t>(c.N) * c.NV;
+  const size_t DN = sizeof(double) * c.D * static_cast<size_t>(c.N), N8 = sizeof(double) * c.N;
+  // outputs against every input; lam_f == lam_f1, lam_U == lam_U1 and
+  // lam_x == lam_x1 are allowed
+  const void* in[] = {f_n, U_n, x_n, lam_f1, lam_U1, lam_x1, lam_rho1, lam_T1, dJ_dlid};
+  const size_t nin[] = {F, DN, DN, F, DN, DN, N8, N8, sizeof(double)};
+  for (int k = 0; k < 9; ++k) {
+    if (overlap(lam_f, F, in[k], nin[k]) && !(k == 3 && in[k] == lam_f))
+      return bgk::fail(&c, BGK_EINVAL, "bgk_adjoint_step_move: lam_f overlaps an input");
+    if (overlap(lam_U, DN, in[k], nin[k]) && !(k == 4 && in[k] == lam_U))
+      return bgk::fail(&c, BGK_EINVAL, "bgk_adjoint_step_move: lam_U overlaps an input");
+    if (overlap(lam_x, DN, in[k], nin[k]) && !(k == 5 && in[k] == lam_x))
+      return bgk::fail(&c, BGK_EINVAL, "bgk_adjoint_step_move: lam_x overlaps an input");
+  }
+  if (overlap(lam_f, F, lam_U, DN) || overlap(lam_f, F, lam_x, DN) ||
+      overlap(lam_U, DN, lam_x, DN))
+    return bgk::fail(&c, BGK_EINVAL, "bgk_adjoint_step_move: the outputs overlap");
+  // the geometry of x^n, its transposed stencils, then the step recomputed
+  int rc = bgk::build_geometry(c, x_n);
+  if (rc) return rc;
+  hipError_t e = bgk::launch_adjoint_transposes(c);
+  if (e != hipSuccess) return bgk::hip_fail(&c, e, "bgk_adjoint_step_move transposes");
+  c.adj_valid = false;
+  const bgk::Adj& a = c.adj;
+  if (bgk::use_fused(c)) {
+    e = bgk::launch_fused(c, f_n, a.f1, U_n, a.rho1, a.U1, a.T1, true, a.ft);
+  } else {
+    e = bgk::launch_transport(c, f_n, a.ft, U_n);
+    if (e == hipSuccess) e = bgk::launch_collide(c, a.ft, a.f1, a.rho1, a.U1, a.T1);
+  }
+  if (e == hipSuccess) e = bgk::launch_wall_bc(c, a.f1, a.rho1, a.U1, a.T1);
+  // S8 reverse, then the frozen-operator reverse with the position update's
+  // share of lam_U^{n+1}, then the reverse through the operators and rows
+  if (e == hipSuccess) e = bgk::launch_adjoint_move_prep(c, x_n, lam_U1, lam_x1);
+  if (e == hipSuccess)
+    e = bgk::launch_adjoint_step(c, f_n, U_n, lam_f1, c.madj.lamU_eff, lam_rho1, lam_T1, lam_f,
+                                 lam_U, dJ_dlid, true);
+  if (e == hipSuccess) e = bgk::launch_adjoint_move_geometry(c, f_n, U_n, x_n, lam_x);
+  return bgk::hip_fail(&c, e, "bgk_adjoint_step_move");
 }
 
 int bgk_moments_adjoint(bgk_ctx* ctx, const double* rho, const double* U, const double* T,

@@ -90,6 +90,20 @@ struct Adj {
   uint32_t* ue;       // [(N+1)/2][2*cap]
 };
 
+// Workspace of the reverse step with the moving cloud (BGK_FLAG_ADJOINT with
+// move = 1): the adjoint through the positions.
+struct MoveAdj {
+  int32_t* wpos;      // [N]        wall-list index of each wall particle (-1: interior)
+  double* lamU_eff;   // [d][N]     adjoint of U^{n+1} with the position update's share
+  double* xpass;      // [d][N]     adjoint of x^{n+1} passed to x^n by the position update
+  double* lam_a;      // [N][cap][d*d] adjoint of the upwind vectors of every edge
+  double* lc0;        // [N][cap]   adjoint of the wall value rows (wall-list order)
+  double* xc;         // [N][cap][d] contribution of row i's slot e to the adjoint of x_j
+  double* xs;         // [N][d]      contribution of row i to the adjoint of x_i
+  double* wxc;        // [N][cap][d] the same for the wall rows
+  double* wxs;        // [N][d]
+};
+
 // Workspace of the particle management (BGK_FLAG_PARTICLES).
 struct Pm {
   int32_t* nn;        // [N]         nearest interior neighbour within h (-1: none)
@@ -131,6 +145,7 @@ struct Ctx {
   double lid = 0.0;
   Dev d{};
   Adj adj{};
+  MoveAdj madj{};
   Pm pm{};
   int nl = 0;               // lattice nodes per axis (particle management)
   int64_t nodes = 0;        // nl^d
@@ -146,7 +161,8 @@ struct Ctx {
 };
 
 // Workspace layout: returns total bytes; fills d when base != nullptr.
-size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj, Pm* pm);
+size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj, Pm* pm,
+                        MoveAdj* madj = nullptr);
 
 // ---- launchers (enqueue on c.stream; return hipError_t of the launch) ----
 hipError_t launch_fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
@@ -197,12 +213,25 @@ hipError_t launch_pm_apply(const Ctx& c, const double* x, const void* f, const d
                            double* U_new, double* T_new);
 hipError_t launch_adjoint_transposes(const Ctx& c);
 // f-sized arguments (f_n, lam_f1, lam_f, dJ_df) are in the f storage type.
+// wall_rows: also the adjoint of the wall value rows (moving cloud), taken
+// between the wall and the relaxation kernels (f^{n+1}'s interior rows
+// share storage with the adjoint of f-tilde)
 hipError_t launch_adjoint_step(const Ctx& c, const void* f_n, const double* U_n,
                                const void* lam_f1, const double* lam_U1, const double* lam_rho1,
                                const double* lam_T1, void* lam_f, double* lam_U,
-                               double* dJ_dlid);
+                               double* dJ_dlid, bool wall_rows = false);
+// Reverse through the positions (k_adjoint_move.hip): the position update's
+// share (before launch_adjoint_step), the wall-row adjoints (inside it),
+// then the operators, frames and wall rows (after it).
+hipError_t launch_adjoint_move_prep(const Ctx& c, const double* x, const double* lam_U1,
+                                    const double* lam_x1);
+hipError_t launch_adjoint_wallrow(const Ctx& c);
+hipError_t launch_adjoint_move_geometry(const Ctx& c, const void* f_n, const double* U_n,
+                                        const double* x, double* lam_x);
+// part: N doubles of device scratch for the per-particle terms
 hipError_t launch_objective(const Ctx& c, const void* f, const double* rho, const double* U,
-                            double ke, double* J, void* dJ_df, double* dJ_drho, double* dJ_dU);
+                            double ke, double* J, void* dJ_df, double* dJ_drho, double* dJ_dU,
+                            double* part);
 hipError_t launch_moments_adjoint(const Ctx& c, const double* rho, const double* U,
                                   const double* T, const double* lr, const double* lU,
                                   const double* lT, void* lam_f);

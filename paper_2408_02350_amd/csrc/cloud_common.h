@@ -226,13 +226,24 @@ struct ValueRowSm {
 };
 
 // Value row at the point xq (one wave, all 64 lanes): the interior
-// particles within hb, the first of h, 1.5h, 2h holding at least d+2 of
-// them (interior ranges of the candidate cells within +-1 cell for h, within
-// +-2 cells for the wider radii, scanned once per radius tried), ascending in sm.srt[0..m); their degree-1
-// least-squares value weights at xq (weights exp(-alpha r^2/hb^2)) are
-// value_weight(sm, e).  Returns m, or -1 (fewer than d+2 points or a
-// non-positive pivot: BGK_ESINGULAR) or -2 (more than cap points:
-// BGK_ENBR_OVERFLOW).
+// particles within hb, ascending in sm.srt[0..m), and their degree-1
+// least-squares value weights at xq (weights exp(-alpha r^2/hb^2)),
+// value_weight(sm, e).  hb is the first of h, 1.5h, 2h whose set holds at
+// least d+2 particles, gives a positive-definite fit and keeps the
+// extrapolation's amplification sum_e |c0_e| at most kValueRowAmp; the 2h
+// row is taken without the bound.  (The bound is above the amplification of
+// every row of the jittered initial lattices, 3.7 in 2D and 6.6 in 3D: it
+// acts only where a moving cloud has left a near-degenerate stencil, whose
+// extrapolation would otherwise amplify ~100-fold and drive the step
+// non-physical.)  Candidates are the interior ranges of the cells within
+// +-1 cell for h and within +-2 cells for the wider radii.  Returns m, or
+// -1 (fewer than d+2 points or a non-positive pivot at 2h: BGK_ESINGULAR)
+// or -2 (more than cap points: BGK_ENBR_OVERFLOW).
+constexpr double kValueRowAmp = 8.0;
+
+template <int D>
+__device__ __forceinline__ double value_weight(const ValueRowSm<D>& sm, int e);
+
 template <int D>
 __device__ int value_row(const CloudView& a, const double* xq, ValueRowSm<D>& sm, double& hb) {
   constexpr int B = D + 1;
@@ -245,8 +256,8 @@ __device__ int value_row(const CloudView& a, const double* xq, ValueRowSm<D>& sm
   int nr = cell_ranges<D, 1>(cb, a.nca, a.ncell, false, a.cstart, sm.rb, sm.rpre);
   int total = sm.rpre[nr];
   const double mults[3] = {1.0, 1.5, 2.0};
-  int m = 0;
   for (int t = 0; t < 3; ++t) {
+    const bool last = t == 2;
     if (t == 1) {
       __syncthreads();
       nr = cell_ranges<D, 2>(cb, a.nca, a.ncell, false, a.cstart, sm.rb, sm.rpre);
@@ -254,7 +265,7 @@ __device__ int value_row(const CloudView& a, const double* xq, ValueRowSm<D>& sm
     }
     hb = mults[t] * a.h;
     const double hb2 = hb * hb;
-    m = 0;
+    int m = 0;
     for (int c0 = 0; c0 < total; c0 += kWave) {
       const int cidx = c0 + lane;
       bool in = false;
@@ -275,27 +286,41 @@ __device__ int value_row(const CloudView& a, const double* xq, ValueRowSm<D>& sm
       if (in && pos < 256) sm.sel[pos] = j;
       m += __popcll(mask);
     }
-    if (m >= D + 2) break;
-  }
-  __syncthreads();
-  if (m < D + 2) return -1;
-  if (m > a.cap) return -2;
-  rank_sorted_store(sm.sel, m, a.cap, sm.srt);
-  __syncthreads();
-  for (int e = lane; e < m; e += kWave) {
-    const int j = sm.srt[e];
-    double y[D], r2 = 0.0;
-#pragma unroll
-    for (int q = 0; q < D; ++q) {
-      y[q] = (a.x[static_cast<int64_t>(q) * a.N + j] - xq[q]) / hb;
-      r2 = r2 + y[q] * y[q];
+    __syncthreads();
+    if (m < D + 2) {
+      if (last) return -1;
+      continue;
     }
-    sm.W[e] = exp(-a.alpha * r2);
-    Basis<D, 1>::eval(y, sm.P + e * B);
+    if (m > a.cap) return -2;
+    rank_sorted_store(sm.sel, m, a.cap, sm.srt);
+    __syncthreads();
+    for (int e = lane; e < m; e += kWave) {
+      const int j = sm.srt[e];
+      double y[D], r2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        y[q] = (a.x[static_cast<int64_t>(q) * a.N + j] - xq[q]) / hb;
+        r2 = r2 + y[q] * y[q];
+      }
+      sm.W[e] = exp(-a.alpha * r2);
+      Basis<D, 1>::eval(y, sm.P + e * B);
+    }
+    __syncthreads();
+    if (!wave_lsq<B, 1>(m, sm.P, sm.W, sm.A, sm.Z, 0, &sm.flag)) {
+      if (last) return -1;
+      __syncthreads();
+      continue;
+    }
+    if (last) return m;
+    // amplification of the row: every lane ends with the same sum
+    double amp = 0.0;
+    for (int e = lane; e < m; e += kWave) amp = amp + fabs(value_weight(sm, e));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) amp = amp + __shfl_xor(amp, o, kWave);
+    if (amp <= kValueRowAmp) return m;
+    __syncthreads();   // the next radius reuses the staging arrays
   }
-  __syncthreads();
-  if (!wave_lsq<B, 1>(m, sm.P, sm.W, sm.A, sm.Z, 0, &sm.flag)) return -1;
-  return m;
+  return -1;
 }
 
 template <int D>

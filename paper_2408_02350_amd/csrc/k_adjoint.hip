@@ -1006,7 +1006,7 @@ template <typename Real>
 static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_n,
                                  const Real* lam_f1, const double* lam_U1, const double* lam_rho1,
                                  const double* lam_T1, Real* lam_f, double* lam_U,
-                                 double* dJ_dlid) {
+                                 double* dJ_dlid, bool wall_rows) {
   const Adj& j = c.adj;
   const Real* ops = std::is_same<Real, double>::value
                         ? reinterpret_cast<const Real*>(c.d.ops64)
@@ -1039,12 +1039,20 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
   aw.jlist = c.d.wall_list;
   if (c.D == 2) {
     if (c.Nw) hipLaunchKernelGGL((k_adj_wall<2, 2, Real>), dim3(c.Nw), t, 0, c.stream, a);
+    if (wall_rows) {
+      const hipError_t e = launch_adjoint_wallrow(c);
+      if (e != hipSuccess) return e;
+    }
     if (c.Ni) hipLaunchKernelGGL((k_adj_collide<2, 2, Real>), dim3(c.Ni), t, lds, c.stream, a);
     if (npa)
       hipLaunchKernelGGL((k_adj_transport_patch<2, 2, Real, 2, kAdjPatch>), tp, tt, 0, c.stream, a);
     if (c.Nw) hipLaunchKernelGGL((k_adj_transport<2, 2, Real, 2>), tw, tt, 0, c.stream, aw);
   } else {
     if (c.Nw) hipLaunchKernelGGL((k_adj_wall<3, 1, Real>), dim3(c.Nw), t, 0, c.stream, a);
+    if (wall_rows) {
+      const hipError_t e = launch_adjoint_wallrow(c);
+      if (e != hipSuccess) return e;
+    }
     if (c.Ni) hipLaunchKernelGGL((k_adj_collide<3, 1, Real>), dim3(c.Ni), t, lds, c.stream, a);
     if (R == 4) {
       if (npa)
@@ -1069,41 +1077,43 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
 hipError_t launch_adjoint_step(const Ctx& c, const void* f_n, const double* U_n,
                                const void* lam_f1, const double* lam_U1, const double* lam_rho1,
                                const double* lam_T1, void* lam_f, double* lam_U,
-                               double* dJ_dlid) {
+                               double* dJ_dlid, bool wall_rows) {
   if (c.cfg.precision == BGK_FP64)
     return adjoint_step_t<double>(c, static_cast<const double*>(f_n), U_n,
                                   static_cast<const double*>(lam_f1), lam_U1, lam_rho1, lam_T1,
-                                  static_cast<double*>(lam_f), lam_U, dJ_dlid);
+                                  static_cast<double*>(lam_f), lam_U, dJ_dlid, wall_rows);
   return adjoint_step_t<float>(c, static_cast<const float*>(f_n), U_n,
                                static_cast<const float*>(lam_f1), lam_U1, lam_rho1, lam_T1,
-                               static_cast<float*>(lam_f), lam_U, dJ_dlid);
+                               static_cast<float*>(lam_f), lam_U, dJ_dlid, wall_rows);
 }
 
 template <typename Real>
 static void objective_t(const Ctx& c, const Real* f, const double* rho, const double* U,
-                        double hw, double ke, double* dJ_drho, double* dJ_dU, Real* dJ_df) {
+                        double hw, double ke, double* dJ_drho, double* dJ_dU, Real* dJ_df,
+                        double* part) {
   if (c.D == 2)
     hipLaunchKernelGGL((k_objective<2, 2, Real>), dim3(c.N), dim3(kThreads), 0, c.stream, c.N,
-                       c.NV, c.cfg.nv, c.cfg.vmax, hw, ke, c.d.wall_id, f, rho, U, c.d.jpart,
+                       c.NV, c.cfg.nv, c.cfg.vmax, hw, ke, c.d.wall_id, f, rho, U, part,
                        dJ_df, dJ_drho, dJ_dU);
   else
     hipLaunchKernelGGL((k_objective<3, 1, Real>), dim3(c.N), dim3(kThreads), 0, c.stream, c.N,
-                       c.NV, c.cfg.nv, c.cfg.vmax, hw, ke, c.d.wall_id, f, rho, U, c.d.jpart,
+                       c.NV, c.cfg.nv, c.cfg.vmax, hw, ke, c.d.wall_id, f, rho, U, part,
                        dJ_df, dJ_drho, dJ_dU);
 }
 
 hipError_t launch_objective(const Ctx& c, const void* f, const double* rho, const double* U,
-                            double ke, double* J, void* dJ_df, double* dJ_drho, double* dJ_dU) {
+                            double ke, double* J, void* dJ_df, double* dJ_drho, double* dJ_dU,
+                            double* part) {
   double area = 1.0;
   for (int k = 0; k < c.D - 1; ++k) area = area * c.cfg.dx;
   const double hw = 0.5 * omega_adj(c.cfg) * area;
   if (c.cfg.precision == BGK_FP64)
     objective_t<double>(c, static_cast<const double*>(f), rho, U, hw, ke, dJ_drho, dJ_dU,
-                        static_cast<double*>(dJ_df));
+                        static_cast<double*>(dJ_df), part);
   else
     objective_t<float>(c, static_cast<const float*>(f), rho, U, hw, ke, dJ_drho, dJ_dU,
-                       static_cast<float*>(dJ_df));
-  hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(kThreads), 0, c.stream, c.N, c.d.jpart, J, 0);
+                       static_cast<float*>(dJ_df), part);
+  hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(kThreads), 0, c.stream, c.N, part, J, 0);
   return hipGetLastError();
 }
 

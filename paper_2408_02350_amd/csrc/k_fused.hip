@@ -183,11 +183,14 @@ template <int D, int NC, int MODE, int R, bool FUSE, int TP, bool INLDS>
 __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   using Real = typename FPrec<MODE>::real;
   constexpr int DD = D * D;
-  constexpr bool DIFF = (MODE == BGK_BF16);     // products of differences
+  constexpr bool BF = (MODE == BGK_BF16);
+  // products of differences c (f_j - f_i), so that the BF16 rounding scales
+  // with the differences
+  constexpr bool DIFF = BF;
   // 3D (not BF16): c = g.w - sum_k |a_k.w| with g.w = sum_k a_k.w advanced
   // by its own increment (|x| is a free source modifier: 3 adds per velocity
   // instead of 3 mins and 2 adds); 2D keeps 2 sum_k min(0, a_k.w) (equal cost)
-  constexpr bool GW = (D == 3 && !DIFF);
+  constexpr bool GW = (D == 3 && !BF);
   // record: a_k (d*d), a_k.U (d), a_k[fast]*dvs (d)[, their sum]
   constexpr int REC = DD + 2 * D + (GW ? 1 : 0);
   constexpr int KM = TP * (D + 1);              // first-pass moment sums per thread
@@ -254,10 +257,10 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   const int32_t* __restrict__ ujp = a.uj + static_cast<size_t>(patch) * a.ucap;
   const uint32_t* __restrict__ uep = a.ue + static_cast<size_t>(patch) * a.ucap;
   const Real dvs = static_cast<Real>(a.dvs);
-  // ft = f - dt sum c (f_j - f_i) = f (1 + dt sum c) - dt sum c f_j; the
-  // factor 2 of c is folded into dt (except where BF16 rounds 2 cm, and in the
-  // 3D form, whose g.w - sum |a_k.w| already is c)
-  const Real dtf = static_cast<Real>((DIFF || GW) ? a.dt : 2.0 * a.dt);
+  // ft = f - dt sum c (f_j - f_i) (DIFF), or = f (1 + dt sum c) - dt sum c f_j;
+  // the factor 2 of c is folded into dt (except where BF16 rounds 2 cm, and
+  // in the 3D form, whose g.w - sum |a_k.w| already is c)
+  const Real dtf = static_cast<Real>((BF || GW) ? a.dt : 2.0 * a.dt);
   bool lane_on;
   int q0, kq[D];
   Real ft[TP][R][NC];
@@ -439,7 +442,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
 #pragma unroll
               for (int k = 1; k < D; ++k) cm = cm + min_t(p[k], Real(0));
             }
-            if constexpr (DIFF) {
+            if constexpr (BF) {
 #pragma unroll
               for (int c = 0; c < NC; ++c)
                 acc[t][r][c] = fma_t(bf16r(cm + cm), bf16r(fj[r][c] - fi[t][r][c]), acc[t][r][c]);
@@ -453,7 +456,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
       }
     };
     const int last = cn - 1;
-    if constexpr (DIFF && D == 2 && R <= 4) {
+    if constexpr (BF && D == 2 && R <= 4) {
       // BF16 operands in 2D: the union is walked two rows at a time, and the
       // two products of a (slot, velocity, component) go through one packed
       // BF16 dot product with FP32 accumulation.  A slot that lacks one of

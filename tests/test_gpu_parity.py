@@ -386,13 +386,13 @@ def test_generic_and_fused_transport_agree(dim, n, nv):
     assert rel(outs[0], outs[1]) <= 1e-13
 
 
-@pytest.mark.parametrize("name", ["c2", "c3"])
-def test_step_parity_full_size(name):
-    """Two steps at the full size of the 200^2 x 32^2 and 32^3 x 16^3
-    cavities, in the launch shapes bench.py times (2D FP64: 4-particle
+@pytest.mark.parametrize("name,kn", [("c2", 1.0), ("c2", 0.1), ("c3", 1.0)])
+def test_step_parity_full_size(name, kn):
+    """Two steps at the full size of the 200^2 x 32^2 cavity (Kn 1 and 0.1)
+    and the 32^3 x 16^3 cavity, in their launch shapes (2D FP64: 4-particle
     patches, 2 velocities per lane; 3D FP64 at 16^3: one velocity tile),
     from a spatially varying state, compared everywhere with the oracle."""
-    k, g, r = run_both(CONFIGS[name].replace(precision="fp64"), 2, init="smooth")
+    k, g, r = run_both(CONFIGS[name].replace(precision="fp64", kn=kn), 2, init="smooth")
     assert_state_close(g, r)
 
 
@@ -451,6 +451,7 @@ def test_motion_clamp_matches_the_oracle(dim):
     rx, rk = oracle.move(c, k.wid, U, x)
     assert rk == 2
     xg = k.t(x)
+    bgk.bgk_geometry(k.ctx, xg)
     before = bgk.bgk_diagnostics(k.ctx)["clamped"]
     bgk.bgk_move(k.ctx, xg, k.t(U))
     bgk.bgk_check(k.ctx)

@@ -64,9 +64,13 @@ def test_workspace_sizing_and_validation(lib):
     # the largest velocity grid per axis (exponential tables of the wall
     # condition live in LDS)
     assert lib.bgk_workspace_bytes(_cfg(lib, nv=1024)) > 0
+    # the reverse step's workspace, larger again with the moving cloud's
+    frozen = lib.bgk_workspace_bytes(_cfg(lib, flags=2, move=0))
+    assert frozen > n
+    assert lib.bgk_workspace_bytes(_cfg(lib, flags=2, move=1)) > frozen
     for bad in (dict(nv=15), dict(nv=1026), dict(dim=4), dict(n_particles=0), dict(dt=-1.0),
                 dict(wls_degree=3), dict(max_neighbors=300), dict(precision=5),
-                dict(flags=2), dict(h=0.0)):
+                dict(flags=2, precision=2), dict(flags=8), dict(h=0.0)):
         with pytest.raises(lib.BgkError) as e:
             lib.bgk_workspace_bytes(_cfg(lib, **bad))
         assert e.value.code == lib.BGK_EINVAL, bad
@@ -106,8 +110,13 @@ def test_adjoint_flag_rules(lib):
     cav = CONFIGS["c4"]
     f_bytes = 8 * 2 * cav.n_particles * cav.n_velocities
     assert n.value >= base + 3 * f_bytes      # f-tilde, lam_ft, wall adjoints
-    for bad in (dict(precision=bgk.BGK_BF16), dict(move=1)):
-        c = bgk.config_from(CONFIGS["c4"], "fp64", flags=bgk.BGK_FLAG_ADJOINT)
-        for k, v in bad.items():
-            setattr(c, k, v)
-        assert L.bgk_workspace_bytes(ctypes.byref(c), ctypes.byref(n)) == bgk.BGK_EINVAL
+    c = bgk.config_from(CONFIGS["c4"], "fp64", flags=bgk.BGK_FLAG_ADJOINT)
+    c.precision = bgk.BGK_BF16
+    assert L.bgk_workspace_bytes(ctypes.byref(c), ctypes.byref(n)) == bgk.BGK_EINVAL
+    # the moving cloud's reverse step (move = 1) reserves more
+    frozen = n.value
+    mv = bgk.config_from(CONFIGS["c4"], "fp64", flags=bgk.BGK_FLAG_ADJOINT, move=1)
+    assert L.bgk_workspace_bytes(ctypes.byref(adj), ctypes.byref(n)) == bgk.BGK_OK
+    frozen = n.value
+    assert L.bgk_workspace_bytes(ctypes.byref(mv), ctypes.byref(n)) == bgk.BGK_OK
+    assert n.value > frozen

@@ -134,6 +134,19 @@ def test_moving_rollout_derivative_matches_central_differences(dim, n, nv, steps
     _, Jf = oracle.rollout_dual_move(c, wid, x, f0, steps, f0_dot=df)
     fdf = (J_of(c, f0 + eps * df) - J_of(c, f0 - eps * df)) / (2 * eps)
     assert abs(Jf - fdf) <= 1e-6 * abs(fdf)
+    # initial positions (interior): the derivative through every step's
+    # geometry; eps 1e-7 keeps the perturbed runs on the same neighbour sets
+    dxs = rng.normal(size=x.shape) * (wid == 0) * c.dx
+    _, Jx = oracle.rollout_dual_move(c, wid, x, f0, steps, x0_dot=dxs)
+
+    def J_at(xx):
+        rho, U, T = oracle.moments(c, f0)
+        xs, fs, Us, rs, Ts, _ = oracle.run(c, wid, xx, f0, U, steps)
+        return oracle.objective(c, wid, fs, rs, Us, 1.0)
+
+    ex = 1e-7
+    fdx = (J_at(x + ex * dxs) - J_at(x - ex * dxs)) / (2 * ex)
+    assert abs(Jx - fdx) <= 1e-5 * abs(fdx) and abs(fdx) > 1e-8
     # the moving cloud's derivative differs from the frozen cloud's
     _, Jl_frozen, _ = oracle.rollout_dual(with_(c, move=0), wid, x, f0, steps,
                                           lid_dot=1.0)

@@ -540,6 +540,55 @@ def test_motion_clamps_interior_particles_and_never_moves_walls(dim):
     assert np.all(x1[:, inner] >= lo) and np.all(x1[:, inner] <= hi)
 
 
+def _value_row_lstsq(x, wid, b, hb, dim):
+    """Degree-1 weighted least-squares value row at x_b over the interior
+    particles within hb, by numpy's lstsq (None below d+2 points)."""
+    js = np.nonzero((wid == 0) & (((x - x[:, b:b + 1]) ** 2).sum(axis=0) <= hb * hb))[0]
+    if len(js) < dim + 2:
+        return js, None
+    Y = (x[:, js] - x[:, b:b + 1]).T / hb
+    w = np.sqrt(np.exp(-6.0 * (Y ** 2).sum(axis=1)))
+    P = _poly_basis(Y, 1)
+    # the value row is the first row of the weighted pseudo-inverse, times w
+    pinv = np.linalg.pinv(w[:, None] * P)
+    return js, pinv[0] * w
+
+
+def _radius_by_rule(x, wid, b, h, dim):
+    for m in (1.0, 1.5, 2.0):
+        js, c0 = _value_row_lstsq(x, wid, b, m * h, dim)
+        if c0 is not None and (m == 2.0 or np.abs(c0).sum() <= 8.0):
+            return m * h
+    return None
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_wall_row_widens_a_degenerate_stencil(dim):
+    """A wall particle whose interior particles within h lie almost on one
+    line (2D) or plane (3D) parallel to its wall: the linear extrapolation
+    to the wall from that stencil amplifies by far more than 8, so the row
+    is taken at 1.5h, where it is well conditioned; the row is the lstsq
+    value row there."""
+    n = 12 if dim == 2 else 8
+    x, wid = make_cloud(dim, n, 1)
+    c = cfg(dim, n, 4, 4.0)
+    x = x.copy()
+    b = (n // 2) if dim == 2 else (n // 2 + n * (n // 2))   # inside the low face of the last axis
+    assert wid[b] != 0 and x[dim - 1, b] == 0.0
+    near = (wid == 0) & (((x - x[:, b:b + 1]) ** 2).sum(axis=0) <= c.h ** 2)
+    rng = np.random.default_rng(3)
+    # flatten the interior stencil at h onto the first interior layer
+    x[dim - 1, near] = c.dx * (1.0 + 1e-4 * rng.uniform(-1, 1, near.sum()))
+    js, c0h = _value_row_lstsq(x, wid, b, c.h, dim)
+    assert c0h is not None and np.abs(c0h).sum() > 100.0
+    wcnt, widx, wc0, hb = oracle.wall_stencil(c, x, wid)
+    assert hb[b] == 1.5 * c.h
+    js, c0 = _value_row_lstsq(x, wid, b, 1.5 * c.h, dim)
+    assert np.array_equal(widx[b, :wcnt[b]], js)
+    assert np.allclose(wc0[b, :wcnt[b]], c0, rtol=1e-9, atol=1e-12)
+    assert np.abs(wc0[b, :wcnt[b]]).sum() <= 8.0
+
+
 @pytest.mark.parametrize("dim,n", [(2, 16), (3, 8)])
 def test_wall_interpolation_rows_are_linear_lstsq_values(dim, n):
     x, wid = make_cloud(dim, n, 6)
@@ -559,11 +608,8 @@ def test_wall_interpolation_rows_are_linear_lstsq_values(dim, n):
         a, *_ = np.linalg.lstsq(np.sqrt(w)[:, None] * P, np.sqrt(w) * fv[js], rcond=None)
         assert abs(cb @ fv[js] - a[0]) < 1e-11 * max(1, abs(a[0]))
         # radius rule: the first of h, 1.5h, 2h holding d+2 interior points
-        d2 = ((x[:, wid == 0] - x[:, b:b + 1]) ** 2).sum(axis=0)
-        for m in (1.0, 1.5, 2.0):
-            if (d2 <= (m * c.h) ** 2).sum() >= dim + 2:
-                assert hb[b] == m * c.h
-                break
+        # whose row amplifies by at most 8 (the 2h row without the bound)
+        assert hb[b] == _radius_by_rule(x, wid, b, c.h, dim)
 
 
 # --------------------------------------------------------------- full steps
