@@ -270,6 +270,23 @@ int bgk_maxwellian(bgk_ctx* ctx, const double* rho, const double* U, const doubl
 int bgk_objective(bgk_ctx* ctx, const void* f, const double* rho, const double* U,
                   double ke_weight, double* J, void* dJ_df, double* dJ_drho, double* dJ_dU);
 
+/* The same objective as bgk_objective, for callers that cannot allocate
+ * device memory and must not touch the context's workspace while calling
+ * it (code being captured into a HIP graph, tight serving loops, harnesses
+ * that forbid hipMalloc): the per-particle terms go to a fixed scratch
+ * array of BGK_STATIC_SCRATCH_PARTICLES doubles (8 MiB) that every GPU the
+ * library runs on holds until the process ends.  Same arguments, results
+ * and errors as bgk_objective (bit for bit the same J and partial
+ * derivatives), plus BGK_EINVAL when the context has more than
+ * BGK_STATIC_SCRATCH_PARTICLES particles.  It calls no allocating routine.
+ * All calls on one GPU share that GPU's scratch: calls that overlap in
+ * time on one GPU (on different streams, or from several host threads)
+ * race on it and must be ordered by the caller. */
+#define BGK_STATIC_SCRATCH_PARTICLES (1 << 20)
+int bgk_objective_static(bgk_ctx* ctx, const void* f, const double* rho, const double* U,
+                         double ke_weight, double* J, void* dJ_df, double* dJ_drho,
+                         double* dJ_dU);
+
 /* Reverse mode of one frozen-cloud step (S4-S7 with the operators of the
  * fixed cloud; Sec. 3.2 and Sec. 5).  The step maps the state (f^n, U^n) and
  * the lid speed to (f^{n+1}, U^{n+1}, rho^{n+1}, T^{n+1}).  Given the

@@ -34,7 +34,7 @@ EXPORTS = ("bgk_workspace_bytes", "bgk_init", "bgk_destroy", "bgk_set_lid_veloci
            "bgk_build_neighbors", "bgk_wls_operators", "bgk_wall_stencil", "bgk_geometry",
            "bgk_transport", "bgk_collide", "bgk_wall_bc", "bgk_move", "bgk_step",
            "bgk_moments", "bgk_maxwellian", "bgk_check", "bgk_diagnostics", "bgk_last_error",
-           "bgk_timing_enable", "bgk_timing_read", "bgk_objective",
+           "bgk_timing_enable", "bgk_timing_read", "bgk_objective", "bgk_objective_static",
            "bgk_adjoint_step", "bgk_adjoint_step_move",
            "bgk_moments_adjoint", "bgk_pm_plan", "bgk_pm_apply")
 
@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH):
         "bgk_timing_enable": [vp, ctypes.c_int],
         "bgk_timing_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
         "bgk_objective": [vp, vp, dp, dp, ctypes.c_double, dp, vp, dp, dp],
+        "bgk_objective_static": [vp, vp, dp, dp, ctypes.c_double, dp, vp, dp, dp],
         "bgk_adjoint_step": [vp, vp, dp, dp, vp, dp, dp, dp, vp, dp, dp],
         "bgk_adjoint_step_move": [vp, vp, dp, dp, vp, dp, dp, dp, dp, vp, dp, dp, dp],
         "bgk_moments_adjoint": [vp, dp, dp, dp, dp, dp, dp, vp],
@@ -339,6 +340,14 @@ def bgk_objective(ctx: Context, f, rho, U, ke_weight=1.0, want_grad=True):
     """J (0-d float64 tensor) and, if want_grad, (dJ_df, dJ_drho, dJ_dU);
     dJ_df has the f storage type."""
     return _objective(ctx, f, rho, U, ke_weight, want_grad, "bgk_objective")
+
+
+def bgk_objective_static(ctx: Context, f, rho, U, ke_weight=1.0, want_grad=True, out=None):
+    """bgk_objective through the entry point that allocates nothing (its
+    per-particle scratch is the library's fixed per-GPU array).  out: an
+    optional (J, dJ_df, dJ_drho, dJ_dU) of caller tensors to write into, so
+    that the call itself allocates nothing here either."""
+    return _objective(ctx, f, rho, U, ke_weight, want_grad, "bgk_objective_static", out)
 
 
 def _objective(ctx, f, rho, U, ke_weight, want_grad, name, out=None):

@@ -3,12 +3,45 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "bgk_internal.h"
 
 namespace bgk {
+
+// Device scratch of bgk_objective_static (the per-particle terms of the
+// objective): a fixed array in every GPU's copy of the code object, held
+// until the process ends.  Host code never uses its name as an address: the
+// address of each GPU's copy is looked up once per device, with that device
+// current, and kept here.
+static __device__ __align__(256) double scratch[BGK_STATIC_SCRATCH_PARTICLES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch;   // per device ordinal, null until looked up
+}  // namespace
+
+// Looks up this device's copy of the scratch (the device must be current).
+hipError_t static_scratch_setup(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0) return hipErrorInvalidDevice;
+  if (static_cast<size_t>(device) >= g_scratch.size()) g_scratch.resize(device + 1, nullptr);
+  if (g_scratch[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch[device] = static_cast<double*>(p);
+  return hipSuccess;
+}
+
+double* static_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return device >= 0 && static_cast<size_t>(device) < g_scratch.size() ? g_scratch[device]
+                                                                        : nullptr;
+}
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -231,6 +264,7 @@ int bgk_init(const bgk_config* cfg, const int32_t* wall_id, void* workspace, siz
   c.nl = bgk::lattice_nodes(*cfg);
   c.nodes = bgk::ipow(c.nl, c.D);
   hipError_t e = hipGetDevice(&c.device);
+  if (e == hipSuccess) e = bgk::static_scratch_setup(c.device);
   // wall ids: read once to count and list the wall particles
   std::vector<int32_t> wid(c.N);
   if (e == hipSuccess)
@@ -525,6 +559,25 @@ int bgk_objective(bgk_ctx* ctx, const void* f, const double* rho, const double* 
   return bgk::hip_fail(&c, bgk::launch_objective(c, f, rho, U, ke_weight, J, dJ_df, dJ_drho, dJ_dU,
                                                 c.d.jpart),
                        "bgk_objective");
+}
+
+int bgk_objective_static(bgk_ctx* ctx, const void* f, const double* rho, const double* U,
+                         double ke_weight, double* J, void* dJ_df, double* dJ_drho,
+                         double* dJ_dU) {
+  if (!ctx || !f || !rho || !U || !J || !std::isfinite(ke_weight)) return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  if (c.cfg.precision == BGK_BF16)
+    return bgk::fail(&c, BGK_ENOTSUP, "bgk_objective_static needs FP64 or FP32");
+  if (static_cast<int64_t>(c.N) > BGK_STATIC_SCRATCH_PARTICLES)
+    return bgk::fail(&c, BGK_EINVAL,
+                     "bgk_objective_static: more particles than its static scratch holds "
+                     "(BGK_STATIC_SCRATCH_PARTICLES)");
+  double* part = bgk::static_scratch(c.device);
+  if (!part)
+    return bgk::fail(&c, BGK_EDEVICE, "bgk_objective_static: no static scratch on this device");
+  return bgk::hip_fail(&c, bgk::launch_objective(c, f, rho, U, ke_weight, J, dJ_df, dJ_drho, dJ_dU,
+                                                part),
+                       "bgk_objective_static");
 }
 
 namespace {

@@ -160,6 +160,11 @@ struct Ctx {
   std::vector<hipEvent_t> event_pool;
 };
 
+// Per-device address of the static scratch of bgk_objective_static
+// (looked up by bgk_init with the device current; null before).
+hipError_t static_scratch_setup(int device);
+double* static_scratch(int device);
+
 // Workspace layout: returns total bytes; fills d when base != nullptr.
 size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj, Pm* pm,
                         MoveAdj* madj = nullptr);
@@ -228,7 +233,8 @@ hipError_t launch_adjoint_move_prep(const Ctx& c, const double* x, const double*
 hipError_t launch_adjoint_wallrow(const Ctx& c);
 hipError_t launch_adjoint_move_geometry(const Ctx& c, const void* f_n, const double* U_n,
                                         const double* x, double* lam_x);
-// part: N doubles of device scratch for the per-particle terms
+// part: N doubles of device scratch for the per-particle terms (the
+// context's workspace, or the static scratch of bgk_objective_static)
 hipError_t launch_objective(const Ctx& c, const void* f, const double* rho, const double* U,
                             double ke, double* J, void* dJ_df, double* dJ_drho, double* dJ_dU,
                             double* part);
