@@ -165,10 +165,12 @@ size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj, Pm*
     a.T1 = reinterpret_cast<double*>(take(N * 8));
     a.larr = take(F * fs);
     a.lidpart = reinterpret_cast<double*>(take(N * 8));
-    a.gpart = reinterpret_cast<double*>(take(adj_tiles(cfg) * D * N * 8));
-    a.ucount = reinterpret_cast<int32_t*>(take((N + 1) / 2 * 4));
-    a.uj = reinterpret_cast<int32_t*>(take((N + 1) / 2 * kAdjPatch * cap * 4));
-    a.ue = reinterpret_cast<uint32_t*>(take((N + 1) / 2 * kAdjPatch * cap * 4));
+    const AdjPlan ap = adj_plan(cfg);
+    const size_t npa = (N + ap.P - 1) / ap.P;
+    a.gpart = reinterpret_cast<double*>(take(static_cast<size_t>(ap.tiles) * D * N * 8));
+    a.ucount = reinterpret_cast<int32_t*>(take(npa * 4));
+    a.uj = reinterpret_cast<int32_t*>(take(npa * ap.P * cap * 4));
+    a.ue = reinterpret_cast<uint32_t*>(take(npa * ap.P * cap * 4));
     if (adj) *adj = a;
     if (cfg.move) {
       MoveAdj v{};

@@ -121,12 +121,28 @@ inline double omega_of(const bgk_config& cfg) {
   return w;
 }
 
-// Velocity tiles of the reverse transport: one wavefront of 64 threads per
-// (particle, tile), 2 velocities per thread.
-inline int64_t adj_tiles(const bgk_config& cfg) {
+// Launch plan of the reverse transport: R velocities per lane along the
+// fastest axis (4 in 3D when 4 divides nv, else 2), interior patches of
+// P = 2 particles, and for the patch kernel nvb velocity blocks of nw
+// wavefronts; tiles = nvb nw 64-lane tiles, the parts of lam_U per
+// particle (t64 of them hold velocities; the per-particle wall kernel runs
+// over those).  nw = 1: blocks of several wavefronts that share one
+// derivation of the edge records were slower in both precisions (the
+// waves of a block then wait on the derivation together).
+struct AdjPlan {
+  int R, P, nw, nvb, t64, tiles;
+};
+inline AdjPlan adj_plan(const bgk_config& cfg) {
   int64_t nvel = 1;
   for (int a = 0; a < cfg.dim; ++a) nvel *= cfg.nv;
-  return (nvel / 2 + 63) / 64;
+  AdjPlan p{};
+  p.R = (cfg.dim == 3 && cfg.nv % 4 == 0) ? 4 : 2;
+  p.P = 2;
+  p.t64 = static_cast<int>((nvel / p.R + 63) / 64);
+  p.nw = 1;
+  p.nvb = p.t64;
+  p.tiles = p.nvb * p.nw;
+  return p;
 }
 
 // Lattice nodes per axis of the initial cloud (spacing dx on [0, 1]).
@@ -190,7 +206,6 @@ hipError_t launch_wall_unions(const Ctx& c);
 hipError_t launch_unions(const Ctx& c, int P, int n, const int32_t* plist, const int32_t* cnt,
                          const int32_t* idx, int drop_self, int ucap, int32_t* ucount,
                          int32_t* uj, uint32_t* ue);
-constexpr int kAdjPatch = 2;  // interior particles per patch of the reverse transport
 
 hipError_t launch_transport(const Ctx& c, const void* f_in, void* f_out, const double* U);
 hipError_t launch_copy_wall_rows(const Ctx& c, const void* f_in, void* f_out);

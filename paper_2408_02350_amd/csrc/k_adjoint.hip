@@ -220,8 +220,34 @@ __global__ __launch_bounds__(kThreads) void k_adj_wall(const AdjArgs<Real> a) {
 // ------------------------------------------------------------ S5-S6 adjoint
 // The velocity nodes and the per-axis factors exp(-(v_k - U_a)^2 / (2T)) of
 // the particle's Maxwellian are tabulated in LDS (dynamic, (D+1)*nv doubles):
-// M = norm * prod_a e_a[k_a], Chu G2 = T G1.
+// M = norm * prod_a e_a[k_a], Chu G2 = T G1.  A thread's velocities are
+// q = tid + m kThreads; their per-axis indices are advanced by the digits of
+// the stride (no integer division per velocity), and the per-particle
+// quotients (1/T, the moment-adjoint coefficients) are formed once.
 constexpr int kAdjKeep = 4;
+
+template <int D>
+struct VelDigits {  // base-nv digits of a velocity index, fastest axis first
+  int k[D], st[D];
+  __device__ void init(int q, int stride, int nv) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      k[a] = q % nv;
+      q /= nv;
+      st[a] = stride % nv;
+      stride /= nv;
+    }
+  }
+  __device__ void advance(int nv) {  // (the carry out of the last digit is
+    int carry = 0;                   //  past N_v: the loops end there)
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int x = k[a] + st[a] + carry;
+      carry = x >= nv;
+      k[a] = carry ? x - nv : x;
+    }
+  }
+};
 
 template <int D, int NC, typename Real>
 __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a) {
@@ -243,6 +269,8 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
   const double den = tau + a.dt;
   const double ca = tau / den, cb = a.dt / den, dtau = a.dt / (den * den);  // d f'/d tau = (ft-M) dtau
   const double kap0 = (D == 3) ? 1.5 : 1.0;
+  // d M / d T = M (-kap/T + |v-U|^2 / (2 T^2)), kap = d/2 (Chu G2: kap = 0)
+  const double iT = 1.0 / T, h2 = 0.5 * iT * iT, kT = -kap0 * iT;
   const int ws = a.wtstart[i], we = a.wtstart[i + 1];
   double* et = vt + a.nv;
   for (int k = threadIdx.x; k < a.nv; k += blockDim.x) vt[k] = vnode(k, a.nv, a.vmax);
@@ -255,15 +283,16 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
   __syncthreads();
   const double tp = 2.0 * kPi * T;
   const double norm = D == 3 ? rho / (tp * sqrt(tp)) : rho / tp;
-  auto vel = [&](int q, double (&v)[3], double& M1) {
-    v[0] = v[1] = v[2] = 0.0;
+  // w = v - U, |w|^2 and the Maxwellian's first component at digits kd
+  auto vel = [&](const int (&kd)[D], double (&w)[3], double& w2, double& M1) {
+    w[0] = w[1] = w[2] = 0.0;
+    w2 = 0.0;
     M1 = norm;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      const int kk = q % a.nv;
-      q /= a.nv;
-      v[k] = vt[kk];
-      M1 = M1 * et[k * a.nv + kk];
+      w[k] = vt[kd[k]] - U[k];
+      w2 = w2 + w[k] * w[k];
+      M1 = M1 * et[k * a.nv + kd[k]];
     }
   };
   // adjoint of f' = lam_f1 + sum over the wall rows that interpolate from i
@@ -279,37 +308,41 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
   double s[D + 3];  // A1 = sum l M, A2 = sum l (ft - M), AU[d], AT
 #pragma unroll
   for (int k = 0; k < D + 3; ++k) s[k] = 0.0;
-  auto sums = [&](int q, double (&lq)[NC]) {
-    double v[3], M1;
-    vel(q, v, M1);
-    double w2 = 0.0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) w2 = w2 + (v[k] - U[k]) * (v[k] - U[k]);
+  auto sums = [&](int q, const int (&kd)[D], double (&lq)[NC]) {
+    double w[3], w2, M1;
+    vel(kd, w, w2, M1);
+    const double dlog = fma(w2, h2, kT);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const double M = c == 0 ? M1 : T * M1;
       const double l = lam_fp(c, q);
       lq[c] = l;
       const double x = a.ft[c * cs + static_cast<size_t>(i) * NVs + q];
-      s[0] = s[0] + l * M;
+      const double lM = l * M;
+      s[0] = s[0] + lM;
       s[1] = s[1] + l * (x - M);
 #pragma unroll
-      for (int k = 0; k < D; ++k) s[2 + k] = s[2 + k] + l * M * (v[k] - U[k]);
-      const double kap = (c == 1) ? 0.0 : kap0;
-      s[2 + D] = s[2 + D] + l * M * (-kap / T + w2 / (2.0 * T * T));
+      for (int k = 0; k < D; ++k) s[2 + k] = s[2 + k] + lM * w[k];
+      s[2 + D] = s[2 + D] + lM * ((c == 1) ? w2 * h2 : dlog);
     }
   };
   // the adjoint of f' at a thread's first kAdjKeep velocities is kept in
   // registers for the second pass (the rest is gathered again)
   double lk[kAdjKeep][NC];
+  {
+    VelDigits<D> vd;
+    vd.init(threadIdx.x, kThreads, a.nv);
+    int q = threadIdx.x;
 #pragma unroll
-  for (int k = 0; k < kAdjKeep; ++k) {
-    const int q = threadIdx.x + k * kThreads;
-    if (q < a.NV) sums(q, lk[k]);
-  }
-  for (int q = threadIdx.x + kAdjKeep * kThreads; q < a.NV; q += kThreads) {
-    double lq[NC];
-    sums(q, lq);
+    for (int k = 0; k < kAdjKeep; ++k, q += kThreads) {
+      if (q < a.NV) sums(q, vd.k, lk[k]);
+      vd.advance(a.nv);
+    }
+    for (; q < a.NV; q += kThreads) {
+      double lq[NC];
+      sums(q, vd.k, lq);
+      vd.advance(a.nv);
+    }
   }
   block_sum<D + 3>(s, sh);
   const double g_rho = lr + cb * s[0] / rho + s[1] * dtau * (-tau / rho);
@@ -317,25 +350,41 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
 #pragma unroll
   for (int k = 0; k < D; ++k) gU[k] = lU[k] + cb * s[2 + k] / T;
   const double g_T = lT + cb * s[2 + D] + s[1] * dtau * (-tau / (2.0 * T));
-  auto write = [&](int q, const double (&lq)[NC]) {
-    double v[3], M1;
-    vel(q, v, M1);
+  // the moments' adjoint at one velocity (S5: rho = omega sum f, U = sum v f
+  // / s0, 3 s0 T = sum |v-U|^2 f (+ sum G2 in the Chu model)) as
+  //   m0 + sum_a mU_a w_a + mT |w|^2  (first component),  mT  (second)
+  const double is0 = 1.0 / s0, mT = g_T * is0 / 3.0, m0 = g_rho * a.omega - g_T * T * is0;
+  double mU[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < D; ++k) mU[k] = gU[k] * is0;
+  auto write = [&](int q, const int (&kd)[D], const double (&lq)[NC]) {
+    double w[3], w2, M1;
+    vel(kd, w, w2, M1);
+    double g0 = fma(mT, w2, m0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) g0 = fma(mU[k], w[k], g0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const double l = ca * lq[c] + mom_adj<D, NC>(c, v, a.omega, s0, U, T, g_rho, gU, g_T);
+      const double l = fma(ca, lq[c], c == 1 ? mT : g0);
       a.lam_ft[c * cs + static_cast<size_t>(i) * NVs + q] = static_cast<Real>(l);
     }
   };
+  {
+    VelDigits<D> vd;
+    vd.init(threadIdx.x, kThreads, a.nv);
+    int q = threadIdx.x;
 #pragma unroll
-  for (int k = 0; k < kAdjKeep; ++k) {
-    const int q = threadIdx.x + k * kThreads;
-    if (q < a.NV) write(q, lk[k]);
-  }
-  for (int q = threadIdx.x + kAdjKeep * kThreads; q < a.NV; q += kThreads) {
-    double lq[NC];
+    for (int k = 0; k < kAdjKeep; ++k, q += kThreads) {
+      if (q < a.NV) write(q, vd.k, lk[k]);
+      vd.advance(a.nv);
+    }
+    for (; q < a.NV; q += kThreads) {
+      double lq[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) lq[c] = lam_fp(c, q);
-    write(q, lq);
+      for (int c = 0; c < NC; ++c) lq[c] = lam_fp(c, q);
+      write(q, vd.k, lq);
+      vd.advance(a.nv);
+    }
   }
 }
 
@@ -584,29 +633,52 @@ __global__ __launch_bounds__(64) void k_adj_transport(const AdjArgs<Real> a) {
 }
 
 // The same reverse transport for the interior particles, taken P at a time
-// in cell order (P = kAdjPatch; the unions are merged once per frozen
-// cloud): one wavefront per (patch, tile) walks the sorted union of the
-// patch's neighbour lists once and loads each neighbour's f^n and lam_ft
-// rows once for all P particles (four particles per patch were slower: the
-// register footprint halves the waves per SIMD).
-// The own and transposed edge records of every (union entry, particle) are
-// staged in LDS per chunk; each particle takes its own edges in its row
-// order.  The flux coefficient is formed as g.w - sum_k |a_k.w| and the
-// U-derivative sums from the signs of the projections (fewer VALU
-// operations than the minima and selects of the per-particle kernel; the
-// same values up to rounding, and the same derivative convention except at
-// a projection of exactly -0).
-constexpr int kAdjUChunk = 16;
+// in cell order (the unions are merged once per frozen cloud): one block
+// per (patch, velocity block of nw <= W wavefronts x 64 lanes x R
+// velocities; the launch plan takes nw = 1).  The block walks the sorted
+// union of the patch's neighbour lists once.  The own and transposed edge
+// records of a chunk of union entries are derived into LDS (with the
+// per-velocity increments and their sum, so the walk adds instead of
+// multiplying) and read with wave-uniform addresses; each lane loads the
+// two rows an entry needs (f^n_i for the U-derivative, lam_ft_i for the
+// transposed term) one entry ahead, once for all P particles.  The
+// per-velocity arithmetic is in the storage precision (FP32 storage: FP32
+// arithmetic, half the registers of FP64 and within that storage's
+// rounding); each lane's lam_U sums are folded per edge and reduced over the
+// wave in FP64 in a fixed order.  The flux coefficient is formed as
+// g.w - sum_k |a_k.w| and the U-derivative sums from the signs of the
+// projections (the same values as the per-particle kernel's minima and
+// selects up to rounding, and the same derivative convention except at a
+// projection of exactly -0).
+constexpr int kAdjUChunk = 32;
 
-template <int D, int NC, typename Real, int R, int P>
-__global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> a) {
-  constexpr int DD = D * D, REC = DD + 2 * D, CH = kAdjUChunk;
-  __shared__ double rown[CH][P][REC], rtr[CH][P][REC];
+template <typename Real, int R>
+__device__ __forceinline__ void load_rs(const Real* __restrict__ p, Real (&o)[R]) {
+  constexpr int W = (R * sizeof(Real)) % 16 == 0 ? 16 / static_cast<int>(sizeof(Real)) : R;
+  typedef Real V __attribute__((ext_vector_type(W)));
+  const V* pv = reinterpret_cast<const V*>(__builtin_assume_aligned(p, W * sizeof(Real)));
+#pragma unroll
+  for (int i = 0; i < R / W; ++i) {
+    const V x = pv[i];
+#pragma unroll
+    for (int w = 0; w < W; ++w) o[i * W + w] = x[w];
+  }
+}
+
+template <int D, int NC, typename Real, int R, int P, int W>
+__global__ __launch_bounds__(64 * W) void k_adj_transport_patch(const AdjArgs<Real> a) {
+  using A = Real;  // arithmetic of the per-velocity work
+  // record: a_k (d*d), a_k.U (d), a_k[fast] dv (d), sum_k a_k[fast] dv
+  constexpr int DD = D * D, REC = DD + 2 * D + 1, CH = kAdjUChunk;
+  __shared__ A rown[CH][P][REC], rtr[CH][P][REC];
   __shared__ int32_t ri[CH], rfl[CH][P];
-  // tile-major logical order, each XCD on one contiguous range of patches
-  const int lb = xcd_logical_block(blockIdx.x, gridDim.x), np = gridDim.x / a.tiles;
-  const int tile = lb / np, pb = lb - tile * np;
-  const int tid = threadIdx.x;
+  // velocity-block-major logical order, each XCD on one contiguous range;
+  // nw <= W waves per block, nvb velocity blocks, a.tiles = nvb nw
+  const int nw = static_cast<int>(blockDim.x) >> 6, nvb = a.tiles / nw;
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x), np = gridDim.x / nvb;
+  const int vb = lb / np, pb = lb - vb * np;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tile = vb * nw + wid;  // this wave's 64-lane tile
   const size_t NVs = a.NV, cs = static_cast<size_t>(a.N) * NVs;
   const double dv = 2.0 * a.vmax / static_cast<double>(a.nv - 1);
   int jt[P];
@@ -617,50 +689,74 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
   }
   const int nu = a.ucount[pb];
   const size_t ub = static_cast<size_t>(pb) * a.ucap;
-  double gU[P][3];
+  A gU[P][D];
 #pragma unroll
-  for (int t = 0; t < P; ++t) gU[t][0] = gU[t][1] = gU[t][2] = 0.0;
+  for (int t = 0; t < P; ++t)
+#pragma unroll
+    for (int k = 0; k < D; ++k) gU[t][k] = A(0);
   const int ngroups = a.NV / R;
-  const int g = tile * 64 + tid;
+  const int g = tile * 64 + lane;
   const bool on = g < ngroups;
   const int q0 = on ? g * R : 0;
-  double v0[D];
+  A v0[D];
   {
     int q = q0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      v0[k] = vnode(q % a.nv, a.nv, a.vmax);
+      v0[k] = static_cast<A>(vnode(q % a.nv, a.nv, a.vmax));
       q /= a.nv;
     }
   }
-  double lf[P][R][NC], lj[P][R][NC], fj[P][R][NC], csum[P][R];
+  // lf = sum_i c_ij lam_ft_i (transposed term, dt applied at the end);
+  // lj, fj: the particle's own lam_ft and f^n; csum = sum_i c_ji
+  A lf[P][R][NC], lj[P][R][NC], fj[P][R][NC], csum[P][R];
 #pragma unroll
   for (int t = 0; t < P; ++t) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      double t1[R], t2[R];
+      A t1[R], t2[R];
       if (jt[t] >= 0) {
-        load_rr<Real, R>(a.lam_ft + c * cs + static_cast<size_t>(jt[t]) * NVs + q0, t1);
-        load_rr<Real, R>(a.f_n + c * cs + static_cast<size_t>(jt[t]) * NVs + q0, t2);
+        load_rs<Real, R>(a.lam_ft + c * cs + static_cast<size_t>(jt[t]) * NVs + q0, t1);
+        load_rs<Real, R>(a.f_n + c * cs + static_cast<size_t>(jt[t]) * NVs + q0, t2);
       } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) t1[r] = t2[r] = 0.0;
+        for (int r = 0; r < R; ++r) t1[r] = t2[r] = A(0);
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        lf[t][r][c] = 0.0;
+        lf[t][r][c] = A(0);
         lj[t][r][c] = t1[r];
         fj[t][r][c] = t2[r];
       }
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) csum[t][r] = 0.0;
+    for (int r = 0; r < R; ++r) csum[t][r] = A(0);
   }
+
+  // one record from the operator row o of particle k (U of particle k)
+  auto make_rec = [&](const Real* o, int k, A* rec) {
+    double ig = 0.0;
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+      double b = 0.0;
+#pragma unroll
+      for (int mm = 0; mm < D; ++mm) {
+        const double xo = static_cast<double>(o[m * D + mm]);
+        rec[m * D + mm] = static_cast<A>(xo);
+        b = b + xo * a.U_n[static_cast<size_t>(mm) * a.N + k];
+      }
+      const double inc = static_cast<double>(o[m * D]) * dv;
+      rec[DD + m] = static_cast<A>(b);
+      rec[DD + D + m] = static_cast<A>(inc);
+      ig = ig + static_cast<double>(static_cast<A>(inc));
+    }
+    rec[DD + 2 * D] = static_cast<A>(ig);
+  };
 
   for (int c0 = 0; c0 < nu; c0 += CH) {
     const int cn = min(CH, nu - c0);
-    __syncthreads();
-    for (int x = tid; x < cn * P; x += 64) {
+    __syncthreads();  // the previous chunk is consumed
+    for (int x = tid; x < cn * P; x += static_cast<int>(blockDim.x)) {
       const int w = x / P, t = x - w * P;
       const size_t u = ub + c0 + w;
       const int i = a.uj[u];
@@ -673,47 +769,21 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
         const int64_t rj = static_cast<int64_t>(j) * a.cap + e;
         const int te = a.tidx[rj];
         fl = 1 | (te >= 0 ? 2 : 0);
-        const Real* o = a.ops + rj * DD;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-          double b = 0.0;
-#pragma unroll
-          for (int mm = 0; mm < D; ++mm) {
-            const double xo = static_cast<double>(o[k * D + mm]);
-            rown[w][t][k * D + mm] = xo;
-            b = b + xo * a.U_n[static_cast<size_t>(mm) * a.N + j];
-          }
-          rown[w][t][DD + k] = b;
-          rown[w][t][DD + D + k] = static_cast<double>(o[k * D]) * dv;
-        }
-        if (te >= 0) {
-          const Real* ot = a.ops + (static_cast<int64_t>(i) * a.cap + te) * DD;
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            double b = 0.0;
-#pragma unroll
-            for (int mm = 0; mm < D; ++mm) {
-              const double xo = static_cast<double>(ot[k * D + mm]);
-              rtr[w][t][k * D + mm] = xo;
-              b = b + xo * a.U_n[static_cast<size_t>(mm) * a.N + i];
-            }
-            rtr[w][t][DD + k] = b;
-            rtr[w][t][DD + D + k] = static_cast<double>(ot[k * D]) * dv;
-          }
-        }
+        make_rec(a.ops + rj * DD, j, rown[w][t]);
+        if (te >= 0) make_rec(a.ops + (static_cast<int64_t>(i) * a.cap + te) * DD, i, rtr[w][t]);
       }
       rfl[w][t] = fl;
     }
     __syncthreads();
     // rows of union entry w: f^n_i and lam_ft_i
-    double fa[R][NC], la[R][NC], fb[R][NC], lb[R][NC];
-    auto load_entry = [&](int w, double (&fi)[R][NC], double (&li)[R][NC]) {
+    A fa[R][NC], la[R][NC], fb[R][NC], lb2[R][NC];
+    auto load_entry = [&](int w, A (&fi)[R][NC], A (&li)[R][NC]) {
       const int i = ri[w];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        double t1[R], t2[R];
-        load_rr<Real, R>(a.f_n + c * cs + static_cast<size_t>(i) * NVs + q0, t1);
-        load_rr<Real, R>(a.lam_ft + c * cs + static_cast<size_t>(i) * NVs + q0, t2);
+        A t1[R], t2[R];
+        load_rs<Real, R>(a.f_n + c * cs + static_cast<size_t>(i) * NVs + q0, t1);
+        load_rs<Real, R>(a.lam_ft + c * cs + static_cast<size_t>(i) * NVs + q0, t2);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           fi[r][c] = t1[r];
@@ -722,106 +792,99 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
       }
       asm volatile("" ::: "memory");
     };
-    // 2 sum_k min(p_k, 0), the flux coefficient of an edge at one velocity,
-    // as g.w - sum_k |p_k| with g.w = sum_k p_k advanced by its own increment
-    // (absolute values are free source modifiers)
-    auto gw_init = [&](const double (&p)[D], const double* rc, double& gw, double& dgw) {
-      gw = p[0];
-      dgw = rc[DD + D];
+    // projections p_k = a_k.(v0 - U) of a record and g.w = sum_k p_k
+    auto proj = [&](const A* rc, A (&p)[D], A& gw) {
 #pragma unroll
-      for (int k = 1; k < D; ++k) {
-        gw = gw + p[k];
-        dgw = dgw + rc[DD + D + k];
+      for (int k = 0; k < D; ++k) {
+        A s1 = -rc[DD + k];
+#pragma unroll
+        for (int mm = 0; mm < D; ++mm) s1 = fma(rc[k * D + mm], v0[mm], s1);
+        p[k] = s1;
       }
-    };
-    auto two_cm = [&](const double (&p)[D], double gw) {
-      double c = gw;
+      gw = p[0];
 #pragma unroll
-      for (int k = 0; k < D; ++k) c = c - fabs(p[k]);
-      return c;
+      for (int k = 1; k < D; ++k) gw = gw + p[k];
     };
-    auto entry = [&](int w, const double (&fi)[R][NC], const double (&li)[R][NC]) {
+    auto entry = [&](int w, const A (&fi)[R][NC], const A (&li)[R][NC]) {
 #pragma unroll
       for (int t = 0; t < P; ++t) {
         const int fl = rfl[w][t];
         if (fl & 1) {
-          const double* rc = rown[w][t];
-          double p[D], S[D];
+          const A* rc = rown[w][t];
+          A p[D], S[D], ik[D], gw;
+          proj(rc, p, gw);
 #pragma unroll
           for (int k = 0; k < D; ++k) {
-            double s1 = -rc[DD + k];
-#pragma unroll
-            for (int mm = 0; mm < D; ++mm) s1 = s1 + rc[k * D + mm] * v0[mm];
-            p[k] = s1;
-            S[k] = 0.0;
+            S[k] = A(0);
+            ik[k] = rc[DD + D + k];
           }
-          double gw = 0.0, dgw = 0.0, sd = 0.0;
-          gw_init(p, rc, gw, dgw);
+          const A dgw = rc[DD + 2 * D];
+          A sd = A(0);
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             if (r > 0) {
 #pragma unroll
-              for (int k = 0; k < D; ++k) p[k] = p[k] + rc[DD + D + k];
+              for (int k = 0; k < D; ++k) p[k] = p[k] + ik[k];
               gw = gw + dgw;
             }
-            csum[t][r] = csum[t][r] + two_cm(p, gw);
-            double sdf = 0.0;
+            A cm = gw;  // 2 sum_k min(0, p_k)
 #pragma unroll
-            for (int c = 0; c < NC; ++c) sdf = sdf + lj[t][r][c] * (fi[r][c] - fj[t][r][c]);
+            for (int k = 0; k < D; ++k) cm = cm - fabs(p[k]);
+            csum[t][r] = csum[t][r] + cm;
+            A sdf = A(0);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sdf = fma(lj[t][r][c], fi[r][c] - fj[t][r][c], sdf);
             // sum over the group of [p_k < 0] sdf as (sum sdf - sum sign(p_k) sdf) / 2
             sd = sd + sdf;
 #pragma unroll
-            for (int k = 0; k < D; ++k) S[k] = fma(copysign(1.0, p[k]), sdf, S[k]);
+            for (int k = 0; k < D; ++k) S[k] = fma(copysign(A(1), p[k]), sdf, S[k]);
           }
           if (on) {
-            double S2[D];  // 2 x the sums of [p_k < 0] sdf
 #pragma unroll
-            for (int k = 0; k < D; ++k) S2[k] = sd - S[k];
+            for (int k = 0; k < D; ++k) S[k] = sd - S[k];  // 2 x the sums of [p_k < 0] sdf
 #pragma unroll
             for (int mm = 0; mm < D; ++mm) {
-              double tt = 0.0;
+              A tt = A(0);
 #pragma unroll
-              for (int k = 0; k < D; ++k) tt = tt + rc[k * D + mm] * S2[k];
+              for (int k = 0; k < D; ++k) tt = fma(rc[k * D + mm], S[k], tt);
               gU[t][mm] = gU[t][mm] - tt;
             }
           }
         }
         if (fl & 2) {
-          const double* rc = rtr[w][t];
-          double p[D];
+          const A* rc = rtr[w][t];
+          A p[D], ik[D], gw;
+          proj(rc, p, gw);
 #pragma unroll
-          for (int k = 0; k < D; ++k) {
-            double s1 = -rc[DD + k];
-#pragma unroll
-            for (int mm = 0; mm < D; ++mm) s1 = s1 + rc[k * D + mm] * v0[mm];
-            p[k] = s1;
-          }
-          double gw = 0.0, dgw = 0.0;
-          gw_init(p, rc, gw, dgw);
+          for (int k = 0; k < D; ++k) ik[k] = rc[DD + D + k];
+          const A dgw = rc[DD + 2 * D];
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             if (r > 0) {
 #pragma unroll
-              for (int k = 0; k < D; ++k) p[k] = p[k] + rc[DD + D + k];
+              for (int k = 0; k < D; ++k) p[k] = p[k] + ik[k];
               gw = gw + dgw;
             }
-            const double dc = a.dt * two_cm(p, gw);
+            A cm = gw;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) lf[t][r][c] = lf[t][r][c] - dc * li[r][c];
+            for (int k = 0; k < D; ++k) cm = cm - fabs(p[k]);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) lf[t][r][c] = fma(cm, li[r][c], lf[t][r][c]);
           }
         }
       }
     };
     load_entry(0, fa, la);
     for (int w = 0; w < cn; w += 2) {
-      if (w + 1 < cn) load_entry(w + 1, fb, lb);
+      if (w + 1 < cn) load_entry(w + 1, fb, lb2);
       entry(w, fa, la);
       if (w + 1 < cn) {
         if (w + 2 < cn) load_entry(w + 2, fa, la);
-        entry(w + 1, fb, lb);
+        entry(w + 1, fb, lb2);
       }
     }
   }
+  const A dt = static_cast<A>(a.dt);
 #pragma unroll
   for (int t = 0; t < P; ++t) {
     if (jt[t] < 0) continue;
@@ -831,7 +894,7 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
         Real out[R];
 #pragma unroll
         for (int r = 0; r < R; ++r)
-          out[r] = static_cast<Real>(lf[t][r][c] + lj[t][r][c] * (1.0 + a.dt * csum[t][r]));
+          out[r] = fma(lj[t][r][c], fma(dt, csum[t][r], A(1)), -dt * lf[t][r][c]);
 #pragma unroll
         for (int r = 0; r < R; ++r)
           a.lam_f[c * cs + static_cast<size_t>(jt[t]) * NVs + q0 + r] = out[r];
@@ -839,13 +902,10 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
     }
 #pragma unroll
     for (int mm = 0; mm < D; ++mm) {
+      double s = static_cast<double>(gU[t][mm]);
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) gU[t][mm] += __shfl_xor(gU[t][mm], o, 64);
-    }
-    if (tid == 0) {
-#pragma unroll
-      for (int mm = 0; mm < D; ++mm)
-        a.gpart[(static_cast<size_t>(tile) * D + mm) * a.N + jt[t]] = gU[t][mm];
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+      if (lane == 0) a.gpart[(static_cast<size_t>(tile) * D + mm) * a.N + jt[t]] = s;
     }
   }
 }
@@ -998,8 +1058,22 @@ hipError_t launch_adjoint_transposes(const Ctx& c) {
                      j.wt);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_unions(c, kAdjPatch, c.Ni, c.d.cperm, c.d.ncnt, c.d.nidx, 1, kAdjPatch * c.cap,
-                       j.ucount, j.uj, j.ue);
+  const int P = adj_plan(c.cfg).P;
+  return launch_unions(c, P, c.Ni, c.d.cperm, c.d.ncnt, c.d.nidx, 1, P * c.cap, j.ucount, j.uj,
+                       j.ue);
+}
+
+// The patch kernel's instantiation for the plan.
+template <int D, int NC, typename Real, int R>
+static hipError_t launch_adj_patch(const Ctx& c, const AdjArgs<Real>& a, const AdjPlan& ap,
+                                   int npa) {
+  constexpr int P = 2, W = 1;
+  if (ap.P != P || ap.nw > W) return hipErrorInvalidValue;
+  const int64_t nb = static_cast<int64_t>(npa) * ap.nvb;
+  if (nb > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_adj_transport_patch<D, NC, Real, R, P, W>), dim3(static_cast<unsigned>(nb)),
+                     dim3(64 * ap.nw), 0, c.stream, a);
+  return hipGetLastError();
 }
 
 template <typename Real>
@@ -1019,50 +1093,48 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
                   j.T1,       lam_f1,     lam_U1,     lam_rho1,    lam_T1,
                   static_cast<Real*>(j.larr), static_cast<Real*>(j.lam_ft), lam_f, lam_U,
                   j.lidpart, j.gpart, 0,
-                  nullptr,    j.ucount,   j.uj,       j.ue,        kAdjPatch * c.cap};
+                  nullptr,    j.ucount,   j.uj,       j.ue,        0};
+  const AdjPlan ap = adj_plan(c.cfg);
+  a.ucap = ap.P * c.cap;
   dim3 t(kThreads);
   const size_t lds = static_cast<size_t>(c.D + 1) * c.cfg.nv * sizeof(double);
-  // reverse transport: one wavefront per (patch of interior particles, tile
-  // of 64 groups of 2 velocities) and per (wall particle, tile), then the
+  // reverse transport: one block per (patch of interior particles, velocity
+  // block) and one wavefront per (wall particle, 64-lane tile), then the
   // tile parts of lam_U summed in tile order
-  // velocities per lane: 4 in 3D when 4 divides nv (the per-edge set-up is
-  // shared by more velocities: the 3D kernel issues VALU work most of the
-  // time), else 2
-  const int R = (c.D == 3 && c.cfg.nv % 4 == 0) ? 4 : 2;
-  a.tiles = static_cast<int>((c.NV / R + 63) / 64);
-  const int npa = (c.Ni + kAdjPatch - 1) / kAdjPatch;
-  const int64_t nbp = static_cast<int64_t>(npa) * a.tiles;
-  const int64_t nbw = static_cast<int64_t>(c.Nw) * a.tiles;
-  if (nbp > INT32_MAX || nbw > INT32_MAX) return hipErrorInvalidValue;
-  const dim3 tp(static_cast<unsigned>(nbp)), tw(static_cast<unsigned>(nbw)), tt(64);
+  const int R = ap.R;
+  a.tiles = ap.tiles;
+  const int npa = (c.Ni + ap.P - 1) / ap.P;
+  const int64_t nbw = static_cast<int64_t>(c.Nw) * ap.t64;
+  if (nbw > INT32_MAX) return hipErrorInvalidValue;
+  const dim3 tw(static_cast<unsigned>(nbw)), tt(64);
   AdjArgs<Real> aw = a;
   aw.jlist = c.d.wall_list;
+  aw.tiles = ap.t64;  // (the wall rows of gpart past t64 are never read)
+  hipError_t e = hipSuccess;
   if (c.D == 2) {
     if (c.Nw) hipLaunchKernelGGL((k_adj_wall<2, 2, Real>), dim3(c.Nw), t, 0, c.stream, a);
     if (wall_rows) {
-      const hipError_t e = launch_adjoint_wallrow(c);
+      e = launch_adjoint_wallrow(c);
       if (e != hipSuccess) return e;
     }
     if (c.Ni) hipLaunchKernelGGL((k_adj_collide<2, 2, Real>), dim3(c.Ni), t, lds, c.stream, a);
-    if (npa)
-      hipLaunchKernelGGL((k_adj_transport_patch<2, 2, Real, 2, kAdjPatch>), tp, tt, 0, c.stream, a);
+    if (npa) e = launch_adj_patch<2, 2, Real, 2>(c, a, ap, npa);
+    if (e != hipSuccess) return e;
     if (c.Nw) hipLaunchKernelGGL((k_adj_transport<2, 2, Real, 2>), tw, tt, 0, c.stream, aw);
   } else {
     if (c.Nw) hipLaunchKernelGGL((k_adj_wall<3, 1, Real>), dim3(c.Nw), t, 0, c.stream, a);
     if (wall_rows) {
-      const hipError_t e = launch_adjoint_wallrow(c);
+      e = launch_adjoint_wallrow(c);
       if (e != hipSuccess) return e;
     }
     if (c.Ni) hipLaunchKernelGGL((k_adj_collide<3, 1, Real>), dim3(c.Ni), t, lds, c.stream, a);
     if (R == 4) {
-      if (npa)
-        hipLaunchKernelGGL((k_adj_transport_patch<3, 1, Real, 4, kAdjPatch>), tp, tt, 0, c.stream,
-                           a);
+      if (npa) e = launch_adj_patch<3, 1, Real, 4>(c, a, ap, npa);
+      if (e != hipSuccess) return e;
       if (c.Nw) hipLaunchKernelGGL((k_adj_transport<3, 1, Real, 4>), tw, tt, 0, c.stream, aw);
     } else {
-      if (npa)
-        hipLaunchKernelGGL((k_adj_transport_patch<3, 1, Real, 2, kAdjPatch>), tp, tt, 0, c.stream,
-                           a);
+      if (npa) e = launch_adj_patch<3, 1, Real, 2>(c, a, ap, npa);
+      if (e != hipSuccess) return e;
       if (c.Nw) hipLaunchKernelGGL((k_adj_transport<3, 1, Real, 2>), tw, tt, 0, c.stream, aw);
     }
   }

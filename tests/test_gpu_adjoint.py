@@ -107,8 +107,10 @@ def test_adjoint_step_is_the_transpose_of_the_dual_step(dim, n, nv, kn, seed):
 
 @pytest.mark.parametrize("dim,n,nv,kn,seed", [CASES[0], CASES[2]])
 def test_adjoint_step_fp32_storage_against_the_dual_step(dim, n, nv, kn, seed):
-    """FP32 storage of f and of the adjoints, FP64 arithmetic inside: the
-    transpose identity holds to the FP32 rounding of the inputs."""
+    """FP32 storage of f and of the adjoints (FP32 arithmetic in the reverse
+    transport's per-velocity work, FP64 in its lam_U reductions and in the
+    other reverse kernels): the transpose identity holds to the FP32
+    rounding."""
     k = AdjCase(cavity(dim, n, nv, kn=kn), seed, precision="fp32")
     c = k.c
     f, U = smooth_state(c, k.x, seed)
