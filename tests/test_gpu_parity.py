@@ -411,10 +411,51 @@ def test_step_parity_2d_fp64_four_particle_patches():
 @pytest.mark.parametrize("n,nv,steps", [(8, 20, 3), (10, 20, 2)])
 def test_step_parity_3d_fp64_two_velocity_tiles(n, nv, steps):
     """3D FP64 with 20^3 velocities (the grid of the 48^3 x 20^3 cavity): 4
-    velocities per lane, two velocity tiles, the relaxation finished after
-    the tiles.  From a spatially varying state."""
+    velocities per lane, two velocity tiles of 1000 lanes walked in turn by
+    one block, which keeps the first tile's f-tilde in LDS and then relaxes
+    both.  From a spatially varying state."""
     k, g, r = run_both(cavity(3, n, nv), steps, 4, init="smooth")
     assert_state_close(g, r)
+
+
+def test_step_parity_c5_sampled_rows():
+    """The benchmark's own configuration and launch shape: one full step of
+    the 48^3 x 20^3 cavity in FP64 (4-particle patches, two velocity tiles of
+    1000 lanes walked in turn by one block with the first tile's f-tilde in
+    LDS, the relaxation in the same block) from a spatially varying state,
+    against the oracle's per-row step (its O(N) neighbour row, least-squares
+    row, transport of the row, moments and relaxation) on sampled interior
+    rows: two lattice rows next to a corner, at a face, at the centre and at
+    the far edge, every velocity, to 1e-12."""
+    cav = CONFIGS["c5"].replace(precision="fp64")
+    k = Case(cav, cav.seed)
+    c, n = k.c, cav.n
+    f0 = smooth_two_maxwellians(c, k.x)
+    rho0, U0, T0 = oracle.moments(c, f0)
+    f = k.t(f0)
+    fn = torch.empty_like(f)
+    x = k.t(k.x)
+    U, rho, T = k.t(U0), k.t(rho0), k.t(T0)
+    say("  c5 step on the GPU")
+    bgk.bgk_step(k.ctx, f, fn, x, U, rho, T)
+    bgk.bgk_check(k.ctx)
+    del f
+    g = fn.cpu().numpy()
+    del fn
+    starts = [n * n + n + 1, n * n + n * (n // 2), n * n * (n // 2) + n * (n // 2),
+              n * n * (n - 2) + n * (n - 3)]
+    checked = 0
+    for i0 in starts:
+        i1 = i0 + 2 * n
+        say(f"  oracle rows {i0}..{i1}")
+        ref, _, nr = oracle.step_rows(c, k.wid, k.x, f0, U0, i0, i1)
+        rows = [i for i in range(i0, i1) if k.wid[i] == 0]
+        assert nr == len(rows) > 0
+        e = rel(g[:, rows, :], ref[:, rows, :])
+        say(f"    {len(rows)} interior rows: f {e:.2e}")
+        assert e <= RTOL
+        checked += len(rows)
+    assert checked >= 4 * n
 
 
 @pytest.mark.parametrize("dim,n,nv", [(2, 12, 16), (3, 7, 8)])
