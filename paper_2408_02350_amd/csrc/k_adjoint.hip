@@ -295,7 +295,12 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
       M1 = M1 * et[k * a.nv + kd[k]];
     }
   };
-  // adjoint of f' = lam_f1 + sum over the wall rows that interpolate from i
+  // adjoint of f' = lam_f1 + sum over the wall rows that interpolate from i.
+  // Near a wall (some rows do) the first pass keeps its gathered value in
+  // the particle's own lam_ft row, which the second pass reads back and then
+  // overwrites (same thread, same velocity; nothing else reads the row).
+  const bool keep = we > ws;
+  Real* __restrict__ lrow = a.lam_ft + static_cast<size_t>(i) * NVs;
   auto lam_fp = [&](int c, int q) {
     double l = a.lam_f1[c * cs + static_cast<size_t>(i) * NVs + q];
     for (int p = ws; p < we; ++p) {
@@ -308,16 +313,24 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
   double s[D + 3];  // A1 = sum l M, A2 = sum l (ft - M), AU[d], AT
 #pragma unroll
   for (int k = 0; k < D + 3; ++k) s[k] = 0.0;
-  auto sums = [&](int q, const int (&kd)[D], double (&lq)[NC]) {
+  // the two inputs of one velocity
+  auto load_in = [&](int q, double (&lq)[NC], double (&xq)[NC]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      lq[c] = lam_fp(c, q);
+      xq[c] = a.ft[c * cs + static_cast<size_t>(i) * NVs + q];
+    }
+  };
+  auto accum = [&](int q, const int (&kd)[D], const double (&lq)[NC], const double (&xq)[NC]) {
     double w[3], w2, M1;
     vel(kd, w, w2, M1);
     const double dlog = fma(w2, h2, kT);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const double M = c == 0 ? M1 : T * M1;
-      const double l = lam_fp(c, q);
-      lq[c] = l;
-      const double x = a.ft[c * cs + static_cast<size_t>(i) * NVs + q];
+      const double l = lq[c];
+      if (keep) lrow[c * cs + q] = static_cast<Real>(l);
+      const double x = xq[c];
       const double lM = l * M;
       s[0] = s[0] + lM;
       s[1] = s[1] + l * (x - M);
@@ -335,12 +348,17 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
     int q = threadIdx.x;
 #pragma unroll
     for (int k = 0; k < kAdjKeep; ++k, q += kThreads) {
-      if (q < a.NV) sums(q, vd.k, lk[k]);
+      if (q < a.NV) {
+        double xk[NC];
+        load_in(q, lk[k], xk);
+        accum(q, vd.k, lk[k], xk);
+      }
       vd.advance(a.nv);
     }
     for (; q < a.NV; q += kThreads) {
-      double lq[NC];
-      sums(q, vd.k, lq);
+      double lq[NC], xq[NC];
+      load_in(q, lq, xq);
+      accum(q, vd.k, lq, xq);
       vd.advance(a.nv);
     }
   }
@@ -378,10 +396,14 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
       if (q < a.NV) write(q, vd.k, lk[k]);
       vd.advance(a.nv);
     }
+    auto load_l = [&](int qq, double (&lq)[NC]) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        lq[c] = keep ? static_cast<double>(lrow[c * cs + qq]) : lam_fp(c, qq);
+    };
     for (; q < a.NV; q += kThreads) {
       double lq[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) lq[c] = lam_fp(c, q);
+      load_l(q, lq);
       write(q, vd.k, lq);
       vd.advance(a.nv);
     }
