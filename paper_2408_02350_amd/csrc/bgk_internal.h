@@ -123,14 +123,13 @@ inline double omega_of(const bgk_config& cfg) {
 
 // Launch plan of the reverse transport: R velocities per lane along the
 // fastest axis (4 in 3D when 4 divides nv, else 2), interior patches of
-// P = 2 particles, and for the patch kernel nvb velocity blocks of nw
-// wavefronts; tiles = nvb nw 64-lane tiles, the parts of lam_U per
-// particle (t64 of them hold velocities; the per-particle wall kernel runs
-// over those).  nw = 1: blocks of several wavefronts that share one
-// derivation of the edge records were slower in both precisions (the
+// P = 2 particles, and tiles = the 64-lane tiles of R velocities the grid
+// needs (one wavefront per (patch or wall particle, tile); each tile holds
+// its part of lam_U per particle).  Blocks of several wavefronts sharing
+// one derivation of the edge records were slower in both precisions (the
 // waves of a block then wait on the derivation together).
 struct AdjPlan {
-  int R, P, nw, nvb, t64, tiles;
+  int R, P, tiles;
 };
 inline AdjPlan adj_plan(const bgk_config& cfg) {
   int64_t nvel = 1;
@@ -138,10 +137,7 @@ inline AdjPlan adj_plan(const bgk_config& cfg) {
   AdjPlan p{};
   p.R = (cfg.dim == 3 && cfg.nv % 4 == 0) ? 4 : 2;
   p.P = 2;
-  p.t64 = static_cast<int>((nvel / p.R + 63) / 64);
-  p.nw = 1;
-  p.nvb = p.t64;
-  p.tiles = p.nvb * p.nw;
+  p.tiles = static_cast<int>((nvel / p.R + 63) / 64);
   return p;
 }
 

@@ -655,9 +655,8 @@ __global__ __launch_bounds__(64) void k_adj_transport(const AdjArgs<Real> a) {
 }
 
 // The same reverse transport for the interior particles, taken P at a time
-// in cell order (the unions are merged once per frozen cloud): one block
-// per (patch, velocity block of nw <= W wavefronts x 64 lanes x R
-// velocities; the launch plan takes nw = 1).  The block walks the sorted
+// in cell order (the unions are merged once per frozen cloud): one
+// wavefront per (patch, tile of 64 lanes x R velocities) walks the sorted
 // union of the patch's neighbour lists once.  The own and transposed edge
 // records of a chunk of union entries are derived into LDS (with the
 // per-velocity increments and their sum, so the walk adds instead of
@@ -687,20 +686,17 @@ __device__ __forceinline__ void load_rs(const Real* __restrict__ p, Real (&o)[R]
   }
 }
 
-template <int D, int NC, typename Real, int R, int P, int W>
-__global__ __launch_bounds__(64 * W) void k_adj_transport_patch(const AdjArgs<Real> a) {
+template <int D, int NC, typename Real, int R, int P>
+__global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> a) {
   using A = Real;  // arithmetic of the per-velocity work
   // record: a_k (d*d), a_k.U (d), a_k[fast] dv (d), sum_k a_k[fast] dv
   constexpr int DD = D * D, REC = DD + 2 * D + 1, CH = kAdjUChunk;
   __shared__ A rown[CH][P][REC], rtr[CH][P][REC];
   __shared__ int32_t ri[CH], rfl[CH][P];
-  // velocity-block-major logical order, each XCD on one contiguous range;
-  // nw <= W waves per block, nvb velocity blocks, a.tiles = nvb nw
-  const int nw = static_cast<int>(blockDim.x) >> 6, nvb = a.tiles / nw;
-  const int lb = xcd_logical_block(blockIdx.x, gridDim.x), np = gridDim.x / nvb;
-  const int vb = lb / np, pb = lb - vb * np;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int tile = vb * nw + wid;  // this wave's 64-lane tile
+  // tile-major logical order, each XCD on one contiguous range of patches
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x), np = gridDim.x / a.tiles;
+  const int tile = lb / np, pb = lb - tile * np;
+  const int tid = threadIdx.x, lane = tid;
   const size_t NVs = a.NV, cs = static_cast<size_t>(a.N) * NVs;
   const double dv = 2.0 * a.vmax / static_cast<double>(a.nv - 1);
   int jt[P];
@@ -778,7 +774,7 @@ __global__ __launch_bounds__(64 * W) void k_adj_transport_patch(const AdjArgs<Re
   for (int c0 = 0; c0 < nu; c0 += CH) {
     const int cn = min(CH, nu - c0);
     __syncthreads();  // the previous chunk is consumed
-    for (int x = tid; x < cn * P; x += static_cast<int>(blockDim.x)) {
+    for (int x = tid; x < cn * P; x += 64) {
       const int w = x / P, t = x - w * P;
       const size_t u = ub + c0 + w;
       const int i = a.uj[u];
@@ -1085,16 +1081,17 @@ hipError_t launch_adjoint_transposes(const Ctx& c) {
                        j.ue);
 }
 
-// The patch kernel's instantiation for the plan.
+// The patch kernel's instantiation for the plan: one wavefront per (patch,
+// 64-lane tile).
 template <int D, int NC, typename Real, int R>
 static hipError_t launch_adj_patch(const Ctx& c, const AdjArgs<Real>& a, const AdjPlan& ap,
                                    int npa) {
-  constexpr int P = 2, W = 1;
-  if (ap.P != P || ap.nw > W) return hipErrorInvalidValue;
-  const int64_t nb = static_cast<int64_t>(npa) * ap.nvb;
+  constexpr int P = 2;
+  if (ap.P != P) return hipErrorInvalidValue;
+  const int64_t nb = static_cast<int64_t>(npa) * ap.tiles;
   if (nb > INT32_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_adj_transport_patch<D, NC, Real, R, P, W>), dim3(static_cast<unsigned>(nb)),
-                     dim3(64 * ap.nw), 0, c.stream, a);
+  hipLaunchKernelGGL((k_adj_transport_patch<D, NC, Real, R, P>), dim3(static_cast<unsigned>(nb)),
+                     dim3(64), 0, c.stream, a);
   return hipGetLastError();
 }
 
@@ -1120,18 +1117,17 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
   a.ucap = ap.P * c.cap;
   dim3 t(kThreads);
   const size_t lds = static_cast<size_t>(c.D + 1) * c.cfg.nv * sizeof(double);
-  // reverse transport: one block per (patch of interior particles, velocity
-  // block) and one wavefront per (wall particle, 64-lane tile), then the
-  // tile parts of lam_U summed in tile order
+  // reverse transport: one wavefront per (patch of interior particles or
+  // wall particle, 64-lane tile), then the tile parts of lam_U summed in
+  // tile order
   const int R = ap.R;
   a.tiles = ap.tiles;
   const int npa = (c.Ni + ap.P - 1) / ap.P;
-  const int64_t nbw = static_cast<int64_t>(c.Nw) * ap.t64;
+  const int64_t nbw = static_cast<int64_t>(c.Nw) * ap.tiles;
   if (nbw > INT32_MAX) return hipErrorInvalidValue;
   const dim3 tw(static_cast<unsigned>(nbw)), tt(64);
   AdjArgs<Real> aw = a;
   aw.jlist = c.d.wall_list;
-  aw.tiles = ap.t64;  // (the wall rows of gpart past t64 are never read)
   hipError_t e = hipSuccess;
   if (c.D == 2) {
     if (c.Nw) hipLaunchKernelGGL((k_adj_wall<2, 2, Real>), dim3(c.Nw), t, 0, c.stream, a);
