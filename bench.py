@@ -454,7 +454,7 @@ def main():
         roof = {"bound": "hbm", "achieved": ach_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": ach_gbs / PEAK_HBM_GBS}
     roof.update({"traffic": measured_traffic(cav.name, args.precision), "kernel": "k_fused",
-                 "kernel_ms": k_ms,
+                 "kernel_ms": k_ms, "kernel_updates_per_s": updates / (k_ms * 1e-3),
                  "algorithmic_bytes": bytes_, "algorithmic_ops": ops, "ops_per_update": k,
                  "hbm_frac": ach_gbs / PEAK_HBM_GBS, "alu_frac": ach_tops / PEAK_VALU_TOPS,
                  "step_share": k_ms / ms})
