@@ -191,8 +191,14 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   // by its own increment (|x| is a free source modifier: 3 adds per velocity
   // instead of 3 mins and 2 adds); 2D keeps 2 sum_k min(0, a_k.w) (equal cost)
   constexpr bool GW = (D == 3 && !BF);
-  // record: a_k (d*d), a_k.U (d), a_k[fast]*dvs (d)[, their sum]
-  constexpr int REC = DD + 2 * D + (GW ? 1 : 0);
+  // record: a_k (d*d), a_k.U (d), a_k[fast]*dvs (d)[, their sum].  FP64 in
+  // 3D keeps only a_k and a_k.U (12 doubles, 6 instead of 8 wave-uniform
+  // 16-byte LDS reads per edge) and forms the increments in the walk: every
+  // wave reads each record of its edges once per 4 velocities, and those
+  // broadcast reads occupy the LDS return path more than the 5 extra VALU
+  // operations cost.
+  constexpr bool LEAN = (D == 3 && MODE == BGK_FP64);
+  constexpr int REC = LEAN ? DD + D : DD + 2 * D + (GW ? 1 : 0);
   constexpr int KM = TP * (D + 1);              // first-pass moment sums per thread
   constexpr int KP = pow2_at_least(KM);
   constexpr int KP2 = pow2_at_least(TP);         // second pass: one sum per particle
@@ -340,9 +346,9 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
           for (int m = 0; m < D; ++m)
             b = fma_t(av[k * D + m], static_cast<Real>(a.U[static_cast<size_t>(m) * a.N + i]), b);
           rec[DD + k] = b;
-          rec[DD + D + k] = av[k * D] * dvs;
+          if constexpr (!LEAN) rec[DD + D + k] = av[k * D] * dvs;
         }
-        if constexpr (GW) {
+        if constexpr (GW && !LEAN) {
           Real gi = rec[DD + D];
 #pragma unroll
           for (int k = 1; k < D; ++k) gi = gi + rec[DD + D + k];
@@ -417,13 +423,19 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
             }
           }
 #pragma unroll
-          for (int k = 0; k < D; ++k) ik[k] = rec[DD + D + k];
+          for (int k = 0; k < D; ++k) ik[k] = LEAN ? rec[k * D] * dvs : rec[DD + D + k];
           Real gw = Real(0), ig = Real(0);
           if constexpr (GW) {
             gw = p[0];
 #pragma unroll
             for (int k = 1; k < D; ++k) gw = gw + p[k];
-            ig = rec[DD + 2 * D];
+            if constexpr (LEAN) {
+              ig = ik[0];
+#pragma unroll
+              for (int k = 1; k < D; ++k) ig = ig + ik[k];
+            } else {
+              ig = rec[DD + 2 * D];
+            }
           }
 #pragma unroll
           for (int r = 0; r < R; ++r) {
