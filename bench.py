@@ -103,7 +103,10 @@ def cav_interior(cav):
 
 def run_gpu(cav, precision, steps, warmup, timing=True, total_steps=None):
     """Time `steps` full steps after `warmup`; then (untimed) continue to
-    total_steps.  Returns the timing and (rho, U, T) at the last step."""
+    total_steps.  Returns the timing and (rho, U, T) at the last step; diag
+    also holds the state check of the last state (smallest f, negative and
+    non-finite counts, moment residuals) and the drift of total mass and
+    energy since the initial state."""
     import torch
 
     import paper_2408_02350_amd.bgk as bgk
@@ -111,6 +114,7 @@ def run_gpu(cav, precision, steps, warmup, timing=True, total_steps=None):
     sim = bgk.Simulation(cav, precision=precision, device="cuda:0")
     log(f"[bench] {cav.name} {precision}: N={cav.n_particles} NV={cav.n_velocities} "
         f"warmup={warmup} steps={steps}")
+    s0 = bgk.bgk_state_check(sim.ctx, sim.f, sim.rho, sim.U, sim.T)
     sim.step(warmup)
     bgk.bgk_check(sim.ctx)
     torch.cuda.synchronize()
@@ -137,6 +141,12 @@ def run_gpu(cav, precision, steps, warmup, timing=True, total_steps=None):
         bgk.bgk_check(sim.ctx)
         done = total_steps
     torch.cuda.synchronize()
+    s1 = bgk.bgk_state_check(sim.ctx, sim.f, sim.rho, sim.U, sim.T)
+    diag["state"] = {k: s1[k] for k in ("min_f", "negatives", "nonfinite", "rho_residual",
+                                        "U_residual", "T_residual")}
+    diag["state"].update({"mass_drift": (s1["mass"] - s0["mass"]) / s0["mass"],
+                          "energy_drift": (s1["energy"] - s0["energy"]) / s0["energy"],
+                          "after_steps": done})
     state = (sim.rho.cpu().numpy(), sim.U.cpu().numpy(), sim.T.cpu().numpy())
     del sim
     torch.cuda.empty_cache()
@@ -478,6 +488,7 @@ def main():
                    "precision": args.precision, "move": cav.move,
                    "parallelism": "single-gpu"},
         "roofline": roof,
+        "state": diag["state"],
     }
 
     if mixed_on:

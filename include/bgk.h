@@ -248,6 +248,25 @@ int bgk_pm_apply(bgk_ctx* ctx, const double* x, const void* f, const double* rho
  * second moment (Chu: plus sum g2) over 3 rho. */
 int bgk_moments(bgk_ctx* ctx, const void* f, double* rho, double* U, double* T);
 
+/* Health of a state (f, rho, U, T), e.g. f^{n+1} with the moments the step
+ * reported; the per-step diagnostics of the method's invariants.  Every
+ * particle's row of f has its moments recomputed as bgk_moments does (Sec. 2
+ * eqs. moments, internal_energy): after a step they differ from the step's
+ * rho, U, T only by the relaxation's conservation defect (Sec. 3.2.1: the
+ * implicit relaxation conserves the moments up to the velocity grid's
+ * quadrature error of the discrete Maxwellian).  f must stay non-negative
+ * (the positivity of the upwind scheme, Sec. 3.4.2).  out: host double[12]:
+ *   [0] smallest finite value of f (any component, particle, velocity),
+ *   [1] number of negative values, [2] number of non-finite values,
+ *   [3] max_i |rho(f_i) - rho_i| / rho_i, [4] max_{i,k} |U_k(f_i) - U_ki|,
+ *   [5] max_i |T(f_i) - T_i| / T_i (NaN if any residual is NaN),
+ *   [6] sum_i rho_i, [7 .. 7+d) sum_i rho_i U_i,
+ *   [7+d] sum_i rho_i (|U_i|^2 + 3 T_i) / 2, the rest 0.
+ * Device inputs as for bgk_moments; synchronises the context stream.  Sums
+ * and extrema are taken in a fixed order (bitwise repeatable). */
+int bgk_state_check(bgk_ctx* ctx, const void* f, const double* rho, const double* U,
+                    const double* T, double* out);
+
 /* Maxwellian (Sec. 2 eq. maxwellian with the exponent's minus sign; Chu:
  * G1, G2 of eqs. Maxw_G1/G2 with the v3-marginal normalisation rho/(2 pi T))
  * of every particle on the grid, into f_out. */

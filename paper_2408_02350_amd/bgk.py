@@ -33,7 +33,7 @@ STATUS = {0: "BGK_OK", 1: "BGK_EINVAL", 2: "BGK_ENOMEM", 3: "BGK_ENBR_OVERFLOW",
 EXPORTS = ("bgk_workspace_bytes", "bgk_init", "bgk_destroy", "bgk_set_lid_velocity",
            "bgk_build_neighbors", "bgk_wls_operators", "bgk_wall_stencil", "bgk_geometry",
            "bgk_transport", "bgk_collide", "bgk_wall_bc", "bgk_move", "bgk_step",
-           "bgk_moments", "bgk_maxwellian", "bgk_check", "bgk_diagnostics", "bgk_last_error",
+           "bgk_moments", "bgk_state_check", "bgk_maxwellian", "bgk_check", "bgk_diagnostics", "bgk_last_error",
            "bgk_timing_enable", "bgk_timing_read", "bgk_objective", "bgk_objective_static",
            "bgk_adjoint_step", "bgk_adjoint_step_move",
            "bgk_moments_adjoint", "bgk_pm_plan", "bgk_pm_apply")
@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH):
         "bgk_move": [vp, dp, dp],
         "bgk_step": [vp, vp, vp, dp, dp, dp, dp],
         "bgk_moments": [vp, vp, dp, dp, dp],
+        "bgk_state_check": [vp, vp, dp, dp, dp, dp],
         "bgk_maxwellian": [vp, dp, dp, dp, vp],
         "bgk_check": [vp],
         "bgk_diagnostics": [vp, ctypes.POINTER(ctypes.c_int64)],
@@ -323,6 +324,31 @@ def bgk_moments(ctx: Context, f, rho=None, U=None, T=None):
     _check(ctx, load_library().bgk_moments(ctx.handle, _ptr(f), _ptr(rho), _ptr(U), _ptr(T)),
            "bgk_moments")
     return rho, U, T
+
+
+STATE_CHECK_KEYS = ("min_f", "negatives", "nonfinite", "rho_residual", "U_residual",
+                    "T_residual", "mass")
+
+
+def bgk_state_check(ctx: Context, f, rho, U, T):
+    """Health of a state (bgk_state_check): a dict with the smallest value
+    of f, the counts of negative and non-finite values, the largest
+    residuals of f's own moments against (rho, U, T), and the totals mass,
+    momentum (a list of d values) and energy."""
+    _f(ctx, f, "f")
+    _sca(ctx, rho, "rho")
+    _vec(ctx, U, "U")
+    _sca(ctx, T, "T")
+    out = (ctypes.c_double * 12)()
+    _check(ctx, load_library().bgk_state_check(ctx.handle, _ptr(f), _ptr(rho), _ptr(U), _ptr(T),
+                                               out), "bgk_state_check")
+    v = list(out)
+    d = {k: v[n] for n, k in enumerate(STATE_CHECK_KEYS)}
+    d["negatives"] = int(d["negatives"])
+    d["nonfinite"] = int(d["nonfinite"])
+    d["momentum"] = v[7:7 + ctx.d]
+    d["energy"] = v[7 + ctx.d]
+    return d
 
 
 def bgk_maxwellian(ctx: Context, rho, U, T, f_out=None):

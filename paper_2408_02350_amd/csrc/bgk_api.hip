@@ -140,6 +140,7 @@ size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj, Pm*
   t.uj = reinterpret_cast<int32_t*>(take((N + 3) * cap * 4));
   t.ue = reinterpret_cast<uint32_t*>(take((N + 3) * cap * 4));
   t.jpart = reinterpret_cast<double*>(take(N * 8));
+  t.scheck = reinterpret_cast<double*>(take((N + 1) * kCheckTerms * 8));
   const int64_t npw = wall_patches_max(N, cfg.dim);
   t.wpl = reinterpret_cast<int32_t*>(take(npw * kWallPatch * 4));
   t.wucount = reinterpret_cast<int32_t*>(take(npw * 4));
@@ -543,6 +544,18 @@ int bgk_pm_apply(bgk_ctx* ctx, const double* x, const void* f, const double* rho
 int bgk_moments(bgk_ctx* ctx, const void* f, double* rho, double* U, double* T) {
   if (!ctx || !f || !rho || !U || !T) return BGK_EINVAL;
   return bgk::hip_fail(&ctx->c, bgk::launch_moments(ctx->c, f, rho, U, T), "bgk_moments");
+}
+
+int bgk_state_check(bgk_ctx* ctx, const void* f, const double* rho, const double* U,
+                    const double* T, double* out) {
+  if (!ctx || !f || !rho || !U || !T || !out) return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  double* dev = c.d.scheck + static_cast<size_t>(c.N) * bgk::kCheckTerms;  // the sums
+  hipError_t e = bgk::launch_state_check(c, f, rho, U, T, dev);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, dev, bgk::kCheckTerms * sizeof(double), hipMemcpyDeviceToHost, c.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+  return bgk::hip_fail(&c, e, "bgk_state_check");
 }
 
 int bgk_maxwellian(bgk_ctx* ctx, const double* rho, const double* U, const double* T,

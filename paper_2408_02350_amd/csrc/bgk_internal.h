@@ -68,6 +68,7 @@ struct Dev {
   int32_t* wuj;          // [npw][kWallPatch*cap] union of the patch's wall rows
   uint32_t* wue;         // [npw][kWallPatch*cap] packed 8-bit slot in each wall row
   double* jpart;         // [N]   per-particle terms of the objective
+  double* scheck;        // [N][kCheckTerms] per-particle terms of bgk_state_check, then its sums
 };
 
 // Workspace of the reverse step (BGK_FLAG_ADJOINT; FP64, frozen cloud).
@@ -218,6 +219,9 @@ hipError_t launch_collide(const Ctx& c, const void* ft, void* fout, double* rho,
 hipError_t launch_wall_bc(const Ctx& c, void* f, double* rho, double* U, double* T);
 hipError_t launch_move(const Ctx& c, double* x, const double* U);
 hipError_t launch_moments(const Ctx& c, const void* f, double* rho, double* U, double* T);
+constexpr int kCheckTerms = 12;  // per-particle slots of the state check (and its outputs)
+hipError_t launch_state_check(const Ctx& c, const void* f, const double* rho, const double* U,
+                              const double* T, double* out_dev);
 hipError_t launch_maxwellian(const Ctx& c, const double* rho, const double* U, const double* T,
                              void* f);
 

@@ -645,6 +645,150 @@ hipError_t launch_moments(const Ctx& c, const void* f, double* rho, double* U, d
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- state check
+// The health of a state (f, rho, U, T), typically f^{n+1} with the moments
+// a step reported: per particle, its row's moments recomputed as bgk_moments
+// does, against the given rho, U, T (after a step the difference is the
+// relaxation's conservation defect: the discrete Maxwellian's moments differ
+// from their parameters by the quadrature error), the smallest value and the
+// counts of negative and of non-finite values over the row, and the
+// particle's mass rho, momentum rho U and energy rho (|U|^2 + 3T)/2 (three
+// degrees of freedom in both models: the Chu g2 carries the third).  Slots:
+//   0 min f, 1 negatives, 2 non-finite, 3 |rho(f) - rho| / rho,
+//   4 max_k |U_k(f) - U_k|, 5 |T(f) - T| / T, 6 rho, 7.. rho U (d), 7+d energy.
+template <int D, int NC, typename Real>
+__global__ __launch_bounds__(kThreads) void k_state_terms(int N, int NV, int nv, double vmax,
+                                                           double omega, const void* fv,
+                                                           const double* __restrict__ rho,
+                                                           const double* __restrict__ U,
+                                                           const double* __restrict__ T,
+                                                           double* __restrict__ part) {
+  __shared__ double sh[4 * (D + 1)];
+  __shared__ double smin[4];
+  extern __shared__ double vt[];
+  const int i = blockIdx.x;
+  const size_t NVs = NV, cs = static_cast<size_t>(N) * NVs;
+  const Real* row = static_cast<const Real*>(fv) + static_cast<size_t>(i) * NVs;
+  fill_vtab(vt, nv, vmax);
+  __syncthreads();
+  double r, u[3] = {0.0, 0.0, 0.0}, t;
+  row_moments<D, NC, Real>(row, cs, NV, nv, vt, omega, sh, r, u, t);
+  double mn = INFINITY, cnt[2] = {0.0, 0.0};
+  for (int q = threadIdx.x; q < NV; q += kThreads) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double x = static_cast<double>(row[c * cs + q]);
+      if (isfinite(x)) {
+        mn = fmin(mn, x);
+        if (x < 0.0) cnt[0] = cnt[0] + 1.0;
+      } else {
+        cnt[1] = cnt[1] + 1.0;
+      }
+    }
+  }
+  block_sum<2>(cnt, sh);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o, 64));
+  if ((threadIdx.x & 63) == 0) smin[threadIdx.x >> 6] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* p = part + static_cast<size_t>(i) * kCheckTerms;
+    const double ri = rho[i], Ti = T[i];
+    double du = 0.0, u2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double Uk = U[static_cast<size_t>(k) * N + i];
+      const double dk = fabs(u[k] - Uk);
+      du = (dk > du || dk != dk) ? dk : du;
+      u2 = u2 + Uk * Uk;
+      p[7 + k] = ri * Uk;
+    }
+    p[0] = fmin(fmin(smin[0], smin[1]), fmin(smin[2], smin[3]));
+    p[1] = cnt[0];
+    p[2] = cnt[1];
+    p[3] = fabs(r - ri) / ri;
+    p[4] = du;
+    p[5] = fabs(t - Ti) / Ti;
+    p[6] = ri;
+    p[7 + D] = 0.5 * ri * (u2 + 3.0 * Ti);
+  }
+}
+
+// One block: slot 0 the minimum, slots 1, 2, 6.. the sums, slots 3-5 the
+// maxima over the particles (NaN residuals propagate), each in a fixed order.
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_state_reduce(int N, const double* __restrict__ part,
+                                                            double* __restrict__ out) {
+  constexpr int NS = 3 + D + 2;  // summed slots: 1, 2, 6 .. 7 + D
+  __shared__ double sh[4 * NS];
+  __shared__ double sx[4][4];
+  double s[NS], mx[4] = {INFINITY, 0.0, 0.0, 0.0};  // min f, three maxima
+#pragma unroll
+  for (int k = 0; k < NS; ++k) s[k] = 0.0;
+  for (int i = threadIdx.x; i < N; i += kThreads) {
+    const double* p = part + static_cast<size_t>(i) * kCheckTerms;
+    mx[0] = fmin(mx[0], p[0]);
+    s[0] = s[0] + p[1];
+    s[1] = s[1] + p[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) mx[1 + k] = (p[3 + k] > mx[1 + k] || p[3 + k] != p[3 + k]) ? p[3 + k] : mx[1 + k];
+#pragma unroll
+    for (int k = 0; k < D + 2; ++k) s[2 + k] = s[2 + k] + p[6 + k];
+  }
+  block_sum<NS>(s, sh);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mx[0] = fmin(mx[0], __shfl_xor(mx[0], o, 64));
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+      const double y = __shfl_xor(mx[k], o, 64);
+      mx[k] = (y > mx[k] || y != y) ? y : mx[k];
+    }
+  }
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sx[threadIdx.x >> 6][k] = mx[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m[k] = sx[0][k];
+    for (int w = 1; w < 4; ++w) {
+      m[0] = fmin(m[0], sx[w][0]);
+#pragma unroll
+      for (int k = 1; k < 4; ++k) m[k] = (sx[w][k] > m[k] || sx[w][k] != sx[w][k]) ? sx[w][k] : m[k];
+    }
+    out[0] = m[0];
+    out[1] = s[0];
+    out[2] = s[1];
+    out[3] = m[1];
+    out[4] = m[2];
+    out[5] = m[3];
+#pragma unroll
+    for (int k = 0; k < D + 2; ++k) out[6 + k] = s[2 + k];
+    for (int k = 8 + D; k < kCheckTerms; ++k) out[k] = 0.0;
+  }
+}
+
+hipError_t launch_state_check(const Ctx& c, const void* f, const double* rho, const double* U,
+                              const double* T, double* out_dev) {
+  const bool f64 = c.cfg.precision == BGK_FP64;
+  const double om = omega_of(c.cfg);
+  dim3 g(c.N), t(kThreads);
+  const size_t lds = static_cast<size_t>(c.D + 1) * c.cfg.nv * sizeof(double);
+  double* part = c.d.scheck;
+  if (c.D == 2) {
+    if (f64) hipLaunchKernelGGL((k_state_terms<2, 2, double>), g, t, lds, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, om, f, rho, U, T, part);
+    else hipLaunchKernelGGL((k_state_terms<2, 2, float>), g, t, lds, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, om, f, rho, U, T, part);
+    hipLaunchKernelGGL(k_state_reduce<2>, dim3(1), t, 0, c.stream, c.N, part, out_dev);
+  } else {
+    if (f64) hipLaunchKernelGGL((k_state_terms<3, 1, double>), g, t, lds, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, om, f, rho, U, T, part);
+    else hipLaunchKernelGGL((k_state_terms<3, 1, float>), g, t, lds, c.stream, c.N, c.NV, c.cfg.nv, c.cfg.vmax, om, f, rho, U, T, part);
+    hipLaunchKernelGGL(k_state_reduce<3>, dim3(1), t, 0, c.stream, c.N, part, out_dev);
+  }
+  return hipGetLastError();
+}
+
 template <int D, int NC, typename Real>
 __global__ __launch_bounds__(kThreads) void k_maxwellian(int N, int NV, int nv, double vmax,
                                                           const double* __restrict__ rho,
