@@ -538,7 +538,12 @@ def bgk_last_error(ctx: Context) -> str:
 
 # ------------------------------------------------------------ convenience
 class Simulation:
-    """A cavity run on one GPU: state tensors plus the stepping calls."""
+    """A cavity run on one GPU: state tensors plus the stepping calls.
+
+    Checkpoint and resume: save(path) writes the configuration and the
+    state (x, wall_id, f, rho, U, T and the step count) as tensors; restore
+    rebuilds the context from them, and the resumed run continues bit for
+    bit as the uninterrupted one (the step depends on nothing else)."""
 
     def __init__(self, cav, precision=None, device="cuda", seed=None, stream=None, **overrides):
         from .inputs import cloud_for
@@ -556,11 +561,40 @@ class Simulation:
         self.f = bgk_maxwellian(self.ctx, self.rho, self.U, self.T)
         self.f_next = torch.empty_like(self.f)
         bgk_moments(self.ctx, self.f, self.rho, self.U, self.T)
+        self.steps = 0
 
     def step(self, n=1):
         for _ in range(n):
             bgk_step(self.ctx, self.f, self.f_next, self.x, self.U, self.rho, self.T)
             self.f, self.f_next = self.f_next, self.f
+            self.steps += 1
+
+    def save(self, path):
+        """Write a checkpoint (torch.save of plain tensors and numbers)."""
+        bgk_check(self.ctx)
+        cfg = {name: getattr(self.cfg, name) for name, _ in BgkConfig._fields_}
+        torch.save({"config": cfg, "steps": self.steps,
+                    "x": self.x.cpu(), "wall_id": self.wall_id.cpu(), "f": self.f.cpu(),
+                    "rho": self.rho.cpu(), "U": self.U.cpu(), "T": self.T.cpu()}, path)
+
+    @classmethod
+    def restore(cls, path, device="cuda", stream=None):
+        """A simulation resumed from a checkpoint written by save (loaded
+        with weights_only=True: tensors and numbers only)."""
+        ck = torch.load(path, map_location="cpu", weights_only=True)
+        sim = cls.__new__(cls)
+        sim.cav = None
+        sim.cfg = BgkConfig(**ck["config"])
+        dev = torch.device(device)
+        sim.wall_id = ck["wall_id"].to(dev)
+        sim.x = ck["x"].to(dev)
+        sim.ctx = bgk_init(sim.cfg, sim.wall_id, stream)
+        sim.f = ck["f"].to(dev)
+        sim.rho, sim.U, sim.T = ck["rho"].to(dev), ck["U"].to(dev), ck["T"].to(dev)
+        _f(sim.ctx, sim.f, "f")
+        sim.f_next = torch.empty_like(sim.f)
+        sim.steps = int(ck["steps"])
+        return sim
 
     def manage_particles(self, merge_radius=None, hole_radius=None):
         """Merge close pairs and fill holes (the context must carry
