@@ -191,13 +191,13 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   // by its own increment (|x| is a free source modifier: 3 adds per velocity
   // instead of 3 mins and 2 adds); 2D keeps 2 sum_k min(0, a_k.w) (equal cost)
   constexpr bool GW = (D == 3 && !BF);
-  // record: a_k (d*d), a_k.U (d), a_k[fast]*dvs (d)[, their sum].  FP64 in
-  // 3D keeps only a_k and a_k.U (12 doubles, 6 instead of 8 wave-uniform
-  // 16-byte LDS reads per edge) and forms the increments in the walk: every
-  // wave reads each record of its edges once per 4 velocities, and those
-  // broadcast reads occupy the LDS return path more than the 5 extra VALU
-  // operations cost.
-  constexpr bool LEAN = (D == 3 && MODE == BGK_FP64);
+  // record: a_k (d*d), a_k.U (d), a_k[fast]*dvs (d)[, their sum].  FP64
+  // keeps only a_k and a_k.U (3D: 12 doubles, 6 instead of 8 wave-uniform
+  // 16-byte LDS reads per edge; 2D: 6 instead of 8 doubles) and forms the
+  // increments in the walk: every wave reads each record of its edges once
+  // per 2-4 velocities, and those broadcast reads occupy the LDS return path
+  // more than the few extra VALU operations cost.
+  constexpr bool LEAN = (MODE == BGK_FP64);
   constexpr int REC = LEAN ? DD + D : DD + 2 * D + (GW ? 1 : 0);
   constexpr int KM = TP * (D + 1);              // first-pass moment sums per thread
   constexpr int KP = pow2_at_least(KM);
