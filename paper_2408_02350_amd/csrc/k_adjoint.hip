@@ -689,8 +689,11 @@ __device__ __forceinline__ void load_rs(const Real* __restrict__ p, Real (&o)[R]
 template <int D, int NC, typename Real, int R, int P>
 __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> a) {
   using A = Real;  // arithmetic of the per-velocity work
-  // record: a_k (d*d), a_k.U (d), a_k[fast] dv (d), sum_k a_k[fast] dv
-  constexpr int DD = D * D, REC = DD + 2 * D + 1, CH = kAdjUChunk;
+  // record: a_k (d*d), a_k.U (d)[, a_k[fast] dv (d), sum_k a_k[fast] dv].
+  // FP64 keeps a_k and a_k.U only and forms the increments per edge (fewer
+  // wave-uniform LDS reads at 2-4 velocities per lane)
+  constexpr bool LEAN = std::is_same<Real, double>::value;
+  constexpr int DD = D * D, REC = LEAN ? DD + D : DD + 2 * D + 1, CH = kAdjUChunk;
   __shared__ A rown[CH][P][REC], rtr[CH][P][REC];
   __shared__ int32_t ri[CH], rfl[CH][P];
   // tile-major logical order, each XCD on one contiguous range of patches
@@ -765,10 +768,27 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
       }
       const double inc = static_cast<double>(o[m * D]) * dv;
       rec[DD + m] = static_cast<A>(b);
-      rec[DD + D + m] = static_cast<A>(inc);
-      ig = ig + static_cast<double>(static_cast<A>(inc));
+      if constexpr (!LEAN) {
+        rec[DD + D + m] = static_cast<A>(inc);
+        ig = ig + static_cast<double>(static_cast<A>(inc));
+      }
     }
-    rec[DD + 2 * D] = static_cast<A>(ig);
+    if constexpr (!LEAN) rec[DD + 2 * D] = static_cast<A>(ig);
+  };
+  const A dva = static_cast<A>(dv);
+  // the per-velocity increments of a record and their sum
+  auto incs = [&](const A* rc, A (&ik)[D], A& dgw) {
+    if constexpr (LEAN) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) ik[k] = rc[k * D] * dva;
+      dgw = ik[0];
+#pragma unroll
+      for (int k = 1; k < D; ++k) dgw = dgw + ik[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < D; ++k) ik[k] = rc[DD + D + k];
+      dgw = rc[DD + 2 * D];
+    }
   };
 
   for (int c0 = 0; c0 < nu; c0 += CH) {
@@ -832,11 +852,9 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
           A p[D], S[D], ik[D], gw;
           proj(rc, p, gw);
 #pragma unroll
-          for (int k = 0; k < D; ++k) {
-            S[k] = A(0);
-            ik[k] = rc[DD + D + k];
-          }
-          const A dgw = rc[DD + 2 * D];
+          for (int k = 0; k < D; ++k) S[k] = A(0);
+          A dgw;
+          incs(rc, ik, dgw);
           A sd = A(0);
 #pragma unroll
           for (int r = 0; r < R; ++r) {
@@ -873,9 +891,8 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
           const A* rc = rtr[w][t];
           A p[D], ik[D], gw;
           proj(rc, p, gw);
-#pragma unroll
-          for (int k = 0; k < D; ++k) ik[k] = rc[DD + D + k];
-          const A dgw = rc[DD + 2 * D];
+          A dgw;
+          incs(rc, ik, dgw);
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             if (r > 0) {
