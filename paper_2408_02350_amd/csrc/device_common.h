@@ -56,6 +56,32 @@ __device__ __forceinline__ double maxwell(int comp, double rho, const double* U,
   return g;
 }
 
+// Base-nv digits of a velocity index (fastest axis first), advanced by a
+// fixed stride without integer division: a thread walking q = q0 + m stride
+// takes the stride's digits once and adds them with carries.
+template <int D>
+struct VelDigits {
+  int k[D], st[D];
+  __device__ void init(int q, int stride, int nv) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      k[a] = q % nv;
+      q /= nv;
+      st[a] = stride % nv;
+      stride /= nv;
+    }
+  }
+  __device__ void advance(int nv) {  // (the carry out of the last digit is
+    int carry = 0;                   //  past N_v: the loops end there)
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int x = k[a] + st[a] + carry;
+      carry = x >= nv;
+      k[a] = carry ? x - nv : x;
+    }
+  }
+};
+
 // Sum K doubles over a block of kThreads (= 4 waves of 64) in a fixed order;
 // every thread receives the totals.  sh must hold 4*K doubles.
 template <int K>

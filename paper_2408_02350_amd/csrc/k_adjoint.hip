@@ -222,32 +222,11 @@ __global__ __launch_bounds__(kThreads) void k_adj_wall(const AdjArgs<Real> a) {
 // the particle's Maxwellian are tabulated in LDS (dynamic, (D+1)*nv doubles):
 // M = norm * prod_a e_a[k_a], Chu G2 = T G1.  A thread's velocities are
 // q = tid + m kThreads; their per-axis indices are advanced by the digits of
-// the stride (no integer division per velocity), and the per-particle
-// quotients (1/T, the moment-adjoint coefficients) are formed once.
+// the stride (VelDigits, no integer division per velocity), and the
+// per-particle quotients (1/T, the moment-adjoint coefficients) are formed
+// once.
 constexpr int kAdjKeep = 4;
 
-template <int D>
-struct VelDigits {  // base-nv digits of a velocity index, fastest axis first
-  int k[D], st[D];
-  __device__ void init(int q, int stride, int nv) {
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      k[a] = q % nv;
-      q /= nv;
-      st[a] = stride % nv;
-      stride /= nv;
-    }
-  }
-  __device__ void advance(int nv) {  // (the carry out of the last digit is
-    int carry = 0;                   //  past N_v: the loops end there)
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const int x = k[a] + st[a] + carry;
-      carry = x >= nv;
-      k[a] = carry ? x - nv : x;
-    }
-  }
-};
 
 template <int D, int NC, typename Real>
 __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a) {

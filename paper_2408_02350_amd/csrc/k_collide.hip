@@ -30,14 +30,6 @@ __device__ __forceinline__ void fill_etab(double* et, const double* vt, int nv, 
   }
 }
 
-template <int D>
-__device__ __forceinline__ void vel_index(int q, int nv, int* kq) {
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    kq[a] = q % nv;
-    q /= nv;
-  }
-}
 
 // Normalisation of the Maxwellian (Sec. 2 eq. maxwellian; Chu G1 in 2D).
 template <int D>
@@ -62,9 +54,10 @@ __device__ __forceinline__ void row_moments(const Real* row, size_t cs, int NV, 
   double s[D + 1];
 #pragma unroll
   for (int k = 0; k <= D; ++k) s[k] = 0.0;
-  for (int q = threadIdx.x; q < NV; q += kThreads) {
-    int kq[D];
-    vel_index<D>(q, nv, kq);
+  VelDigits<D> vd;
+  vd.init(threadIdx.x, kThreads, nv);
+  for (int q = threadIdx.x; q < NV; q += kThreads, vd.advance(nv)) {
+    const int* kq = vd.k;
     const double f1 = static_cast<double>(row[q]);
     s[0] = s[0] + f1;
 #pragma unroll
@@ -76,9 +69,9 @@ __device__ __forceinline__ void row_moments(const Real* row, size_t cs, int NV, 
 #pragma unroll
   for (int k = 0; k < D; ++k) U[k] = s[1 + k] / s0;
   double e[1] = {0.0};
-  for (int q = threadIdx.x; q < NV; q += kThreads) {
-    int kq[D];
-    vel_index<D>(q, nv, kq);
+  vd.init(threadIdx.x, kThreads, nv);
+  for (int q = threadIdx.x; q < NV; q += kThreads, vd.advance(nv)) {
+    const int* kq = vd.k;
     double w2 = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -130,9 +123,10 @@ __global__ __launch_bounds__(kThreads) void k_collide(const CollideArgs a) {
   fill_etab<D>(et, vt, a.nv, U, T);
   __syncthreads();
   const double norm = maxwell_norm<D>(rho, T);
-  for (int q = threadIdx.x; q < a.NV; q += kThreads) {
-    int kq[D];
-    vel_index<D>(q, a.nv, kq);
+  VelDigits<D> vd;
+  vd.init(threadIdx.x, kThreads, a.nv);
+  for (int q = threadIdx.x; q < a.NV; q += kThreads, vd.advance(a.nv)) {
+    const int* kq = vd.k;
     double M = norm;
 #pragma unroll
     for (int k = 0; k < D; ++k) M = M * et[k * a.nv + kq[k]];
@@ -808,9 +802,10 @@ __global__ __launch_bounds__(kThreads) void k_maxwellian(int N, int NV, int nv, 
   fill_etab<D>(et, vt, nv, u, t);
   __syncthreads();
   const double norm = maxwell_norm<D>(r, t);
-  for (int q = threadIdx.x; q < NV; q += kThreads) {
-    int kq[D];
-    vel_index<D>(q, nv, kq);
+  VelDigits<D> vd;
+  vd.init(threadIdx.x, kThreads, nv);
+  for (int q = threadIdx.x; q < NV; q += kThreads, vd.advance(nv)) {
+    const int* kq = vd.k;
     double M = norm;
 #pragma unroll
     for (int k = 0; k < D; ++k) M = M * et[k * nv + kq[k]];
