@@ -323,8 +323,9 @@ int bgk_objective_static(bgk_ctx* ctx, const void* f, const double* rho, const d
  * derivative of their + branch at 0.  The transposed stencils make every
  * sum a gather: results are deterministic.  Needs a context created with
  * BGK_FLAG_ADJOINT and move = 0, else BGK_ENOTSUP.  f_n, lam_f1 and lam_f
- * are in the f storage type (FP64, or FP32 with FP64 arithmetic and
- * reductions inside). */
+ * are in the f storage type (FP64; or FP32, with FP32 arithmetic in the
+ * reverse transport's per-velocity work and FP64 in every reduction and in
+ * the other reverse kernels). */
 int bgk_adjoint_step(bgk_ctx* ctx, const void* f_n, const double* U_n, const double* x,
                      const void* lam_f1, const double* lam_U1, const double* lam_rho1,
                      const double* lam_T1, void* lam_f, double* lam_U, double* dJ_dlid);
