@@ -1,5 +1,6 @@
 // Host side of the libbgk C interface (include/bgk.h): argument checks,
 // workspace layout, and the order of kernel launches of one time step.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -168,7 +169,8 @@ size_t workspace_layout(const bgk_config& cfg, char* base, Dev* d, Adj* adj, Pm*
     a.lidpart = reinterpret_cast<double*>(take(N * 8));
     const AdjPlan ap = adj_plan(cfg);
     const size_t npa = (N + ap.P - 1) / ap.P;
-    a.gpart = reinterpret_cast<double*>(take(static_cast<size_t>(ap.tiles) * D * N * 8));
+    a.gpart = reinterpret_cast<double*>(
+        take(static_cast<size_t>(std::max(ap.tiles, ap.tiles_w)) * D * N * 8));
     a.ucount = reinterpret_cast<int32_t*>(take(npa * 4));
     a.uj = reinterpret_cast<int32_t*>(take(npa * ap.P * cap * 4));
     a.ue = reinterpret_cast<uint32_t*>(take(npa * ap.P * cap * 4));

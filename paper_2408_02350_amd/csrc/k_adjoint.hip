@@ -409,7 +409,9 @@ constexpr int kAdjChunk = 32;
 
 template <typename Real, int R>
 __device__ __forceinline__ void load_rr(const Real* __restrict__ p, double (&o)[R]) {
-  constexpr int W = (R * sizeof(Real)) % 16 == 0 ? 16 / static_cast<int>(sizeof(Real)) : R;
+  constexpr int B = R * static_cast<int>(sizeof(Real));
+  constexpr int W = B % 16 == 0 ? 16 / static_cast<int>(sizeof(Real))
+                                : (B % 8 == 0 ? 8 / static_cast<int>(sizeof(Real)) : 1);
   typedef Real V __attribute__((ext_vector_type(W)));
   const V* pv = reinterpret_cast<const V*>(__builtin_assume_aligned(p, W * sizeof(Real)));
 #pragma unroll
@@ -654,7 +656,9 @@ constexpr int kAdjUChunk = 32;
 
 template <typename Real, int R>
 __device__ __forceinline__ void load_rs(const Real* __restrict__ p, Real (&o)[R]) {
-  constexpr int W = (R * sizeof(Real)) % 16 == 0 ? 16 / static_cast<int>(sizeof(Real)) : R;
+  constexpr int B = R * static_cast<int>(sizeof(Real));
+  constexpr int W = B % 16 == 0 ? 16 / static_cast<int>(sizeof(Real))
+                                : (B % 8 == 0 ? 8 / static_cast<int>(sizeof(Real)) : 1);
   typedef Real V __attribute__((ext_vector_type(W)));
   const V* pv = reinterpret_cast<const V*>(__builtin_assume_aligned(p, W * sizeof(Real)));
 #pragma unroll
@@ -1119,11 +1123,12 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
   const int R = ap.R;
   a.tiles = ap.tiles;
   const int npa = (c.Ni + ap.P - 1) / ap.P;
-  const int64_t nbw = static_cast<int64_t>(c.Nw) * ap.tiles;
+  const int64_t nbw = static_cast<int64_t>(c.Nw) * ap.tiles_w;
   if (nbw > INT32_MAX) return hipErrorInvalidValue;
   const dim3 tw(static_cast<unsigned>(nbw)), tt(64);
   AdjArgs<Real> aw = a;
   aw.jlist = c.d.wall_list;
+  aw.tiles = ap.tiles_w;  // (wall rows of gpart: never summed into lam_U)
   hipError_t e = hipSuccess;
   if (c.D == 2) {
     if (c.Nw) hipLaunchKernelGGL((k_adj_wall<2, 2, Real>), dim3(c.Nw), t, 0, c.stream, a);
@@ -1142,14 +1147,19 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
       if (e != hipSuccess) return e;
     }
     if (c.Ni) hipLaunchKernelGGL((k_adj_collide<3, 1, Real>), dim3(c.Ni), t, lds, c.stream, a);
-    if (R == 4) {
-      if (npa) e = launch_adj_patch<3, 1, Real, 4>(c, a, ap, npa);
-      if (e != hipSuccess) return e;
-      if (c.Nw) hipLaunchKernelGGL((k_adj_transport<3, 1, Real, 4>), tw, tt, 0, c.stream, aw);
-    } else {
-      if (npa) e = launch_adj_patch<3, 1, Real, 2>(c, a, ap, npa);
-      if (e != hipSuccess) return e;
-      if (c.Nw) hipLaunchKernelGGL((k_adj_transport<3, 1, Real, 2>), tw, tt, 0, c.stream, aw);
+    if (npa) {
+      if constexpr (std::is_same<Real, float>::value) {
+        if (R == 5) e = launch_adj_patch<3, 1, Real, 5>(c, a, ap, npa);
+      } else {
+        if (R == 5) return hipErrorInvalidValue;  // (the plan takes 5 for FP32 storage only)
+      }
+      if (R == 4) e = launch_adj_patch<3, 1, Real, 4>(c, a, ap, npa);
+      if (R == 2) e = launch_adj_patch<3, 1, Real, 2>(c, a, ap, npa);
+    }
+    if (e != hipSuccess) return e;
+    if (c.Nw) {
+      if (ap.Rw == 4) hipLaunchKernelGGL((k_adj_transport<3, 1, Real, 4>), tw, tt, 0, c.stream, aw);
+      else hipLaunchKernelGGL((k_adj_transport<3, 1, Real, 2>), tw, tt, 0, c.stream, aw);
     }
   }
   const int64_t nu = static_cast<int64_t>(c.N) * c.D;

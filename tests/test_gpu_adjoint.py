@@ -105,12 +105,13 @@ def test_adjoint_step_is_the_transpose_of_the_dual_step(dim, n, nv, kn, seed):
     assert np.all(lam_U[:, k.wid != 0] == 0)
 
 
-@pytest.mark.parametrize("dim,n,nv,kn,seed", [CASES[0], CASES[2]])
+@pytest.mark.parametrize("dim,n,nv,kn,seed", [CASES[0], CASES[2], (3, 6, 10, 1.0, 3)])
 def test_adjoint_step_fp32_storage_against_the_dual_step(dim, n, nv, kn, seed):
     """FP32 storage of f and of the adjoints (FP32 arithmetic in the reverse
     transport's per-velocity work, FP64 in its lam_U reductions and in the
     other reverse kernels): the transpose identity holds to the FP32
-    rounding."""
+    rounding.  The 10^3 velocity grid takes 5 velocities per lane in the
+    interior patches and 2 in the wall kernel (different tile counts)."""
     k = AdjCase(cavity(dim, n, nv, kn=kn), seed, precision="fp32")
     c = k.c
     f, U = smooth_state(c, k.x, seed)
