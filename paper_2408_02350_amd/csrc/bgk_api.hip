@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "bgk_internal.h"
+#include "adjoint_plan.h"
 
 namespace bgk {
 

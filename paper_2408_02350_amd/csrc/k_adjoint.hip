@@ -21,6 +21,7 @@
 #include <type_traits>
 
 #include "device_common.h"
+#include "adjoint_plan.h"
 
 namespace bgk {
 
@@ -1137,9 +1138,15 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
       if (e != hipSuccess) return e;
     }
     if (c.Ni) hipLaunchKernelGGL((k_adj_collide<2, 2, Real>), dim3(c.Ni), t, lds, c.stream, a);
-    if (npa) e = launch_adj_patch<2, 2, Real, 2>(c, a, ap, npa);
-    if (e != hipSuccess) return e;
-    if (c.Nw) hipLaunchKernelGGL((k_adj_transport<2, 2, Real, 2>), tw, tt, 0, c.stream, aw);
+    if (R == 4) {
+      if (npa) e = launch_adj_patch<2, 2, Real, 4>(c, a, ap, npa);
+      if (e != hipSuccess) return e;
+      if (c.Nw) hipLaunchKernelGGL((k_adj_transport<2, 2, Real, 4>), tw, tt, 0, c.stream, aw);
+    } else {
+      if (npa) e = launch_adj_patch<2, 2, Real, 2>(c, a, ap, npa);
+      if (e != hipSuccess) return e;
+      if (c.Nw) hipLaunchKernelGGL((k_adj_transport<2, 2, Real, 2>), tw, tt, 0, c.stream, aw);
+    }
   } else {
     if (c.Nw) hipLaunchKernelGGL((k_adj_wall<3, 1, Real>), dim3(c.Nw), t, 0, c.stream, a);
     if (wall_rows) {
