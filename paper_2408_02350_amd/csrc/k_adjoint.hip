@@ -137,9 +137,9 @@ struct AdjArgs {  // Real: storage of f-sized arrays and operators (FP64 or FP32
   double* lidpart;         // [Nw] dJ/dlid contributions
   double* gpart;           // [tiles][D][N] per-tile parts of lam_U
   int tiles;
-  // reverse transport over the forward's patch unions: the per-particle
-  // kernel then runs over jlist (the wall particles) only
-  const int32_t* jlist;    // [njl] particles of the per-particle kernel (null: all N)
+  // reverse transport over the forward's patch unions (interior particles);
+  // the wall kernel runs over jlist (the wall particles)
+  const int32_t* jlist;    // [Nw] particles of the wall kernel
   const int32_t* ucount;   // [npatch]
   const int32_t* uj;       // [npatch][ucap]
   const uint32_t* ue;      // [npatch][ucap]
@@ -391,25 +391,21 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
 }
 
 // ------------------------------------------------------------ S4 adjoint
-// One wavefront per (particle j, tile of 64 groups of R velocities), for
-// interior and wall particles:
-//   lam_f_j = [j interior] lam_ft_j (1 + dt sum_k c_jk)
-//             - dt sum_{i in N_j interior, i != j} c_ij lam_ft_i
-//   lam_U_j = -dt sum_v lam_ft_j . sum_k dc_jk/dU (f_k - f_j)   (interior)
-// with c = 2 sum_a min(0, a_a.(v - U)) and dc/dU = -2 sum_{a: a_a.(v-U) < 0} a_a.
-// A thread handles groups of R consecutive velocities along the fastest
-// axis: each projection is formed once per group and advanced by a constant
-// per velocity.  The per-edge data of both directions (j's own edge to i,
-// with U_j; i's edge to j, with U_i) is staged in LDS per chunk of 32
-// neighbours; the two rows an edge needs (f^n_i for the U-derivative,
-// lam_ft_i for the transposed term) are loaded one edge ahead.  The
-// U-derivative is summed per (edge, projection) over the group and folded
-// with a_a once per edge; each tile writes its part of lam_U, and the parts
-// are summed in tile order by a second kernel (deterministic, no atomics).
+// Wall particles: not transported themselves, so their adjoint of f^n is
+// only the transposed term,
+//   lam_f_j = - dt sum_{i in N_j interior, i != j} c_ij lam_ft_i,
+// with c_ij = 2 sum_k min(0, a_k.(v - U_i)) from i's operator at the slot
+// where j sits in i's row (transposed index), and they take no part in
+// lam_U (the sum over tiles zeroes their rows).  One wavefront per (wall
+// particle, tile of 64 lanes x R velocities along the fastest axis): the
+// records (a_k, a_k.U_i) of a chunk of 32 neighbours are staged in LDS, c
+// is formed as g.w - sum_k |a_k.w| with the projections advanced by their
+// per-velocity increments, and each neighbour's lam_ft row is loaded one
+// neighbour ahead.  Arithmetic in the storage precision.
 constexpr int kAdjChunk = 32;
 
 template <typename Real, int R>
-__device__ __forceinline__ void load_rr(const Real* __restrict__ p, double (&o)[R]) {
+__device__ __forceinline__ void load_rs(const Real* __restrict__ p, Real (&o)[R]) {
   constexpr int B = R * static_cast<int>(sizeof(Real));
   constexpr int W = B % 16 == 0 ? 16 / static_cast<int>(sizeof(Real))
                                 : (B % 8 == 0 ? 8 / static_cast<int>(sizeof(Real)) : 1);
@@ -419,220 +415,132 @@ __device__ __forceinline__ void load_rr(const Real* __restrict__ p, double (&o)[
   for (int i = 0; i < R / W; ++i) {
     const V x = pv[i];
 #pragma unroll
-    for (int w = 0; w < W; ++w) o[i * W + w] = static_cast<double>(x[w]);
+    for (int w = 0; w < W; ++w) o[i * W + w] = x[w];
   }
 }
 
+
 template <int D, int NC, typename Real, int R>
-__global__ __launch_bounds__(64) void k_adj_transport(const AdjArgs<Real> a) {
-  constexpr int DD = D * D, REC = DD + 2 * D;  // a (d*d), a.U (d), a[fast]*dv (d)
-  __shared__ double rown[kAdjChunk][REC], rtr[kAdjChunk][REC];
+__global__ __launch_bounds__(64) void k_adj_transport_wall(const AdjArgs<Real> a) {
+  using A = Real;
+  constexpr int DD = D * D, REC = DD + D;  // a_k (d*d), a_k.U_i (d)
+  __shared__ A rtr[kAdjChunk][REC];
   __shared__ int32_t ri[kAdjChunk], rfl[kAdjChunk];
-  // tile-major logical order, each XCD on one contiguous range: the
-  // neighbouring particles one XCD runs together read the same row slices
+  // tile-major logical order, each XCD on one contiguous range of particles
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x), nj = gridDim.x / a.tiles;
   const int tile = lb / nj, jb = lb - tile * nj;
-  const int j = a.jlist ? a.jlist[jb] : jb;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const bool inner = a.wall_id[j] == 0;
+  const int j = a.jlist[jb];
+  const int tid = threadIdx.x;
   const size_t NVs = a.NV, cs = static_cast<size_t>(a.N) * NVs;
   const int m = min(a.ncnt[j], a.cap);
   const int64_t row = static_cast<int64_t>(j) * a.cap;
-  const double dv = 2.0 * a.vmax / static_cast<double>(a.nv - 1);
-  double Uj[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int q = 0; q < D; ++q) Uj[q] = a.U_n[static_cast<size_t>(q) * a.N + j];
-  double gU[3] = {0.0, 0.0, 0.0};
+  const A dva = static_cast<A>(2.0 * a.vmax / static_cast<double>(a.nv - 1));
   const int ngroups = a.NV / R;
+  const int g = tile * 64 + tid;
+  const bool on = g < ngroups;
+  const int q0 = on ? g * R : 0;
+  A v0[D];
   {
-    const int g = tile * nt + tid;
-    const bool on = g < ngroups;
-    const int q0 = on ? g * R : 0;
-    double v0[D];
-    {
-      int q = q0;
+    int q = q0;
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
-        v0[k] = vnode(q % a.nv, a.nv, a.vmax);
-        q /= a.nv;
-      }
+    for (int k = 0; k < D; ++k) {
+      v0[k] = static_cast<A>(vnode(q % a.nv, a.nv, a.vmax));
+      q /= a.nv;
     }
-    double lf[R][NC], lj[R][NC], fj[R][NC], csum[R];
+  }
+  A lf[R][NC];  // sum_i c_ij lam_ft_i (dt applied at the end)
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      double t1[R], t2[R];
-      load_rr<Real, R>(a.lam_ft + c * cs + static_cast<size_t>(j) * NVs + q0, t1);
-      load_rr<Real, R>(a.f_n + c * cs + static_cast<size_t>(j) * NVs + q0, t2);
+  for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        lf[r][c] = 0.0;
-        lj[r][c] = inner ? t1[r] : 0.0;
-        fj[r][c] = t2[r];
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) csum[r] = 0.0;
+    for (int c = 0; c < NC; ++c) lf[r][c] = A(0);
 
-    for (int c0 = 0; c0 < m; c0 += kAdjChunk) {
-      const int cn = min(kAdjChunk, m - c0);
-      __syncthreads();
-      for (int w = tid; w < cn; w += nt) {
-        const int e = c0 + w;
-        const int i = a.nidx[row + e];
-        const int te = a.tidx[row + e];
-        const bool own = inner && i != j, tr = te >= 0 && i != j;
-        ri[w] = i;
-        rfl[w] = (own ? 1 : 0) | (tr ? 2 : 0);
-        if (own) {
-          const Real* o = a.ops + (row + e) * DD;
+  for (int c0 = 0; c0 < m; c0 += kAdjChunk) {
+    const int cn = min(kAdjChunk, m - c0);
+    __syncthreads();  // the previous chunk is consumed
+    for (int w = tid; w < cn; w += 64) {
+      const int e = c0 + w;
+      const int i = a.nidx[row + e];
+      const int te = a.tidx[row + e];
+      const bool tr = te >= 0 && i != j;
+      ri[w] = i;
+      rfl[w] = tr ? 1 : 0;
+      if (tr) {
+        const Real* o = a.ops + (static_cast<int64_t>(i) * a.cap + te) * DD;
 #pragma unroll
-          for (int k = 0; k < D; ++k) {
-            double b = 0.0;
+        for (int k = 0; k < D; ++k) {
+          double b = 0.0;
 #pragma unroll
-            for (int mm = 0; mm < D; ++mm) {
-              const double x = static_cast<double>(o[k * D + mm]);
-              rown[w][k * D + mm] = x;
-              b = b + x * Uj[mm];
-            }
-            rown[w][DD + k] = b;
-            rown[w][DD + D + k] = static_cast<double>(o[k * D]) * dv;
+          for (int mm = 0; mm < D; ++mm) {
+            const double x = static_cast<double>(o[k * D + mm]);
+            rtr[w][k * D + mm] = static_cast<A>(x);
+            b = b + x * a.U_n[static_cast<size_t>(mm) * a.N + i];
           }
-        }
-        if (tr) {
-          const Real* o = a.ops + (static_cast<int64_t>(i) * a.cap + te) * DD;
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            double b = 0.0;
-#pragma unroll
-            for (int mm = 0; mm < D; ++mm) {
-              const double x = static_cast<double>(o[k * D + mm]);
-              rtr[w][k * D + mm] = x;
-              b = b + x * a.U_n[static_cast<size_t>(mm) * a.N + i];
-            }
-            rtr[w][DD + k] = b;
-            rtr[w][DD + D + k] = static_cast<double>(o[k * D]) * dv;
-          }
-        }
-      }
-      __syncthreads();
-      // rows of edge w: fi (f^n_i, own) and li (lam_ft_i, transposed)
-      double fa[R][NC], la[R][NC], fb[R][NC], lb[R][NC];
-      auto load_edge = [&](int w, double (&fi)[R][NC], double (&li)[R][NC]) {
-        const int i = ri[w], fl = rfl[w];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          double t[R];
-          if (fl & 1) {
-            load_rr<Real, R>(a.f_n + c * cs + static_cast<size_t>(i) * NVs + q0, t);
-#pragma unroll
-            for (int r = 0; r < R; ++r) fi[r][c] = t[r];
-          }
-          if (fl & 2) {
-            load_rr<Real, R>(a.lam_ft + c * cs + static_cast<size_t>(i) * NVs + q0, t);
-#pragma unroll
-            for (int r = 0; r < R; ++r) li[r][c] = t[r];
-          }
-        }
-        asm volatile("" ::: "memory");
-      };
-      auto edge = [&](int w, const double (&fi)[R][NC], const double (&li)[R][NC]) {
-        const int fl = rfl[w];
-        if (fl & 1) {
-          const double* rc = rown[w];
-          double p[D], S[D];
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            double s1 = -rc[DD + k];
-#pragma unroll
-            for (int mm = 0; mm < D; ++mm) s1 = s1 + rc[k * D + mm] * v0[mm];
-            p[k] = s1;
-            S[k] = 0.0;
-          }
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            if (r > 0) {
-#pragma unroll
-              for (int k = 0; k < D; ++k) p[k] = p[k] + rc[DD + D + k];
-            }
-            double cm = fmin(p[0], 0.0);
-#pragma unroll
-            for (int k = 1; k < D; ++k) cm = cm + fmin(p[k], 0.0);
-            csum[r] = csum[r] + 2.0 * cm;
-            double sdf = 0.0;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) sdf = sdf + lj[r][c] * (fi[r][c] - fj[r][c]);
-#pragma unroll
-            for (int k = 0; k < D; ++k) S[k] = S[k] + (p[k] < 0.0 ? sdf : 0.0);
-          }
-          if (on) {
-#pragma unroll
-            for (int mm = 0; mm < D; ++mm) {
-              double t = 0.0;
-#pragma unroll
-              for (int k = 0; k < D; ++k) t = t + rc[k * D + mm] * S[k];
-              gU[mm] = gU[mm] - 2.0 * t;
-            }
-          }
-        }
-        if (fl & 2) {
-          const double* rc = rtr[w];
-          double p[D];
-#pragma unroll
-          for (int k = 0; k < D; ++k) {
-            double s1 = -rc[DD + k];
-#pragma unroll
-            for (int mm = 0; mm < D; ++mm) s1 = s1 + rc[k * D + mm] * v0[mm];
-            p[k] = s1;
-          }
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            if (r > 0) {
-#pragma unroll
-              for (int k = 0; k < D; ++k) p[k] = p[k] + rc[DD + D + k];
-            }
-            double cm = fmin(p[0], 0.0);
-#pragma unroll
-            for (int k = 1; k < D; ++k) cm = cm + fmin(p[k], 0.0);
-            const double dc = a.dt * (2.0 * cm);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) lf[r][c] = lf[r][c] - dc * li[r][c];
-          }
-        }
-      };
-      load_edge(0, fa, la);
-      for (int w = 0; w < cn; w += 2) {
-        if (w + 1 < cn) load_edge(w + 1, fb, lb);
-        edge(w, fa, la);
-        if (w + 1 < cn) {
-          if (w + 2 < cn) load_edge(w + 2, fa, la);
-          edge(w + 1, fb, lb);
+          rtr[w][DD + k] = static_cast<A>(b);
         }
       }
     }
-    if (on) {
+    __syncthreads();
+    A la[R][NC], lb2[R][NC];
+    auto load_edge = [&](int w, A (&li)[R][NC]) {
+      const int i = ri[w];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        Real out[R];
+        A t[R];
+        load_rs<Real, R>(a.lam_ft + c * cs + static_cast<size_t>(i) * NVs + q0, t);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          double l = lf[r][c];
-          if (inner) l = l + lj[r][c] * (1.0 + a.dt * csum[r]);
-          out[r] = static_cast<Real>(l);
+        for (int r = 0; r < R; ++r) li[r][c] = t[r];
+      }
+      asm volatile("" ::: "memory");
+    };
+    auto edge = [&](int w, const A (&li)[R][NC]) {
+      if (!rfl[w]) return;
+      const A* rc = rtr[w];
+      A p[D], ik[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        A s1 = -rc[DD + k];
+#pragma unroll
+        for (int mm = 0; mm < D; ++mm) s1 = fma(rc[k * D + mm], v0[mm], s1);
+        p[k] = s1;
+        ik[k] = rc[k * D] * dva;
+      }
+      A gw = p[0], dgw = ik[0];
+#pragma unroll
+      for (int k = 1; k < D; ++k) {
+        gw = gw + p[k];
+        dgw = dgw + ik[k];
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (r > 0) {
+#pragma unroll
+          for (int k = 0; k < D; ++k) p[k] = p[k] + ik[k];
+          gw = gw + dgw;
         }
+        A cm = gw;  // 2 sum_k min(0, p_k)
 #pragma unroll
-        for (int r = 0; r < R; ++r) a.lam_f[c * cs + static_cast<size_t>(j) * NVs + q0 + r] = out[r];
+        for (int k = 0; k < D; ++k) cm = cm - fabs(p[k]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) lf[r][c] = fma(cm, li[r][c], lf[r][c]);
+      }
+    };
+    load_edge(0, la);
+    for (int w = 0; w < cn; w += 2) {
+      if (w + 1 < cn) load_edge(w + 1, lb2);
+      edge(w, la);
+      if (w + 1 < cn) {
+        if (w + 2 < cn) load_edge(w + 2, la);
+        edge(w + 1, lb2);
       }
     }
   }
+  if (on) {
+    const A dt = static_cast<A>(a.dt);
 #pragma unroll
-  for (int mm = 0; mm < D; ++mm) {
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) gU[mm] += __shfl_xor(gU[mm], o, 64);
-  }
-  if (tid == 0) {
-#pragma unroll
-    for (int mm = 0; mm < D; ++mm)
-      a.gpart[(static_cast<size_t>(tile) * D + mm) * a.N + j] = gU[mm];
+      for (int r = 0; r < R; ++r)
+        a.lam_f[c * cs + static_cast<size_t>(j) * NVs + q0 + r] = static_cast<Real>(-dt * lf[r][c]);
   }
 }
 
@@ -649,26 +557,11 @@ __global__ __launch_bounds__(64) void k_adj_transport(const AdjArgs<Real> a) {
 // arithmetic, half the registers of FP64 and within that storage's
 // rounding); each lane's lam_U sums are folded per edge and reduced over the
 // wave in FP64 in a fixed order.  The flux coefficient is formed as
-// g.w - sum_k |a_k.w| and the U-derivative sums from the signs of the
-// projections (the same values as the per-particle kernel's minima and
-// selects up to rounding, and the same derivative convention except at a
-// projection of exactly -0).
+// g.w - sum_k |a_k.w| (2 sum_k min(0, a_k.w) up to rounding) and the
+// U-derivative sums from the signs of the projections (the derivative of
+// the + branch at 0, except at a projection of exactly -0).
 constexpr int kAdjUChunk = 32;
 
-template <typename Real, int R>
-__device__ __forceinline__ void load_rs(const Real* __restrict__ p, Real (&o)[R]) {
-  constexpr int B = R * static_cast<int>(sizeof(Real));
-  constexpr int W = B % 16 == 0 ? 16 / static_cast<int>(sizeof(Real))
-                                : (B % 8 == 0 ? 8 / static_cast<int>(sizeof(Real)) : 1);
-  typedef Real V __attribute__((ext_vector_type(W)));
-  const V* pv = reinterpret_cast<const V*>(__builtin_assume_aligned(p, W * sizeof(Real)));
-#pragma unroll
-  for (int i = 0; i < R / W; ++i) {
-    const V x = pv[i];
-#pragma unroll
-    for (int w = 0; w < W; ++w) o[i * W + w] = x[w];
-  }
-}
 
 template <int D, int NC, typename Real, int R, int P>
 __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> a) {
@@ -1141,11 +1034,11 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
     if (R == 4) {
       if (npa) e = launch_adj_patch<2, 2, Real, 4>(c, a, ap, npa);
       if (e != hipSuccess) return e;
-      if (c.Nw) hipLaunchKernelGGL((k_adj_transport<2, 2, Real, 4>), tw, tt, 0, c.stream, aw);
+      if (c.Nw) hipLaunchKernelGGL((k_adj_transport_wall<2, 2, Real, 4>), tw, tt, 0, c.stream, aw);
     } else {
       if (npa) e = launch_adj_patch<2, 2, Real, 2>(c, a, ap, npa);
       if (e != hipSuccess) return e;
-      if (c.Nw) hipLaunchKernelGGL((k_adj_transport<2, 2, Real, 2>), tw, tt, 0, c.stream, aw);
+      if (c.Nw) hipLaunchKernelGGL((k_adj_transport_wall<2, 2, Real, 2>), tw, tt, 0, c.stream, aw);
     }
   } else {
     if (c.Nw) hipLaunchKernelGGL((k_adj_wall<3, 1, Real>), dim3(c.Nw), t, 0, c.stream, a);
@@ -1165,8 +1058,8 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
     }
     if (e != hipSuccess) return e;
     if (c.Nw) {
-      if (ap.Rw == 4) hipLaunchKernelGGL((k_adj_transport<3, 1, Real, 4>), tw, tt, 0, c.stream, aw);
-      else hipLaunchKernelGGL((k_adj_transport<3, 1, Real, 2>), tw, tt, 0, c.stream, aw);
+      if (ap.Rw == 4) hipLaunchKernelGGL((k_adj_transport_wall<3, 1, Real, 4>), tw, tt, 0, c.stream, aw);
+      else hipLaunchKernelGGL((k_adj_transport_wall<3, 1, Real, 2>), tw, tt, 0, c.stream, aw);
     }
   }
   const int64_t nu = static_cast<int64_t>(c.N) * c.D;
