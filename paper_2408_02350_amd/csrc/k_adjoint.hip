@@ -219,17 +219,86 @@ __global__ __launch_bounds__(kThreads) void k_adj_wall(const AdjArgs<Real> a) {
 }
 
 // ------------------------------------------------------------ S5-S6 adjoint
-// The velocity nodes and the per-axis factors exp(-(v_k - U_a)^2 / (2T)) of
-// the particle's Maxwellian are tabulated in LDS (dynamic, (D+1)*nv doubles):
-// M = norm * prod_a e_a[k_a], Chu G2 = T G1.  A thread's velocities are
-// q = tid + m kThreads; their per-axis indices are advanced by the digits of
-// the stride (VelDigits, no integer division per velocity), and the
-// per-particle quotients (1/T, the moment-adjoint coefficients) are formed
-// once.
-constexpr int kAdjKeep = 4;
+// Row loads and stores of R consecutive values as 16-byte (or 8-byte)
+// vectors; the row offsets the callers pass are multiples of R.
+template <typename Real, int R>
+__device__ __forceinline__ void load_rs(const Real* __restrict__ p, Real (&o)[R]) {
+  constexpr int B = R * static_cast<int>(sizeof(Real));
+  constexpr int W = B % 16 == 0 ? 16 / static_cast<int>(sizeof(Real))
+                                : (B % 8 == 0 ? 8 / static_cast<int>(sizeof(Real)) : 1);
+  typedef Real V __attribute__((ext_vector_type(W)));
+  const V* pv = reinterpret_cast<const V*>(__builtin_assume_aligned(p, W * sizeof(Real)));
+#pragma unroll
+  for (int i = 0; i < R / W; ++i) {
+    const V x = pv[i];
+#pragma unroll
+    for (int w = 0; w < W; ++w) o[i * W + w] = x[w];
+  }
+}
 
+template <typename Real, int R>
+__device__ __forceinline__ void store_rs(Real* __restrict__ p, const Real (&o)[R]) {
+  constexpr int B = R * static_cast<int>(sizeof(Real));
+  constexpr int W = B % 16 == 0 ? 16 / static_cast<int>(sizeof(Real))
+                                : (B % 8 == 0 ? 8 / static_cast<int>(sizeof(Real)) : 1);
+  typedef Real V __attribute__((ext_vector_type(W)));
+  V* pv = reinterpret_cast<V*>(__builtin_assume_aligned(p, W * sizeof(Real)));
+#pragma unroll
+  for (int i = 0; i < R / W; ++i) {
+    V x;
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = o[i * W + w];
+    pv[i] = x;
+  }
+}
 
-template <int D, int NC, typename Real>
+// Digits of a group of R consecutive nodes along the fastest velocity axis:
+// k[0] counts groups (nv/R per row of that axis), k[1..] are node indices.
+// Advanced by the digits of a fixed stride, with no division per group.
+template <int D>
+struct GroupDigits {
+  int k[D], st[D];
+  __device__ void init(int g, int stride, int ng0, int nv) {
+    k[0] = g % ng0;
+    g /= ng0;
+    st[0] = stride % ng0;
+    stride /= ng0;
+#pragma unroll
+    for (int a = 1; a < D; ++a) {
+      k[a] = g % nv;
+      g /= nv;
+      st[a] = stride % nv;
+      stride /= nv;
+    }
+  }
+  __device__ void advance(int ng0, int nv) {  // (the carry out of the last
+    int x = k[0] + st[0];                      //  digit is past the grid)
+    int carry = x >= ng0;
+    k[0] = carry ? x - ng0 : x;
+#pragma unroll
+    for (int a = 1; a < D; ++a) {
+      x = k[a] + st[a] + carry;
+      carry = x >= nv;
+      k[a] = carry ? x - nv : x;
+    }
+  }
+};
+
+// One block per interior particle.  A thread takes groups of R consecutive
+// nodes along the fastest velocity axis (group g = tid + m kThreads), so the
+// rows move as 16-byte vectors and the factors of the slower axes are formed
+// once per group.  The velocity nodes and the per-axis factors
+// exp(-(v_k - U_a)^2 / (2T)) of the particle's Maxwellian are tabulated in
+// LDS (dynamic, (D+1)*nv doubles): M = norm * prod_a e_a[k_a], Chu G2 = T G1.
+// Pass 1 gathers the adjoint of f' (lam_f1 plus what the wall rows that
+// interpolate from the particle send back) and reduces the D+3 sums of the
+// relaxation's and the moments' adjoint; pass 2 writes lam_ft.  The first
+// KEEP groups of a thread keep the adjoint of f' in registers between the
+// passes, in the storage precision (the whole row at the configured grids);
+// later groups are gathered again, or, near a wall, read back from the
+// particle's own lam_ft row, where pass 1 left them (same thread, same
+// velocities; nothing else reads the row).
+template <int D, int NC, typename Real, int R, int KEEP>
 __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a) {
   __shared__ double sh[4 * (D + 4)];
   extern __shared__ double vt[];  // nodes [nv], then factors [D][nv]
@@ -252,94 +321,107 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
   // d M / d T = M (-kap/T + |v-U|^2 / (2 T^2)), kap = d/2 (Chu G2: kap = 0)
   const double iT = 1.0 / T, h2 = 0.5 * iT * iT, kT = -kap0 * iT;
   const int ws = a.wtstart[i], we = a.wtstart[i + 1];
-  double* et = vt + a.nv;
-  for (int k = threadIdx.x; k < a.nv; k += blockDim.x) vt[k] = vnode(k, a.nv, a.vmax);
+  const int nv = a.nv, ng0 = nv / R, ng = a.NV / R;
+  double* et = vt + nv;
+  for (int k = threadIdx.x; k < nv; k += blockDim.x) vt[k] = vnode(k, nv, a.vmax);
   __syncthreads();
-  for (int t = threadIdx.x; t < D * a.nv; t += blockDim.x) {
-    const int ax = t / a.nv, k = t - ax * a.nv;
+  for (int t = threadIdx.x; t < D * nv; t += blockDim.x) {
+    const int ax = t / nv, k = t - ax * nv;
     const double d = vt[k] - U[ax];
     et[t] = exp(-(d * d) / (2.0 * T));
   }
   __syncthreads();
   const double tp = 2.0 * kPi * T;
   const double norm = D == 3 ? rho / (tp * sqrt(tp)) : rho / tp;
-  // w = v - U, |w|^2 and the Maxwellian's first component at digits kd
-  auto vel = [&](const int (&kd)[D], double (&w)[3], double& w2, double& M1) {
+  const Real* __restrict__ l1 = a.lam_f1 + static_cast<size_t>(i) * NVs;
+  const Real* __restrict__ xr = a.ft + static_cast<size_t>(i) * NVs;
+  Real* __restrict__ lrow = a.lam_ft + static_cast<size_t>(i) * NVs;
+  const bool near = we > ws;
+  // the slower axes of a group: their offsets w_a, sum w_a^2, prod e_a
+  auto slow = [&](const int (&kd)[D], double (&w)[3], double& w2s, double& Ms) {
     w[0] = w[1] = w[2] = 0.0;
-    w2 = 0.0;
-    M1 = norm;
+    w2s = 0.0;
+    Ms = norm;
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
+    for (int k = 1; k < D; ++k) {
       w[k] = vt[kd[k]] - U[k];
-      w2 = w2 + w[k] * w[k];
-      M1 = M1 * et[k * a.nv + kd[k]];
+      w2s = w2s + w[k] * w[k];
+      Ms = Ms * et[k * nv + kd[k]];
     }
   };
-  // adjoint of f' = lam_f1 + sum over the wall rows that interpolate from i.
-  // Near a wall (some rows do) the first pass keeps its gathered value in
-  // the particle's own lam_ft row, which the second pass reads back and then
-  // overwrites (same thread, same velocity; nothing else reads the row).
-  const bool keep = we > ws;
-  Real* __restrict__ lrow = a.lam_ft + static_cast<size_t>(i) * NVs;
-  auto lam_fp = [&](int c, int q) {
-    double l = a.lam_f1[c * cs + static_cast<size_t>(i) * NVs + q];
+  // adjoint of f' at a group's R nodes (component c), rounded to storage
+  auto gather = [&](int c, size_t q, Real (&o)[R]) {
+    load_rs<Real, R>(l1 + c * cs + q, o);
+    if (!near) return;
+    double l[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) l[r] = static_cast<double>(o[r]);
     for (int p = ws; p < we; ++p) {
       const int kk = a.wt[p] >> 8, e = a.wt[p] & 0xFF;
-      l = l + a.wc0[static_cast<size_t>(kk) * a.cap + e] *
-                  a.larr[(static_cast<size_t>(kk) * NC + c) * NVs + q];
+      const double wgt = a.wc0[static_cast<size_t>(kk) * a.cap + e];
+      Real y[R];
+      load_rs<Real, R>(a.larr + (static_cast<size_t>(kk) * NC + c) * NVs + q, y);
+#pragma unroll
+      for (int r = 0; r < R; ++r) l[r] = l[r] + wgt * static_cast<double>(y[r]);
     }
-    return l;
+#pragma unroll
+    for (int r = 0; r < R; ++r) o[r] = static_cast<Real>(l[r]);
   };
   double s[D + 3];  // A1 = sum l M, A2 = sum l (ft - M), AU[d], AT
 #pragma unroll
   for (int k = 0; k < D + 3; ++k) s[k] = 0.0;
-  // the two inputs of one velocity
-  auto load_in = [&](int q, double (&lq)[NC], double (&xq)[NC]) {
+  auto accum = [&](size_t q, const int (&kd)[D], const Real (&lq)[NC][R]) {
+    double w[3], w2s, Ms;
+    slow(kd, w, w2s, Ms);
+    Real xq[NC][R];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      lq[c] = lam_fp(c, q);
-      xq[c] = a.ft[c * cs + static_cast<size_t>(i) * NVs + q];
-    }
-  };
-  auto accum = [&](int q, const int (&kd)[D], const double (&lq)[NC], const double (&xq)[NC]) {
-    double w[3], w2, M1;
-    vel(kd, w, w2, M1);
-    const double dlog = fma(w2, h2, kT);
+    for (int c = 0; c < NC; ++c) load_rs<Real, R>(xr + c * cs + q, xq[c]);
+    const int k0 = kd[0] * R;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const double M = c == 0 ? M1 : T * M1;
-      const double l = lq[c];
-      if (keep) lrow[c * cs + q] = static_cast<Real>(l);
-      const double x = xq[c];
-      const double lM = l * M;
-      s[0] = s[0] + lM;
-      s[1] = s[1] + l * (x - M);
+    for (int r = 0; r < R; ++r) {
+      const double w0 = vt[k0 + r] - U[0];
+      const double w2 = fma(w0, w0, w2s);
+      const double M1 = Ms * et[k0 + r];
+      const double dlog = fma(w2, h2, kT);
 #pragma unroll
-      for (int k = 0; k < D; ++k) s[2 + k] = s[2 + k] + lM * w[k];
-      s[2 + D] = s[2 + D] + lM * ((c == 1) ? w2 * h2 : dlog);
-    }
-  };
-  // the adjoint of f' at a thread's first kAdjKeep velocities is kept in
-  // registers for the second pass (the rest is gathered again)
-  double lk[kAdjKeep][NC];
-  {
-    VelDigits<D> vd;
-    vd.init(threadIdx.x, kThreads, a.nv);
-    int q = threadIdx.x;
+      for (int c = 0; c < NC; ++c) {
+        const double M = c == 0 ? M1 : T * M1;
+        const double l = static_cast<double>(lq[c][r]);
+        const double lM = l * M;
+        s[0] = s[0] + lM;
+        s[1] = fma(l, static_cast<double>(xq[c][r]) - M, s[1]);
+        s[2] = fma(lM, w0, s[2]);
 #pragma unroll
-    for (int k = 0; k < kAdjKeep; ++k, q += kThreads) {
-      if (q < a.NV) {
-        double xk[NC];
-        load_in(q, lk[k], xk);
-        accum(q, vd.k, lk[k], xk);
+        for (int k = 1; k < D; ++k) s[2 + k] = fma(lM, w[k], s[2 + k]);
+        s[2 + D] = fma(lM, (c == 1) ? w2 * h2 : dlog, s[2 + D]);
       }
-      vd.advance(a.nv);
     }
-    for (; q < a.NV; q += kThreads) {
-      double lq[NC], xq[NC];
-      load_in(q, lq, xq);
-      accum(q, vd.k, lq, xq);
-      vd.advance(a.nv);
+  };
+  Real lk[KEEP][NC][R];
+  {
+    GroupDigits<D> gd;
+    gd.init(threadIdx.x, kThreads, ng0, nv);
+    int g = threadIdx.x;
+#pragma unroll
+    for (int m = 0; m < KEEP; ++m, g += kThreads) {
+      if (g < ng) {
+        const size_t q = static_cast<size_t>(g) * R;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) gather(c, q, lk[m][c]);
+        accum(q, gd.k, lk[m]);
+      }
+      gd.advance(ng0, nv);
+    }
+    for (; g < ng; g += kThreads) {
+      const size_t q = static_cast<size_t>(g) * R;
+      Real lq[NC][R];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        gather(c, q, lq[c]);
+        if (near) store_rs<Real, R>(lrow + c * cs + q, lq[c]);
+      }
+      accum(q, gd.k, lq);
+      gd.advance(ng0, nv);
     }
   }
   block_sum<D + 3>(s, sh);
@@ -355,37 +437,44 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
   double mU[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < D; ++k) mU[k] = gU[k] * is0;
-  auto write = [&](int q, const int (&kd)[D], const double (&lq)[NC]) {
-    double w[3], w2, M1;
-    vel(kd, w, w2, M1);
-    double g0 = fma(mT, w2, m0);
+  auto write = [&](size_t q, const int (&kd)[D], const Real (&lq)[NC][R]) {
+    double w[3], w2s, Ms;
+    slow(kd, w, w2s, Ms);
+    double gs = fma(mT, w2s, m0);
 #pragma unroll
-    for (int k = 0; k < D; ++k) g0 = fma(mU[k], w[k], g0);
+    for (int k = 1; k < D; ++k) gs = fma(mU[k], w[k], gs);
+    Real o[NC][R];
+    const int k0 = kd[0] * R;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const double l = fma(ca, lq[c], c == 1 ? mT : g0);
-      a.lam_ft[c * cs + static_cast<size_t>(i) * NVs + q] = static_cast<Real>(l);
-    }
-  };
-  {
-    VelDigits<D> vd;
-    vd.init(threadIdx.x, kThreads, a.nv);
-    int q = threadIdx.x;
-#pragma unroll
-    for (int k = 0; k < kAdjKeep; ++k, q += kThreads) {
-      if (q < a.NV) write(q, vd.k, lk[k]);
-      vd.advance(a.nv);
-    }
-    auto load_l = [&](int qq, double (&lq)[NC]) {
+    for (int r = 0; r < R; ++r) {
+      const double w0 = vt[k0 + r] - U[0];
+      const double g0 = fma(mU[0], w0, fma(mT, w0 * w0, gs));
 #pragma unroll
       for (int c = 0; c < NC; ++c)
-        lq[c] = keep ? static_cast<double>(lrow[c * cs + qq]) : lam_fp(c, qq);
-    };
-    for (; q < a.NV; q += kThreads) {
-      double lq[NC];
-      load_l(q, lq);
-      write(q, vd.k, lq);
-      vd.advance(a.nv);
+        o[c][r] = static_cast<Real>(fma(ca, static_cast<double>(lq[c][r]), c == 1 ? mT : g0));
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) store_rs<Real, R>(lrow + c * cs + q, o[c]);
+  };
+  {
+    GroupDigits<D> gd;
+    gd.init(threadIdx.x, kThreads, ng0, nv);
+    int g = threadIdx.x;
+#pragma unroll
+    for (int m = 0; m < KEEP; ++m, g += kThreads) {
+      if (g < ng) write(static_cast<size_t>(g) * R, gd.k, lk[m]);
+      gd.advance(ng0, nv);
+    }
+    for (; g < ng; g += kThreads) {
+      const size_t q = static_cast<size_t>(g) * R;
+      Real lq[NC][R];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        if (near) load_rs<Real, R>(lrow + c * cs + q, lq[c]);
+        else load_rs<Real, R>(l1 + c * cs + q, lq[c]);
+      }
+      write(q, gd.k, lq);
+      gd.advance(ng0, nv);
     }
   }
 }
@@ -403,22 +492,6 @@ __global__ __launch_bounds__(kThreads) void k_adj_collide(const AdjArgs<Real> a)
 // per-velocity increments, and each neighbour's lam_ft row is loaded one
 // neighbour ahead.  Arithmetic in the storage precision.
 constexpr int kAdjChunk = 32;
-
-template <typename Real, int R>
-__device__ __forceinline__ void load_rs(const Real* __restrict__ p, Real (&o)[R]) {
-  constexpr int B = R * static_cast<int>(sizeof(Real));
-  constexpr int W = B % 16 == 0 ? 16 / static_cast<int>(sizeof(Real))
-                                : (B % 8 == 0 ? 8 / static_cast<int>(sizeof(Real)) : 1);
-  typedef Real V __attribute__((ext_vector_type(W)));
-  const V* pv = reinterpret_cast<const V*>(__builtin_assume_aligned(p, W * sizeof(Real)));
-#pragma unroll
-  for (int i = 0; i < R / W; ++i) {
-    const V x = pv[i];
-#pragma unroll
-    for (int w = 0; w < W; ++w) o[i * W + w] = x[w];
-  }
-}
-
 
 template <int D, int NC, typename Real, int R>
 __global__ __launch_bounds__(64) void k_adj_transport_wall(const AdjArgs<Real> a) {
@@ -989,6 +1062,22 @@ static hipError_t launch_adj_patch(const Ctx& c, const AdjArgs<Real>& a, const A
   return hipGetLastError();
 }
 
+// S5-S6 adjoint: 16-byte row pieces (R = 2 doubles, or 4 floats when 4
+// divides nv), and 32 registers of the adjoint of f' kept per thread.
+template <int D, int NC, typename Real>
+static void launch_adj_collide(const Ctx& c, const AdjArgs<Real>& a, dim3 t, size_t lds) {
+  constexpr int W = static_cast<int>(sizeof(Real)) / 4;
+  if constexpr (W == 1) {
+    if (c.cfg.nv % 4 == 0) {
+      constexpr int R = 4, KEEP = 32 / (R * NC);
+      hipLaunchKernelGGL((k_adj_collide<D, NC, Real, R, KEEP>), dim3(c.Ni), t, lds, c.stream, a);
+      return;
+    }
+  }
+  constexpr int R = 2, KEEP = 32 / (R * NC * W);
+  hipLaunchKernelGGL((k_adj_collide<D, NC, Real, R, KEEP>), dim3(c.Ni), t, lds, c.stream, a);
+}
+
 template <typename Real>
 static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_n,
                                  const Real* lam_f1, const double* lam_U1, const double* lam_rho1,
@@ -1030,7 +1119,7 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
       e = launch_adjoint_wallrow(c);
       if (e != hipSuccess) return e;
     }
-    if (c.Ni) hipLaunchKernelGGL((k_adj_collide<2, 2, Real>), dim3(c.Ni), t, lds, c.stream, a);
+    if (c.Ni) launch_adj_collide<2, 2, Real>(c, a, t, lds);
     if (R == 4) {
       if (npa) e = launch_adj_patch<2, 2, Real, 4>(c, a, ap, npa);
       if (e != hipSuccess) return e;
@@ -1046,7 +1135,7 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
       e = launch_adjoint_wallrow(c);
       if (e != hipSuccess) return e;
     }
-    if (c.Ni) hipLaunchKernelGGL((k_adj_collide<3, 1, Real>), dim3(c.Ni), t, lds, c.stream, a);
+    if (c.Ni) launch_adj_collide<3, 1, Real>(c, a, t, lds);
     if (npa) {
       if constexpr (std::is_same<Real, float>::value) {
         if (R == 5) e = launch_adj_patch<3, 1, Real, 5>(c, a, ap, npa);
