@@ -199,6 +199,12 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   // more than the few extra VALU operations cost.
   constexpr bool LEAN = (MODE == BGK_FP64);
   constexpr int REC = LEAN ? DD + D : DD + 2 * D + (GW ? 1 : 0);
+  // In 3D the third frame vector b has no z component, so neither has R =
+  // gamma b: the walk skips that product (the same sums, bit for bit), and
+  // the lean record stores the increment of g.w, sum_k a_k[fast] dvs, in
+  // its slot.
+  constexpr bool RZ0 = (D == 3);
+  constexpr int IG = DD - 1;  // (lean 3D records)
   constexpr int KM = TP * (D + 1);              // first-pass moment sums per thread
   constexpr int KP = pow2_at_least(KM);
   constexpr int KP2 = pow2_at_least(TP);         // second pass: one sum per particle
@@ -356,6 +362,12 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
         }
 #pragma unroll
         for (int k = 0; k < DD; ++k) rec[k] = av[k];
+        if constexpr (LEAN && GW) {
+          Real gi = av[0] * dvs;
+#pragma unroll
+          for (int k = 1; k < D; ++k) gi = gi + av[k * D] * dvs;
+          rec[IG] = gi;
+        }
       }
     }
     __syncthreads();
@@ -404,21 +416,23 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
             for (int k = 0; k < D; ++k) {
               Real s1 = -rec[DD + k];
 #pragma unroll
-              for (int m = 0; m < D; ++m) s1 = fma_t(rec[k * D + m], v0[m], s1);
+              for (int m = 0; m < D; ++m)
+                if (!(RZ0 && k == D - 1 && m == D - 1)) s1 = fma_t(rec[k * D + m], v0[m], s1);
               p[k] = s1;
               asm volatile("" ::: "memory");
             }
           } else {
             Real av[DD], bk[D];
 #pragma unroll
-            for (int k = 0; k < DD; ++k) av[k] = rec[k];
+            for (int k = 0; k < DD; ++k) av[k] = (RZ0 && k == DD - 1) ? Real(0) : rec[k];
 #pragma unroll
             for (int k = 0; k < D; ++k) bk[k] = rec[DD + k];
 #pragma unroll
             for (int k = 0; k < D; ++k) {
               Real s1 = -bk[k];
 #pragma unroll
-              for (int m = 0; m < D; ++m) s1 = fma_t(av[k * D + m], v0[m], s1);
+              for (int m = 0; m < D; ++m)
+                if (!(RZ0 && k == D - 1 && m == D - 1)) s1 = fma_t(av[k * D + m], v0[m], s1);
               p[k] = s1;
             }
           }
@@ -430,9 +444,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
 #pragma unroll
             for (int k = 1; k < D; ++k) gw = gw + p[k];
             if constexpr (LEAN) {
-              ig = ik[0];
-#pragma unroll
-              for (int k = 1; k < D; ++k) ig = ig + ik[k];
+              ig = rec[IG];
             } else {
               ig = rec[DD + 2 * D];
             }
