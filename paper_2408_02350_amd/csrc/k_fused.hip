@@ -193,10 +193,12 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   constexpr bool GW = (D == 3 && !BF);
   // record: a_k (d*d), a_k.U (d), a_k[fast]*dvs (d)[, their sum].  FP64
   // keeps only a_k and a_k.U (3D: 12 doubles, 6 instead of 8 wave-uniform
-  // 16-byte LDS reads per edge; 2D: 6 instead of 8 doubles) and forms the
-  // increments in the walk: every wave reads each record of its edges once
-  // per 2-4 velocities, and those broadcast reads occupy the LDS return path
-  // more than the few extra VALU operations cost.
+  // 16-byte LDS reads per edge; 2D: 6 instead of 8 doubles): every wave
+  // reads each record of its edges once per 2-4 velocities, and those
+  // broadcast reads occupy the LDS return path.  Its fast-axis column is
+  // held in units of the velocity step, a_k[fast] dvs, which is then the
+  // per-step increment itself, and the lane's fast velocity enters as
+  // v_fast / dvs = k_fast - (nv - 1) / 2 (exact).
   constexpr bool LEAN = (MODE == BGK_FP64);
   constexpr int REC = LEAN ? DD + D : DD + 2 * D + (GW ? 1 : 0);
   // In 3D the third frame vector b has no z component, so neither has R =
@@ -282,6 +284,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   Real v0[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) v0[k] = static_cast<Real>(vtab[kq[k]]);
+  if constexpr (LEAN) v0[0] = static_cast<Real>(kq[0]) - static_cast<Real>(0.5 * (a.nv - 1));
 
   auto load_self = [&](int t, int c, Real (&o)[R]) {
     Real tmp[R];
@@ -361,11 +364,11 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
           rec[DD + 2 * D] = gi;
         }
 #pragma unroll
-        for (int k = 0; k < DD; ++k) rec[k] = av[k];
+        for (int k = 0; k < DD; ++k) rec[k] = (LEAN && k % D == 0) ? av[k] * dvs : av[k];
         if constexpr (LEAN && GW) {
-          Real gi = av[0] * dvs;
+          Real gi = rec[0];
 #pragma unroll
-          for (int k = 1; k < D; ++k) gi = gi + av[k * D] * dvs;
+          for (int k = 1; k < D; ++k) gi = gi + rec[k * D];
           rec[IG] = gi;
         }
       }
@@ -437,7 +440,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
             }
           }
 #pragma unroll
-          for (int k = 0; k < D; ++k) ik[k] = LEAN ? rec[k * D] * dvs : rec[DD + D + k];
+          for (int k = 0; k < D; ++k) ik[k] = LEAN ? rec[k * D] : rec[DD + D + k];
           Real gw = Real(0), ig = Real(0);
           if constexpr (GW) {
             gw = p[0];
