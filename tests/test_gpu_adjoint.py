@@ -69,9 +69,12 @@ def dot(a, b):
 
 
 CASES = [(2, 8, 8, 1.0, 0), (2, 11, 6, 0.1, 1), (3, 6, 4, 1.0, 0), (3, 7, 6, 0.5, 2)]
+# a velocity grid larger than the reverse relaxation keeps in registers
+# (2D FP64: 2 x 2 x 4 values per thread, 2048 velocities per block)
+LARGE_NV = [(2, 8, 48, 1.0, 4)]
 
 
-@pytest.mark.parametrize("dim,n,nv,kn,seed", CASES)
+@pytest.mark.parametrize("dim,n,nv,kn,seed", CASES + LARGE_NV)
 def test_adjoint_step_is_the_transpose_of_the_dual_step(dim, n, nv, kn, seed):
     k = AdjCase(cavity(dim, n, nv, kn=kn), seed)
     c = k.c
@@ -105,13 +108,19 @@ def test_adjoint_step_is_the_transpose_of_the_dual_step(dim, n, nv, kn, seed):
     assert np.all(lam_U[:, k.wid != 0] == 0)
 
 
-@pytest.mark.parametrize("dim,n,nv,kn,seed", [CASES[0], CASES[2], (3, 6, 10, 1.0, 3)])
+@pytest.mark.parametrize("dim,n,nv,kn,seed", [CASES[0], CASES[2], (3, 6, 10, 1.0, 3),
+                                               (2, 8, 68, 1.0, 5), (3, 5, 24, 1.0, 6),
+                                               (3, 5, 22, 1.0, 7)])
 def test_adjoint_step_fp32_storage_against_the_dual_step(dim, n, nv, kn, seed):
     """FP32 storage of f and of the adjoints (FP32 arithmetic in the reverse
     transport's per-velocity work, FP64 in its lam_U reductions and in the
     other reverse kernels): the transpose identity holds to the FP32
     rounding.  The 10^3 velocity grid takes 5 velocities per lane in the
-    interior patches and 2 in the wall kernel (different tile counts)."""
+    interior patches and 2 in the wall kernel (different tile counts).  The
+    68^2, 24^3 and 22^3 grids are larger than what the reverse relaxation
+    keeps in registers between its passes (4096 velocities per block in 2D,
+    8192 in 3D at 4 per group, 8192 at 2 per group), so part of each row is
+    gathered a second time."""
     k = AdjCase(cavity(dim, n, nv, kn=kn), seed, precision="fp32")
     c = k.c
     f, U = smooth_state(c, k.x, seed)
