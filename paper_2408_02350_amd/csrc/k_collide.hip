@@ -257,14 +257,16 @@ __device__ __forceinline__ void store_vec(Real* __restrict__ p, const Real (&x)[
 // bit for bit, with each f_j row read once per patch.
 // The Maxwellian is a product of per-axis exponentials held in LDS, and the
 // emitted outflow sum factorises into per-axis sums.  The particle's moments
-// follow in two passes (U first, then the centred second moment).  A thread
-// re-reads only velocities it wrote itself.
+// are summed as its values are written: sum f, sum v f and the second moment
+// about the wall velocity, shifted exactly to the centred one once U is
+// known, so no row is read back.
 template <int D, int NC, typename Real, int R, int P>
 __global__ __launch_bounds__(kThreads) void k_wall_bc(const WallBcArgs a) {
   // v_k [nv], exp(-(v_k - Uw_a)^2 / (2 T_w)) [D][nv]; wall patches then
   // hold the union's weights [wucap][P] and rows [wucap]
   extern __shared__ double wtab[];
-  __shared__ double sh[16 * P * (D + 1)];
+  constexpr int SM = D + 2;  // per particle: sum f, sum v f (d), sum |v - U_w|^2 f (+ sum g2)
+  __shared__ double sh[16 * P * SM];
   __shared__ double axsum[D];
   const int nv = a.nv, hv = nv / 2;
   double* vtab = wtab;
@@ -354,11 +356,11 @@ __global__ __launch_bounds__(kThreads) void k_wall_bc(const WallBcArgs a) {
   };
 
   double inflow[P];
-  double sm[P * (D + 1)];
+  double sm[P * SM];
 #pragma unroll
   for (int t = 0; t < P; ++t) inflow[t] = 0.0;
 #pragma unroll
-  for (int kk = 0; kk < P * (D + 1); ++kk) sm[kk] = 0.0;
+  for (int kk = 0; kk < P * SM; ++kk) sm[kk] = 0.0;
   for (int g = threadIdx.x; g < G; g += blockDim.x) {
     int kq[3] = {0, 0, 0};
     const int q0 = group_q(g, off_in, kq);
@@ -408,9 +410,12 @@ __global__ __launch_bounds__(kThreads) void k_wall_bc(const WallBcArgs a) {
           for (int r = 0; r < R; ++r) s[t][c][r] = s[t][c][r] + wu * static_cast<double>(x[c][r]);
       }
     }
-    double v[3] = {0.0, 0.0, 0.0};
+    double v[3] = {0.0, 0.0, 0.0}, wfix = 0.0;
 #pragma unroll
-    for (int ax = 1; ax < D; ++ax) v[ax] = vtab[kq[ax]];
+    for (int ax = 1; ax < D; ++ax) {
+      v[ax] = vtab[kq[ax]];
+      wfix = wfix + v[ax] * v[ax];  // (U_w has no component off axis 0)
+    }
 #pragma unroll
     for (int t = 0; t < P; ++t) {
       if (bt[t] < 0) continue;
@@ -421,16 +426,19 @@ __global__ __launch_bounds__(kThreads) void k_wall_bc(const WallBcArgs a) {
 #pragma unroll
         for (int r = 0; r < R; ++r) y[r] = static_cast<Real>(s[t][c][r]);
         store_vec<Real, R>(fb + c * cs + q0, y);
-        if (c == 0) {
 #pragma unroll
-          for (int r = 0; r < R; ++r) {
+        for (int r = 0; r < R; ++r) {
+          const double x0 = static_cast<double>(y[r]);
+          if (c == 0) {
             v[0] = vtab[kq[0] + r];
-            const double x0 = static_cast<double>(y[r]);
+            const double w0 = v[0] - Uw[0];
             inflow[t] = inflow[t] + (-sgn * v[axis]) * x0;
-            sm[t * (D + 1)] = sm[t * (D + 1)] + x0;
+            sm[t * SM] = sm[t * SM] + x0;
 #pragma unroll
-            for (int ax = 0; ax < D; ++ax)
-              sm[t * (D + 1) + 1 + ax] = sm[t * (D + 1) + 1 + ax] + v[ax] * x0;
+            for (int ax = 0; ax < D; ++ax) sm[t * SM + 1 + ax] = sm[t * SM + 1 + ax] + v[ax] * x0;
+            sm[t * SM + 1 + D] = sm[t * SM + 1 + D] + (w0 * w0 + wfix) * x0;
+          } else {
+            sm[t * SM + 1 + D] = sm[t * SM + 1 + D] + x0;
           }
         }
       }
@@ -449,9 +457,12 @@ __global__ __launch_bounds__(kThreads) void k_wall_bc(const WallBcArgs a) {
   for (int g = threadIdx.x; g < G; g += blockDim.x) {
     int kq[3] = {0, 0, 0};
     const int q0 = group_q(g, off_out, kq);
-    double v[3] = {0.0, 0.0, 0.0};
+    double v[3] = {0.0, 0.0, 0.0}, wfix = 0.0;
 #pragma unroll
-    for (int ax = 1; ax < D; ++ax) v[ax] = vtab[kq[ax]];
+    for (int ax = 1; ax < D; ++ax) {
+      v[ax] = vtab[kq[ax]];
+      wfix = wfix + v[ax] * v[ax];
+    }
 #pragma unroll
     for (int t = 0; t < P; ++t) {
       if (bt[t] < 0) continue;
@@ -465,61 +476,42 @@ __global__ __launch_bounds__(kThreads) void k_wall_bc(const WallBcArgs a) {
         y[0][r] = static_cast<Real>(g1);
         if (NC == 2) y[NC - 1][r] = static_cast<Real>(Tw * g1);
         v[0] = vtab[kq[0] + r];
+        const double w0 = v[0] - Uw[0];
         const double x0 = static_cast<double>(y[0][r]);
-        sm[t * (D + 1)] = sm[t * (D + 1)] + x0;
+        sm[t * SM] = sm[t * SM] + x0;
 #pragma unroll
-        for (int ax = 0; ax < D; ++ax)
-          sm[t * (D + 1) + 1 + ax] = sm[t * (D + 1) + 1 + ax] + v[ax] * x0;
+        for (int ax = 0; ax < D; ++ax) sm[t * SM + 1 + ax] = sm[t * SM + 1 + ax] + v[ax] * x0;
+        sm[t * SM + 1 + D] = sm[t * SM + 1 + D] + (w0 * w0 + wfix) * x0;
+        if (NC == 2) sm[t * SM + 1 + D] = sm[t * SM + 1 + D] + static_cast<double>(y[NC - 1][r]);
       }
       Real* fb = f + static_cast<size_t>(bt[t]) * NVs;
 #pragma unroll
       for (int c = 0; c < NC; ++c) store_vec<Real, R>(fb + c * cs + q0, y[c]);
     }
   }
-  block_sum_n<P * (D + 1)>(sm, sh, nw);
-  double U[P][3];
+  block_sum_n<P * SM>(sm, sh, nw);
+  // the centred second moment from the sums about U_w: sum |v - U|^2 f =
+  // sum |v - U_w|^2 f - s0 |U - U_w|^2 (exact; |U - U_w| is small, so
+  // nothing cancels), without reading the row a third time
+  double U[P][3], e2[P];
 #pragma unroll
   for (int t = 0; t < P; ++t) {
     U[t][0] = U[t][1] = U[t][2] = 0.0;
+    double du = 0.0;
 #pragma unroll
-    for (int ax = 0; ax < D; ++ax) U[t][ax] = sm[t * (D + 1) + 1 + ax] / sm[t * (D + 1)];
-  }
-  double e2[P];
-#pragma unroll
-  for (int t = 0; t < P; ++t) e2[t] = 0.0;
-  for (int half = 0; half < 2; ++half) {
-    for (int g = threadIdx.x; g < G; g += blockDim.x) {
-      int kq[3] = {0, 0, 0};
-      const int q0 = group_q(g, half == 0 ? off_in : off_out, kq);
-#pragma unroll
-      for (int t = 0; t < P; ++t) {
-        if (bt[t] < 0) continue;
-        double wfix = 0.0;
-#pragma unroll
-        for (int ax = 1; ax < D; ++ax) {
-          const double wk = vtab[kq[ax]] - U[t][ax];
-          wfix = wfix + wk * wk;
-        }
-        const Real* fb = f + static_cast<size_t>(bt[t]) * NVs;
-        Real x[NC][R];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) load_vec<Real, R>(fb + c * cs + q0, x[c]);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const double w0 = vtab[kq[0] + r] - U[t][0];
-          e2[t] = e2[t] + (w0 * w0 + wfix) * static_cast<double>(x[0][r]);
-          if (NC == 2) e2[t] = e2[t] + static_cast<double>(x[NC - 1][r]);
-        }
-      }
+    for (int ax = 0; ax < D; ++ax) {
+      U[t][ax] = sm[t * SM + 1 + ax] / sm[t * SM];
+      const double d = U[t][ax] - Uw[ax];
+      du = du + d * d;
     }
+    e2[t] = sm[t * SM + 1 + D] - sm[t * SM] * du;
   }
-  block_sum_n<P>(e2, sh, nw);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int t = 0; t < P; ++t) {
       if (bt[t] < 0) continue;
       const int b = bt[t];
-      const double s0 = sm[t * (D + 1)];
+      const double s0 = sm[t * SM];
       const double rho = a.omega * s0;
       const double T = e2[t] / (3.0 * s0);
       a.rho[b] = rho;
