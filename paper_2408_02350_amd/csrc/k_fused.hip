@@ -220,7 +220,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
     Real lrec[kChunk][TP][REC];
     Post post;
   };
-  __shared__ Shared sh;
+  __shared__ __align__(16) Shared sh;
   __shared__ double vtab[kMaxNv];
   __shared__ double pstat[TP][D + 5];           // rho, U[d], T, norm, a, b
   extern __shared__ __align__(16) unsigned char fts_raw[];  // INLDS tiles
@@ -412,6 +412,15 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
         if (mask & (1u << t)) {
           const Real* rec = lrec[u][t];
           Real ik[D], p[D];
+          // up to 4 velocities per thread: the whole record in registers,
+          // read as 16-byte pieces where it is a whole number of them (one
+          // broadcast read per 16 bytes instead of one per 8)
+          constexpr bool V16 = R < 8 && (REC * sizeof(Real)) % 16 == 0;
+          Real rv[V16 ? REC : 1];
+          auto rc = [&](int k) -> Real {
+            if constexpr (V16) return rv[k];
+            return rec[k];
+          };
           if constexpr (R >= 8) {
             // many velocities per thread: read the per-edge rows one at a
             // time, so that their registers are not all live at once
@@ -425,11 +434,22 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
               asm volatile("" ::: "memory");
             }
           } else {
+            if constexpr (V16) {
+              constexpr int W = 16 / static_cast<int>(sizeof(Real));
+              typedef Real V __attribute__((ext_vector_type(W)));
+              const V* rp = reinterpret_cast<const V*>(__builtin_assume_aligned(rec, 16));
+#pragma unroll
+              for (int i = 0; i < REC / W; ++i) {
+                const V x = rp[i];
+#pragma unroll
+                for (int w = 0; w < W; ++w) rv[i * W + w] = x[w];
+              }
+            }
             Real av[DD], bk[D];
 #pragma unroll
-            for (int k = 0; k < DD; ++k) av[k] = (RZ0 && k == DD - 1) ? Real(0) : rec[k];
+            for (int k = 0; k < DD; ++k) av[k] = (RZ0 && k == DD - 1) ? Real(0) : rc(k);
 #pragma unroll
-            for (int k = 0; k < D; ++k) bk[k] = rec[DD + k];
+            for (int k = 0; k < D; ++k) bk[k] = rc(DD + k);
 #pragma unroll
             for (int k = 0; k < D; ++k) {
               Real s1 = -bk[k];
@@ -440,16 +460,16 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
             }
           }
 #pragma unroll
-          for (int k = 0; k < D; ++k) ik[k] = LEAN ? rec[k * D] : rec[DD + D + k];
+          for (int k = 0; k < D; ++k) ik[k] = LEAN ? rc(k * D) : rc(DD + D + k);
           Real gw = Real(0), ig = Real(0);
           if constexpr (GW) {
             gw = p[0];
 #pragma unroll
             for (int k = 1; k < D; ++k) gw = gw + p[k];
             if constexpr (LEAN) {
-              ig = rec[IG];
+              ig = rc(IG);
             } else {
-              ig = rec[DD + 2 * D];
+              ig = rc(DD + 2 * D);
             }
           }
 #pragma unroll
