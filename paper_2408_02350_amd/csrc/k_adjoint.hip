@@ -147,9 +147,13 @@ struct AdjArgs {  // Real: storage of f-sized arrays and operators (FP64 or FP32
 };
 
 // ------------------------------------------------------------ S7 adjoint
+// The velocity nodes and the per-axis factors exp(-(v_k - U_w,a)^2 / (2 T_w))
+// of the wall Maxwellian are tabulated in LDS (dynamic, (D+1)*nv doubles),
+// and a thread's velocity digits are advanced by those of the block stride.
 template <int D, int NC, typename Real>
 __global__ __launch_bounds__(kThreads) void k_adj_wall(const AdjArgs<Real> a) {
   __shared__ double sh[4 * 4];
+  extern __shared__ double vt[];  // nodes [nv], then factors [D][nv]
   const int k = blockIdx.x;
   const int b = a.wall_list[k];
   const int w = a.wall_id[b];
@@ -170,17 +174,34 @@ __global__ __launch_bounds__(kThreads) void k_adj_wall(const AdjArgs<Real> a) {
   const double lr = a.lam_rho1 ? a.lam_rho1[b] : 0.0;
   const double lT = a.lam_T1 ? a.lam_T1[b] : 0.0;
   const double s0 = rho / a.omega;
+  const int nv = a.nv;
+  double* et = vt + nv;
+  for (int kk = threadIdx.x; kk < nv; kk += blockDim.x) vt[kk] = vnode(kk, nv, a.vmax);
+  __syncthreads();
+  for (int t = threadIdx.x; t < D * nv; t += blockDim.x) {
+    const int ax = t / nv, kk = t - ax * nv;
+    const double d = vt[kk] - Uw[ax];
+    et[t] = exp(-(d * d) / (2.0 * a.wall_T));
+  }
+  __syncthreads();
+  const double tpw = 2.0 * kPi * a.wall_T;
+  const double normw = D == 3 ? 1.0 / (tpw * sqrt(tpw)) : 1.0 / tpw;  // M[1, U_w, T_w]
   // pass 1: fluxes and the adjoint reaching rho_w and the lid
   double acc[4] = {0.0, 0.0, 0.0, 0.0};  // F_in, F_out, g_rhow, dF_out/dlid
   double glid = 0.0;
-  for (int q = threadIdx.x; q < a.NV; q += kThreads) {
-    double v[3];
-    velocity_of<D>(q, a.nv, a.vmax, v);
+  VelDigits<D> vd;
+  vd.init(threadIdx.x, kThreads, nv);
+  for (int q = threadIdx.x; q < a.NV; q += kThreads, vd.advance(nv)) {
+    double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) v[ax] = vt[vd.k[ax]];
     const double vn = sgn * v[axis];
     if (vn <= 0.0) {
       acc[0] = acc[0] + (-vn) * fb[q];
     } else {
-      const double M0 = maxwell<D>(0, 1.0, Uw, a.wall_T, v);
+      double M0 = normw;
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) M0 = M0 * et[ax * nv + vd.k[ax]];
       acc[1] = acc[1] + vn * M0;
       const double dM = (v[0] - Uw[0]) / a.wall_T;  // dM/dlid / M (lid walls)
       if (is_lid) acc[3] = acc[3] + vn * M0 * dM;
@@ -200,9 +221,11 @@ __global__ __launch_bounds__(kThreads) void k_adj_wall(const AdjArgs<Real> a) {
   const double rho_w = Fin / Fout;
   // pass 2: adjoint on the arriving (interpolated) half
   Real* lo = a.larr + static_cast<size_t>(k) * NC * NVs;
-  for (int q = threadIdx.x; q < a.NV; q += kThreads) {
-    double v[3];
-    velocity_of<D>(q, a.nv, a.vmax, v);
+  vd.init(threadIdx.x, kThreads, nv);
+  for (int q = threadIdx.x; q < a.NV; q += kThreads, vd.advance(nv)) {
+    double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) v[ax] = vt[vd.k[ax]];
     const double vn = sgn * v[axis];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -1114,7 +1137,7 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
   aw.tiles = ap.tiles_w;  // (wall rows of gpart: never summed into lam_U)
   hipError_t e = hipSuccess;
   if (c.D == 2) {
-    if (c.Nw) hipLaunchKernelGGL((k_adj_wall<2, 2, Real>), dim3(c.Nw), t, 0, c.stream, a);
+    if (c.Nw) hipLaunchKernelGGL((k_adj_wall<2, 2, Real>), dim3(c.Nw), t, lds, c.stream, a);
     if (wall_rows) {
       e = launch_adjoint_wallrow(c);
       if (e != hipSuccess) return e;
@@ -1130,7 +1153,7 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
       if (c.Nw) hipLaunchKernelGGL((k_adj_transport_wall<2, 2, Real, 2>), tw, tt, 0, c.stream, aw);
     }
   } else {
-    if (c.Nw) hipLaunchKernelGGL((k_adj_wall<3, 1, Real>), dim3(c.Nw), t, 0, c.stream, a);
+    if (c.Nw) hipLaunchKernelGGL((k_adj_wall<3, 1, Real>), dim3(c.Nw), t, lds, c.stream, a);
     if (wall_rows) {
       e = launch_adjoint_wallrow(c);
       if (e != hipSuccess) return e;
