@@ -206,7 +206,14 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   // the lean record stores the increment of g.w, sum_k a_k[fast] dvs, in
   // its slot.
   constexpr bool RZ0 = (D == 3);
-  constexpr int IG = DD - 1;  // (lean 3D records)
+  // Record layout.  Lean: the rows a_k (d*d), then a_k.U (d).  Full: for
+  // each k the row a_k followed by a_k.U (in 3D one 16-byte piece of FP32),
+  // then the increments a_k[fast] dvs (d)[, their sum].
+  constexpr int RW = LEAN ? D : D + 1;                       // stride of the rows
+  constexpr int IG = LEAN ? DD - 1 : D * RW + D;             // increment of g.w (3D)
+  auto ia = [](int k, int m) constexpr { return k * RW + m; };                // a_k[m]
+  auto ib = [](int k) constexpr { return LEAN ? DD + k : k * RW + D; };       // a_k.U
+  auto ii = [](int k) constexpr { return LEAN ? k * D : D * RW + k; };        // increment of p_k
   constexpr int KM = TP * (D + 1);              // first-pass moment sums per thread
   constexpr int KP = pow2_at_least(KM);
   constexpr int KP2 = pow2_at_least(TP);         // second pass: one sum per particle
@@ -354,21 +361,24 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
 #pragma unroll
           for (int m = 0; m < D; ++m)
             b = fma_t(av[k * D + m], static_cast<Real>(a.U[static_cast<size_t>(m) * a.N + i]), b);
-          rec[DD + k] = b;
-          if constexpr (!LEAN) rec[DD + D + k] = av[k * D] * dvs;
+          rec[ib(k)] = b;
+          if constexpr (!LEAN) rec[ii(k)] = av[k * D] * dvs;
         }
         if constexpr (GW && !LEAN) {
-          Real gi = rec[DD + D];
+          Real gi = rec[ii(0)];
 #pragma unroll
-          for (int k = 1; k < D; ++k) gi = gi + rec[DD + D + k];
-          rec[DD + 2 * D] = gi;
+          for (int k = 1; k < D; ++k) gi = gi + rec[ii(k)];
+          rec[IG] = gi;
         }
 #pragma unroll
-        for (int k = 0; k < DD; ++k) rec[k] = (LEAN && k % D == 0) ? av[k] * dvs : av[k];
-        if constexpr (LEAN && GW) {
-          Real gi = rec[0];
+        for (int k = 0; k < D; ++k)
 #pragma unroll
-          for (int k = 1; k < D; ++k) gi = gi + rec[k * D];
+          for (int m = 0; m < D; ++m)
+            rec[ia(k, m)] = (LEAN && m == 0) ? av[k * D] * dvs : av[k * D + m];
+        if constexpr (LEAN && GW) {
+          Real gi = rec[ii(0)];
+#pragma unroll
+          for (int k = 1; k < D; ++k) gi = gi + rec[ii(k)];
           rec[IG] = gi;
         }
       }
@@ -426,10 +436,10 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
             // time, so that their registers are not all live at once
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-              Real s1 = -rec[DD + k];
+              Real s1 = -rec[ib(k)];
 #pragma unroll
               for (int m = 0; m < D; ++m)
-                if (!(RZ0 && k == D - 1 && m == D - 1)) s1 = fma_t(rec[k * D + m], v0[m], s1);
+                if (!(RZ0 && k == D - 1 && m == D - 1)) s1 = fma_t(rec[ia(k, m)], v0[m], s1);
               p[k] = s1;
               asm volatile("" ::: "memory");
             }
@@ -447,9 +457,12 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
             }
             Real av[DD], bk[D];
 #pragma unroll
-            for (int k = 0; k < DD; ++k) av[k] = (RZ0 && k == DD - 1) ? Real(0) : rc(k);
+            for (int k = 0; k < D; ++k)
 #pragma unroll
-            for (int k = 0; k < D; ++k) bk[k] = rc(DD + k);
+              for (int m = 0; m < D; ++m)
+                av[k * D + m] = (RZ0 && k == D - 1 && m == D - 1) ? Real(0) : rc(ia(k, m));
+#pragma unroll
+            for (int k = 0; k < D; ++k) bk[k] = rc(ib(k));
 #pragma unroll
             for (int k = 0; k < D; ++k) {
               Real s1 = -bk[k];
@@ -460,17 +473,13 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
             }
           }
 #pragma unroll
-          for (int k = 0; k < D; ++k) ik[k] = LEAN ? rc(k * D) : rc(DD + D + k);
+          for (int k = 0; k < D; ++k) ik[k] = rc(ii(k));
           Real gw = Real(0), ig = Real(0);
           if constexpr (GW) {
             gw = p[0];
 #pragma unroll
             for (int k = 1; k < D; ++k) gw = gw + p[k];
-            if constexpr (LEAN) {
-              ig = rc(IG);
-            } else {
-              ig = rc(DD + 2 * D);
-            }
+            ig = rc(IG);
           }
 #pragma unroll
           for (int r = 0; r < R; ++r) {
@@ -521,11 +530,11 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
         const Real* rec = lrec[uu][t];
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-          Real s1 = -rec[DD + k];
+          Real s1 = -rec[ib(k)];
 #pragma unroll
-          for (int m = 0; m < D; ++m) s1 = fma_t(rec[k * D + m], v0[m], s1);
+          for (int m = 0; m < D; ++m) s1 = fma_t(rec[ia(k, m)], v0[m], s1);
           p[k] = s1;
-          ik[k] = rec[DD + D + k];
+          ik[k] = rec[ii(k)];
         }
       };
       auto process2 = [&](int u, const Real (&fa)[R][NC], const Real (&fb)[R][NC]) {
