@@ -218,9 +218,11 @@ def time_particle_management(cav, reps):
 
 def time_adjoint(cav, precision, nsteps, every, reps):
     """The reverse mode on one GPU: wall time of one checkpointed rollout
-    (forward pass, then backward pass: segment recomputation plus the
-    reverse steps) and the device time of one reverse step alone
-    (bgk_adjoint_step, HIP events on the library stream, mean over reps).
+    (forward pass, then backward pass: segment recomputation keeping each
+    step's state, plus the reverse steps on them), the device time of one
+    reverse step alone (bgk_adjoint_step, which recomputes its forward step;
+    HIP events on the library stream, mean over reps), and that of the
+    reverse kernels alone (bgk_adjoint_step_kept on a kept state).
 
     Roofline of the reverse step: bytes = 3 n_c N N_v s (read the adjoint
     of f-tilde and f^n, write lam_f; s = 8 in FP64, 4 in FP32 storage);
@@ -265,6 +267,21 @@ def time_adjoint(cav, precision, nsteps, every, reps):
     torch.cuda.synchronize()
     bgk.bgk_check(c)
     step_ms = ev[0].elapsed_time(ev[1]) / reps
+    # the reverse kernels alone, on the state bgk_step_keep kept
+    f1, ft, U1 = torch.empty_like(f), torch.empty_like(f), U.clone()
+    rho1, T1 = torch.empty_like(rho), torch.empty_like(T)
+    bgk.bgk_step_keep(c, f, f1, problem.x, U1, rho1, T1, ft)
+    kept = (ft, f1, rho1, U1, T1)
+    bgk.bgk_adjoint_step_kept(c, f, U, problem.x, kept, lam_f, lam_U, None, None, out_f, out_U)
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for _ in range(reps):
+        bgk.bgk_adjoint_step_kept(c, f, U, problem.x, kept, lam_f, lam_U, None, None, out_f, out_U)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    bgk.bgk_check(c)
+    kern_ms = ev[0].elapsed_time(ev[1]) / reps
+    del f1, ft, kept
     cnt, _ = bgk.bgk_build_neighbors(c, problem.x)
     edges = int((cnt[problem.wall_id == 0] - 1).sum().item())
     s = 8 if precision == "fp64" else 4
@@ -276,6 +293,8 @@ def time_adjoint(cav, precision, nsteps, every, reps):
             "rollout_backward_ms": bwd_ms, "reverse_step_ms": step_ms,
             "reverse_step_hbm_frac": bytes_ / (step_ms * 1e-3) / (PEAK_HBM_GBS * 1e9),
             "reverse_step_alu_frac": ops / (step_ms * 1e-3) / (PEAK_VALU_TOPS * 1e12),
+            "reverse_kernels_ms": kern_ms,
+            "reverse_kernels_alu_frac": ops / (kern_ms * 1e-3) / (PEAK_VALU_TOPS * 1e12),
             "algorithmic_bytes": bytes_, "algorithmic_ops": ops}
 
 

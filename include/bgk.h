@@ -204,6 +204,17 @@ int bgk_move(bgk_ctx* ctx, double* x, const double* U);
 int bgk_step(bgk_ctx* ctx, const void* f_in, void* f_out, double* x, double* U, double* rho,
              double* T);
 
+/* bgk_step that also keeps the transported field: f_tilde receives the
+ * interior rows of f-tilde = f^n - dt sum_j c_ij (f_j - f_i) (Sec. 3.2.1,
+ * eq. explicit), the input of the relaxation; its wall rows are left
+ * untouched.  Same arguments, results and errors as bgk_step otherwise;
+ * f_tilde is f-sized, in the f storage type, and may not overlap f_in,
+ * f_out or the other arrays (BGK_EINVAL).  With the step's outputs it is
+ * what bgk_adjoint_step_kept reads, so that a reverse pass that keeps its
+ * forward states does not recompute them. */
+int bgk_step_keep(bgk_ctx* ctx, const void* f_in, void* f_out, double* x, double* U, double* rho,
+                  double* T, void* f_tilde);
+
 /* Particle management (Sec. 3.5.2, adding and removing points), plan.  The
  * paper replaces two points that come too close by one at their midpoint
  * and adds points where holes open, filling f there by least squares; it
@@ -329,6 +340,18 @@ int bgk_objective_static(bgk_ctx* ctx, const void* f, const double* rho, const d
 int bgk_adjoint_step(bgk_ctx* ctx, const void* f_n, const double* U_n, const double* x,
                      const void* lam_f1, const double* lam_U1, const double* lam_rho1,
                      const double* lam_T1, void* lam_f, double* lam_U, double* dJ_dlid);
+
+/* bgk_adjoint_step with the forward step's state supplied instead of
+ * recomputed: f_tilde, f_n1, rho_n1, U_n1, T_n1 are what bgk_step_keep(f_n,
+ * U_n) returned (f-tilde's interior rows, f^{n+1}, and the moments of n+1,
+ * each [N] or [d][N] double).  The results are those of bgk_adjoint_step on
+ * (f_n, U_n), bit for bit.  The kept arrays are inputs (no output may
+ * overlap them, BGK_EINVAL); otherwise as bgk_adjoint_step. */
+int bgk_adjoint_step_kept(bgk_ctx* ctx, const void* f_n, const double* U_n, const double* x,
+                          const void* f_tilde, const void* f_n1, const double* rho_n1,
+                          const double* U_n1, const double* T_n1, const void* lam_f1,
+                          const double* lam_U1, const double* lam_rho1, const double* lam_T1,
+                          void* lam_f, double* lam_U, double* dJ_dlid);
 
 /* Reverse mode of one full step S1-S8 with the MOVING cloud (Sec. 3.2.1 with
  * the position update; Sec. 3.4.1 least squares; Sec. 3.4.2 edge frames;

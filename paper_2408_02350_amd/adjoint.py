@@ -7,8 +7,13 @@ state (lid heat flux plus weighted kinetic energy, see ``bgk_objective``).
 
 ``rollout_objective`` wraps it in a ``torch.autograd.Function``: the forward
 pass keeps (f, U) every ``checkpoint_every`` steps; the backward pass walks
-the segments in reverse, recomputes each segment's states with ``bgk_step``
-and runs ``bgk_adjoint_step`` over them, accumulating dJ/dlid on the device.
+the segments in reverse, recomputes each segment's steps with
+``bgk_step_keep``, which also keeps what the reverse step reads (f-tilde,
+f^{n+1} and the new moments; about two f-sized arrays per step of the
+segment), and runs ``bgk_adjoint_step_kept`` over them, accumulating dJ/dlid
+on the device.  With ``keep_states=False`` the segment keeps only its
+states and every ``bgk_adjoint_step`` recomputes its step (one f-sized
+array per step, twice the forward work; the same gradients bit for bit).
 All arithmetic runs in libbgk; torch only holds the buffers.
 """
 from __future__ import annotations
@@ -35,10 +40,11 @@ class FrozenCavity:
     workload's initial cloud), e.g. where a moving-cloud run left it."""
 
     def __init__(self, cav, device="cuda", seed=None, stream=None, precision="fp64", x=None,
-                 **overrides):
+                 keep_states=True, **overrides):
         if precision not in ("fp64", "fp32"):
             raise ValueError("the reverse mode runs in fp64 or fp32 storage")
         self.cav = cav
+        self.keep_states = bool(keep_states)
         overrides = dict(overrides)
         overrides.update(move=0, flags=overrides.get("flags", 0) | B.BGK_FLAG_ADJOINT)
         self.cfg = B.config_from(cav, precision, **overrides)
@@ -112,6 +118,22 @@ class _Rollout(torch.autograd.Function):
         first = True  # only the last step's rho, T feed the objective
         for s0, s1 in reversed(segments(actx.nsteps, actx.every)):
             fs, Us = actx.saved[s0]
+            if p.keep_states:
+                steps = []
+                fa, Ua = fs, Us
+                for _ in range(s0, s1):
+                    fb, ft = torch.empty_like(fa), torch.empty_like(fa)
+                    Ub = Ua.clone()  # U^n in, U^{n+1} out
+                    rho_t, T_t = torch.empty_like(rho), torch.empty_like(rho)
+                    B.bgk_step_keep(c, fa, fb, p.x, Ub, rho_t, T_t, ft)
+                    steps.append((fa, Ua, (ft, fb, rho_t, Ub, T_t)))
+                    fa, Ua = fb, Ub
+                for fn, Un, kept in reversed(steps):
+                    B.bgk_adjoint_step_kept(c, fn, Un, p.x, kept, lam_f, lam_U,
+                                            lam_rho if first else None, None, lam_f, lam_U, dlid)
+                    first = False
+                del steps
+                continue
             states = [(fs, Us)]
             fa, Ua = fs, Us.clone()
             rho_t = torch.empty_like(rho)

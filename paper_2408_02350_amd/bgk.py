@@ -32,10 +32,10 @@ STATUS = {0: "BGK_OK", 1: "BGK_EINVAL", 2: "BGK_ENOMEM", 3: "BGK_ENBR_OVERFLOW",
 # every symbol include/bgk.h declares
 EXPORTS = ("bgk_workspace_bytes", "bgk_init", "bgk_destroy", "bgk_set_lid_velocity",
            "bgk_build_neighbors", "bgk_wls_operators", "bgk_wall_stencil", "bgk_geometry",
-           "bgk_transport", "bgk_collide", "bgk_wall_bc", "bgk_move", "bgk_step",
+           "bgk_transport", "bgk_collide", "bgk_wall_bc", "bgk_move", "bgk_step", "bgk_step_keep",
            "bgk_moments", "bgk_state_check", "bgk_maxwellian", "bgk_check", "bgk_diagnostics", "bgk_last_error",
            "bgk_timing_enable", "bgk_timing_read", "bgk_objective", "bgk_objective_static",
-           "bgk_adjoint_step", "bgk_adjoint_step_move",
+           "bgk_adjoint_step", "bgk_adjoint_step_kept", "bgk_adjoint_step_move",
            "bgk_moments_adjoint", "bgk_pm_plan", "bgk_pm_apply")
 
 
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
         "bgk_wall_bc": [vp, vp, dp, dp, dp],
         "bgk_move": [vp, dp, dp],
         "bgk_step": [vp, vp, vp, dp, dp, dp, dp],
+        "bgk_step_keep": [vp, vp, vp, dp, dp, dp, dp, vp],
         "bgk_moments": [vp, vp, dp, dp, dp],
         "bgk_state_check": [vp, vp, dp, dp, dp, dp],
         "bgk_maxwellian": [vp, dp, dp, dp, vp],
@@ -96,6 +97,7 @@ def load_library(path: str = LIB_PATH):
         "bgk_objective": [vp, vp, dp, dp, ctypes.c_double, dp, vp, dp, dp],
         "bgk_objective_static": [vp, vp, dp, dp, ctypes.c_double, dp, vp, dp, dp],
         "bgk_adjoint_step": [vp, vp, dp, dp, vp, dp, dp, dp, vp, dp, dp],
+        "bgk_adjoint_step_kept": [vp, vp, dp, dp, vp, vp, dp, dp, dp, vp, dp, dp, dp, vp, dp, dp],
         "bgk_adjoint_step_move": [vp, vp, dp, dp, vp, dp, dp, dp, dp, vp, dp, dp, dp],
         "bgk_moments_adjoint": [vp, dp, dp, dp, dp, dp, dp, vp],
         "bgk_pm_plan": [vp, dp, ctypes.c_double, ctypes.c_double,
@@ -313,6 +315,21 @@ def bgk_step(ctx: Context, f_in, f_out, x, U, rho, T):
                                         _ptr(rho), _ptr(T)), "bgk_step")
 
 
+def bgk_step_keep(ctx: Context, f_in, f_out, x, U, rho, T, f_tilde):
+    """bgk_step that also writes the interior rows of the transported field
+    into f_tilde (f-sized, the f storage type)."""
+    _f(ctx, f_in, "f_in")
+    _f(ctx, f_out, "f_out")
+    _f(ctx, f_tilde, "f_tilde")
+    _vec(ctx, x, "x")
+    _vec(ctx, U, "U")
+    _sca(ctx, rho, "rho")
+    _sca(ctx, T, "T")
+    _check(ctx, load_library().bgk_step_keep(ctx.handle, _ptr(f_in), _ptr(f_out), _ptr(x),
+                                             _ptr(U), _ptr(rho), _ptr(T), _ptr(f_tilde)),
+           "bgk_step_keep")
+
+
 def bgk_moments(ctx: Context, f, rho=None, U=None, T=None):
     _f(ctx, f, "f")
     rho = _empty(ctx, (ctx.N,), torch.float64) if rho is None else rho
@@ -420,6 +437,42 @@ def bgk_adjoint_step(ctx: Context, f_n, U_n, x, lam_f1, lam_U1=None, lam_rho1=No
     _check(ctx, load_library().bgk_adjoint_step(
         ctx.handle, _ptr(f_n), _ptr(U_n), _ptr(x), _ptr(lam_f1), _ptr(lam_U1), _ptr(lam_rho1),
         _ptr(lam_T1), _ptr(lam_f), _ptr(lam_U), _ptr(dJ_dlid)), "bgk_adjoint_step")
+    return lam_f, lam_U
+
+
+def bgk_adjoint_step_kept(ctx: Context, f_n, U_n, x, kept, lam_f1, lam_U1=None, lam_rho1=None,
+                          lam_T1=None, lam_f=None, lam_U=None, dJ_dlid=None):
+    """bgk_adjoint_step with the forward step's state supplied: kept =
+    (f_tilde, f_n1, rho_n1, U_n1, T_n1) as bgk_step_keep(f_n, U_n) left them.
+    Returns (lam_f, lam_U)."""
+    f_tilde, f_n1, rho_n1, U_n1, T_n1 = kept
+    _f(ctx, f_n, "f_n")
+    _vec(ctx, U_n, "U_n")
+    _vec(ctx, x, "x")
+    _f(ctx, f_tilde, "f_tilde")
+    _f(ctx, f_n1, "f_n1")
+    _sca(ctx, rho_n1, "rho_n1")
+    _vec(ctx, U_n1, "U_n1")
+    _sca(ctx, T_n1, "T_n1")
+    _f(ctx, lam_f1, "lam_f1")
+    if lam_U1 is not None:
+        _vec(ctx, lam_U1, "lam_U1")
+    if lam_rho1 is not None:
+        _sca(ctx, lam_rho1, "lam_rho1")
+    if lam_T1 is not None:
+        _sca(ctx, lam_T1, "lam_T1")
+    lam_f = torch.empty_like(lam_f1) if lam_f is None else lam_f
+    lam_U = _empty(ctx, (ctx.d, ctx.N), torch.float64) if lam_U is None else lam_U
+    _f(ctx, lam_f, "lam_f")
+    _vec(ctx, lam_U, "lam_U")
+    if dJ_dlid is not None:
+        _expect(dJ_dlid, torch.float64, tuple(dJ_dlid.shape), "dJ_dlid", ctx.device)
+        if dJ_dlid.numel() != 1:
+            raise ValueError("dJ_dlid must hold one element")
+    _check(ctx, load_library().bgk_adjoint_step_kept(
+        ctx.handle, _ptr(f_n), _ptr(U_n), _ptr(x), _ptr(f_tilde), _ptr(f_n1), _ptr(rho_n1),
+        _ptr(U_n1), _ptr(T_n1), _ptr(lam_f1), _ptr(lam_U1), _ptr(lam_rho1), _ptr(lam_T1),
+        _ptr(lam_f), _ptr(lam_U), _ptr(dJ_dlid)), "bgk_adjoint_step_kept")
     return lam_f, lam_U
 
 

@@ -3,11 +3,30 @@
 #ifndef BGK_ADJOINT_PLAN_H
 #define BGK_ADJOINT_PLAN_H
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 #include "bgk.h"
 
 namespace bgk {
+
+struct Ctx;
+
+// A forward step's state that the reverse step reads (f-tilde's interior
+// rows, f^{n+1}, and the moments of n+1), when the caller kept it from the
+// forward pass instead of having the reverse step recompute it.
+struct AdjState {
+  const void* ft;
+  const void* f1;
+  const double* rho1;
+  const double* U1;
+  const double* T1;
+};
+hipError_t launch_adjoint_step_kept(const Ctx& c, const void* f_n, const double* U_n,
+                                    const AdjState& s, const void* lam_f1, const double* lam_U1,
+                                    const double* lam_rho1, const double* lam_T1, void* lam_f,
+                                    double* lam_U, double* dJ_dlid);
 
 // R velocities per lane along the fastest axis for the interior patches
 // (4 when 4 divides nv, else 2; FP32 storage in 3D: 5 when 5 divides nv,

@@ -463,10 +463,11 @@ int bgk_move(bgk_ctx* ctx, double* x, const double* U) {
   return bgk::hip_fail(&c, e, "bgk_move");
 }
 
-int bgk_step(bgk_ctx* ctx, const void* f_in, void* f_out, double* x, double* U, double* rho,
-             double* T) {
-  if (!ctx || !f_in || !f_out || !x || !U || !rho || !T || f_in == f_out) return BGK_EINVAL;
-  Ctx& c = ctx->c;
+namespace {
+// One full step; f_tilde (nullable) also receives the interior rows of the
+// transported field.
+int step_impl(Ctx& c, const void* f_in, void* f_out, double* x, double* U, double* rho,
+              double* T, void* f_tilde) {
   if (c.cfg.move || !c.geom_valid) {
     const int rc = bgk::build_geometry(c, x);
     if (rc) return rc;
@@ -479,13 +480,14 @@ int bgk_step(bgk_ctx* ctx, const void* f_in, void* f_out, double* x, double* U, 
     hipEventRecord(ev0, c.stream);
   }
   const bool fused = bgk::use_fused(c);
-  hipError_t e = fused ? bgk::launch_fused(c, f_in, f_out, U, rho, U, T, true)
-                       : bgk::launch_transport(c, f_in, f_out, U);
+  void* ft = f_tilde ? f_tilde : f_out;  // (the generic path's transport output)
+  hipError_t e = fused ? bgk::launch_fused(c, f_in, f_out, U, rho, U, T, true, f_tilde)
+                       : bgk::launch_transport(c, f_in, ft, U);
   if (c.timing) {
     hipEventRecord(ev1, c.stream);
     c.timed.emplace_back(ev0, ev1);
   }
-  if (e == hipSuccess && !fused) e = bgk::launch_collide(c, f_out, f_out, rho, U, T);
+  if (e == hipSuccess && !fused) e = bgk::launch_collide(c, ft, f_out, rho, U, T);
   if (e == hipSuccess) e = bgk::launch_wall_bc(c, f_out, rho, U, T);
   if (e == hipSuccess && c.cfg.move) {
     e = bgk::launch_move(c, x, U);
@@ -495,6 +497,31 @@ int bgk_step(bgk_ctx* ctx, const void* f_in, void* f_out, double* x, double* U, 
   if (e != hipSuccess) return bgk::hip_fail(&c, e, "bgk_step");
   ++c.steps;
   return BGK_OK;
+}
+}  // namespace
+
+int bgk_step(bgk_ctx* ctx, const void* f_in, void* f_out, double* x, double* U, double* rho,
+             double* T) {
+  if (!ctx || !f_in || !f_out || !x || !U || !rho || !T || f_in == f_out) return BGK_EINVAL;
+  return step_impl(ctx->c, f_in, f_out, x, U, rho, T, nullptr);
+}
+
+int bgk_step_keep(bgk_ctx* ctx, const void* f_in, void* f_out, double* x, double* U, double* rho,
+                  double* T, void* f_tilde) {
+  if (!ctx || !f_in || !f_out || !x || !U || !rho || !T || !f_tilde || f_in == f_out)
+    return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  const size_t F = (c.cfg.precision == BGK_FP64 ? 8 : 4) * c.NC * static_cast<size_t>(c.N) * c.NV;
+  const size_t DN = sizeof(double) * c.D * static_cast<size_t>(c.N), N8 = sizeof(double) * c.N;
+  const void* other[] = {f_in, f_out, x, U, rho, T};
+  const size_t nother[] = {F, F, DN, DN, N8, N8};
+  for (int k = 0; k < 6; ++k) {
+    const char* a = static_cast<const char*>(f_tilde);
+    const char* b = static_cast<const char*>(other[k]);
+    if (a < b + nother[k] && b < a + F)
+      return bgk::fail(&c, BGK_EINVAL, "bgk_step_keep: f_tilde overlaps another argument");
+  }
+  return step_impl(c, f_in, f_out, x, U, rho, T, f_tilde);
 }
 
 int bgk_pm_plan(bgk_ctx* ctx, const double* x, double merge_radius, double hole_radius,
@@ -656,6 +683,50 @@ int bgk_adjoint_step(bgk_ctx* ctx, const void* f_n, const double* U_n, const dou
     e = bgk::launch_adjoint_step(c, f_n, U_n, lam_f1, lam_U1, lam_rho1, lam_T1, lam_f, lam_U,
                                  dJ_dlid);
   return bgk::hip_fail(&c, e, "bgk_adjoint_step");
+}
+
+int bgk_adjoint_step_kept(bgk_ctx* ctx, const void* f_n, const double* U_n, const double* x,
+                          const void* f_tilde, const void* f_n1, const double* rho_n1,
+                          const double* U_n1, const double* T_n1, const void* lam_f1,
+                          const double* lam_U1, const double* lam_rho1, const double* lam_T1,
+                          void* lam_f, double* lam_U, double* dJ_dlid) {
+  if (!ctx || !f_n || !U_n || !x || !f_tilde || !f_n1 || !rho_n1 || !U_n1 || !T_n1 || !lam_f1 ||
+      !lam_f || !lam_U)
+    return BGK_EINVAL;
+  Ctx& c = ctx->c;
+  if (!(c.cfg.flags & BGK_FLAG_ADJOINT))
+    return bgk::fail(&c, BGK_ENOTSUP, "bgk_adjoint_step_kept needs a context with BGK_FLAG_ADJOINT");
+  if (c.cfg.move)
+    return bgk::fail(&c, BGK_ENOTSUP,
+                     "bgk_adjoint_step_kept is the frozen-cloud reverse step (move = 0)");
+  const size_t F = (c.cfg.precision == BGK_FP64 ? 8 : 4) * c.NC * static_cast<size_t>(c.N) * c.NV;
+  const size_t DN = sizeof(double) * c.D * static_cast<size_t>(c.N), N8 = sizeof(double) * c.N;
+  // outputs against every input; lam_f == lam_f1 and lam_U == lam_U1 are allowed
+  const void* in[] = {f_n, U_n, x, lam_f1, lam_U1, lam_rho1, lam_T1, dJ_dlid,
+                      f_tilde, f_n1, rho_n1, U_n1, T_n1};
+  const size_t nin[] = {F, DN, DN, F, DN, N8, N8, sizeof(double), F, F, N8, DN, N8};
+  for (int k = 0; k < 13; ++k) {
+    if (overlap(lam_f, F, in[k], nin[k]) && !(k == 3 && in[k] == lam_f))
+      return bgk::fail(&c, BGK_EINVAL, "bgk_adjoint_step_kept: lam_f overlaps an input");
+    if (overlap(lam_U, DN, in[k], nin[k]) && !(k == 4 && in[k] == lam_U))
+      return bgk::fail(&c, BGK_EINVAL, "bgk_adjoint_step_kept: lam_U overlaps an input");
+  }
+  if (overlap(lam_f, F, lam_U, DN))
+    return bgk::fail(&c, BGK_EINVAL, "bgk_adjoint_step_kept: lam_f overlaps lam_U");
+  if (!c.geom_valid) {
+    const int rc = bgk::build_geometry(c, x);
+    if (rc) return rc;
+  }
+  hipError_t e = hipSuccess;
+  if (!c.adj_valid) {
+    e = bgk::launch_adjoint_transposes(c);
+    if (e != hipSuccess) return bgk::hip_fail(&c, e, "bgk_adjoint_step_kept transposes");
+    c.adj_valid = true;
+  }
+  const bgk::AdjState st{f_tilde, f_n1, rho_n1, U_n1, T_n1};
+  e = bgk::launch_adjoint_step_kept(c, f_n, U_n, st, lam_f1, lam_U1, lam_rho1, lam_T1, lam_f,
+                                    lam_U, dJ_dlid);
+  return bgk::hip_fail(&c, e, "bgk_adjoint_step_kept");
 }
 
 int bgk_adjoint_step_move(bgk_ctx* ctx, const void* f_n, const double* U_n, const double* x_n,

@@ -1105,8 +1105,10 @@ template <typename Real>
 static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_n,
                                  const Real* lam_f1, const double* lam_U1, const double* lam_rho1,
                                  const double* lam_T1, Real* lam_f, double* lam_U,
-                                 double* dJ_dlid, bool wall_rows) {
+                                 double* dJ_dlid, bool wall_rows, const AdjState* kept = nullptr) {
   const Adj& j = c.adj;
+  // the recomputed step (the adjoint workspace), or the one the caller kept
+  const AdjState st = kept ? *kept : AdjState{j.ft, j.f1, j.rho1, j.U1, j.T1};
   const Real* ops = std::is_same<Real, double>::value
                         ? reinterpret_cast<const Real*>(c.d.ops64)
                         : reinterpret_cast<const Real*>(c.d.ops32);
@@ -1114,8 +1116,8 @@ static hipError_t adjoint_step_t(const Ctx& c, const Real* f_n, const double* U_
                   c.cfg.vmax, omega_adj(c.cfg), c.cfg.kn, c.cfg.dt,  c.lid,    c.cfg.wall_T,
                   c.d.wall_id, c.d.wall_list, c.d.cperm, c.d.ncnt, c.d.nidx, j.tidx, ops,
                   c.d.wcnt,   c.d.widx,   c.d.wc0,    j.wtstart,   j.wt,     f_n,      U_n,
-                  static_cast<const Real*>(j.ft), static_cast<const Real*>(j.f1), j.rho1, j.U1,
-                  j.T1,       lam_f1,     lam_U1,     lam_rho1,    lam_T1,
+                  static_cast<const Real*>(st.ft), static_cast<const Real*>(st.f1), st.rho1, st.U1,
+                  st.T1,      lam_f1,     lam_U1,     lam_rho1,    lam_T1,
                   static_cast<Real*>(j.larr), static_cast<Real*>(j.lam_ft), lam_f, lam_U,
                   j.lidpart, j.gpart, 0,
                   nullptr,    j.ucount,   j.uj,       j.ue,        0};
@@ -1193,6 +1195,19 @@ hipError_t launch_adjoint_step(const Ctx& c, const void* f_n, const double* U_n,
   return adjoint_step_t<float>(c, static_cast<const float*>(f_n), U_n,
                                static_cast<const float*>(lam_f1), lam_U1, lam_rho1, lam_T1,
                                static_cast<float*>(lam_f), lam_U, dJ_dlid, wall_rows);
+}
+
+hipError_t launch_adjoint_step_kept(const Ctx& c, const void* f_n, const double* U_n,
+                                    const AdjState& s, const void* lam_f1, const double* lam_U1,
+                                    const double* lam_rho1, const double* lam_T1, void* lam_f,
+                                    double* lam_U, double* dJ_dlid) {
+  if (c.cfg.precision == BGK_FP64)
+    return adjoint_step_t<double>(c, static_cast<const double*>(f_n), U_n,
+                                  static_cast<const double*>(lam_f1), lam_U1, lam_rho1, lam_T1,
+                                  static_cast<double*>(lam_f), lam_U, dJ_dlid, false, &s);
+  return adjoint_step_t<float>(c, static_cast<const float*>(f_n), U_n,
+                               static_cast<const float*>(lam_f1), lam_U1, lam_rho1, lam_T1,
+                               static_cast<float*>(lam_f), lam_U, dJ_dlid, false, &s);
 }
 
 template <typename Real>

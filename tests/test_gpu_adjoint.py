@@ -164,6 +164,66 @@ def test_adjoint_step_in_place_and_deterministic():
     assert e.value.code == bgk.BGK_EINVAL
 
 
+@pytest.mark.parametrize("dim,n,nv,precision", [(2, 10, 8, "fp64"), (3, 6, 6, "fp64"),
+                                                 (3, 6, 10, "fp32"), (2, 9, 8, "fp32")])
+def test_adjoint_step_kept_is_adjoint_step(dim, n, nv, precision):
+    """The reverse step on the state bgk_step_keep kept equals the reverse
+    step that recomputes it, bit for bit; the forward step with the kept
+    field equals bgk_step, bit for bit."""
+    k = AdjCase(cavity(dim, n, nv), 5, precision=precision)
+    c = k.c
+    f, U = smooth_state(c, k.x, 5)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    fn, Un = t(f).to(dt), t(U)
+    f1, ft = torch.empty_like(fn), torch.empty_like(fn)
+    U1 = Un.clone()
+    rho1 = torch.empty(c.n_particles, dtype=torch.float64, device=DEV)
+    T1 = torch.empty_like(rho1)
+    bgk.bgk_step_keep(k.ctx, fn, f1, k.x_t, U1, rho1, T1, ft)
+    g1, gU = torch.empty_like(fn), Un.clone()
+    grho, gT = torch.empty_like(rho1), torch.empty_like(rho1)
+    bgk.bgk_step(k.ctx, fn, g1, k.x_t, gU, grho, gT)
+    bgk.bgk_check(k.ctx)
+    assert torch.equal(f1, g1) and torch.equal(U1, gU) and torch.equal(rho1, grho)
+    assert torch.equal(T1, gT)
+    rng = np.random.default_rng(11)
+    lf = t(rng.normal(size=f.shape)).to(dt)
+    lU, lr, lT = (t(rng.normal(size=U.shape)), t(rng.normal(size=c.n_particles)),
+                  t(rng.normal(size=c.n_particles)))
+    d1, d2 = t(np.zeros(1)), t(np.zeros(1))
+    a_f, a_U = bgk.bgk_adjoint_step(k.ctx, fn, Un, k.x_t, lf, lU, lr, lT, dJ_dlid=d1)
+    b_f, b_U = bgk.bgk_adjoint_step_kept(k.ctx, fn, Un, k.x_t, (ft, f1, rho1, U1, T1), lf, lU,
+                                         lr, lT, dJ_dlid=d2)
+    bgk.bgk_check(k.ctx)
+    assert torch.equal(a_f, b_f) and torch.equal(a_U, b_U) and torch.equal(d1, d2)
+    with pytest.raises(bgk.BgkError) as e:   # the kept field over an input of the step
+        bgk.bgk_step_keep(k.ctx, fn, f1, k.x_t, U1, rho1, T1, fn)
+    assert e.value.code == bgk.BGK_EINVAL
+    with pytest.raises(bgk.BgkError) as e:   # an output over a kept input
+        bgk.bgk_adjoint_step_kept(k.ctx, fn, Un, k.x_t, (ft, f1, rho1, U1, T1), lf, lU,
+                                  lam_f=ft)
+    assert e.value.code == bgk.BGK_EINVAL
+
+
+@pytest.mark.parametrize("dim,n,nv,precision", [(2, 9, 8, "fp64"), (3, 6, 6, "fp32")])
+def test_kept_states_give_the_same_gradients(dim, n, nv, precision):
+    """The rollout's backward pass with the kept forward states (one forward
+    evaluation per step) and with recomputing reverse steps (two): the same
+    J and gradients, bit for bit."""
+    cav = cavity(dim, n, nv, kn=0.5)
+    out = []
+    for keep in (True, False):
+        prob = FrozenCavity(cav, DEV, seed=1, precision=precision, keep_states=keep)
+        f0 = prob.rest_state().requires_grad_(True)
+        lid = torch.tensor(0.1, dtype=torch.float64, device=DEV, requires_grad=True)
+        J = rollout_objective(prob, f0, lid, 7, 3)
+        J.backward()
+        out.append((J.item(), f0.grad.clone(), lid.grad.item()))
+        del prob
+    assert out[0][0] == out[1][0] and out[0][2] == out[1][2]
+    assert torch.equal(out[0][1], out[1][1])
+
+
 def test_adjoint_step_needs_the_adjoint_workspace():
     cav = cavity(2, 8, 4)
     x, wid = make_cloud(2, 8, 0)
