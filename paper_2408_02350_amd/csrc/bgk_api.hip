@@ -464,6 +464,14 @@ int bgk_move(bgk_ctx* ctx, double* x, const double* U) {
 }
 
 namespace {
+// [a, a + na) and [b, b + nb) share a byte (null pointers share none)
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b) return false;
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
 // One full step; f_tilde (nullable) also receives the interior rows of the
 // transported field.
 int step_impl(Ctx& c, const void* f_in, void* f_out, double* x, double* U, double* rho,
@@ -515,12 +523,9 @@ int bgk_step_keep(bgk_ctx* ctx, const void* f_in, void* f_out, double* x, double
   const size_t DN = sizeof(double) * c.D * static_cast<size_t>(c.N), N8 = sizeof(double) * c.N;
   const void* other[] = {f_in, f_out, x, U, rho, T};
   const size_t nother[] = {F, F, DN, DN, N8, N8};
-  for (int k = 0; k < 6; ++k) {
-    const char* a = static_cast<const char*>(f_tilde);
-    const char* b = static_cast<const char*>(other[k]);
-    if (a < b + nother[k] && b < a + F)
+  for (int k = 0; k < 6; ++k)
+    if (overlap(f_tilde, F, other[k], nother[k]))
       return bgk::fail(&c, BGK_EINVAL, "bgk_step_keep: f_tilde overlaps another argument");
-  }
   return step_impl(c, f_in, f_out, x, U, rho, T, f_tilde);
 }
 
@@ -624,15 +629,6 @@ int bgk_objective_static(bgk_ctx* ctx, const void* f, const double* rho, const d
                                                 part),
                        "bgk_objective_static");
 }
-
-namespace {
-bool overlap(const void* a, size_t na, const void* b, size_t nb) {
-  if (!a || !b) return false;
-  const char* pa = static_cast<const char*>(a);
-  const char* pb = static_cast<const char*>(b);
-  return pa < pb + nb && pb < pa + na;
-}
-}  // namespace
 
 int bgk_adjoint_step(bgk_ctx* ctx, const void* f_n, const double* U_n, const double* x,
                      const void* lam_f1, const double* lam_U1, const double* lam_rho1,
