@@ -53,11 +53,11 @@ def smooth_state(c, x, seed):
 
 
 class AdjCase:
-    def __init__(self, cav, seed=0, precision="fp64"):
+    def __init__(self, cav, seed=0, precision="fp64", flags=0):
         self.cav = cav
         self.c = oracle.config(cav)
         self.x, self.wid = make_cloud(cav.dim, cav.n, seed)
-        cfg = bgk.config_from(cav, precision, flags=bgk.BGK_FLAG_ADJOINT)
+        cfg = bgk.config_from(cav, precision, flags=bgk.BGK_FLAG_ADJOINT | flags)
         self.fdt = bgk.f_dtype(cfg)
         say(f"adjoint case {cav.name} seed={seed} N={cav.n_particles} NV={cav.n_velocities}")
         self.ctx = bgk.bgk_init(cfg, t(self.wid))
@@ -164,13 +164,14 @@ def test_adjoint_step_in_place_and_deterministic():
     assert e.value.code == bgk.BGK_EINVAL
 
 
-@pytest.mark.parametrize("dim,n,nv,precision", [(2, 10, 8, "fp64"), (3, 6, 6, "fp64"),
-                                                 (3, 6, 10, "fp32"), (2, 9, 8, "fp32")])
-def test_adjoint_step_kept_is_adjoint_step(dim, n, nv, precision):
+@pytest.mark.parametrize("dim,n,nv,precision,flags", [
+    (2, 10, 8, "fp64", 0), (3, 6, 6, "fp64", 0), (3, 6, 10, "fp32", 0), (2, 9, 8, "fp32", 0),
+    (2, 10, 8, "fp64", bgk.BGK_FLAG_GENERIC), (3, 6, 6, "fp64", bgk.BGK_FLAG_GENERIC)])
+def test_adjoint_step_kept_is_adjoint_step(dim, n, nv, precision, flags):
     """The reverse step on the state bgk_step_keep kept equals the reverse
     step that recomputes it, bit for bit; the forward step with the kept
-    field equals bgk_step, bit for bit."""
-    k = AdjCase(cavity(dim, n, nv), 5, precision=precision)
+    field equals bgk_step, bit for bit (fused and generic transport)."""
+    k = AdjCase(cavity(dim, n, nv), 5, precision=precision, flags=flags)
     c = k.c
     f, U = smooth_state(c, k.x, 5)
     dt = torch.float64 if precision == "fp64" else torch.float32
