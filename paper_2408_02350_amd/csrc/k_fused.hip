@@ -6,11 +6,15 @@
 //   rho, U, T of ft in FP64                                           (S5)
 //   f_i^{n+1} = (tau ft_i + dt M[rho, U, T]) / (tau + dt)             (S6)
 //
-// Layout of the work: a block owns one patch; thread tid handles the R
-// consecutive velocities q = q0 + r (r < R, R divides nv), which differ
-// only in the fastest velocity component: each projection a_k.(v - U) is
-// formed once and then advanced by a constant per r (one add), and every
-// row access of a thread is one contiguous R-element vector load or store.
+// Layout of the work: a block owns one patch; thread tid handles R
+// velocities q = q0 + r zs (r < R, R divides nv) that differ only in one
+// velocity component, the stepping axis: each projection a_k.(v - U) is
+// formed once and then advanced by a constant per r (one add).  In 2D the
+// stepping axis is the fastest one, x (zs = 1: every row access of a thread
+// is one contiguous R-element vector load or store).  In 3D it is z (zs =
+// nv^2): the third frame vector has no z component, so its projection is
+// the same for all R velocities and is formed once per edge; a row access
+// is then R loads, each contiguous across the lanes of a wave.
 // The block walks the sorted union of its particles' neighbour lists in
 // chunks of one wave width: every wave holds the chunk's row indices and
 // slot masks one per lane (read back with readlane, no LDS round trip on
@@ -58,7 +62,7 @@ constexpr int kMaxNv = 64;   // velocity points per axis supported by the fused 
 
 struct FusedArgs {
   int N, NV, nv, cap, Ni, npatch, ucap, bte;  // bte: velocity lanes per block
-  double vmax, dt, kn, omega, dvs;  // dvs: velocity step between r and r+1 (fast axis)
+  double vmax, dt, kn, omega, dvs;  // dvs: velocity step between r and r+1 (stepping axis)
   const void* f;
   void* fo;          // f-tilde (unfused) or f^{n+1} (fused)
   const double* U;   // U^n
@@ -128,6 +132,39 @@ __device__ __forceinline__ void load_rb(const Real* row, uint32_t lane_off, Real
   }
 }
 
+// R elements of a row at a stride of zsb bytes (the lane's byte offset of the
+// first in lane_off; the element offsets in scalar registers).  Lanes with
+// consecutive offsets read one contiguous piece per element.
+template <typename Real, int R>
+__device__ __forceinline__ void load_rz(const Real* row, uint32_t lane_off, uint32_t zsb,
+                                        Real (&o)[R]) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<Real*>(row), 0, 0x7fffffff, 0x00020000);
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if constexpr (sizeof(Real) == 8)
+      o[r] = __builtin_bit_cast(Real, __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off, r * zsb, 0));
+    else
+      o[r] = __builtin_bit_cast(Real, __builtin_amdgcn_raw_buffer_load_b32(rs, lane_off, r * zsb, 0));
+  }
+}
+
+template <typename Real, int R>
+__device__ __forceinline__ void store_rz(Real* row, uint32_t lane_off, uint32_t zsb,
+                                         const Real (&o)[R]) {
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(row, 0, 0x7fffffff, 0x00020000);
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if constexpr (sizeof(Real) == 8)
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, o[r]), rs, lane_off, r * zsb, 0);
+    else
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, o[r]), rs, lane_off,
+                                            r * zsb, 0);
+  }
+}
+
 template <typename Real, int R>
 __device__ __forceinline__ void store_r(Real* __restrict__ p, const Real (&o)[R]) {
   constexpr int B = R * static_cast<int>(sizeof(Real));
@@ -191,29 +228,35 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   // by its own increment (|x| is a free source modifier: 3 adds per velocity
   // instead of 3 mins and 2 adds); 2D keeps 2 sum_k min(0, a_k.w) (equal cost)
   constexpr bool GW = (D == 3 && !BF);
-  // record: a_k (d*d), a_k.U (d), a_k[fast]*dvs (d)[, their sum].  FP64
+  // record: a_k (d*d), a_k.U (d), a_k[FA]*dvs (d)[, their sum].  FP64
   // keeps only a_k and a_k.U (3D: 12 doubles, 6 instead of 8 wave-uniform
   // 16-byte LDS reads per edge; 2D: 6 instead of 8 doubles): every wave
   // reads each record of its edges once per 2-4 velocities, and those
-  // broadcast reads occupy the LDS return path.  Its fast-axis column is
-  // held in units of the velocity step, a_k[fast] dvs, which is then the
-  // per-step increment itself, and the lane's fast velocity enters as
-  // v_fast / dvs = k_fast - (nv - 1) / 2 (exact).
+  // broadcast reads occupy the LDS return path.  Its column FA (the
+  // stepping axis, below) is held in units of the velocity step, a_k[FA]
+  // dvs, which is then the per-step increment itself, and the lane's
+  // velocity on that axis enters as v_FA / dvs = k_FA - (nv - 1) / 2 (exact).
   constexpr bool LEAN = (MODE == BGK_FP64);
   constexpr int REC = LEAN ? DD + D : DD + 2 * D + (GW ? 1 : 0);
   // In 3D the third frame vector b has no z component, so neither has R =
   // gamma b: the walk skips that product (the same sums, bit for bit), and
-  // the lean record stores the increment of g.w, sum_k a_k[fast] dvs, in
+  // the lean record stores the increment of g.w, sum_k a_k[FA] dvs, in
   // its slot.
   constexpr bool RZ0 = (D == 3);
+  // The R velocities of a lane step along axis FA: in 3D the z axis (memory
+  // stride nv^2), along which R.w is constant (R has no z component), so only
+  // the first KV projections advance and |R.w| is formed once per edge and
+  // lane; in 2D the fastest axis, x (stride 1).
+  constexpr int FA = (D == 3) ? D - 1 : 0;
+  constexpr int KV = (D == 3) ? D - 1 : D;
   // Record layout.  Lean: the rows a_k (d*d), then a_k.U (d).  Full: for
   // each k the row a_k followed by a_k.U (in 3D one 16-byte piece of FP32),
-  // then the increments a_k[fast] dvs (d)[, their sum].
+  // then the increments a_k[FA] dvs (d)[, their sum].
   constexpr int RW = LEAN ? D : D + 1;                       // stride of the rows
   constexpr int IG = LEAN ? DD - 1 : D * RW + D;             // increment of g.w (3D)
   auto ia = [](int k, int m) constexpr { return k * RW + m; };                // a_k[m]
   auto ib = [](int k) constexpr { return LEAN ? DD + k : k * RW + D; };       // a_k.U
-  auto ii = [](int k) constexpr { return LEAN ? k * D : D * RW + k; };        // increment of p_k
+  auto ii = [](int k) constexpr { return LEAN ? k * D + FA : D * RW + k; };   // increment of p_k
   constexpr int KM = TP * (D + 1);              // first-pass moment sums per thread
   constexpr int KP = pow2_at_least(KM);
   constexpr int KP2 = pow2_at_least(TP);         // second pass: one sum per particle
@@ -251,6 +294,17 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   const Real* __restrict__ ops = static_cast<const Real*>(a.ops);
   const size_t NVs = static_cast<size_t>(a.NV);
   const size_t cs = static_cast<size_t>(a.N) * NVs;
+  // elements between a lane's consecutive velocities
+  const int zs = FA == 0 ? 1 : a.nv * a.nv;
+  const uint32_t zsb = static_cast<uint32_t>(zs) * sizeof(Real);
+  // R velocities of this thread at row offsets q0 + r zs, from a row's base
+  auto store_v = [&](Real* base, int qq0, const Real (&o)[R]) {
+    if constexpr (FA == 0) {
+      store_r<Real, R>(base + qq0, o);
+    } else {
+      store_rz<Real, R>(base, static_cast<uint32_t>(qq0) * sizeof(Real), zsb, o);
+    }
+  };
 
   int pt[TP];
 #pragma unroll
@@ -261,11 +315,14 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   if (tid < a.nv) vtab[tid] = vnode(tid, a.nv, a.vmax);
   __syncthreads();
 
-  // velocities of this thread in tile tile0 + tl: q = q0 + r; the fast
-  // component is kq[0] + r, the others are fixed
+  // velocities of this thread in tile tile0 + tl: q = q0 + r zs; component
+  // FA is kq[FA] + r, the others are fixed.  Lane L of the patch takes the
+  // L-th group of R velocities, the groups of one z plane first (3D), so
+  // that consecutive lanes hold consecutive velocities of each plane.
   auto tile_vel = [&](int tl, bool& on, int& qq0, int (&kk)[D]) {
-    const int qs = (tile0 + tl) * (a.bte * R) + R * tid;
-    on = tid < a.bte && qs < a.NV;
+    const int L = (tile0 + tl) * a.bte + tid;
+    const int qs = FA == 0 ? R * L : L % zs + (L / zs) * zs * R;
+    on = tid < a.bte && R * L < a.NV;
     qq0 = on ? qs : 0;
     int q = qq0;
 #pragma unroll
@@ -291,11 +348,15 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
   Real v0[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) v0[k] = static_cast<Real>(vtab[kq[k]]);
-  if constexpr (LEAN) v0[0] = static_cast<Real>(kq[0]) - static_cast<Real>(0.5 * (a.nv - 1));
+  if constexpr (LEAN) v0[FA] = static_cast<Real>(kq[FA]) - static_cast<Real>(0.5 * (a.nv - 1));
 
   auto load_self = [&](int t, int c, Real (&o)[R]) {
     Real tmp[R];
-    load_r<Real, R>(f + c * cs + static_cast<size_t>(max(pt[t], 0)) * NVs + q0, tmp);
+    const Real* src = f + c * cs + static_cast<size_t>(max(pt[t], 0)) * NVs + q0;
+    if constexpr (FA == 0)
+      load_r<Real, R>(src, tmp);
+    else
+      load_rz<Real, R>(src - q0, static_cast<uint32_t>(q0) * sizeof(Real), zsb, tmp);
 #pragma unroll
     for (int r = 0; r < R; ++r) o[r] = (pt[t] >= 0 && lane_on) ? tmp[r] : Real(0);
   };
@@ -362,7 +423,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
           for (int m = 0; m < D; ++m)
             b = fma_t(av[k * D + m], static_cast<Real>(a.U[static_cast<size_t>(m) * a.N + i]), b);
           rec[ib(k)] = b;
-          if constexpr (!LEAN) rec[ii(k)] = av[k * D] * dvs;
+          if constexpr (!LEAN) rec[ii(k)] = av[k * D + FA] * dvs;
         }
         if constexpr (GW && !LEAN) {
           Real gi = rec[ii(0)];
@@ -374,7 +435,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
         for (int k = 0; k < D; ++k)
 #pragma unroll
           for (int m = 0; m < D; ++m)
-            rec[ia(k, m)] = (LEAN && m == 0) ? av[k * D] * dvs : av[k * D + m];
+            rec[ia(k, m)] = (LEAN && m == FA) ? av[k * D + m] * dvs : av[k * D + m];
         if constexpr (LEAN && GW) {
           Real gi = rec[ii(0)];
 #pragma unroll
@@ -397,7 +458,9 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         Real tmp[R];
-        if constexpr ((R * sizeof(Real)) % 16 == 0)
+        if constexpr (FA != 0)
+          load_rz<Real, R>(src + c * cs, lane_off, zsb, tmp);
+        else if constexpr ((R * sizeof(Real)) % 16 == 0)
           load_rb<Real, R>(src + c * cs, lane_off, tmp);
         else
           load_r<Real, R>(src + c * cs + q0, tmp);
@@ -473,30 +536,39 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
             }
           }
 #pragma unroll
-          for (int k = 0; k < D; ++k) ik[k] = rc(ii(k));
-          Real gw = Real(0), ig = Real(0);
+          for (int k = 0; k < KV; ++k) ik[k] = rc(ii(k));
+          // the projections past KV are constant along the lane's velocities:
+          // their terms are formed once (GW: folded into g.w)
+          Real gw = Real(0), ig = Real(0), cfix = Real(0);
           if constexpr (GW) {
             gw = p[0];
 #pragma unroll
             for (int k = 1; k < D; ++k) gw = gw + p[k];
+#pragma unroll
+            for (int k = KV; k < D; ++k) gw = gw - abs_t(p[k]);
             ig = rc(IG);
+          } else if constexpr (KV < D) {
+            cfix = min_t(p[KV], Real(0));
+#pragma unroll
+            for (int k = KV + 1; k < D; ++k) cfix = cfix + min_t(p[k], Real(0));
           }
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             if (r > 0) {
 #pragma unroll
-              for (int k = 0; k < D; ++k) p[k] = p[k] + ik[k];
+              for (int k = 0; k < KV; ++k) p[k] = p[k] + ik[k];
               if constexpr (GW) gw = gw + ig;
             }
             Real cm;
             if constexpr (GW) {
               cm = gw;  // = 2 sum_k min(0, p_k)
 #pragma unroll
-              for (int k = 0; k < D; ++k) cm = cm - abs_t(p[k]);
+              for (int k = 0; k < KV; ++k) cm = cm - abs_t(p[k]);
             } else {
               cm = min_t(p[0], Real(0));
 #pragma unroll
-              for (int k = 1; k < D; ++k) cm = cm + min_t(p[k], Real(0));
+              for (int k = 1; k < KV; ++k) cm = cm + min_t(p[k], Real(0));
+              if constexpr (KV < D) cm = cm + cfix;
             }
             if constexpr (BF) {
 #pragma unroll
@@ -649,7 +721,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
           Real tmp[R];
 #pragma unroll
           for (int r = 0; r < R; ++r) tmp[r] = ft[t][r][c];
-          store_r<Real, R>(fto + c * cs + static_cast<size_t>(pt[t]) * NVs + q0, tmp);
+          store_v(fto + c * cs + static_cast<size_t>(pt[t]) * NVs, q0, tmp);
         }
   }
   if constexpr (INLDS) {
@@ -674,7 +746,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
           Real tmp[R];
 #pragma unroll
           for (int r = 0; r < R; ++r) tmp[r] = ft[t][r][c];
-          store_r<Real, R>(fo + c * cs + static_cast<size_t>(pt[t]) * NVs + q0, tmp);
+          store_v(fo + c * cs + static_cast<size_t>(pt[t]) * NVs, q0, tmp);
         }
     return;
   } else {
@@ -715,7 +787,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
       for (int r = 0; r < R; ++r) {
         double v[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) v[k] = vtab[k == 0 ? kk[0] + r : kk[k]];
+        for (int k = 0; k < D; ++k) v[k] = vtab[k == FA ? kk[FA] + r : kk[k]];
 #pragma unroll
         for (int t = 0; t < TP; ++t) {
           const double x = ftv(tl, t, r, 0);
@@ -758,7 +830,7 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
       for (int r = 0; r < R; ++r) {
         double v[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) v[k] = vtab[k == 0 ? kk[0] + r : kk[k]];
+        for (int k = 0; k < D; ++k) v[k] = vtab[k == FA ? kk[FA] + r : kk[k]];
 #pragma unroll
         for (int t = 0; t < TP; ++t) {
           double w2 = 0.0;
@@ -830,11 +902,12 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
         const double ca = pstat[t][D + 3], cb = pstat[t][D + 4];
         double efix = norm;
 #pragma unroll
-        for (int k = 1; k < D; ++k) efix = efix * etab[t][k][kk[k]];
+        for (int k = 0; k < D; ++k)
+          if (k != FA) efix = efix * etab[t][k][kk[k]];
         Real out[NC][R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const double M1 = efix * etab[t][0][kk[0] + r];
+          const double M1 = efix * etab[t][FA][kk[FA] + r];
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
             const double M = (c == 1) ? T * M1 : M1;
@@ -843,13 +916,13 @@ __global__ __launch_bounds__(1024) void k_fused(const FusedArgs a) {
         }
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-          store_r<Real, R>(fo + c * cs + static_cast<size_t>(pt[t]) * NVs + qq0, out[c]);
+          store_v(fo + c * cs + static_cast<size_t>(pt[t]) * NVs, qq0, out[c]);
       }
     }
   }
 }
 
-// Launch plan: R velocities per thread along the fastest axis (R divides
+// Launch plan: R velocities per thread along the stepping axis (R divides
 // nv, so a thread's R velocities share every other component), at most
 // Rmax for the precision and model (the per-thread accumulators are
 // tp * R * (n_c + 1) values), and the fewest velocity tiles of at most
