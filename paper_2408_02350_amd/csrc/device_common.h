@@ -102,6 +102,39 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* sh) {
   __syncthreads();
 }
 
+// R elements of a row at a stride of zsb bytes (the lane's byte offset of the
+// first in lane_off; the element offsets in scalar registers).  Lanes with
+// consecutive offsets read one contiguous piece per element.
+template <typename Real, int R>
+__device__ __forceinline__ void load_rz(const Real* row, uint32_t lane_off, uint32_t zsb,
+                                        Real (&o)[R]) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<Real*>(row), 0, 0x7fffffff, 0x00020000);
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if constexpr (sizeof(Real) == 8)
+      o[r] = __builtin_bit_cast(Real, __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off, r * zsb, 0));
+    else
+      o[r] = __builtin_bit_cast(Real, __builtin_amdgcn_raw_buffer_load_b32(rs, lane_off, r * zsb, 0));
+  }
+}
+
+template <typename Real, int R>
+__device__ __forceinline__ void store_rz(Real* row, uint32_t lane_off, uint32_t zsb,
+                                         const Real (&o)[R]) {
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(row, 0, 0x7fffffff, 0x00020000);
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if constexpr (sizeof(Real) == 8)
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, o[r]), rs, lane_off, r * zsb, 0);
+    else
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, o[r]), rs, lane_off,
+                                            r * zsb, 0);
+  }
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  Map the hardware block id to a logical id so that each XCD works on
 // one contiguous range of logical blocks (neighbouring patches share f rows).

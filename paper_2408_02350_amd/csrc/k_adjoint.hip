@@ -662,10 +662,16 @@ constexpr int kAdjUChunk = 32;
 template <int D, int NC, typename Real, int R, int P>
 __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> a) {
   using A = Real;  // arithmetic of the per-velocity work
-  // record: a_k (d*d), a_k.U (d)[, a_k[fast] dv (d), sum_k a_k[fast] dv].
+  // record: a_k (d*d), a_k.U (d)[, a_k[FA] dv (d), sum_k a_k[FA] dv].
   // FP64 keeps a_k and a_k.U only and forms the increments per edge (fewer
   // wave-uniform LDS reads at 2-4 velocities per lane)
   constexpr bool LEAN = std::is_same<Real, double>::value;
+  // A lane's R velocities step along axis FA: x in 2D (consecutive nodes);
+  // z in 3D (stride nv^2), along which R.w is constant (R has no z
+  // component), so only the first KV projections advance, |R.w| is formed
+  // once per edge, and its U-derivative sum is sign(R.w) times the group's.
+  constexpr int FA = (D == 3) ? D - 1 : 0;
+  constexpr int KV = (D == 3) ? D - 1 : D;
   constexpr int DD = D * D, REC = LEAN ? DD + D : DD + 2 * D + 1, CH = kAdjUChunk;
   __shared__ A rown[CH][P][REC], rtr[CH][P][REC];
   __shared__ int32_t ri[CH], rfl[CH][P];
@@ -691,7 +697,17 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
   const int ngroups = a.NV / R;
   const int g = tile * 64 + lane;
   const bool on = g < ngroups;
-  const int q0 = on ? g * R : 0;
+  // groups of one z plane first (3D), so consecutive lanes read consecutive
+  // nodes of each plane
+  const int zs = FA == 0 ? 1 : a.nv * a.nv;
+  const uint32_t zsb = static_cast<uint32_t>(zs) * sizeof(Real);
+  const int q0 = on ? (FA == 0 ? g * R : g % zs + (g / zs) * zs * R) : 0;
+  const uint32_t qoff = static_cast<uint32_t>(q0) * sizeof(Real);
+  // R values of this lane from / into the row that starts at p
+  auto ldg = [&](const Real* p, A (&o)[R]) {
+    if constexpr (FA == 0) load_rs<Real, R>(p + q0, o);
+    else load_rz<Real, R>(p, qoff, zsb, o);
+  };
   A v0[D];
   {
     int q = q0;
@@ -710,8 +726,8 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
     for (int c = 0; c < NC; ++c) {
       A t1[R], t2[R];
       if (jt[t] >= 0) {
-        load_rs<Real, R>(a.lam_ft + c * cs + static_cast<size_t>(jt[t]) * NVs + q0, t1);
-        load_rs<Real, R>(a.f_n + c * cs + static_cast<size_t>(jt[t]) * NVs + q0, t2);
+        ldg(a.lam_ft + c * cs + static_cast<size_t>(jt[t]) * NVs, t1);
+        ldg(a.f_n + c * cs + static_cast<size_t>(jt[t]) * NVs, t2);
       } else {
 #pragma unroll
         for (int r = 0; r < R; ++r) t1[r] = t2[r] = A(0);
@@ -739,7 +755,7 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
         rec[m * D + mm] = static_cast<A>(xo);
         b = b + xo * a.U_n[static_cast<size_t>(mm) * a.N + k];
       }
-      const double inc = static_cast<double>(o[m * D]) * dv;
+      const double inc = static_cast<double>(o[m * D + FA]) * dv;
       rec[DD + m] = static_cast<A>(b);
       if constexpr (!LEAN) {
         rec[DD + D + m] = static_cast<A>(inc);
@@ -753,7 +769,7 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
   auto incs = [&](const A* rc, A (&ik)[D], A& dgw) {
     if constexpr (LEAN) {
 #pragma unroll
-      for (int k = 0; k < D; ++k) ik[k] = rc[k * D] * dva;
+      for (int k = 0; k < D; ++k) ik[k] = rc[k * D + FA] * dva;
       dgw = ik[0];
 #pragma unroll
       for (int k = 1; k < D; ++k) dgw = dgw + ik[k];
@@ -793,8 +809,8 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         A t1[R], t2[R];
-        load_rs<Real, R>(a.f_n + c * cs + static_cast<size_t>(i) * NVs + q0, t1);
-        load_rs<Real, R>(a.lam_ft + c * cs + static_cast<size_t>(i) * NVs + q0, t2);
+        ldg(a.f_n + c * cs + static_cast<size_t>(i) * NVs, t1);
+        ldg(a.lam_ft + c * cs + static_cast<size_t>(i) * NVs, t2);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           fi[r][c] = t1[r];
@@ -815,6 +831,9 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
       gw = p[0];
 #pragma unroll
       for (int k = 1; k < D; ++k) gw = gw + p[k];
+      // the constant projections' |.| once
+#pragma unroll
+      for (int k = KV; k < D; ++k) gw = gw - fabs(p[k]);
     };
     auto entry = [&](int w, const A (&fi)[R][NC], const A (&li)[R][NC]) {
 #pragma unroll
@@ -833,12 +852,12 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
           for (int r = 0; r < R; ++r) {
             if (r > 0) {
 #pragma unroll
-              for (int k = 0; k < D; ++k) p[k] = p[k] + ik[k];
+              for (int k = 0; k < KV; ++k) p[k] = p[k] + ik[k];
               gw = gw + dgw;
             }
             A cm = gw;  // 2 sum_k min(0, p_k)
 #pragma unroll
-            for (int k = 0; k < D; ++k) cm = cm - fabs(p[k]);
+            for (int k = 0; k < KV; ++k) cm = cm - fabs(p[k]);
             csum[t][r] = csum[t][r] + cm;
             A sdf = A(0);
 #pragma unroll
@@ -846,8 +865,11 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
             // sum over the group of [p_k < 0] sdf as (sum sdf - sum sign(p_k) sdf) / 2
             sd = sd + sdf;
 #pragma unroll
-            for (int k = 0; k < D; ++k) S[k] = fma(copysign(A(1), p[k]), sdf, S[k]);
+            for (int k = 0; k < KV; ++k) S[k] = fma(copysign(A(1), p[k]), sdf, S[k]);
           }
+          // a constant projection's sum: sign times the group's (exact)
+#pragma unroll
+          for (int k = KV; k < D; ++k) S[k] = copysign(A(1), p[k]) * sd;
           if (on) {
 #pragma unroll
             for (int k = 0; k < D; ++k) S[k] = sd - S[k];  // 2 x the sums of [p_k < 0] sdf
@@ -870,12 +892,12 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
           for (int r = 0; r < R; ++r) {
             if (r > 0) {
 #pragma unroll
-              for (int k = 0; k < D; ++k) p[k] = p[k] + ik[k];
+              for (int k = 0; k < KV; ++k) p[k] = p[k] + ik[k];
               gw = gw + dgw;
             }
             A cm = gw;
 #pragma unroll
-            for (int k = 0; k < D; ++k) cm = cm - fabs(p[k]);
+            for (int k = 0; k < KV; ++k) cm = cm - fabs(p[k]);
 #pragma unroll
             for (int c = 0; c < NC; ++c) lf[t][r][c] = fma(cm, li[r][c], lf[t][r][c]);
           }
@@ -903,9 +925,13 @@ __global__ __launch_bounds__(64) void k_adj_transport_patch(const AdjArgs<Real> 
 #pragma unroll
         for (int r = 0; r < R; ++r)
           out[r] = fma(lj[t][r][c], fma(dt, csum[t][r], A(1)), -dt * lf[t][r][c]);
+        Real* row = a.lam_f + c * cs + static_cast<size_t>(jt[t]) * NVs;
+        if constexpr (FA == 0) {
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-          a.lam_f[c * cs + static_cast<size_t>(jt[t]) * NVs + q0 + r] = out[r];
+          for (int r = 0; r < R; ++r) row[q0 + r] = out[r];
+        } else {
+          store_rz<Real, R>(row, qoff, zsb, out);
+        }
       }
     }
 #pragma unroll
