@@ -28,8 +28,8 @@ hipError_t launch_adjoint_step_kept(const Ctx& c, const void* f_n, const double*
                                     const double* lam_rho1, const double* lam_T1, void* lam_f,
                                     double* lam_U, double* dJ_dlid);
 
-// R velocities per lane along the fastest axis for the interior patches
-// (4 when 4 divides nv, else 2; FP32 storage in 3D: 5 when 5 divides nv,
+// R velocities per lane for the interior patches, stepping along z in 3D
+// and x in 2D (4 when 4 divides nv, else 2; FP32 storage in 3D: 5 when 5 divides nv,
 // with 4 velocities' set-up cost spread over 5), Rw for the per-particle
 // wall kernel (4 when 4 divides nv, else 2: at 5 its register footprint
 // halves its waves), interior patches of P = 2 particles, and the 64-lane
